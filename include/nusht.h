@@ -1,0 +1,167 @@
+/*
+ * nusht: spin-0 nonuniform spherical harmonic transforms on one AMD Instinct MI355X (gfx950).
+ *
+ * Method: arXiv:2406.14542 (cuNUSHT), Sec. II.B.  The type-2 transform (synthesis, Eq. 3)
+ * is factored as Y = N F D S (Eq. 5): S is an iso-latitude Legendre synthesis onto an
+ * equi-spaced Clenshaw-Curtis ring grid, D doubles the map over the poles onto a torus
+ * (Fig. 1), F is a 2D FFT and N a type-2 nonuniform FFT to the points.  The type-1
+ * transform (adjoint, Eq. 2) is Y^H = S^H D^H F^H N^H (Eq. 6).  N uses the
+ * exponential-of-semicircle (ES) kernel; plans are built once and reused (Sec. III).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * - Device pointers.  Every array argument of an execution call is a device pointer on the
+ *   device that was current when the plan was created (for example a torch tensor's
+ *   data_ptr()).  Nothing is copied to or from the host inside an execution call.
+ * - Coefficients: complex128, interleaved (re, im), shape [nmaps][nalm], m-major triangle
+ *   index(l, m) = m (2 lmax + 1 - m) / 2 + l for 0 <= m <= mmax, m <= l <= lmax.  Only m >= 0
+ *   is stored: the map is real, so a_{l,-m} = (-1)^m conj(a_lm) (Eq. 3 with a real field).
+ *   The imaginary part of a_l0 is ignored on input and written as 0 on output.
+ * - Maps: float64, shape [nmaps][npts], in the caller's point order.
+ * - Inner product on coefficients under which synthesis and adjoint are exact adjoints:
+ *   <a, b>_m = sum_l [Re(a_l0* b_l0) + 2 sum_{m>0} Re(a_lm* b_lm)].
+ * - Streams.  `stream` is a hipStream_t (0 = the null stream).  Execution calls only enqueue
+ *   work and return; the caller keeps the buffers alive until the stream has finished.
+ *   nusht_plan* and nusht_solve synchronise.  A plan runs on one stream at a time.
+ * - Precision.  `dtype` selects the internal precision only; user arrays are always FP64.
+ *   NUSHT_F64: everything in FP64.  NUSHT_MIXED (eps >= 1e-6): Legendre step, ring FFTs and
+ *   point coordinates in FP64; torus, 2D FFTs, deconvolution, spreading and interpolation
+ *   in FP32, with each point's grid offset formed in FP64 before the cast (Sec. IV: an FP32
+ *   nuFFT with FP32 coordinates cannot get below about 1e-4).
+ * - Errors.  Every call returns a status code; nothing is thrown across the ABI.  On error
+ *   no output is written by a call that fails validation on the host.
+ */
+#ifndef NUSHT_H
+#define NUSHT_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct nusht_plan_s* nusht_plan_t;
+
+enum { NUSHT_F64 = 0, NUSHT_MIXED = 1 };
+
+enum {
+    NUSHT_OK = 0,
+    NUSHT_EINVAL = -1,     /* bad argument (host check) or bad point (device check in plan) */
+    NUSHT_ENOMEM = -2,     /* device allocation failed */
+    NUSHT_EDEVICE = -3,    /* HIP or rocFFT call failed */
+    NUSHT_ENOCONV = -4,    /* nusht_solve reached maxiter; iterate and residual still written */
+    NUSHT_EPRECISION = -5  /* NUSHT_MIXED requested with eps < 1e-6 */
+};
+
+/* How the torus spectrum is produced from the Legendre output.
+   NUSHT_DFS_PAPER: S includes a phi-FFT per ring, D doubles the (theta, phi) ring map and F
+     is a full 2D FFT of the torus, exactly the composition of Eq. (5)/(6).
+   NUSHT_DFS_FUSED: the phi-FFT inside S and the phi half of F cancel (Sec. III, last
+     paragraphs): the doubling is applied per m in (theta, m) space and only a 1D FFT over
+     the doubled theta axis remains.  Same result up to rounding. */
+enum { NUSHT_DFS_FUSED = 0, NUSHT_DFS_PAPER = 1 };
+
+typedef struct {
+    double sigma;        /* fine-grid upsampling factor; 0 -> 2.0 */
+    int width;           /* ES kernel width w in grid cells; 0 -> from eps and sigma */
+    double beta_per_w;   /* ES shape beta = beta_per_w * w; 0 -> 0.97 pi (1 - 1/(2 sigma)) */
+    int dfs_mode;        /* NUSHT_DFS_FUSED (default) or NUSHT_DFS_PAPER */
+    int timing;          /* nonzero: record one hipEvent pair per stage (nusht_stage_times) */
+    int reserved[6];     /* must be zero */
+} nusht_plan_opts;
+
+/* Sizes a plan uses; filled by nusht_geometry_for and nusht_plan_info. */
+typedef struct {
+    int lmax, mmax;
+    int nrings;          /* N_r: CC rings theta_j = j pi / (N_r - 1), N_r >= lmax + 2 */
+    int ntorus;          /* N_t = 2 (N_r - 1): rows of the doubled map */
+    int nphi;            /* N_phi >= 2 mmax + 2, even: samples per ring */
+    int n1, n2;          /* fine grid (theta, phi), >= sigma (2 lmax + 1), sigma (2 mmax + 1) */
+    int width;           /* ES width w */
+    double beta;         /* ES shape beta */
+    double sigma;
+    int tile;            /* side of the square point-binning tiles on the fine grid */
+    int dtype;
+    int dfs_mode;
+    int64_t npts;
+    int64_t nalm;
+    int64_t ntiles_used; /* tiles holding at least one point (plan only; 0 from nusht_geometry_for) */
+} nusht_geometry;
+
+/* Number of stored coefficients for (lmax, mmax); -1 if the arguments are invalid. */
+int64_t nusht_nalm(int lmax, int mmax);
+
+/* Sizes that nusht_plan_ex would choose (host only, touches no device).
+   Returns NUSHT_EINVAL / NUSHT_EPRECISION like nusht_plan_ex. `opts` may be NULL. */
+int nusht_geometry_for(int lmax, int mmax, double eps, int dtype, const nusht_plan_opts* opts,
+                   nusht_geometry* out);
+
+/* Build a plan for `npts` points (theta in [0, pi], phi any finite value, taken mod 2 pi),
+   both device arrays of float64 that the plan copies (the caller may free them afterwards).
+   0 <= mmax <= lmax <= 16383, 1 <= npts < 2^31, 1e-14 <= eps <= 1e-1.
+   Planning (the point binning of the nuFFT, Sec. III) is done here, once, and synchronises
+   `stream`.  NUSHT_EINVAL also reports a theta outside [0, pi] or a non-finite coordinate,
+   found by a device check.  On success *out owns all device scratch until nusht_destroy. */
+int nusht_plan(int lmax, int mmax, int64_t npts, const double* theta, const double* phi,
+               double eps, int dtype, nusht_plan_t* out);
+int nusht_plan_ex(int lmax, int mmax, int64_t npts, const double* theta, const double* phi,
+                  double eps, int dtype, const nusht_plan_opts* opts, void* stream,
+                  nusht_plan_t* out);
+
+/* Fills *out with the plan's sizes. */
+int nusht_plan_info(nusht_plan_t plan, nusht_geometry* out);
+
+/* Type 2 (synthesis), Eq. (3): map[b][i] = sum_lm a_lm Y_lm(theta_i, phi_i), to accuracy eps.
+   alm: [nmaps][nalm] complex128, map: [nmaps][npts] float64, nmaps >= 1.
+   Scratch grows on the first call with a larger nmaps than before (that call allocates). */
+int nusht_synthesis(nusht_plan_t plan, const double* alm, double* map, int nmaps, void* stream);
+
+/* Type 1 (adjoint), Eq. (2): alm[b][lm] = sum_i map[b][i] conj(Y_lm(theta_i, phi_i)),
+   0 <= m <= mmax.  No quadrature weights: this is the adjoint, not an inverse (Sec. II.A). */
+int nusht_adjoint(nusht_plan_t plan, const double* map, double* alm, int nmaps, void* stream);
+
+/* Synthesis plus the derivatives of the map with respect to the point coordinates:
+   dtheta[b][i] = d map[b][i] / d theta_i, dphi[b][i] = d map[b][i] / d phi_i.  FP64 plans only
+   (NUSHT_EPRECISION otherwise).  Used for gradients with respect to lensing deflections. */
+int nusht_synthesis_deriv(nusht_plan_t plan, const double* alm, double* map, double* dtheta,
+                          double* dphi, int nmaps, void* stream);
+
+/* Iso-latitude parts on their own (the S operator of Eq. 5 and its adjoint) on the plan's
+   CC grid: ring[b][j][k] = map at (theta_j = j pi/(N_r-1), phi_k = 2 pi k / N_phi).
+   ring: [nmaps][N_r][N_phi] float64.  The adjoint returns sum_jk ring[b][j][k] Y*_lm. */
+int nusht_ring_synthesis(nusht_plan_t plan, const double* alm, double* ring, int nmaps,
+                         void* stream);
+int nusht_ring_adjoint(nusht_plan_t plan, const double* ring, double* alm, int nmaps,
+                       void* stream);
+
+/* Least-squares inverse (spec CG solve; Sec. I: iterative algorithms call the
+   transforms repeatedly).  CGLS on min || W^(1/2) (S a - d) ||_2 in the <.,.>_m geometry:
+   each iteration runs one synthesis and one adjoint plus FP64 device reductions.
+   map: d [npts] (one map); alm: in = initial iterate x0 [nalm], out = solution;
+   weights: [npts] float32 row weights W (NULL = all ones).  Stops when the recurred
+   ||d - S a|| / ||d|| <= tol, checked every iteration through one 8-byte device-to-host read,
+   and then recomputes the true residual once.  *iters, *relres (true residual) are written.
+   Returns NUSHT_ENOCONV after maxiter iterations without convergence.  Synchronises. */
+int nusht_solve(nusht_plan_t plan, const double* map, double* alm, const float* weights,
+                double tol, int maxiter, int* iters, double* relres, void* stream);
+
+/* Per-stage device times (ms) of the last execution call when the plan was built with
+   opts.timing != 0.  Synchronises on the plan's last event.  Writes up to maxn values to
+   ms and the stage names (static strings) to names (may be NULL); returns the count. */
+int nusht_stage_times(nusht_plan_t plan, double* ms, const char** names, int maxn);
+
+/* Frees everything the plan owns.  NULL is a no-op. */
+void nusht_destroy(nusht_plan_t plan);
+
+/* Static description of a status code. */
+const char* nusht_strerror(int status);
+
+/* Text naming the first failing check or HIP/rocFFT call of the calling thread's last failed
+   call (empty if none).  Valid until the next failing call on the same thread. */
+const char* nusht_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* NUSHT_H */

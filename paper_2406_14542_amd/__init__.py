@@ -1,0 +1,17 @@
+"""nusht: spin-0 nonuniform spherical harmonic transforms on one MI355X (gfx950).
+
+Thin Python binding over the C ABI of ``libnusht.so`` (declared in ``include/nusht.h``):
+argument marshalling only.  Every step of a transform runs in the library's HIP kernels
+and rocFFT; torch supplies device memory and the current stream.  Importing this package
+does not load the library; the first call does, and raises if it is missing.
+
+Method: arXiv:2406.14542 (cuNUSHT), Sec. II.B: synthesis Y = N F D S (Eq. 5) and its
+adjoint Y^H = S^H D^H F^H N^H (Eq. 6).
+"""
+from __future__ import annotations
+
+from ._binding import (  # noqa: F401
+    NUSHT_DFS_FUSED, NUSHT_DFS_PAPER, NUSHT_EDEVICE, NUSHT_EINVAL, NUSHT_ENOCONV, NUSHT_ENOMEM,
+    NUSHT_EPRECISION, NUSHT_F64, NUSHT_MIXED, NUSHT_OK, NushtError, Plan, geometry, lib,
+    library_path, nalm,
+)

@@ -1,0 +1,280 @@
+"""ctypes binding of libnusht.so (include/nusht.h), plus a torch-facing ``Plan`` wrapper.
+
+The C functions keep their names (``lib().nusht_synthesis`` ...).  ``Plan`` only checks
+shapes/dtypes/devices of torch tensors and forwards their data pointers and the current
+HIP stream; it does no arithmetic of its own.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+_SO = os.path.join(HERE, "libnusht.so")
+
+NUSHT_F64, NUSHT_MIXED = 0, 1
+NUSHT_OK, NUSHT_EINVAL, NUSHT_ENOMEM, NUSHT_EDEVICE, NUSHT_ENOCONV, NUSHT_EPRECISION = \
+    0, -1, -2, -3, -4, -5
+NUSHT_DFS_FUSED, NUSHT_DFS_PAPER = 0, 1
+
+
+class PlanOpts(ctypes.Structure):
+    _fields_ = [("sigma", ctypes.c_double), ("width", ctypes.c_int),
+                ("beta_per_w", ctypes.c_double), ("dfs_mode", ctypes.c_int),
+                ("timing", ctypes.c_int), ("reserved", ctypes.c_int * 6)]
+
+
+class Geometry(ctypes.Structure):
+    _fields_ = [("lmax", ctypes.c_int), ("mmax", ctypes.c_int), ("nrings", ctypes.c_int),
+                ("ntorus", ctypes.c_int), ("nphi", ctypes.c_int), ("n1", ctypes.c_int),
+                ("n2", ctypes.c_int), ("width", ctypes.c_int), ("beta", ctypes.c_double),
+                ("sigma", ctypes.c_double), ("tile", ctypes.c_int), ("dtype", ctypes.c_int),
+                ("dfs_mode", ctypes.c_int), ("npts", ctypes.c_int64), ("nalm", ctypes.c_int64),
+                ("ntiles_used", ctypes.c_int64)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class NushtError(RuntimeError):
+    def __init__(self, status, where, detail=""):
+        self.status = status
+        msg = f"{where}: {lib().nusht_strerror(status).decode()} ({status})"
+        if detail:
+            msg += f" [{detail}]"
+        super().__init__(msg)
+
+
+_lib = None
+_vp = ctypes.c_void_p
+_i64 = ctypes.c_int64
+
+
+def library_path() -> str:
+    return _SO
+
+
+def lib():
+    """Load libnusht.so once.  torch is imported first so that the library binds to the HIP
+    runtime and rocFFT that torch already loaded (same sonames) instead of a second copy."""
+    global _lib
+    if _lib is None:
+        import torch  # noqa: F401
+
+        if not os.path.exists(_SO):
+            raise ImportError(f"{_SO} is missing: build it with `python -m "
+                              "paper_2406_14542_amd.build` (the HIP path has no fallback)")
+        L = ctypes.CDLL(_SO)
+        sig = {
+            "nusht_nalm": (_i64, [ctypes.c_int, ctypes.c_int]),
+            "nusht_geometry_for": (ctypes.c_int, [ctypes.c_int, ctypes.c_int, ctypes.c_double,
+                                                  ctypes.c_int, ctypes.POINTER(PlanOpts),
+                                                  ctypes.POINTER(Geometry)]),
+            "nusht_plan": (ctypes.c_int, [ctypes.c_int, ctypes.c_int, _i64, _vp, _vp,
+                                          ctypes.c_double, ctypes.c_int, ctypes.POINTER(_vp)]),
+            "nusht_plan_ex": (ctypes.c_int, [ctypes.c_int, ctypes.c_int, _i64, _vp, _vp,
+                                             ctypes.c_double, ctypes.c_int,
+                                             ctypes.POINTER(PlanOpts), _vp, ctypes.POINTER(_vp)]),
+            "nusht_plan_info": (ctypes.c_int, [_vp, ctypes.POINTER(Geometry)]),
+            "nusht_synthesis": (ctypes.c_int, [_vp, _vp, _vp, ctypes.c_int, _vp]),
+            "nusht_adjoint": (ctypes.c_int, [_vp, _vp, _vp, ctypes.c_int, _vp]),
+            "nusht_synthesis_deriv": (ctypes.c_int, [_vp, _vp, _vp, _vp, _vp, ctypes.c_int,
+                                                     _vp]),
+            "nusht_ring_synthesis": (ctypes.c_int, [_vp, _vp, _vp, ctypes.c_int, _vp]),
+            "nusht_ring_adjoint": (ctypes.c_int, [_vp, _vp, _vp, ctypes.c_int, _vp]),
+            "nusht_solve": (ctypes.c_int, [_vp, _vp, _vp, _vp, ctypes.c_double, ctypes.c_int,
+                                           ctypes.POINTER(ctypes.c_int),
+                                           ctypes.POINTER(ctypes.c_double), _vp]),
+            "nusht_stage_times": (ctypes.c_int, [_vp, ctypes.POINTER(ctypes.c_double),
+                                                 ctypes.POINTER(ctypes.c_char_p), ctypes.c_int]),
+            "nusht_destroy": (None, [_vp]),
+            "nusht_strerror": (ctypes.c_char_p, [ctypes.c_int]),
+            "nusht_last_error": (ctypes.c_char_p, []),
+        }
+        for name, (res, args) in sig.items():
+            fn = getattr(L, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = L
+    return _lib
+
+
+def _check(status, where):
+    if status != NUSHT_OK:
+        raise NushtError(status, where, lib().nusht_last_error().decode())
+
+
+def nalm(lmax: int, mmax: int) -> int:
+    return int(lib().nusht_nalm(lmax, mmax))
+
+
+def _opts(sigma=0.0, width=0, beta_per_w=0.0, dfs_mode="fused", timing=False):
+    o = PlanOpts()
+    o.sigma = float(sigma)
+    o.width = int(width)
+    o.beta_per_w = float(beta_per_w)
+    o.dfs_mode = {"fused": NUSHT_DFS_FUSED, "paper": NUSHT_DFS_PAPER}[dfs_mode]
+    o.timing = 1 if timing else 0
+    return o
+
+
+def _dtype_code(dtype):
+    return {"f64": NUSHT_F64, "mixed": NUSHT_MIXED}[dtype]
+
+
+def geometry(lmax, mmax, eps, dtype="f64", **opts) -> dict:
+    """Sizes a plan would use (host-only query)."""
+    g = Geometry()
+    o = _opts(**opts)
+    _check(lib().nusht_geometry_for(lmax, mmax, eps, _dtype_code(dtype), ctypes.byref(o),
+                                    ctypes.byref(g)), "nusht_geometry_for")
+    return g.as_dict()
+
+
+def _stream():
+    import torch
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+class Plan:
+    """A nusht plan for fixed points (theta, phi) -- torch float64 tensors on the GPU."""
+
+    def __init__(self, lmax, mmax, theta, phi, eps, dtype="f64", sigma=0.0, width=0,
+                 beta_per_w=0.0, dfs_mode="fused", timing=False):
+        import torch
+        if theta.dtype != torch.float64 or phi.dtype != torch.float64:
+            raise TypeError("theta and phi must be float64")
+        if not (theta.is_cuda and phi.is_cuda) or theta.shape != phi.shape or theta.dim() != 1:
+            raise ValueError("theta and phi must be 1-D device tensors of equal length")
+        theta = theta.contiguous()
+        phi = phi.contiguous()
+        self.lmax, self.mmax, self.eps = int(lmax), int(mmax), float(eps)
+        self.dtype = dtype
+        self.npts = int(theta.numel())
+        self.device = theta.device
+        o = _opts(sigma, width, beta_per_w, dfs_mode, timing)
+        h = _vp()
+        _check(lib().nusht_plan_ex(self.lmax, self.mmax, self.npts, theta.data_ptr(),
+                                   phi.data_ptr(), self.eps, _dtype_code(dtype), ctypes.byref(o),
+                                   _stream(), ctypes.byref(h)), "nusht_plan_ex")
+        self._h = h
+        g = Geometry()
+        _check(lib().nusht_plan_info(h, ctypes.byref(g)), "nusht_plan_info")
+        self.geometry = g.as_dict()
+        self.nalm = int(self.geometry["nalm"])
+
+    # ---- helpers ----
+    def _alm_in(self, alm):
+        import torch
+        if alm.dtype != torch.complex128 or not alm.is_cuda:
+            raise TypeError("alm must be a complex128 device tensor")
+        a = alm.reshape(-1, self.nalm) if alm.dim() == 1 else alm
+        if a.dim() != 2 or a.shape[1] != self.nalm:
+            raise ValueError(f"alm must have shape [B, {self.nalm}]")
+        return a.contiguous()
+
+    def _map_in(self, m):
+        import torch
+        if m.dtype != torch.float64 or not m.is_cuda:
+            raise TypeError("maps must be float64 device tensors")
+        x = m.reshape(1, -1) if m.dim() == 1 else m
+        if x.dim() != 2 or x.shape[1] != self.npts:
+            raise ValueError(f"map must have shape [B, {self.npts}]")
+        return x.contiguous()
+
+    # ---- transforms ----
+    def synthesis(self, alm, out=None):
+        import torch
+        a = self._alm_in(alm)
+        B = a.shape[0]
+        out = torch.empty((B, self.npts), dtype=torch.float64, device=a.device) if out is None else out
+        _check(lib().nusht_synthesis(self._h, a.data_ptr(), out.data_ptr(), B, _stream()),
+               "nusht_synthesis")
+        return out
+
+    def adjoint(self, m, out=None):
+        import torch
+        x = self._map_in(m)
+        B = x.shape[0]
+        out = torch.empty((B, self.nalm), dtype=torch.complex128, device=x.device) if out is None else out
+        _check(lib().nusht_adjoint(self._h, x.data_ptr(), out.data_ptr(), B, _stream()),
+               "nusht_adjoint")
+        return out
+
+    def synthesis_deriv(self, alm):
+        import torch
+        a = self._alm_in(alm)
+        B = a.shape[0]
+        f = torch.empty((B, self.npts), dtype=torch.float64, device=a.device)
+        dt = torch.empty_like(f)
+        dp = torch.empty_like(f)
+        _check(lib().nusht_synthesis_deriv(self._h, a.data_ptr(), f.data_ptr(), dt.data_ptr(),
+                                           dp.data_ptr(), B, _stream()), "nusht_synthesis_deriv")
+        return f, dt, dp
+
+    def ring_synthesis(self, alm):
+        import torch
+        a = self._alm_in(alm)
+        B = a.shape[0]
+        g = self.geometry
+        out = torch.empty((B, g["nrings"], g["nphi"]), dtype=torch.float64, device=a.device)
+        _check(lib().nusht_ring_synthesis(self._h, a.data_ptr(), out.data_ptr(), B, _stream()),
+               "nusht_ring_synthesis")
+        return out
+
+    def ring_adjoint(self, ring):
+        import torch
+        g = self.geometry
+        r = ring.reshape(-1, g["nrings"], g["nphi"]).contiguous()
+        if r.dtype != torch.float64 or not r.is_cuda:
+            raise TypeError("ring maps must be float64 device tensors")
+        B = r.shape[0]
+        out = torch.empty((B, self.nalm), dtype=torch.complex128, device=r.device)
+        _check(lib().nusht_ring_adjoint(self._h, r.data_ptr(), out.data_ptr(), B, _stream()),
+               "nusht_ring_adjoint")
+        return out
+
+    def solve(self, d, x0=None, weights=None, tol=1e-8, maxiter=1000, check=True):
+        """CGLS inverse (nusht_solve).  Returns (alm, iterations, true relative residual)."""
+        import torch
+        x = self._map_in(d)
+        if x.shape[0] != 1:
+            raise ValueError("solve takes one map")
+        alm = torch.zeros(self.nalm, dtype=torch.complex128, device=x.device) if x0 is None \
+            else self._alm_in(x0).reshape(-1).clone()
+        wptr = None
+        if weights is not None:
+            if weights.dtype != torch.float32 or weights.numel() != self.npts:
+                raise ValueError("weights must be float32 [npts]")
+            weights = weights.contiguous()
+            wptr = weights.data_ptr()
+        it = ctypes.c_int(0)
+        rr = ctypes.c_double(0.0)
+        st = lib().nusht_solve(self._h, x.data_ptr(), alm.data_ptr(), wptr, float(tol),
+                               int(maxiter), ctypes.byref(it), ctypes.byref(rr), _stream())
+        if st not in (NUSHT_OK, NUSHT_ENOCONV) or (check and st != NUSHT_OK):
+            _check(st, "nusht_solve")
+        return alm, it.value, rr.value, st
+
+    def stage_times(self) -> dict:
+        ms = (ctypes.c_double * 16)()
+        names = (ctypes.c_char_p * 16)()
+        n = lib().nusht_stage_times(self._h, ms, names, 16)
+        if n < 0:
+            _check(n, "nusht_stage_times")
+        return {names[i].decode(): ms[i] for i in range(n)}
+
+    @property
+    def handle(self):
+        return self._h
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().nusht_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

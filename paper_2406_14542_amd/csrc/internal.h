@@ -1,0 +1,179 @@
+// Internal declarations of the nusht library (gfx950).  Not part of the public ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <rocfft/rocfft.h>
+
+#include <cstddef>
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/nusht.h"
+
+namespace nusht {
+
+// Side of the square tiles the points are binned into on the fine grid.  Every tile
+// window (tile + w - 1 halo) must fit in LDS; w <= 16 keeps the halo inside one
+// neighbouring tile, which the halo reduction relies on.
+constexpr int kTile = 32;
+constexpr int kMaxWidth = 16;
+constexpr int kMinWidth = 2;
+
+// Status that keeps the first failing HIP/rocFFT call for diagnostics.
+struct Err {
+    int code = NUSHT_OK;
+};
+
+#define NUSHT_HIP(call)                                                   \
+    do {                                                                  \
+        hipError_t e_ = (call);                                           \
+        if (e_ != hipSuccess) {                                           \
+            ::nusht::set_last_error(#call, hipGetErrorString(e_));        \
+            return e_ == hipErrorOutOfMemory ? NUSHT_ENOMEM : NUSHT_EDEVICE; \
+        }                                                                 \
+    } while (0)
+
+#define NUSHT_FFT(call)                                                   \
+    do {                                                                  \
+        rocfft_status s_ = (call);                                        \
+        if (s_ != rocfft_status_success) {                                \
+            ::nusht::set_last_error(#call, "rocfft failure");             \
+            return NUSHT_EDEVICE;                                         \
+        }                                                                 \
+    } while (0)
+
+#define NUSHT_TRY(expr)             \
+    do {                            \
+        int r_ = (expr);            \
+        if (r_ != NUSHT_OK) return r_; \
+    } while (0)
+
+void set_last_error(const char* what, const char* why);
+
+// One rocFFT transform with its execution info (stream and work buffer bound per call).
+struct FftPlan {
+    rocfft_plan plan = nullptr;
+    rocfft_execution_info info = nullptr;
+    size_t work_bytes = 0;
+};
+
+// Stage identifiers for the optional per-stage timing.
+enum Stage {
+    ST_LEGENDRE = 0,  // a1 / b7
+    ST_RING_FFT,      // a2 / b6 (paper mode)
+    ST_DOUBLE,        // a3 / b5
+    ST_TORUS_FFT,     // a4 / b4
+    ST_DECONV,        // a5 / b3
+    ST_FINE_FFT,      // a6 / b2
+    ST_POINTS,        // a7 / b1 (interpolation or spreading)
+    ST_HALO,          // b1 halo reduction
+    ST_COUNT
+};
+
+}  // namespace nusht
+
+struct nusht_plan_s {
+    nusht_geometry g{};
+    double eps = 0;
+    int device = 0;
+    hipStream_t plan_stream = nullptr;
+
+    // Legendre tables (host-computed, FP64).
+    double2* rec = nullptr;      // [nalm]: (a_lm, a_lm * b_lm) of the recurrence, l >= m+1
+    double* cm_mant = nullptr;   // [mmax+1]: lam_mm prefactor mantissa, sign (-1)^m included
+    int* cm_exp = nullptr;       // [mmax+1]: its power-of-two exponent
+
+    // Deconvolution factors (include the FFT normalisation of the torus transform).
+    double* dec1 = nullptr;      // [lmax+1], indexed by |kappa|
+    double* dec2 = nullptr;      // [mmax+1], indexed by mu
+    float* dec1f = nullptr;
+    float* dec2f = nullptr;
+
+    // Points binned into tiles ("slots" are the tiles that hold points, in tile order).
+    double* sth = nullptr;       // [npts] theta, sorted by tile
+    double* sph = nullptr;       // [npts] phi mod 2 pi, sorted by tile
+    int* perm = nullptr;         // [npts] user index of each sorted point
+    int* slot_off = nullptr;     // [nslots+1] first sorted point of each slot
+    int* slot_tile = nullptr;    // [nslots] tile id of each slot
+    int* tile_slot = nullptr;    // [ntiles] slot of each tile or -1
+    int nslots = 0;
+    int nt1 = 0, nt2 = 0;        // tiles per fine-grid axis
+    int* dflag = nullptr;        // device error flag used by plan validation
+
+    // Scratch, grown to the largest batch seen.  Two ping-pong regions and one for the
+    // spread subgrids.
+    int bcap = 0;
+    void* X = nullptr;
+    size_t Xbytes = 0;
+    void* Y = nullptr;
+    size_t Ybytes = 0;
+    void* Z = nullptr;           // spreading subgrids
+    size_t Zbytes = 0;
+    void* fftwork = nullptr;
+    size_t fftwork_bytes = 0;
+    double* red = nullptr;       // small reduction scratch for the CG solve
+    size_t redbytes = 0;
+
+    // rocFFT plans (all per map; executed once per map of a batch).
+    nusht::FftPlan ring_c2r, ring_r2c;      // 1D over phi, batch N_r, FP64
+    nusht::FftPlan torus_r2c, torus_c2r;    // 2D N_t x N_phi (paper mode)
+    nusht::FftPlan theta_fwd, theta_bwd;    // 1D C2C over N_t, batch mmax+1 (fused mode)
+    nusht::FftPlan fine_c2r, fine_r2c;      // 2D n1 x n2
+
+    // Timing.
+    int timing = 0;
+    hipEvent_t ev[nusht::ST_COUNT][2]{};
+    int ev_used[nusht::ST_COUNT]{};
+};
+
+namespace nusht {
+
+// Maps are processed by the point kernels in groups of four, the remainder one by one.
+inline int point_groups(int nmaps) { return nmaps / 4 + nmaps % 4; }
+inline int group_width(int nmaps, int b) { return (nmaps - b) >= 4 ? 4 : 1; }
+
+// ---- geometry (plan.hip) ----
+int compute_geometry(int lmax, int mmax, double eps, int dtype, const nusht_plan_opts* opts,
+                     nusht_geometry* g);
+int ensure_capacity(nusht_plan_s* p, int nmaps);
+size_t fine_elem_bytes(const nusht_plan_s* p);
+
+// ---- FFT helpers (transform.hip) ----
+int fft_exec(nusht_plan_s* p, FftPlan& f, void* in, void* out, hipStream_t s);
+
+// ---- timing helpers (transform.hip) ----
+void stage_begin(nusht_plan_s* p, Stage st, hipStream_t s);
+void stage_end(nusht_plan_s* p, Stage st, hipStream_t s);
+
+// ---- Legendre (legendre.hip) ----
+// Output layouts of the synthesis: PAPER writes G[b][j][m] (rows of N_phi/2+1 complex, the
+// ring FFT's input); FUSED writes the doubled column Gt[b][m][t], t < N_t.
+int launch_legendre_synth(const nusht_plan_s* p, const double* alm, void* out, int nmaps,
+                          int fused, int out_f32, hipStream_t s);
+int launch_legendre_adjoint(const nusht_plan_s* p, const void* in, double* alm, int nmaps,
+                            int fused, int in_f32, hipStream_t s);
+
+// ---- DFS glue (dfs.hip) ----
+int launch_zero_nyquist_rows(const nusht_plan_s* p, double* G, int nmaps, hipStream_t s);
+int launch_double(const nusht_plan_s* p, const double* ring, void* torus, int nmaps, int f32,
+                  hipStream_t s);
+int launch_fold(const nusht_plan_s* p, const void* torus, double* ring, int nmaps, int f32,
+                hipStream_t s);
+int launch_deconv_pad(const nusht_plan_s* p, const void* tspec, void* fspec, int nmaps, int fused,
+                      int f32, hipStream_t s);
+int launch_deconv_trunc(const nusht_plan_s* p, const void* fspec, void* tspec, int nmaps,
+                        int fused, int f32, hipStream_t s);
+
+// ---- nonuniform part (nufft_*.hip) ----
+int launch_interp(const nusht_plan_s* p, const void* fine, double* out, int nmaps, int f32,
+                  hipStream_t s);
+int launch_interp_deriv(const nusht_plan_s* p, const double* fine, double* out, double* dth,
+                        double* dph, int nmaps, hipStream_t s);
+int launch_spread(const nusht_plan_s* p, const double* in, void* fine, int nmaps, int f32,
+                  hipStream_t s);
+
+// ---- point binning (plan.hip) ----
+int bin_points(nusht_plan_s* p, const double* theta, const double* phi, hipStream_t s);
+
+}  // namespace nusht

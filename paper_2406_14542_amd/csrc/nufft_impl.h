@@ -1,0 +1,397 @@
+// Type-2 interpolation and type-1 spreading of the ES-kernel nuFFT on the fine torus grid
+// (arXiv:2406.14542 Sec. III: N and N^H, "shared memory" spreading).
+//
+// Kernel: psi(z) = exp(beta (sqrt(1 - z^2) - 1)) for |z| < 1, z = 2 (x - x_l) / (w h).
+// For a coordinate x with t = x / h (grid units) the w taps start at cell
+//   ls = ceil(t - w/2),  and tap a has z_a = 2 (t - ls - a) / w  in (-1, 1].
+// Points were binned by the plan into kTile x kTile tiles by (ls1 mod n1, ls2 mod n2); a
+// workgroup owns one non-empty tile ("slot") and the tile's window of
+// (kTile + w - 1)^2 cells, which it stages in LDS.
+//  * interpolation: window loaded once from HBM, every point of the tile reads its w x w taps
+//    from LDS, result written straight to the caller's point order;
+//  * spreading: points add their w x w contributions into the LDS window (LDS float atomics),
+//    the window is written once to a per-slot subgrid; a second pass sums, for every fine
+//    cell, the subgrids of the (at most four) windows that cover it.  No global atomics.
+// Offsets are formed in FP64 from FP64 coordinates before any cast to the kernel's type T.
+#pragma once
+
+#include "internal.h"
+
+namespace nusht {
+
+struct PointBins {
+    const double* sth;
+    const double* sph;
+    const int* perm;
+    const int* slot_off;
+    const int* slot_tile;
+    int nt2;
+    int n1, n2;
+    double s1, s2;  // n / (2 pi)
+};
+
+// first tap cell and its fractional offset; no fused multiply-add so that the plan and the
+// kernels bin every point identically
+__device__ inline int first_tap(double x, double scale, int w, double& d)
+{
+#pragma clang fp contract(off)
+    const double t = x * scale;
+    const int ls = (int)ceil(t - 0.5 * (double)w);
+    d = t - (double)ls;
+    return ls;
+}
+
+__device__ inline int wrap_index(int i, int n)
+{
+    i %= n;
+    return i < 0 ? i + n : i;
+}
+
+template <typename T>
+__device__ inline T es_value(T z, T beta)
+{
+    const T q = (T(1) - z) * (T(1) + z);
+    return q > T(0) ? (T)exp(beta * (sqrt(q) - T(1))) : T(0);
+}
+
+template <typename T, int W>
+__device__ inline void es_taps(double d, T beta, T (&psi)[W])
+{
+    const T dd = (T)d;
+    const T c = T(2) / T(W);
+#pragma unroll
+    for (int a = 0; a < W; ++a) psi[a] = es_value<T>((dd - T(a)) * c, beta);
+}
+
+// taps and their derivatives with respect to t (grid units):
+// d psi / dt = psi(z) * beta * (-z / sqrt(1 - z^2)) * 2 / w, set to 0 on the support edge
+template <int W>
+__device__ inline void es_taps_d(double d, double beta, double (&psi)[W], double (&dpsi)[W])
+{
+    const double c = 2.0 / W;
+#pragma unroll
+    for (int a = 0; a < W; ++a) {
+        const double z = (d - a) * c;
+        const double q = (1.0 - z) * (1.0 + z);
+        if (q > 0.0) {
+            const double sq = sqrt(q);
+            const double v = exp(beta * (sq - 1.0));
+            psi[a] = v;
+            dpsi[a] = -v * beta * z / sq * c;
+        } else {
+            psi[a] = 0.0;
+            dpsi[a] = 0.0;
+        }
+    }
+}
+
+template <typename T, int W, int MB>
+__global__ __launch_bounds__(256) void k_interp(const T* __restrict__ fine, int64_t map_stride,
+                                                PointBins pb, T beta, double* __restrict__ out,
+                                                int64_t npts)
+{
+    constexpr int P = kTile + W - 1;
+    __shared__ T win[P * P * MB];
+    const int slot = blockIdx.x;
+    const int tile = pb.slot_tile[slot];
+    const int r0 = (tile / pb.nt2) * kTile;
+    const int c0 = (tile % pb.nt2) * kTile;
+    for (int e = threadIdx.x; e < P * P; e += blockDim.x) {
+        const int r = e / P, c = e - (e / P) * P;
+        int gr = r0 + r;
+        if (gr >= pb.n1) gr -= pb.n1;
+        int gc = c0 + c;
+        if (gc >= pb.n2) gc -= pb.n2;
+        const int64_t off = (int64_t)gr * pb.n2 + gc;
+#pragma unroll
+        for (int b = 0; b < MB; ++b) win[e * MB + b] = fine[b * map_stride + off];
+    }
+    __syncthreads();
+    const int p0 = pb.slot_off[slot], p1 = pb.slot_off[slot + 1];
+    for (int p = p0 + threadIdx.x; p < p1; p += blockDim.x) {
+        double d1, d2;
+        const int l1 = first_tap(pb.sth[p], pb.s1, W, d1);
+        const int l2 = first_tap(pb.sph[p], pb.s2, W, d2);
+        int r = wrap_index(l1, pb.n1) - r0;
+        int c = wrap_index(l2, pb.n2) - c0;
+        r = min(max(r, 0), kTile - 1);
+        c = min(max(c, 0), kTile - 1);
+        T p1v[W], p2v[W];
+        es_taps<T, W>(d1, beta, p1v);
+        es_taps<T, W>(d2, beta, p2v);
+        T acc[MB];
+#pragma unroll
+        for (int b = 0; b < MB; ++b) acc[b] = T(0);
+#pragma unroll
+        for (int a = 0; a < W; ++a) {
+            T row[MB];
+#pragma unroll
+            for (int b = 0; b < MB; ++b) row[b] = T(0);
+            const T* wr = win + ((r + a) * P + c) * MB;
+#pragma unroll
+            for (int q = 0; q < W; ++q) {
+#pragma unroll
+                for (int b = 0; b < MB; ++b) row[b] += p2v[q] * wr[q * MB + b];
+            }
+#pragma unroll
+            for (int b = 0; b < MB; ++b) acc[b] += p1v[a] * row[b];
+        }
+        const int64_t dst = pb.perm[p];
+#pragma unroll
+        for (int b = 0; b < MB; ++b) out[b * npts + dst] = (double)acc[b];
+    }
+}
+
+template <int W, int MB>
+__global__ __launch_bounds__(256) void k_interp_deriv(const double* __restrict__ fine,
+                                                      int64_t map_stride, PointBins pb,
+                                                      double beta, double* __restrict__ out,
+                                                      double* __restrict__ dth,
+                                                      double* __restrict__ dph, int64_t npts)
+{
+    constexpr int P = kTile + W - 1;
+    __shared__ double win[P * P * MB];
+    const int slot = blockIdx.x;
+    const int tile = pb.slot_tile[slot];
+    const int r0 = (tile / pb.nt2) * kTile;
+    const int c0 = (tile % pb.nt2) * kTile;
+    for (int e = threadIdx.x; e < P * P; e += blockDim.x) {
+        const int r = e / P, c = e - (e / P) * P;
+        int gr = r0 + r;
+        if (gr >= pb.n1) gr -= pb.n1;
+        int gc = c0 + c;
+        if (gc >= pb.n2) gc -= pb.n2;
+        const int64_t off = (int64_t)gr * pb.n2 + gc;
+#pragma unroll
+        for (int b = 0; b < MB; ++b) win[e * MB + b] = fine[b * map_stride + off];
+    }
+    __syncthreads();
+    const int p0 = pb.slot_off[slot], p1 = pb.slot_off[slot + 1];
+    for (int p = p0 + threadIdx.x; p < p1; p += blockDim.x) {
+        double d1, d2;
+        const int l1 = first_tap(pb.sth[p], pb.s1, W, d1);
+        const int l2 = first_tap(pb.sph[p], pb.s2, W, d2);
+        int r = wrap_index(l1, pb.n1) - r0;
+        int c = wrap_index(l2, pb.n2) - c0;
+        r = min(max(r, 0), kTile - 1);
+        c = min(max(c, 0), kTile - 1);
+        double p1v[W], p2v[W], q1v[W], q2v[W];
+        es_taps_d<W>(d1, beta, p1v, q1v);
+        es_taps_d<W>(d2, beta, p2v, q2v);
+        double acc[MB], a1[MB], a2[MB];
+#pragma unroll
+        for (int b = 0; b < MB; ++b) acc[b] = a1[b] = a2[b] = 0.0;
+#pragma unroll
+        for (int a = 0; a < W; ++a) {
+            double row[MB], rowd[MB];
+#pragma unroll
+            for (int b = 0; b < MB; ++b) row[b] = rowd[b] = 0.0;
+            const double* wr = win + ((r + a) * P + c) * MB;
+#pragma unroll
+            for (int q = 0; q < W; ++q) {
+#pragma unroll
+                for (int b = 0; b < MB; ++b) {
+                    const double u = wr[q * MB + b];
+                    row[b] = fma(p2v[q], u, row[b]);
+                    rowd[b] = fma(q2v[q], u, rowd[b]);
+                }
+            }
+#pragma unroll
+            for (int b = 0; b < MB; ++b) {
+                acc[b] = fma(p1v[a], row[b], acc[b]);
+                a1[b] = fma(q1v[a], row[b], a1[b]);
+                a2[b] = fma(p1v[a], rowd[b], a2[b]);
+            }
+        }
+        const int64_t dst = pb.perm[p];
+#pragma unroll
+        for (int b = 0; b < MB; ++b) {
+            out[b * npts + dst] = acc[b];
+            dth[b * npts + dst] = a1[b] * pb.s1;
+            dph[b * npts + dst] = a2[b] * pb.s2;
+        }
+    }
+}
+
+template <typename T, int W, int MB>
+__global__ __launch_bounds__(256) void k_spread(const double* __restrict__ in, int64_t npts,
+                                                PointBins pb, T beta, T* __restrict__ sub)
+{
+    constexpr int P = kTile + W - 1;
+    __shared__ T win[P * P * MB];
+    const int slot = blockIdx.x;
+    const int tile = pb.slot_tile[slot];
+    const int r0 = (tile / pb.nt2) * kTile;
+    const int c0 = (tile % pb.nt2) * kTile;
+    for (int e = threadIdx.x; e < P * P * MB; e += blockDim.x) win[e] = T(0);
+    __syncthreads();
+    const int p0 = pb.slot_off[slot], p1 = pb.slot_off[slot + 1];
+    for (int p = p0 + threadIdx.x; p < p1; p += blockDim.x) {
+        double d1, d2;
+        const int l1 = first_tap(pb.sth[p], pb.s1, W, d1);
+        const int l2 = first_tap(pb.sph[p], pb.s2, W, d2);
+        int r = wrap_index(l1, pb.n1) - r0;
+        int c = wrap_index(l2, pb.n2) - c0;
+        r = min(max(r, 0), kTile - 1);
+        c = min(max(c, 0), kTile - 1);
+        T p1v[W], p2v[W];
+        es_taps<T, W>(d1, beta, p1v);
+        es_taps<T, W>(d2, beta, p2v);
+        const int64_t src = pb.perm[p];
+        T f[MB];
+#pragma unroll
+        for (int b = 0; b < MB; ++b) f[b] = (T)in[b * npts + src];
+#pragma unroll
+        for (int a = 0; a < W; ++a) {
+            T fa[MB];
+#pragma unroll
+            for (int b = 0; b < MB; ++b) fa[b] = f[b] * p1v[a];
+            T* wr = win + ((r + a) * P + c) * MB;
+#pragma unroll
+            for (int q = 0; q < W; ++q) {
+#pragma unroll
+                for (int b = 0; b < MB; ++b) atomicAdd(wr + q * MB + b, fa[b] * p2v[q]);
+            }
+        }
+    }
+    __syncthreads();
+    T* dst = sub + (int64_t)slot * (P * P * MB);
+    for (int e = threadIdx.x; e < P * P * MB; e += blockDim.x) dst[e] = win[e];
+}
+
+// fine[b][i][j] = sum of the subgrids of the windows covering cell (i, j); zero elsewhere
+template <typename T, int W, int MB>
+__global__ __launch_bounds__(256) void k_halo(const T* __restrict__ sub,
+                                              const int* __restrict__ tile_slot, int nt1, int nt2,
+                                              int n1, int n2, T* __restrict__ fine,
+                                              int64_t map_stride)
+{
+    constexpr int P = kTile + W - 1;
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    const int i = blockIdx.y;
+    if (j >= n2) return;
+    const int tr = i / kTile, rr = i - tr * kTile;
+    const int tc = j / kTile, cc = j - tc * kTile;
+    const int trp = tr == 0 ? nt1 - 1 : tr - 1;
+    const int tcp = tc == 0 ? nt2 - 1 : tc - 1;
+    T acc[MB];
+#pragma unroll
+    for (int b = 0; b < MB; ++b) acc[b] = T(0);
+    auto add = [&](int t_r, int t_c, int r, int c) {
+        const int sl = tile_slot[t_r * nt2 + t_c];
+        if (sl < 0) return;
+        const T* s = sub + (int64_t)sl * (P * P * MB) + (r * P + c) * MB;
+#pragma unroll
+        for (int b = 0; b < MB; ++b) acc[b] += s[b];
+    };
+    add(tr, tc, rr, cc);
+    if (rr < W - 1) add(trp, tc, rr + kTile, cc);
+    if (cc < W - 1) add(tr, tcp, rr, cc + kTile);
+    if (rr < W - 1 && cc < W - 1) add(trp, tcp, rr + kTile, cc + kTile);
+    const int64_t off = (int64_t)i * n2 + j;
+#pragma unroll
+    for (int b = 0; b < MB; ++b) fine[b * map_stride + off] = acc[b];
+}
+
+// ---- dispatch over the kernel width ---------------------------------------------------
+
+inline PointBins make_bins(const nusht_plan_s* p)
+{
+    PointBins pb;
+    pb.sth = p->sth;
+    pb.sph = p->sph;
+    pb.perm = p->perm;
+    pb.slot_off = p->slot_off;
+    pb.slot_tile = p->slot_tile;
+    pb.nt2 = p->nt2;
+    pb.n1 = p->g.n1;
+    pb.n2 = p->g.n2;
+    pb.s1 = p->g.n1 / (2.0 * M_PI);
+    pb.s2 = p->g.n2 / (2.0 * M_PI);
+    return pb;
+}
+
+#define NUSHT_WIDTH_SWITCH(W_, BODY) \
+    switch (W_) {                    \
+        case 2: { constexpr int WV = 2; BODY; } break;   \
+        case 3: { constexpr int WV = 3; BODY; } break;   \
+        case 4: { constexpr int WV = 4; BODY; } break;   \
+        case 5: { constexpr int WV = 5; BODY; } break;   \
+        case 6: { constexpr int WV = 6; BODY; } break;   \
+        case 7: { constexpr int WV = 7; BODY; } break;   \
+        case 8: { constexpr int WV = 8; BODY; } break;   \
+        case 9: { constexpr int WV = 9; BODY; } break;   \
+        case 10: { constexpr int WV = 10; BODY; } break; \
+        case 11: { constexpr int WV = 11; BODY; } break; \
+        case 12: { constexpr int WV = 12; BODY; } break; \
+        case 13: { constexpr int WV = 13; BODY; } break; \
+        case 14: { constexpr int WV = 14; BODY; } break; \
+        case 15: { constexpr int WV = 15; BODY; } break; \
+        case 16: { constexpr int WV = 16; BODY; } break; \
+        default: set_last_error("nufft", "unsupported kernel width"); return NUSHT_EINVAL; \
+    }
+
+template <typename T>
+int dispatch_interp_impl(const nusht_plan_s* p, const T* fine, double* out, int nmaps, T beta,
+                         hipStream_t s)
+{
+    if (p->nslots == 0) return NUSHT_OK;
+    const PointBins pb = make_bins(p);
+    const int64_t ms = (int64_t)p->g.n1 * p->g.n2;
+    const int64_t npts = p->g.npts;
+    int b = 0;
+    while (b < nmaps) {
+        const int mb = group_width(nmaps, b);
+        NUSHT_WIDTH_SWITCH(p->g.width, {
+            if (mb == 4)
+                hipLaunchKernelGGL((k_interp<T, WV, 4>), dim3(p->nslots), dim3(256), 0, s,
+                                   fine + b * ms, ms, pb, beta, out + b * npts, npts);
+            else
+                hipLaunchKernelGGL((k_interp<T, WV, 1>), dim3(p->nslots), dim3(256), 0, s,
+                                   fine + b * ms, ms, pb, beta, out + b * npts, npts);
+        });
+        NUSHT_HIP(hipGetLastError());
+        b += mb;
+    }
+    return NUSHT_OK;
+}
+
+// spreading of maps [b, b + mb) into the slot subgrids (mb = 1 or 4)
+template <typename T>
+int spread_group_impl(const nusht_plan_s* p, const double* in, T* sub, int b, int mb, T beta,
+                      hipStream_t s)
+{
+    if (p->nslots == 0) return NUSHT_OK;
+    const PointBins pb = make_bins(p);
+    const int64_t npts = p->g.npts;
+    NUSHT_WIDTH_SWITCH(p->g.width, {
+        if (mb == 4)
+            hipLaunchKernelGGL((k_spread<T, WV, 4>), dim3(p->nslots), dim3(256), 0, s,
+                               in + b * npts, npts, pb, beta, sub);
+        else
+            hipLaunchKernelGGL((k_spread<T, WV, 1>), dim3(p->nslots), dim3(256), 0, s,
+                               in + b * npts, npts, pb, beta, sub);
+    });
+    NUSHT_HIP(hipGetLastError());
+    return NUSHT_OK;
+}
+
+// halo reduction of the slot subgrids into fine maps [b, b + mb)
+template <typename T>
+int halo_group_impl(const nusht_plan_s* p, const T* sub, T* fine, int b, int mb, hipStream_t s)
+{
+    const int64_t ms = (int64_t)p->g.n1 * p->g.n2;
+    dim3 hgrid((p->g.n2 + 255) / 256, p->g.n1);
+    NUSHT_WIDTH_SWITCH(p->g.width, {
+        if (mb == 4)
+            hipLaunchKernelGGL((k_halo<T, WV, 4>), hgrid, dim3(256), 0, s, sub, p->tile_slot,
+                               p->nt1, p->nt2, p->g.n1, p->g.n2, fine + b * ms, ms);
+        else
+            hipLaunchKernelGGL((k_halo<T, WV, 1>), hgrid, dim3(256), 0, s, sub, p->tile_slot,
+                               p->nt1, p->nt2, p->g.n1, p->g.n2, fine + b * ms, ms);
+    });
+    NUSHT_HIP(hipGetLastError());
+    return NUSHT_OK;
+}
+
+}  // namespace nusht

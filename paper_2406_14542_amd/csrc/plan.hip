@@ -1,0 +1,540 @@
+// Plans: sizes, host-computed tables, point binning and scratch (arXiv:2406.14542 Sec. III:
+// the nuFFT plans are built once, before the transforms, and reused; planning is excluded
+// from the timings).
+#include <hipcub/hipcub.hpp>
+
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <mutex>
+
+#include "internal.h"
+#include "nufft_impl.h"
+
+namespace nusht {
+
+static thread_local std::string g_last_error;
+
+void set_last_error(const char* what, const char* why)
+{
+    g_last_error = std::string(what) + ": " + why;
+}
+
+namespace {
+
+bool smooth7(long n)
+{
+    if (n < 1) return false;
+    for (long p : {2L, 3L, 5L, 7L})
+        while (n % p == 0) n /= p;
+    return n == 1;
+}
+
+// Gauss-Legendre nodes and weights on [-1, 1] (Newton on P_n in long double).
+void gauss_legendre(int n, std::vector<double>& x, std::vector<double>& w)
+{
+    x.resize(n);
+    w.resize(n);
+    for (int i = 0; i < n; ++i) {
+        long double z = cosl(3.14159265358979323846264338327950288L * (i + 0.75L) / (n + 0.5L));
+        long double dp = 0;
+        for (int it = 0; it < 100; ++it) {
+            long double p0 = 1, p1 = z;
+            for (int k = 2; k <= n; ++k) {
+                long double p2 = ((2 * k - 1) * z * p1 - (k - 1) * p0) / k;
+                p0 = p1;
+                p1 = p2;
+            }
+            if (n == 1) {
+                p1 = z;
+                p0 = 1;
+            }
+            dp = n * (z * p1 - p0) / (z * z - 1);
+            long double dz = p1 / dp;
+            z -= dz;
+            if (fabsl(dz) < 1e-19L) break;
+        }
+        x[i] = (double)z;
+        w[i] = (double)(2.0L / ((1 - z * z) * dp * dp));
+    }
+}
+
+// I(k) = int_{-1}^{1} exp(beta (sqrt(1 - z^2) - 1)) cos(alpha k z) dz, via z = sin(t), so the
+// integrand exp(beta (cos t - 1)) cos(alpha k sin t) cos t is analytic on [-pi/2, pi/2].
+void es_fourier(double beta, double alpha, int kmax, std::vector<double>& out)
+{
+    const int nq = 2 * (int)std::ceil(beta + alpha * kmax) + 64;
+    std::vector<double> x, w;
+    gauss_legendre(nq, x, w);
+    out.assign(kmax + 1, 0.0);
+    const double half_pi = 0.5 * M_PI;
+    for (int q = 0; q < nq; ++q) {
+        const double t = half_pi * x[q];
+        const double base = w[q] * half_pi * std::exp(beta * (std::cos(t) - 1.0)) * std::cos(t);
+        const double st = std::sin(t);
+        for (int k = 0; k <= kmax; ++k) out[k] += base * std::cos(alpha * k * st);
+    }
+}
+
+template <typename T>
+int dmalloc(T** p, size_t n)
+{
+    *p = nullptr;
+    if (n == 0) return NUSHT_OK;
+    hipError_t e = hipMalloc((void**)p, n * sizeof(T));
+    if (e != hipSuccess) {
+        set_last_error("hipMalloc", hipGetErrorString(e));
+        *p = nullptr;
+        return e == hipErrorOutOfMemory ? NUSHT_ENOMEM : NUSHT_EDEVICE;
+    }
+    return NUSHT_OK;
+}
+
+// ---- point binning kernels ----
+
+__global__ void k_bin_keys(const double* __restrict__ theta, const double* __restrict__ phi,
+                           int64_t n, int w, double s1, double s2, int n1, int n2, int nt2,
+                           double* __restrict__ phw, int* __restrict__ keys,
+                           int* __restrict__ idx, int* __restrict__ flag)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const double th = theta[i];
+    double ph = phi[i];
+    const bool bad = !(th >= 0.0 && th <= M_PI) || !isfinite(ph);
+    if (bad) {
+        atomicOr(flag, 1);
+        ph = 0.0;
+    }
+    const double tp = 2.0 * M_PI;
+    ph = ph - tp * floor(ph / tp);
+    if (ph >= tp) ph -= tp;
+    if (ph < 0.0) ph = 0.0;
+    const double thc = bad ? 0.0 : th;
+    double d;
+    const int l1 = wrap_index(first_tap(thc, s1, w, d), n1);
+    const int l2 = wrap_index(first_tap(ph, s2, w, d), n2);
+    keys[i] = (l1 / kTile) * nt2 + (l2 / kTile);
+    idx[i] = (int)i;
+    phw[i] = ph;
+}
+
+__global__ void k_gather_sorted(const double* __restrict__ theta, const double* __restrict__ phw,
+                                const int* __restrict__ perm, int64_t n, double* __restrict__ sth,
+                                double* __restrict__ sph)
+{
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= n) return;
+    const int i = perm[k];
+    sth[k] = theta[i];
+    sph[k] = phw[i];
+}
+
+__global__ void k_mark(const int* __restrict__ keys, int64_t n, int* __restrict__ first)
+{
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= n) return;
+    first[k] = (k == 0 || keys[k] != keys[k - 1]) ? 1 : 0;
+}
+
+__global__ void k_slots(const int* __restrict__ keys, const int* __restrict__ first,
+                        const int* __restrict__ slotidx, int64_t n, int* __restrict__ slot_off,
+                        int* __restrict__ slot_tile, int* __restrict__ tile_slot)
+{
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= n) return;
+    if (first[k]) {
+        const int s = slotidx[k];
+        slot_off[s] = (int)k;
+        slot_tile[s] = keys[k];
+        tile_slot[keys[k]] = s;
+    }
+}
+
+__global__ void k_fill_int(int* p, int64_t n, int v)
+{
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k < n) p[k] = v;
+}
+
+}  // namespace
+
+int compute_geometry(int lmax, int mmax, double eps, int dtype, const nusht_plan_opts* opts,
+                     nusht_geometry* g)
+{
+    if (!g) return NUSHT_EINVAL;
+    std::memset(g, 0, sizeof(*g));
+    if (lmax < 0 || lmax > 16383 || mmax < 0 || mmax > lmax) {
+        set_last_error("geometry", "need 0 <= mmax <= lmax <= 16383");
+        return NUSHT_EINVAL;
+    }
+    if (!(eps >= 1e-14 && eps <= 1e-1)) {
+        set_last_error("geometry", "eps must lie in [1e-14, 1e-1]");
+        return NUSHT_EINVAL;
+    }
+    if (dtype != NUSHT_F64 && dtype != NUSHT_MIXED) {
+        set_last_error("geometry", "dtype must be NUSHT_F64 or NUSHT_MIXED");
+        return NUSHT_EINVAL;
+    }
+    if (dtype == NUSHT_MIXED && eps < 1e-6) {
+        set_last_error("geometry", "NUSHT_MIXED needs eps >= 1e-6");
+        return NUSHT_EPRECISION;
+    }
+    double sigma = 2.0, bpw = 0.0;
+    int width = 0, mode = NUSHT_DFS_FUSED;
+    if (opts) {
+        for (int r : opts->reserved)
+            if (r != 0) {
+                set_last_error("geometry", "opts.reserved must be zero");
+                return NUSHT_EINVAL;
+            }
+        if (opts->sigma != 0.0) sigma = opts->sigma;
+        width = opts->width;
+        bpw = opts->beta_per_w;
+        mode = opts->dfs_mode;
+    }
+    if (!(sigma >= 1.2 && sigma <= 4.0)) {
+        set_last_error("geometry", "sigma must lie in [1.2, 4]");
+        return NUSHT_EINVAL;
+    }
+    if (mode != NUSHT_DFS_FUSED && mode != NUSHT_DFS_PAPER) {
+        set_last_error("geometry", "unknown dfs_mode");
+        return NUSHT_EINVAL;
+    }
+    if (width == 0) {
+        // ES kernel: error ~ exp(-pi w sqrt(1 - 1/sigma)); one extra cell of margin
+        width = (int)std::ceil(std::log(1.0 / eps) / (M_PI * std::sqrt(1.0 - 1.0 / sigma))) + 1;
+        if (width < kMinWidth) width = kMinWidth;
+    }
+    if (width < kMinWidth || width > kMaxWidth) {
+        set_last_error("geometry", "kernel width outside [2, 16] (raise sigma or eps)");
+        return NUSHT_EINVAL;
+    }
+    if (bpw == 0.0) bpw = (sigma == 2.0) ? 2.30 : 0.97 * M_PI * (1.0 - 0.5 / sigma);
+    if (!(bpw > 0.0 && bpw < 10.0)) {
+        set_last_error("geometry", "beta_per_w out of range");
+        return NUSHT_EINVAL;
+    }
+    // CC rings: N_t = 2 (N_r - 1) must carry |kappa| <= lmax without touching the Nyquist bin,
+    // so N_r >= lmax + 2 (N_r = lmax + 1 aliases odd-m modes), and N_t should be FFT-friendly.
+    int nr = lmax + 2;
+    while (!smooth7(2L * (nr - 1))) ++nr;
+    int nphi = 2 * mmax + 2;
+    while (!smooth7(nphi) || (nphi & 1)) ++nphi;
+    auto fine = [&](int band) {
+        long n = (long)std::ceil(sigma * (2.0 * band + 1.0));
+        if (n < 2 * kTile) n = 2 * kTile;
+        n = ((n + kTile - 1) / kTile) * kTile;
+        while (!smooth7(n)) n += kTile;
+        return (int)n;
+    };
+    g->lmax = lmax;
+    g->mmax = mmax;
+    g->nrings = nr;
+    g->ntorus = 2 * (nr - 1);
+    g->nphi = nphi;
+    g->n1 = fine(lmax);
+    g->n2 = fine(mmax);
+    g->width = width;
+    g->beta = bpw * width;
+    g->sigma = sigma;
+    g->tile = kTile;
+    g->dtype = dtype;
+    g->dfs_mode = mode;
+    g->nalm = (int64_t)(mmax + 1) * (lmax + 1) - (int64_t)mmax * (mmax + 1) / 2;
+    return NUSHT_OK;
+}
+
+size_t fine_elem_bytes(const nusht_plan_s* p)
+{
+    return p->g.dtype == NUSHT_MIXED ? sizeof(float) : sizeof(double);
+}
+
+// Scratch for `nmaps` maps.  X and Y each hold the largest per-map intermediate of either
+// mode times the batch; Z holds the spreading subgrids of every group of four maps.
+int ensure_capacity(nusht_plan_s* p, int nmaps)
+{
+    if (nmaps <= p->bcap) return NUSHT_OK;
+    const nusht_geometry& g = p->g;
+    const size_t e = fine_elem_bytes(p);
+    const size_t fine_real = (size_t)g.n1 * g.n2 * e;
+    const size_t fine_spec = (size_t)g.n1 * (g.n2 / 2 + 1) * 2 * e;
+    const size_t gpaper = (size_t)g.nrings * (g.nphi / 2 + 1) * 16;
+    const size_t ring = (size_t)g.nrings * g.nphi * 8;
+    const size_t torus = (size_t)g.ntorus * g.nphi * e;
+    const size_t tspec = (size_t)g.ntorus * (g.nphi / 2 + 1) * 2 * e;
+    const size_t gfused = (size_t)(g.mmax + 1) * g.ntorus * 2 * 8;  // doubled columns, <= c128
+    size_t per = fine_real;
+    for (size_t v : {fine_spec, gpaper, ring, torus, tspec, gfused}) per = v > per ? v : per;
+    const int groups = point_groups(nmaps);
+    const int P = kTile + g.width - 1;
+    const size_t zbytes = (size_t)groups * p->nslots * P * P * 4 * e;
+    NUSHT_HIP(hipDeviceSynchronize());
+    if (p->X) hipFree(p->X);
+    if (p->Y) hipFree(p->Y);
+    if (p->Z) hipFree(p->Z);
+    p->X = p->Y = p->Z = nullptr;
+    p->bcap = 0;
+    NUSHT_TRY(dmalloc((char**)&p->X, per * nmaps));
+    NUSHT_TRY(dmalloc((char**)&p->Y, per * nmaps));
+    NUSHT_TRY(dmalloc((char**)&p->Z, zbytes > 0 ? zbytes : 256));
+    p->Xbytes = p->Ybytes = per * nmaps;
+    p->Zbytes = zbytes;
+    p->bcap = nmaps;
+    return NUSHT_OK;
+}
+
+int bin_points(nusht_plan_s* p, const double* theta, const double* phi, hipStream_t s)
+{
+    const nusht_geometry& g = p->g;
+    const int64_t n = g.npts;
+    p->nt1 = g.n1 / kTile;
+    p->nt2 = g.n2 / kTile;
+    const int64_t ntiles = (int64_t)p->nt1 * p->nt2;
+    int *keys = nullptr, *keys_s = nullptr, *idx = nullptr, *first = nullptr, *sidx = nullptr;
+    double* phw = nullptr;
+    void* tmp = nullptr;
+    int rc = NUSHT_OK;
+    size_t tbytes = 0, t2 = 0;
+    const int blocks = (int)((n + 255) / 256);
+    int bits = 1;
+    while ((1LL << bits) < ntiles) ++bits;
+    do {
+        if ((rc = dmalloc(&keys, n)) || (rc = dmalloc(&keys_s, n)) || (rc = dmalloc(&idx, n)) ||
+            (rc = dmalloc(&first, n)) || (rc = dmalloc(&sidx, n)) || (rc = dmalloc(&phw, n)) ||
+            (rc = dmalloc(&p->perm, n)) || (rc = dmalloc(&p->sth, n)) ||
+            (rc = dmalloc(&p->sph, n)) || (rc = dmalloc(&p->tile_slot, ntiles)) ||
+            (rc = dmalloc(&p->dflag, 1)))
+            break;
+        if (hipMemsetAsync(p->dflag, 0, sizeof(int), s) != hipSuccess) { rc = NUSHT_EDEVICE; break; }
+        hipLaunchKernelGGL(k_bin_keys, dim3(blocks), dim3(256), 0, s, theta, phi, n, g.width,
+                           g.n1 / (2.0 * M_PI), g.n2 / (2.0 * M_PI), g.n1, g.n2, p->nt2, phw,
+                           keys, idx, p->dflag);
+        if (hipcub::DeviceRadixSort::SortPairs(nullptr, tbytes, keys, keys_s, idx, p->perm,
+                                               (int)n, 0, bits, s) != hipSuccess) { rc = NUSHT_EDEVICE; break; }
+        if (hipcub::DeviceScan::ExclusiveSum(nullptr, t2, first, sidx, (int)n, s) != hipSuccess) { rc = NUSHT_EDEVICE; break; }
+        if (t2 > tbytes) tbytes = t2;
+        if ((rc = dmalloc((char**)&tmp, tbytes + 16))) break;
+        if (hipcub::DeviceRadixSort::SortPairs(tmp, tbytes, keys, keys_s, idx, p->perm, (int)n, 0,
+                                               bits, s) != hipSuccess) { rc = NUSHT_EDEVICE; break; }
+        hipLaunchKernelGGL(k_gather_sorted, dim3(blocks), dim3(256), 0, s, theta, phw, p->perm, n,
+                           p->sth, p->sph);
+        hipLaunchKernelGGL(k_mark, dim3(blocks), dim3(256), 0, s, keys_s, n, first);
+        if (hipcub::DeviceScan::ExclusiveSum(tmp, tbytes, first, sidx, (int)n, s) != hipSuccess) { rc = NUSHT_EDEVICE; break; }
+        int last_first = 0, last_idx = 0, flag = 0;
+        if (hipMemcpyAsync(&last_first, first + n - 1, sizeof(int), hipMemcpyDeviceToHost, s) != hipSuccess ||
+            hipMemcpyAsync(&last_idx, sidx + n - 1, sizeof(int), hipMemcpyDeviceToHost, s) != hipSuccess ||
+            hipMemcpyAsync(&flag, p->dflag, sizeof(int), hipMemcpyDeviceToHost, s) != hipSuccess ||
+            hipStreamSynchronize(s) != hipSuccess) { rc = NUSHT_EDEVICE; break; }
+        if (flag) {
+            set_last_error("nusht_plan", "theta outside [0, pi] or non-finite coordinate");
+            rc = NUSHT_EINVAL;
+            break;
+        }
+        p->nslots = last_idx + last_first;
+        if ((rc = dmalloc(&p->slot_off, p->nslots + 1)) || (rc = dmalloc(&p->slot_tile, p->nslots))) break;
+        hipLaunchKernelGGL(k_fill_int, dim3((int)((ntiles + 255) / 256)), dim3(256), 0, s,
+                           p->tile_slot, ntiles, -1);
+        hipLaunchKernelGGL(k_slots, dim3(blocks), dim3(256), 0, s, keys_s, first, sidx, n,
+                           p->slot_off, p->slot_tile, p->tile_slot);
+        const int nn = (int)n;
+        if (hipMemcpyAsync(p->slot_off + p->nslots, &nn, sizeof(int), hipMemcpyHostToDevice, s) != hipSuccess ||
+            hipStreamSynchronize(s) != hipSuccess) { rc = NUSHT_EDEVICE; break; }
+        if (hipGetLastError() != hipSuccess) { rc = NUSHT_EDEVICE; break; }
+    } while (0);
+    hipFree(keys);
+    hipFree(keys_s);
+    hipFree(idx);
+    hipFree(first);
+    hipFree(sidx);
+    hipFree(phw);
+    hipFree(tmp);
+    return rc;
+}
+
+static int build_tables(nusht_plan_s* p)
+{
+    const nusht_geometry& g = p->g;
+    const int L = g.lmax, M = g.mmax;
+    // recurrence coefficients (a_lm, a_lm b_lm) in long double, rounded once
+    std::vector<double> rec(2 * (size_t)g.nalm, 0.0);
+    for (int m = 0; m <= M; ++m) {
+        const int64_t moff = (int64_t)m * (2 * L + 1 - m) / 2;
+        for (int l = m + 1; l <= L; ++l) {
+            const long double ll = l, mm = m, l1 = l - 1;
+            const long double a = sqrtl((4 * ll * ll - 1) / (ll * ll - mm * mm));
+            const long double b = sqrtl((l1 * l1 - mm * mm) / (4 * l1 * l1 - 1));
+            rec[2 * (moff + l)] = (double)a;
+            rec[2 * (moff + l) + 1] = (double)(a * b);
+        }
+    }
+    // lam_mm prefactor (-1)^m sqrt((2m+1)/(4 pi) prod_{k<=m} (2k-1)/(2k)) as mantissa * 2^e
+    std::vector<double> cm(M + 1);
+    std::vector<int> ce(M + 1);
+    {
+        long double prod = 1.0L;
+        int pe = 0;
+        for (int m = 0; m <= M; ++m) {
+            if (m > 0) {
+                prod *= (2.0L * m - 1.0L) / (2.0L * m);
+                int t;
+                prod = frexpl(prod, &t);
+                pe += t;
+            }
+            long double v = (2.0L * m + 1.0L) / (4.0L * 3.14159265358979323846264338327950288L) * prod;
+            int e2 = pe;
+            if (e2 & 1) {
+                v *= 2.0L;
+                e2 -= 1;
+            }
+            long double r = sqrtl(v);
+            int t;
+            r = frexpl(r, &t);
+            cm[m] = (double)((m & 1) ? -r : r);
+            ce[m] = e2 / 2 + t;
+        }
+    }
+    // deconvolution: h / psi^(k) = 2 / (w I(k)), with the 1/N_t of the theta transform
+    std::vector<double> i1, i2;
+    es_fourier(g.beta, g.width * M_PI / g.n1, L, i1);
+    es_fourier(g.beta, g.width * M_PI / g.n2, M, i2);
+    std::vector<double> d1(L + 1), d2(M + 1);
+    std::vector<float> d1f(L + 1), d2f(M + 1);
+    for (int k = 0; k <= L; ++k) {
+        d1[k] = 2.0 / (g.width * i1[k]) / g.ntorus;
+        d1f[k] = (float)d1[k];
+    }
+    for (int k = 0; k <= M; ++k) {
+        d2[k] = 2.0 / (g.width * i2[k]);
+        d2f[k] = (float)d2[k];
+    }
+    NUSHT_TRY(dmalloc(&p->rec, (size_t)g.nalm));
+    NUSHT_TRY(dmalloc(&p->cm_mant, M + 1));
+    NUSHT_TRY(dmalloc(&p->cm_exp, M + 1));
+    NUSHT_TRY(dmalloc(&p->dec1, L + 1));
+    NUSHT_TRY(dmalloc(&p->dec2, M + 1));
+    NUSHT_TRY(dmalloc(&p->dec1f, L + 1));
+    NUSHT_TRY(dmalloc(&p->dec2f, M + 1));
+    NUSHT_HIP(hipMemcpy(p->rec, rec.data(), rec.size() * sizeof(double), hipMemcpyHostToDevice));
+    NUSHT_HIP(hipMemcpy(p->cm_mant, cm.data(), cm.size() * sizeof(double), hipMemcpyHostToDevice));
+    NUSHT_HIP(hipMemcpy(p->cm_exp, ce.data(), ce.size() * sizeof(int), hipMemcpyHostToDevice));
+    NUSHT_HIP(hipMemcpy(p->dec1, d1.data(), d1.size() * sizeof(double), hipMemcpyHostToDevice));
+    NUSHT_HIP(hipMemcpy(p->dec2, d2.data(), d2.size() * sizeof(double), hipMemcpyHostToDevice));
+    NUSHT_HIP(hipMemcpy(p->dec1f, d1f.data(), d1f.size() * sizeof(float), hipMemcpyHostToDevice));
+    NUSHT_HIP(hipMemcpy(p->dec2f, d2f.data(), d2f.size() * sizeof(float), hipMemcpyHostToDevice));
+    return NUSHT_OK;
+}
+
+int create_fft_plans(nusht_plan_s* p);
+void destroy_fft_plans(nusht_plan_s* p);
+
+}  // namespace nusht
+
+using namespace nusht;
+
+extern "C" {
+
+int64_t nusht_nalm(int lmax, int mmax)
+{
+    if (lmax < 0 || mmax < 0 || mmax > lmax) return -1;
+    return (int64_t)(mmax + 1) * (lmax + 1) - (int64_t)mmax * (mmax + 1) / 2;
+}
+
+int nusht_geometry_for(int lmax, int mmax, double eps, int dtype, const nusht_plan_opts* opts,
+                   nusht_geometry* out)
+{
+    return compute_geometry(lmax, mmax, eps, dtype, opts, out);
+}
+
+const char* nusht_strerror(int status)
+{
+    switch (status) {
+        case NUSHT_OK: return "success";
+        case NUSHT_EINVAL: return "invalid argument";
+        case NUSHT_ENOMEM: return "device memory allocation failed";
+        case NUSHT_EDEVICE: return "HIP or rocFFT call failed";
+        case NUSHT_ENOCONV: return "iterative solve did not converge within maxiter";
+        case NUSHT_EPRECISION: return "requested accuracy needs NUSHT_F64";
+        default: return "unknown status";
+    }
+}
+
+const char* nusht_last_error(void) { return g_last_error.c_str(); }
+
+void nusht_destroy(nusht_plan_t p)
+{
+    if (!p) return;
+    int cur = 0;
+    hipGetDevice(&cur);
+    hipSetDevice(p->device);
+    hipDeviceSynchronize();
+    destroy_fft_plans(p);
+    void* bufs[] = {p->rec,  p->cm_mant, p->cm_exp,   p->dec1,      p->dec2,      p->dec1f,
+                    p->dec2f, p->sth,    p->sph,      p->perm,      p->slot_off,  p->slot_tile,
+                    p->tile_slot, p->dflag, p->X,     p->Y,         p->Z,         p->fftwork,
+                    p->red};
+    for (void* b : bufs)
+        if (b) hipFree(b);
+    for (int i = 0; i < ST_COUNT; ++i) {
+        if (p->ev[i][0]) hipEventDestroy(p->ev[i][0]);
+        if (p->ev[i][1]) hipEventDestroy(p->ev[i][1]);
+    }
+    hipSetDevice(cur);
+    delete p;
+}
+
+int nusht_plan_ex(int lmax, int mmax, int64_t npts, const double* theta, const double* phi,
+                  double eps, int dtype, const nusht_plan_opts* opts, void* stream,
+                  nusht_plan_t* out)
+{
+    if (!out) return NUSHT_EINVAL;
+    *out = nullptr;
+    nusht_geometry g;
+    NUSHT_TRY(compute_geometry(lmax, mmax, eps, dtype, opts, &g));
+    if (npts < 1 || npts >= (int64_t)1 << 31 || !theta || !phi) {
+        set_last_error("nusht_plan", "need 1 <= npts < 2^31 and non-null coordinates");
+        return NUSHT_EINVAL;
+    }
+    g.npts = npts;
+    nusht_plan_s* p = new nusht_plan_s();
+    p->g = g;
+    p->eps = eps;
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    p->plan_stream = s;
+    int rc = NUSHT_OK;
+    do {
+        if (hipGetDevice(&p->device) != hipSuccess) { rc = NUSHT_EDEVICE; break; }
+        p->timing = opts ? opts->timing : 0;
+        if ((rc = build_tables(p))) break;
+        if ((rc = bin_points(p, theta, phi, s))) break;
+        p->g.ntiles_used = p->nslots;
+        if ((rc = create_fft_plans(p))) break;
+        if (p->timing) {
+            for (int i = 0; i < ST_COUNT; ++i) {
+                if (hipEventCreate(&p->ev[i][0]) != hipSuccess ||
+                    hipEventCreate(&p->ev[i][1]) != hipSuccess) { rc = NUSHT_EDEVICE; break; }
+            }
+        }
+    } while (0);
+    if (rc != NUSHT_OK) {
+        nusht_destroy(p);
+        return rc;
+    }
+    *out = p;
+    return NUSHT_OK;
+}
+
+int nusht_plan(int lmax, int mmax, int64_t npts, const double* theta, const double* phi,
+               double eps, int dtype, nusht_plan_t* out)
+{
+    return nusht_plan_ex(lmax, mmax, npts, theta, phi, eps, dtype, nullptr, nullptr, out);
+}
+
+int nusht_plan_info(nusht_plan_t p, nusht_geometry* out)
+{
+    if (!p || !out) return NUSHT_EINVAL;
+    *out = p->g;
+    return NUSHT_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,462 @@
+// Stage sequencing of the synthesis Y = N F D S (Eq. 5) and the adjoint Y^H = S^H D^H F^H N^H
+// (Eq. 6) of arXiv:2406.14542 on one HIP stream, with rocFFT for the uniform FFTs.
+// Everything is enqueued asynchronously; intermediates live in two ping-pong scratch
+// regions X and Y (and Z for the spreading subgrids) that the plan owns.
+#include <cstring>
+#include <mutex>
+
+#include "internal.h"
+
+namespace nusht {
+
+int interp_f64(const nusht_plan_s* p, const double* fine, double* out, int nmaps, hipStream_t s);
+int interp_f32(const nusht_plan_s* p, const float* fine, double* out, int nmaps, hipStream_t s);
+int spread_group_f64(const nusht_plan_s* p, const double* in, double* sub, int b, int mb,
+                     hipStream_t s);
+int spread_group_f32(const nusht_plan_s* p, const double* in, float* sub, int b, int mb,
+                     hipStream_t s);
+int halo_group_f64(const nusht_plan_s* p, const double* sub, double* fine, int b, int mb,
+                   hipStream_t s);
+int halo_group_f32(const nusht_plan_s* p, const float* sub, float* fine, int b, int mb,
+                   hipStream_t s);
+
+namespace {
+
+std::once_flag g_fft_once;
+
+int make_fft(FftPlan& f, rocfft_transform_type type, rocfft_precision prec, size_t dim,
+             const size_t* lengths, size_t batch, rocfft_result_placement place)
+{
+    rocfft_plan_description desc = nullptr;
+    NUSHT_FFT(rocfft_plan_description_create(&desc));
+    if (type == rocfft_transform_type_real_forward || type == rocfft_transform_type_real_inverse) {
+        // default packed layouts for real transforms
+        rocfft_array_type in_t = type == rocfft_transform_type_real_forward
+                                     ? rocfft_array_type_real
+                                     : rocfft_array_type_hermitian_interleaved;
+        rocfft_array_type out_t = type == rocfft_transform_type_real_forward
+                                      ? rocfft_array_type_hermitian_interleaved
+                                      : rocfft_array_type_real;
+        NUSHT_FFT(rocfft_plan_description_set_data_layout(desc, in_t, out_t, nullptr, nullptr, 0,
+                                                          nullptr, 0, 0, nullptr, 0));
+    }
+    rocfft_status st = rocfft_plan_create(&f.plan, place, type, prec, dim, lengths, batch, desc);
+    rocfft_plan_description_destroy(desc);
+    if (st != rocfft_status_success) {
+        set_last_error("rocfft_plan_create", "failed");
+        return NUSHT_EDEVICE;
+    }
+    NUSHT_FFT(rocfft_plan_get_work_buffer_size(f.plan, &f.work_bytes));
+    NUSHT_FFT(rocfft_execution_info_create(&f.info));
+    return NUSHT_OK;
+}
+
+void free_fft(FftPlan& f)
+{
+    if (f.info) rocfft_execution_info_destroy(f.info);
+    if (f.plan) rocfft_plan_destroy(f.plan);
+    f.info = nullptr;
+    f.plan = nullptr;
+}
+
+int ensure_ring_plans(nusht_plan_s* p);
+
+}  // namespace
+
+int create_fft_plans(nusht_plan_s* p)
+{
+    std::call_once(g_fft_once, [] { rocfft_setup(); });
+    const nusht_geometry& g = p->g;
+    const rocfft_precision prec =
+        g.dtype == NUSHT_MIXED ? rocfft_precision_single : rocfft_precision_double;
+    const size_t fine_len[2] = {(size_t)g.n2, (size_t)g.n1};
+    NUSHT_TRY(make_fft(p->fine_c2r, rocfft_transform_type_real_inverse, prec, 2, fine_len, 1,
+                       rocfft_placement_notinplace));
+    NUSHT_TRY(make_fft(p->fine_r2c, rocfft_transform_type_real_forward, prec, 2, fine_len, 1,
+                       rocfft_placement_notinplace));
+    if (g.dfs_mode == NUSHT_DFS_FUSED) {
+        const size_t len = (size_t)g.ntorus;
+        NUSHT_TRY(make_fft(p->theta_fwd, rocfft_transform_type_complex_forward, prec, 1, &len,
+                           (size_t)g.mmax + 1, rocfft_placement_inplace));
+        NUSHT_TRY(make_fft(p->theta_bwd, rocfft_transform_type_complex_inverse, prec, 1, &len,
+                           (size_t)g.mmax + 1, rocfft_placement_inplace));
+    } else {
+        const size_t tl[2] = {(size_t)g.nphi, (size_t)g.ntorus};
+        NUSHT_TRY(make_fft(p->torus_r2c, rocfft_transform_type_real_forward, prec, 2, tl, 1,
+                           rocfft_placement_notinplace));
+        NUSHT_TRY(make_fft(p->torus_c2r, rocfft_transform_type_real_inverse, prec, 2, tl, 1,
+                           rocfft_placement_notinplace));
+        NUSHT_TRY(ensure_ring_plans(p));
+    }
+    size_t work = 0;
+    for (FftPlan* f : {&p->fine_c2r, &p->fine_r2c, &p->theta_fwd, &p->theta_bwd, &p->torus_r2c,
+                       &p->torus_c2r, &p->ring_c2r, &p->ring_r2c})
+        if (f->plan && f->work_bytes > work) work = f->work_bytes;
+    if (work > p->fftwork_bytes) {
+        if (p->fftwork) hipFree(p->fftwork);
+        p->fftwork = nullptr;
+        NUSHT_HIP(hipMalloc(&p->fftwork, work));
+        p->fftwork_bytes = work;
+    }
+    return NUSHT_OK;
+}
+
+namespace {
+
+int ensure_ring_plans(nusht_plan_s* p)
+{
+    if (p->ring_c2r.plan) return NUSHT_OK;
+    const nusht_geometry& g = p->g;
+    const size_t len = (size_t)g.nphi;
+    NUSHT_TRY(make_fft(p->ring_c2r, rocfft_transform_type_real_inverse, rocfft_precision_double,
+                       1, &len, (size_t)g.nrings, rocfft_placement_notinplace));
+    NUSHT_TRY(make_fft(p->ring_r2c, rocfft_transform_type_real_forward, rocfft_precision_double,
+                       1, &len, (size_t)g.nrings, rocfft_placement_notinplace));
+    const size_t work = p->ring_c2r.work_bytes > p->ring_r2c.work_bytes ? p->ring_c2r.work_bytes
+                                                                         : p->ring_r2c.work_bytes;
+    if (work > p->fftwork_bytes) {
+        if (p->fftwork) {
+            NUSHT_HIP(hipDeviceSynchronize());
+            hipFree(p->fftwork);
+        }
+        p->fftwork = nullptr;
+        NUSHT_HIP(hipMalloc(&p->fftwork, work));
+        p->fftwork_bytes = work;
+    }
+    return NUSHT_OK;
+}
+
+}  // namespace
+
+void destroy_fft_plans(nusht_plan_s* p)
+{
+    for (FftPlan* f : {&p->fine_c2r, &p->fine_r2c, &p->theta_fwd, &p->theta_bwd, &p->torus_r2c,
+                       &p->torus_c2r, &p->ring_c2r, &p->ring_r2c})
+        free_fft(*f);
+}
+
+int fft_exec(nusht_plan_s* p, FftPlan& f, void* in, void* out, hipStream_t s)
+{
+    NUSHT_FFT(rocfft_execution_info_set_stream(f.info, s));
+    if (f.work_bytes) NUSHT_FFT(rocfft_execution_info_set_work_buffer(f.info, p->fftwork, f.work_bytes));
+    void* ib[1] = {in};
+    void* ob[1] = {out};
+    NUSHT_FFT(rocfft_execute(f.plan, ib, out ? ob : nullptr, f.info));
+    return NUSHT_OK;
+}
+
+void stage_begin(nusht_plan_s* p, Stage st, hipStream_t s)
+{
+    if (!p->timing) return;
+    hipEventRecord(p->ev[st][0], s);
+    p->ev_used[st] = 1;
+}
+
+void stage_end(nusht_plan_s* p, Stage st, hipStream_t s)
+{
+    if (!p->timing) return;
+    hipEventRecord(p->ev[st][1], s);
+}
+
+namespace {
+
+struct DeviceGuard {
+    int prev = -1;
+    explicit DeviceGuard(int dev)
+    {
+        hipGetDevice(&prev);
+        if (prev != dev) hipSetDevice(dev);
+    }
+    ~DeviceGuard()
+    {
+        int cur = -1;
+        hipGetDevice(&cur);
+        if (prev >= 0 && cur != prev) hipSetDevice(prev);
+    }
+};
+
+void reset_timing(nusht_plan_s* p)
+{
+    for (int i = 0; i < ST_COUNT; ++i) p->ev_used[i] = 0;
+}
+
+inline char* bytes(void* v) { return reinterpret_cast<char*>(v); }
+
+// fine grid (real) of map b and its half spectrum, in elements of the plan's precision
+size_t fine_real_bytes(const nusht_plan_s* p) { return (size_t)p->g.n1 * p->g.n2 * fine_elem_bytes(p); }
+size_t fine_spec_bytes(const nusht_plan_s* p)
+{
+    return (size_t)p->g.n1 * (p->g.n2 / 2 + 1) * 2 * fine_elem_bytes(p);
+}
+
+// S (Legendre + per-ring phi-FFT) of the paper composition into ring maps [b][N_r][N_phi]
+int ring_synthesis_into(nusht_plan_s* p, const double* alm, double* ring, void* G, int nmaps,
+                        hipStream_t s)
+{
+    const nusht_geometry& g = p->g;
+    stage_begin(p, ST_LEGENDRE, s);
+    NUSHT_TRY(launch_legendre_synth(p, alm, G, nmaps, 0, 0, s));
+    NUSHT_TRY(launch_zero_nyquist_rows(p, reinterpret_cast<double*>(G), nmaps, s));
+    stage_end(p, ST_LEGENDRE, s);
+    stage_begin(p, ST_RING_FFT, s);
+    const size_t gstride = (size_t)g.nrings * (g.nphi / 2 + 1) * 16;
+    const size_t rstride = (size_t)g.nrings * g.nphi * 8;
+    for (int b = 0; b < nmaps; ++b)
+        NUSHT_TRY(fft_exec(p, p->ring_c2r, bytes(G) + b * gstride, bytes(ring) + b * rstride, s));
+    stage_end(p, ST_RING_FFT, s);
+    return NUSHT_OK;
+}
+
+// torus spectrum (fused: doubled theta-columns [b][m][t] transformed over t; paper: 2D R2C
+// of the doubled map) into X, for maps [0, nmaps)
+int synthesis_to_fine(nusht_plan_s* p, const double* alm, int nmaps, hipStream_t s, void** fine_out)
+{
+    const nusht_geometry& g = p->g;
+    const int f32 = g.dtype == NUSHT_MIXED;
+    const size_t e = fine_elem_bytes(p);
+    if (g.dfs_mode == NUSHT_DFS_FUSED) {
+        stage_begin(p, ST_LEGENDRE, s);
+        NUSHT_TRY(launch_legendre_synth(p, alm, p->X, nmaps, 1, f32, s));
+        stage_end(p, ST_LEGENDRE, s);
+        stage_begin(p, ST_TORUS_FFT, s);
+        const size_t cstride = (size_t)(g.mmax + 1) * g.ntorus * 2 * e;
+        for (int b = 0; b < nmaps; ++b)
+            NUSHT_TRY(fft_exec(p, p->theta_fwd, bytes(p->X) + b * cstride, nullptr, s));
+        stage_end(p, ST_TORUS_FFT, s);
+        stage_begin(p, ST_DECONV, s);
+        NUSHT_TRY(launch_deconv_pad(p, p->X, p->Y, nmaps, 1, f32, s));
+        stage_end(p, ST_DECONV, s);
+        stage_begin(p, ST_FINE_FFT, s);
+        for (int b = 0; b < nmaps; ++b)
+            NUSHT_TRY(fft_exec(p, p->fine_c2r, bytes(p->Y) + b * fine_spec_bytes(p),
+                               bytes(p->X) + b * fine_real_bytes(p), s));
+        stage_end(p, ST_FINE_FFT, s);
+        *fine_out = p->X;
+    } else {
+        NUSHT_TRY(ring_synthesis_into(p, alm, reinterpret_cast<double*>(p->Y), p->X, nmaps, s));
+        stage_begin(p, ST_DOUBLE, s);
+        NUSHT_TRY(launch_double(p, reinterpret_cast<const double*>(p->Y), p->X, nmaps, f32, s));
+        stage_end(p, ST_DOUBLE, s);
+        stage_begin(p, ST_TORUS_FFT, s);
+        const size_t tstride = (size_t)g.ntorus * g.nphi * e;
+        const size_t sstride = (size_t)g.ntorus * (g.nphi / 2 + 1) * 2 * e;
+        for (int b = 0; b < nmaps; ++b)
+            NUSHT_TRY(fft_exec(p, p->torus_r2c, bytes(p->X) + b * tstride,
+                               bytes(p->Y) + b * sstride, s));
+        stage_end(p, ST_TORUS_FFT, s);
+        stage_begin(p, ST_DECONV, s);
+        NUSHT_TRY(launch_deconv_pad(p, p->Y, p->X, nmaps, 0, f32, s));
+        stage_end(p, ST_DECONV, s);
+        stage_begin(p, ST_FINE_FFT, s);
+        for (int b = 0; b < nmaps; ++b)
+            NUSHT_TRY(fft_exec(p, p->fine_c2r, bytes(p->X) + b * fine_spec_bytes(p),
+                               bytes(p->Y) + b * fine_real_bytes(p), s));
+        stage_end(p, ST_FINE_FFT, s);
+        *fine_out = p->Y;
+    }
+    return NUSHT_OK;
+}
+
+int check_exec(nusht_plan_s* p, const void* a, const void* b, int nmaps)
+{
+    if (!p) {
+        set_last_error("nusht", "null plan");
+        return NUSHT_EINVAL;
+    }
+    if (!a || !b || nmaps < 1) {
+        set_last_error("nusht", "null buffer or nmaps < 1");
+        return NUSHT_EINVAL;
+    }
+    return NUSHT_OK;
+}
+
+}  // namespace
+}  // namespace nusht
+
+using namespace nusht;
+
+extern "C" {
+
+int nusht_synthesis(nusht_plan_t p, const double* alm, double* map, int nmaps, void* stream)
+{
+    NUSHT_TRY(check_exec(p, alm, map, nmaps));
+    DeviceGuard dg(p->device);
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    NUSHT_TRY(ensure_capacity(p, nmaps));
+    reset_timing(p);
+    void* fine = nullptr;
+    NUSHT_TRY(synthesis_to_fine(p, alm, nmaps, s, &fine));
+    stage_begin(p, ST_POINTS, s);
+    if (p->g.dtype == NUSHT_MIXED)
+        NUSHT_TRY(interp_f32(p, reinterpret_cast<const float*>(fine), map, nmaps, s));
+    else
+        NUSHT_TRY(interp_f64(p, reinterpret_cast<const double*>(fine), map, nmaps, s));
+    stage_end(p, ST_POINTS, s);
+    return NUSHT_OK;
+}
+
+int nusht_synthesis_deriv(nusht_plan_t p, const double* alm, double* map, double* dtheta,
+                          double* dphi, int nmaps, void* stream)
+{
+    NUSHT_TRY(check_exec(p, alm, map, nmaps));
+    if (!dtheta || !dphi) return NUSHT_EINVAL;
+    if (p->g.dtype != NUSHT_F64) {
+        set_last_error("nusht_synthesis_deriv", "needs an FP64 plan");
+        return NUSHT_EPRECISION;
+    }
+    DeviceGuard dg(p->device);
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    NUSHT_TRY(ensure_capacity(p, nmaps));
+    reset_timing(p);
+    void* fine = nullptr;
+    NUSHT_TRY(synthesis_to_fine(p, alm, nmaps, s, &fine));
+    stage_begin(p, ST_POINTS, s);
+    NUSHT_TRY(launch_interp_deriv(p, reinterpret_cast<const double*>(fine), map, dtheta, dphi,
+                                  nmaps, s));
+    stage_end(p, ST_POINTS, s);
+    return NUSHT_OK;
+}
+
+int nusht_adjoint(nusht_plan_t p, const double* map, double* alm, int nmaps, void* stream)
+{
+    NUSHT_TRY(check_exec(p, map, alm, nmaps));
+    DeviceGuard dg(p->device);
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    NUSHT_TRY(ensure_capacity(p, nmaps));
+    reset_timing(p);
+    const nusht_geometry& g = p->g;
+    const int f32 = g.dtype == NUSHT_MIXED;
+    const size_t e = fine_elem_bytes(p);
+    const int P = kTile + g.width - 1;
+    const size_t zgroup = (size_t)p->nslots * P * P * 4 * e;
+    // N^H (i): spreading into per-slot subgrids, then the halo reduction onto the fine grid
+    if ((size_t)point_groups(nmaps) * zgroup > p->Zbytes) {
+        set_last_error("nusht_adjoint", "spreading scratch too small for this batch");
+        return NUSHT_EINVAL;
+    }
+    stage_begin(p, ST_POINTS, s);
+    for (int b = 0, grp = 0; b < nmaps; ++grp) {
+        const int mb = group_width(nmaps, b);
+        void* sub = bytes(p->Z) + grp * zgroup;
+        if (f32)
+            NUSHT_TRY(spread_group_f32(p, map, reinterpret_cast<float*>(sub), b, mb, s));
+        else
+            NUSHT_TRY(spread_group_f64(p, map, reinterpret_cast<double*>(sub), b, mb, s));
+        b += mb;
+    }
+    stage_end(p, ST_POINTS, s);
+    stage_begin(p, ST_HALO, s);
+    for (int b = 0, grp = 0; b < nmaps; ++grp) {
+        const int mb = group_width(nmaps, b);
+        const void* sub = bytes(p->Z) + grp * zgroup;
+        if (f32)
+            NUSHT_TRY(halo_group_f32(p, reinterpret_cast<const float*>(sub),
+                                     reinterpret_cast<float*>(p->X), b, mb, s));
+        else
+            NUSHT_TRY(halo_group_f64(p, reinterpret_cast<const double*>(sub),
+                                     reinterpret_cast<double*>(p->X), b, mb, s));
+        b += mb;
+    }
+    stage_end(p, ST_HALO, s);
+    // N^H (ii): fine-grid R2C
+    stage_begin(p, ST_FINE_FFT, s);
+    for (int b = 0; b < nmaps; ++b)
+        NUSHT_TRY(fft_exec(p, p->fine_r2c, bytes(p->X) + b * fine_real_bytes(p),
+                           bytes(p->Y) + b * fine_spec_bytes(p), s));
+    stage_end(p, ST_FINE_FFT, s);
+    if (g.dfs_mode == NUSHT_DFS_FUSED) {
+        stage_begin(p, ST_DECONV, s);
+        NUSHT_TRY(launch_deconv_trunc(p, p->Y, p->X, nmaps, 1, f32, s));
+        stage_end(p, ST_DECONV, s);
+        stage_begin(p, ST_TORUS_FFT, s);
+        const size_t cstride = (size_t)(g.mmax + 1) * g.ntorus * 2 * e;
+        for (int b = 0; b < nmaps; ++b)
+            NUSHT_TRY(fft_exec(p, p->theta_bwd, bytes(p->X) + b * cstride, nullptr, s));
+        stage_end(p, ST_TORUS_FFT, s);
+        stage_begin(p, ST_LEGENDRE, s);
+        NUSHT_TRY(launch_legendre_adjoint(p, p->X, alm, nmaps, 1, f32, s));
+        stage_end(p, ST_LEGENDRE, s);
+    } else {
+        stage_begin(p, ST_DECONV, s);
+        NUSHT_TRY(launch_deconv_trunc(p, p->Y, p->X, nmaps, 0, f32, s));
+        stage_end(p, ST_DECONV, s);
+        stage_begin(p, ST_TORUS_FFT, s);
+        const size_t tstride = (size_t)g.ntorus * g.nphi * e;
+        const size_t sstride = (size_t)g.ntorus * (g.nphi / 2 + 1) * 2 * e;
+        for (int b = 0; b < nmaps; ++b)
+            NUSHT_TRY(fft_exec(p, p->torus_c2r, bytes(p->X) + b * sstride,
+                               bytes(p->Y) + b * tstride, s));
+        stage_end(p, ST_TORUS_FFT, s);
+        stage_begin(p, ST_DOUBLE, s);
+        NUSHT_TRY(launch_fold(p, p->Y, reinterpret_cast<double*>(p->X), nmaps, f32, s));
+        stage_end(p, ST_DOUBLE, s);
+        stage_begin(p, ST_RING_FFT, s);
+        const size_t rstride = (size_t)g.nrings * g.nphi * 8;
+        const size_t gstride = (size_t)g.nrings * (g.nphi / 2 + 1) * 16;
+        for (int b = 0; b < nmaps; ++b)
+            NUSHT_TRY(fft_exec(p, p->ring_r2c, bytes(p->X) + b * rstride,
+                               bytes(p->Y) + b * gstride, s));
+        stage_end(p, ST_RING_FFT, s);
+        stage_begin(p, ST_LEGENDRE, s);
+        NUSHT_TRY(launch_legendre_adjoint(p, p->Y, alm, nmaps, 0, 0, s));
+        stage_end(p, ST_LEGENDRE, s);
+    }
+    return NUSHT_OK;
+}
+
+int nusht_ring_synthesis(nusht_plan_t p, const double* alm, double* ring, int nmaps, void* stream)
+{
+    NUSHT_TRY(check_exec(p, alm, ring, nmaps));
+    DeviceGuard dg(p->device);
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    NUSHT_TRY(ensure_ring_plans(p));
+    NUSHT_TRY(ensure_capacity(p, nmaps));
+    reset_timing(p);
+    return ring_synthesis_into(p, alm, ring, p->X, nmaps, s);
+}
+
+int nusht_ring_adjoint(nusht_plan_t p, const double* ring, double* alm, int nmaps, void* stream)
+{
+    NUSHT_TRY(check_exec(p, ring, alm, nmaps));
+    DeviceGuard dg(p->device);
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    NUSHT_TRY(ensure_ring_plans(p));
+    NUSHT_TRY(ensure_capacity(p, nmaps));
+    reset_timing(p);
+    const nusht_geometry& g = p->g;
+    const size_t rstride = (size_t)g.nrings * g.nphi * 8;
+    const size_t gstride = (size_t)g.nrings * (g.nphi / 2 + 1) * 16;
+    // rocFFT may overwrite the input of an out-of-place transform: work on a copy
+    NUSHT_HIP(hipMemcpyAsync(p->X, ring, rstride * nmaps, hipMemcpyDeviceToDevice, s));
+    stage_begin(p, ST_RING_FFT, s);
+    for (int b = 0; b < nmaps; ++b)
+        NUSHT_TRY(fft_exec(p, p->ring_r2c, bytes(p->X) + b * rstride, bytes(p->Y) + b * gstride, s));
+    stage_end(p, ST_RING_FFT, s);
+    stage_begin(p, ST_LEGENDRE, s);
+    NUSHT_TRY(launch_legendre_adjoint(p, p->Y, alm, nmaps, 0, 0, s));
+    stage_end(p, ST_LEGENDRE, s);
+    return NUSHT_OK;
+}
+
+int nusht_stage_times(nusht_plan_t p, double* ms, const char** names, int maxn)
+{
+    static const char* kNames[ST_COUNT] = {"legendre", "ring_fft", "double_fold", "torus_fft",
+                                           "deconv", "fine_fft", "points", "halo"};
+    if (!p || !ms || maxn < 0) return NUSHT_EINVAL;
+    if (!p->timing) return 0;
+    int n = 0;
+    for (int i = 0; i < ST_COUNT && n < maxn; ++i) {
+        float t = 0.0f;
+        if (p->ev_used[i]) {
+            if (hipEventSynchronize(p->ev[i][1]) != hipSuccess ||
+                hipEventElapsedTime(&t, p->ev[i][0], p->ev[i][1]) != hipSuccess)
+                t = -1.0f;
+        }
+        ms[n] = p->ev_used[i] ? (double)t : 0.0;
+        if (names) names[n] = kNames[i];
+        ++n;
+    }
+    return n;
+}
+
+}  // extern "C"
