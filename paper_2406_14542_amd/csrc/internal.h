@@ -83,6 +83,8 @@ struct nusht_plan_s {
     double2* rec = nullptr;      // [nalm]: (a_lm, a_lm * b_lm) of the recurrence, l >= m+1
     double* cm_mant = nullptr;   // [mmax+1]: lam_mm prefactor mantissa, sign (-1)^m included
     int* cm_exp = nullptr;       // [mmax+1]: its power-of-two exponent
+    int* jlive = nullptr;        // [mmax+1]: first ring pair with any lam_lm above 2^-300
+    std::vector<int> jlive_host;
 
     // Deconvolution factors (include the FFT normalisation of the torus transform).
     double* dec1 = nullptr;      // [lmax+1], indexed by |kappa|
@@ -152,7 +154,10 @@ void stage_end(nusht_plan_s* p, Stage st, hipStream_t s);
 int launch_legendre_synth(const nusht_plan_s* p, const double* alm, void* out, int nmaps,
                           int fused, int out_f32, hipStream_t s);
 int launch_legendre_adjoint(const nusht_plan_s* p, const void* in, double* alm, int nmaps,
-                            int fused, int in_f32, hipStream_t s);
+                            int fused, int in_f32, void* scratch, size_t scratch_bytes,
+                            hipStream_t s);
+// bytes of partial sums the adjoint needs (one slice per chunk of ring pairs)
+size_t legendre_adjoint_scratch(const nusht_plan_s* p, int nmaps);
 
 // ---- DFS glue (dfs.hip) ----
 int launch_zero_nyquist_rows(const nusht_plan_s* p, double* G, int nmaps, hipStream_t s);

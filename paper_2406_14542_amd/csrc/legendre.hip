@@ -109,109 +109,164 @@ __device__ inline void accum(double (&acc)[MB][2], const double2* __restrict__ a
 // space: out(t) = G(t) for t < N_r and (-1)^m G(N_t - t) for t >= N_r.  PAPER:
 // out[b][j][m], rows of length (N_phi/2 + 1), the input of the per-ring phi-FFT.
 // ------------------------------------------------------------------------------------
-template <int MB, bool FUSED, typename OutT>
+template <typename OutT>
+__device__ inline OutT make_out(double re, double im)
+{
+    OutT o;
+    o.x = re;
+    o.y = im;
+    return o;
+}
+
+// Each lane owns R ring pairs j = base + lane + 64 r; a wave therefore covers 64 R
+// consecutive pairs and loads every coefficient once for all of them.
+template <int MB, int R, bool FUSED, typename OutT>
 __global__ __launch_bounds__(256) void k_legendre_synth(
     const double2* __restrict__ alm, int64_t nalm, int lmax,
     const double2* __restrict__ rec, const double* __restrict__ cm_mant,
-    const int* __restrict__ cm_exp, int nr, int nt, OutT* __restrict__ out,
-    int64_t out_map_stride, int64_t out_row_stride)
+    const int* __restrict__ cm_exp, const int* __restrict__ jlive, int nr, int nt,
+    OutT* __restrict__ out, int64_t out_map_stride, int64_t out_row_stride)
 {
     const int m = blockIdx.y;
     const int npairs = (nr + 1) / 2;
-    const int j0 = blockIdx.x * blockDim.x + threadIdx.x;
-    const bool active = j0 < npairs;
-    const int j = active ? j0 : npairs - 1;
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int wbase = (blockIdx.x * (blockDim.x >> 6) + wave) * 64 * R;
+    if (wbase >= npairs) return;
     alm += (int64_t)blockIdx.z * MB * nalm;
     out += (int64_t)blockIdx.z * MB * out_map_stride;
-
-    double s, y;
-    ring_geom(j, nr, s, y);
     const int64_t moff = (int64_t)m * (2 * lmax + 1 - m) / 2;  // index(l, m) = moff + l
+    const bool wave_dead = wbase + 64 * R <= jlive[m];
 
-    double E[MB][2], O[MB][2];
+    double E[R][MB][2], O[R][MB][2];
 #pragma unroll
-    for (int b = 0; b < MB; ++b) E[b][0] = E[b][1] = O[b][0] = O[b][1] = 0.0;
+    for (int r = 0; r < R; ++r)
+#pragma unroll
+        for (int b = 0; b < MB; ++b) E[r][b][0] = E[r][b][1] = O[r][b][0] = O[r][b][1] = 0.0;
 
-    double vc, vp = 0.0;
-    int k;
-    lambda_mm_scaled(cm_mant[m], cm_exp[m], s, m, vc, k);
-    if (k == 0) accum<MB>(E, alm, nalm, moff + m, vc);
+    if (!wave_dead) {
+        double y[R], vc[R], vp[R];
+        int k[R];
+        bool any_scaled = false;
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const int j = min(wbase + lane + 64 * r, npairs - 1);
+            double s;
+            ring_geom(j, nr, s, y[r]);
+            vp[r] = 0.0;
+            lambda_mm_scaled(cm_mant[m], cm_exp[m], s, m, vc[r], k[r]);
+            if (k[r] == 0) accum<MB>(E[r], alm, nalm, moff + m, vc[r]);
+            any_scaled |= k[r] > 0;
+        }
+        int l = m + 1;
+        // scaled phase: some lane of the wave still carries a 2^256 factor
+        while (l <= lmax && __any(any_scaled)) {
+            const double2 c = rec[moff + l];
+            any_scaled = false;
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                const double vn = rec_step(c, y[r], vc[r], vp[r]);
+                vp[r] = vc[r];
+                vc[r] = vn;
+                const bool big = (k[r] > 0) && (fabs(vc[r]) >= kBig);
+                const double sc = big ? kUnit : 1.0;
+                vc[r] *= sc;
+                vp[r] *= sc;
+                k[r] -= big ? 1 : 0;
+                any_scaled |= k[r] > 0;
+                const double lam = (k[r] == 0) ? vc[r] : 0.0;
+                if ((l - m) & 1)
+                    accum<MB>(O[r], alm, nalm, moff + l, lam);
+                else
+                    accum<MB>(E[r], alm, nalm, moff + l, lam);
+            }
+            ++l;
+        }
+        // plain phase, two steps at a time so that the parity of l - m is static
+        if (l <= lmax && ((l - m) & 1)) {
+            const double2 c = rec[moff + l];
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                const double vn = rec_step(c, y[r], vc[r], vp[r]);
+                vp[r] = vc[r];
+                vc[r] = vn;
+                accum<MB>(O[r], alm, nalm, moff + l, vc[r]);
+            }
+            ++l;
+        }
+        for (; l + 1 <= lmax; l += 2) {
+            const double2 c0 = rec[moff + l], c1 = rec[moff + l + 1];
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                double vn = rec_step(c0, y[r], vc[r], vp[r]);
+                vp[r] = vc[r];
+                vc[r] = vn;
+                accum<MB>(E[r], alm, nalm, moff + l, vc[r]);
+                vn = rec_step(c1, y[r], vc[r], vp[r]);
+                vp[r] = vc[r];
+                vc[r] = vn;
+                accum<MB>(O[r], alm, nalm, moff + l + 1, vc[r]);
+            }
+        }
+        if (l <= lmax) {
+            const double2 c = rec[moff + l];
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                const double vn = rec_step(c, y[r], vc[r], vp[r]);
+                accum<MB>(E[r], alm, nalm, moff + l, vn);
+            }
+        }
+    }
 
-    int l = m + 1;
-    // scaled phase: some lane of the wave still carries a 2^256 factor
-    while (l <= lmax && __any(k > 0)) {
-        double vn = rec_step(rec[moff + l], y, vc, vp);
-        vp = vc;
-        vc = vn;
-        const bool big = (k > 0) && (fabs(vc) >= kBig);
-        const double sc = big ? kUnit : 1.0;
-        vc *= sc;
-        vp *= sc;
-        k -= big ? 1 : 0;
-        const double lam = (k == 0) ? vc : 0.0;
-        if ((l - m) & 1)
-            accum<MB>(O, alm, nalm, moff + l, lam);
-        else
-            accum<MB>(E, alm, nalm, moff + l, lam);
-        ++l;
-    }
-    // plain phase, two steps at a time so that the parity of l - m is static
-    if (l <= lmax && ((l - m) & 1)) {
-        double vn = rec_step(rec[moff + l], y, vc, vp);
-        vp = vc;
-        vc = vn;
-        accum<MB>(O, alm, nalm, moff + l, vc);
-        ++l;
-    }
-    for (; l + 1 <= lmax; l += 2) {
-        double vn = rec_step(rec[moff + l], y, vc, vp);
-        vp = vc;
-        vc = vn;
-        accum<MB>(E, alm, nalm, moff + l, vc);
-        vn = rec_step(rec[moff + l + 1], y, vc, vp);
-        vp = vc;
-        vc = vn;
-        accum<MB>(O, alm, nalm, moff + l + 1, vc);
-    }
-    if (l <= lmax) {
-        double vn = rec_step(rec[moff + l], y, vc, vp);
-        accum<MB>(E, alm, nalm, moff + l, vn);
-    }
-    if (!active) return;
-
-    const int js = nr - 1 - j;
     const double sgn = (m & 1) ? -1.0 : 1.0;
 #pragma unroll
-    for (int b = 0; b < MB; ++b) {
-        double nre = E[b][0] + O[b][0], nim = E[b][1] + O[b][1];
-        double sre = E[b][0] - O[b][0], sim = E[b][1] - O[b][1];
-        if (m == 0) nim = sim = 0.0;  // Im a_l0 is ignored
-        OutT* o = out + b * out_map_stride;
-        if (FUSED) {
-            OutT* col = o + (int64_t)m * out_row_stride;
-            col[j] = OutT{nre, nim};
-            if (j >= 1 && j <= nr - 2) col[nt - j] = OutT{sgn * nre, sgn * nim};
-            if (js != j) {
-                col[js] = OutT{sre, sim};
-                if (js >= 1 && js <= nr - 2) col[nt - js] = OutT{sgn * sre, sgn * sim};
+    for (int r = 0; r < R; ++r) {
+        const int j = wbase + lane + 64 * r;
+        if (j >= npairs) continue;
+        const int js = nr - 1 - j;
+#pragma unroll
+        for (int b = 0; b < MB; ++b) {
+            double nre = E[r][b][0] + O[r][b][0], nim = E[r][b][1] + O[r][b][1];
+            double sre = E[r][b][0] - O[r][b][0], sim = E[r][b][1] - O[r][b][1];
+            if (m == 0) nim = sim = 0.0;  // Im a_l0 is ignored
+            OutT* o = out + b * out_map_stride;
+            if (FUSED) {
+                OutT* col = o + (int64_t)m * out_row_stride;
+                col[j] = make_out<OutT>(nre, nim);
+                if (j >= 1 && j <= nr - 2) col[nt - j] = make_out<OutT>(sgn * nre, sgn * nim);
+                if (js != j) {
+                    col[js] = make_out<OutT>(sre, sim);
+                    if (js >= 1 && js <= nr - 2) col[nt - js] = make_out<OutT>(sgn * sre, sgn * sim);
+                }
+            } else {
+                o[(int64_t)j * out_row_stride + m] = make_out<OutT>(nre, nim);
+                if (js != j) o[(int64_t)js * out_row_stride + m] = make_out<OutT>(sre, sim);
             }
-        } else {
-            o[(int64_t)j * out_row_stride + m] = OutT{nre, nim};
-            if (js != j) o[(int64_t)js * out_row_stride + m] = OutT{sre, sim};
         }
     }
 }
 
 // ------------------------------------------------------------------------------------
-// Adjoint.  One block per (m, map); thread t owns ring pairs t, t + T, ..., (R of them).
-// Per l the thread forms sum_r lam_lm(x_r) H_r with H = G'(j) + G'(j') for even l - m and
-// G'(j) - G'(j') for odd l - m; the block sums these over threads through LDS, CH values
-// of l at a time.  FUSED input: Tp[b][m][t] (t < N_t), folded here:
+// Adjoint.  c_lm = sum_j lam_lm(x_j) G'_m(theta_j) is, for one m, a product of the
+// (L - m + 1) x N_r matrix of lam values (generated by the recurrence) with the N_r x
+// (2 B) matrix of ring data, reduced over rings.  gfx950 mapping:
+//  * one lane = one ring pair (j, N_r-1-j); it runs the recurrence for 16 consecutive l
+//    and parks the 16 values in LDS;
+//  * the reduction over ring pairs is done by v_mfma_f64_16x16x4: per MFMA, A (16 x 4) holds
+//    the ring data of 4 pairs -- rows = {north re, north im, south re, south im} x 4 maps --
+//    and B (4 x 16) the lam values of those 4 pairs for the 16 l of the chunk, so 16 MFMAs
+//    reduce the wave's 64 pairs into D (16 x 16); the south rows enter with the parity sign
+//    lam_lm(-x) = (-1)^(l+m) lam_lm(x), applied once per l when the rows are combined;
+//  * the waves of a block (one pair-chunk) are summed through LDS; pair-chunks write
+//    partial sums that k_adj_finalize adds in a fixed order (deterministic, no atomics).
+// Input: FUSED Tp[b][m][t] (t < N_t), folded here:
 //   G'_m(j) = Tp(j) + [1 <= j <= N_r - 2] (-1)^m Tp(N_t - j)      (D^H of Eq. 6)
-// PAPER input: G'[b][j][m] rows of length (N_phi/2 + 1) (output of the per-ring R2C).
+// PAPER G'[b][j][m] rows of length (N_phi/2 + 1) (output of the per-ring R2C).
 // ------------------------------------------------------------------------------------
-constexpr int kChunk = 8;
-constexpr int kAdjMaxThreads = 640;
+typedef double d4_t __attribute__((ext_vector_type(4)));
+
+constexpr int kAdjWaves = 4;     // waves per block: one block reduces up to 256 ring pairs
+constexpr int kLC = 16;          // l values per chunk = the MFMA N dimension
+constexpr int kLS = kLC + 1;     // padded row of the lam staging area
 
 template <typename InT>
 __device__ inline double2 load_c(const InT* p)
@@ -220,128 +275,191 @@ __device__ inline double2 load_c(const InT* p)
     return make_double2((double)v.x, (double)v.y);
 }
 
-template <int R, bool FUSED, typename InT>
-__global__ __launch_bounds__(kAdjMaxThreads) void k_legendre_adj(
-    const InT* __restrict__ in, int64_t in_map_stride, int64_t in_row_stride,
-    double2* __restrict__ alm, int64_t nalm, int lmax, const double2* __restrict__ rec,
-    const double* __restrict__ cm_mant, const int* __restrict__ cm_exp, int nr, int nt)
+template <bool FUSED, typename InT>
+__device__ inline double2 ring_value(const InT* in_map, int64_t row_stride, int m, int j, int nr,
+                                     int nt, double sgn)
 {
-    __shared__ double red[2 * kChunk][kAdjMaxThreads];
-    const int m = blockIdx.x;
-    const int map = blockIdx.y;
-    const int T = blockDim.x;
-    const int tid = threadIdx.x;
-    const int npairs = (nr + 1) / 2;
-    in += (int64_t)map * in_map_stride;
-    alm += (int64_t)map * nalm;
-    const int64_t moff = (int64_t)m * (2 * lmax + 1 - m) / 2;
-    const double sgn = (m & 1) ? -1.0 : 1.0;
-
-    double y[R], vc[R], vp[R], Sr[R], Si[R], Dr[R], Di[R];
-    int k[R];
-    bool scaled = false;
-#pragma unroll
-    for (int r = 0; r < R; ++r) {
-        const int jr = tid + r * T;
-        const bool valid = jr < npairs;
-        const int j = valid ? jr : 0;
-        const int js = nr - 1 - j;
-        double s;
-        ring_geom(j, nr, s, y[r]);
-        double2 gn, gs;
-        if (FUSED) {
-            const InT* col = in + (int64_t)m * in_row_stride;
-            gn = load_c(col + j);
-            if (j >= 1 && j <= nr - 2) {
-                double2 t = load_c(col + (nt - j));
-                gn.x += sgn * t.x;
-                gn.y += sgn * t.y;
-            }
-            gs = load_c(col + js);
-            if (js >= 1 && js <= nr - 2) {
-                double2 t = load_c(col + (nt - js));
-                gs.x += sgn * t.x;
-                gs.y += sgn * t.y;
-            }
-        } else {
-            gn = load_c(in + (int64_t)j * in_row_stride + m);
-            gs = load_c(in + (int64_t)js * in_row_stride + m);
+    if (FUSED) {
+        const InT* col = in_map + (int64_t)m * row_stride;
+        double2 g = load_c(col + j);
+        if (j >= 1 && j <= nr - 2) {
+            const double2 t = load_c(col + (nt - j));
+            g.x += sgn * t.x;
+            g.y += sgn * t.y;
         }
-        if (!valid) {
-            gn = gs = make_double2(0.0, 0.0);
-        }
-        if (js == j) {  // the equator ring (odd N_r) is its own mirror: count it once
-            Sr[r] = gn.x;
-            Si[r] = gn.y;
-            Dr[r] = gn.x;
-            Di[r] = gn.y;
-        } else {
-            Sr[r] = gn.x + gs.x;
-            Si[r] = gn.y + gs.y;
-            Dr[r] = gn.x - gs.x;
-            Di[r] = gn.y - gs.y;
-        }
-        vp[r] = 0.0;
-        lambda_mm_scaled(cm_mant[m], cm_exp[m], s, m, vc[r], k[r]);
-        scaled |= k[r] > 0;
+        return g;
     }
+    return load_c(in_map + (int64_t)j * row_stride + m);
+}
 
-    const int nwaves = (T + 63) / 64;
-    const int wave = tid / 64, lane = tid % 64;
-    for (int l0 = m; l0 <= lmax; l0 += kChunk) {
-        double pr[kChunk], pi[kChunk];
+template <bool FUSED, typename InT>
+__global__ __launch_bounds__(kAdjWaves * 64) void k_legendre_adj(
+    const InT* __restrict__ in, int64_t in_map_stride, int64_t in_row_stride, int nmaps,
+    double* __restrict__ part, int npc, int64_t nalm, int lmax,
+    const double2* __restrict__ rec, const double* __restrict__ cm_mant,
+    const int* __restrict__ cm_exp, const int* __restrict__ jlive, int nr, int nt,
+    int pairs_per_block)
+{
+    __shared__ double stage[kAdjWaves][64 * kLS];
+    __shared__ double dsum[kAdjWaves][256];
+    const int m = blockIdx.x;
+    const int pc = blockIdx.y;
+    const int grp = blockIdx.z;
+    const int nmb = min(4, nmaps - 4 * grp);
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int nwaves = blockDim.x >> 6;
+    const int npairs = (nr + 1) / 2;
+    const int local = wave * 64 + lane;
+    const int pair = pc * pairs_per_block + local;
+    const bool valid = local < pairs_per_block && pair < npairs;
+    const int j = valid ? pair : 0;
+    const int js = nr - 1 - j;
+    const int64_t moff = (int64_t)m * (2 * lmax + 1 - m) / 2;
+    const double msgn = (m & 1) ? -1.0 : 1.0;
+    in += (int64_t)(4 * grp) * in_map_stride;
+    double* st = stage[wave];
+    const int jl = jlive[m];
+    // pairs below jl never carry lam above 2^-300 for l <= lmax: a block made only of them
+    // writes zero partial sums, a wave made only of them skips its recurrence and MFMAs
+    if (pc * pairs_per_block + pairs_per_block <= jl) {
+        for (int l = m + threadIdx.x; l <= lmax; l += blockDim.x)
+            for (int b = 0; b < nmb; ++b) {
+                double* dst = part + (((int64_t)(grp * npc + pc) * 4 + b) * nalm + moff + l) * 2;
+                dst[0] = 0.0;
+                dst[1] = 0.0;
+            }
+        return;
+    }
+    const bool wave_dead = pc * pairs_per_block + wave * 64 + 64 <= jl;
+
+    // ring data of this lane's pair: rows 4 b + {N re, N im, S re, S im}
+    {
+        double hv[16];
 #pragma unroll
-        for (int i = 0; i < kChunk; ++i) {
-            const int l = l0 + i;
-            pr[i] = pi[i] = 0.0;
-            if (l > lmax) continue;
-            const bool even = ((l - m) & 1) == 0;
-            if (l > m) {
-                const double2 c = rec[moff + l];
-                const bool wscaled = __any(scaled);
-                bool still = false;
+        for (int b = 0; b < 4; ++b) {
+            double2 gn = make_double2(0.0, 0.0), gs = make_double2(0.0, 0.0);
+            if (valid && b < nmb) {
+                const InT* im = in + (int64_t)b * in_map_stride;
+                gn = ring_value<FUSED, InT>(im, in_row_stride, m, j, nr, nt, msgn);
+                if (js != j) gs = ring_value<FUSED, InT>(im, in_row_stride, m, js, nr, nt, msgn);
+            }
+            hv[4 * b + 0] = gn.x;
+            hv[4 * b + 1] = gn.y;
+            hv[4 * b + 2] = gs.x;
+            hv[4 * b + 3] = gs.y;
+        }
 #pragma unroll
-                for (int r = 0; r < R; ++r) {
-                    const double vn = rec_step(c, y[r], vc[r], vp[r]);
-                    vp[r] = vc[r];
-                    vc[r] = vn;
+        for (int c = 0; c < 16; ++c) st[lane * kLS + c] = hv[c];
+    }
+    __syncthreads();
+    // A operand of MFMA q: A[i][k] = ring data of pair 4q + k, row i; lane = i + 16 k
+    double aop[16];
+#pragma unroll
+    for (int q = 0; q < 16; ++q) aop[q] = st[(4 * q + (lane >> 4)) * kLS + (lane & 15)];
+    __syncthreads();
+
+    double s, y;
+    ring_geom(j, nr, s, y);
+    double vc, vp = 0.0;
+    int k;
+    lambda_mm_scaled(cm_mant[m], cm_exp[m], s, m, vc, k);
+    if (!valid) {
+        vc = 0.0;
+        k = 0;
+    }
+    bool scaled = k > 0;
+
+    for (int l0 = m; l0 <= lmax; l0 += kLC) {
+        d4_t acc = {0.0, 0.0, 0.0, 0.0};
+        if (!wave_dead) {
+            double lam[kLC];
+            const bool wscaled = __any(scaled);
+#pragma unroll
+            for (int i = 0; i < kLC; ++i) {
+                const int l = l0 + i;
+                if (l > lmax) {
+                    lam[i] = 0.0;
+                    continue;
+                }
+                if (l > m) {
+                    const double2 c = rec[moff + l];
+                    const double vn = rec_step(c, y, vc, vp);
+                    vp = vc;
+                    vc = vn;
                     if (wscaled) {
-                        const bool big = (k[r] > 0) && (fabs(vc[r]) >= kBig);
+                        const bool big = (k > 0) && (fabs(vc) >= kBig);
                         const double sc = big ? kUnit : 1.0;
-                        vc[r] *= sc;
-                        vp[r] *= sc;
-                        k[r] -= big ? 1 : 0;
-                        still |= k[r] > 0;
+                        vc *= sc;
+                        vp *= sc;
+                        k -= big ? 1 : 0;
                     }
                 }
-                if (wscaled) scaled = still;
+                lam[i] = (k == 0) ? vc : 0.0;
             }
+            scaled = k > 0;
 #pragma unroll
-            for (int r = 0; r < R; ++r) {
-                const double lam = (k[r] == 0) ? vc[r] : 0.0;
-                pr[i] = fma(lam, even ? Sr[r] : Dr[r], pr[i]);
-                pi[i] = fma(lam, even ? Si[r] : Di[r], pi[i]);
+            for (int i = 0; i < kLC; ++i) st[lane * kLS + i] = lam[i];
+            // the wave reads back only its own staging rows
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+            // B[k][j] = lam_{l0 + j}(pair 4q + k); lane = j + 16 k.  Four independent
+            // accumulator chains keep the matrix pipe busy.
+            d4_t a1 = {0.0, 0.0, 0.0, 0.0}, a2 = a1, a3 = a1;
+#pragma unroll
+            for (int q = 0; q < 16; q += 4) {
+                const double b0 = st[(4 * q + (lane >> 4)) * kLS + (lane & 15)];
+                const double b1 = st[(4 * (q + 1) + (lane >> 4)) * kLS + (lane & 15)];
+                const double b2 = st[(4 * (q + 2) + (lane >> 4)) * kLS + (lane & 15)];
+                const double b3 = st[(4 * (q + 3) + (lane >> 4)) * kLS + (lane & 15)];
+                acc = __builtin_amdgcn_mfma_f64_16x16x4f64(aop[q], b0, acc, 0, 0, 0);
+                a1 = __builtin_amdgcn_mfma_f64_16x16x4f64(aop[q + 1], b1, a1, 0, 0, 0);
+                a2 = __builtin_amdgcn_mfma_f64_16x16x4f64(aop[q + 2], b2, a2, 0, 0, 0);
+                a3 = __builtin_amdgcn_mfma_f64_16x16x4f64(aop[q + 3], b3, a3, 0, 0, 0);
             }
+            acc = acc + a1 + a2 + a3;
         }
+        // gfx950 f64 16x16 accumulator layout (measured): D[i][j] sits in lane j + 16 (i % 4),
+        // register i / 4, i.e. i = lane / 16 + 4 r, j = lane % 16
 #pragma unroll
-        for (int i = 0; i < kChunk; ++i) {
-            red[2 * i][tid] = pr[i];
-            red[2 * i + 1][tid] = pi[i];
-        }
+        for (int r = 0; r < 4; ++r) dsum[wave][((lane >> 4) + 4 * r) * 16 + (lane & 15)] = acc[r];
         __syncthreads();
-        for (int v = wave; v < 2 * kChunk; v += nwaves) {
-            double acc = 0.0;
-            for (int q = lane; q < T; q += 64) acc += red[v][q];
-#pragma unroll
-            for (int off = 32; off >= 1; off >>= 1) acc += __shfl_xor(acc, off, 64);
-            const int l = l0 + v / 2;
-            if (lane == 0 && l <= lmax) {
-                double* dst = reinterpret_cast<double*>(alm + moff + l);
-                dst[v & 1] = (m == 0 && (v & 1)) ? 0.0 : acc;
+        // combine: c_l = D[N] + (-1)^(l+m) D[S], summed over the block's waves
+        for (int t = threadIdx.x; t < 128; t += blockDim.x) {
+            const int jj = t & 15;
+            const int comp = (t >> 4) & 1;
+            const int b = t >> 5;
+            const int l = l0 + jj;
+            if (l > lmax || b >= nmb) continue;
+            double n = 0.0, so = 0.0;
+            for (int w = 0; w < nwaves; ++w) {
+                n += dsum[w][(4 * b + comp) * 16 + jj];
+                so += dsum[w][(4 * b + 2 + comp) * 16 + jj];
             }
+            const double v = ((l - m) & 1) ? n - so : n + so;
+            part[(((int64_t)(grp * npc + pc) * 4 + b) * nalm + moff + l) * 2 + comp] = v;
         }
         __syncthreads();
     }
+}
+
+// alm[b][idx] = sum over pair-chunks of the partial sums, in chunk order
+__global__ void k_adj_finalize(const double* __restrict__ part, int npc, int nmaps, int64_t nalm,
+                               int lmax, int mmax, double2* __restrict__ alm)
+{
+    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int b = blockIdx.y;
+    if (idx >= nalm) return;
+    const int grp = b >> 2, bb = b & 3;
+    double re = 0.0, im = 0.0;
+    for (int pc = 0; pc < npc; ++pc) {
+        const double* src = part + (((int64_t)(grp * npc + pc) * 4 + bb) * nalm + idx) * 2;
+        re += src[0];
+        im += src[1];
+    }
+    // m = 0 occupies idx 0..lmax: c_l0 is real
+    if (idx <= lmax) im = 0.0;
+    alm[(int64_t)b * nalm + idx] = make_double2(re, im);
 }
 
 }  // namespace
@@ -351,8 +469,12 @@ int launch_legendre_synth(const nusht_plan_s* p, const double* alm, void* out, i
 {
     const nusht_geometry& g = p->g;
     const int npairs = (g.nrings + 1) / 2;
-    const int threads = npairs >= 256 ? 256 : ((npairs + 63) / 64) * 64;
-    const int bx = (npairs + threads - 1) / threads;
+    // two ring pairs per lane once there are enough pairs to fill the waves
+    const int R = npairs >= 1024 ? 2 : 1;
+    const int waves_needed = (npairs + 64 * R - 1) / (64 * R);
+    const int wpb = waves_needed >= 4 ? 4 : waves_needed;
+    const int threads = 64 * wpb;
+    const int bx = (waves_needed + wpb - 1) / wpb;
     const int64_t nalm = g.nalm;
     const double2* a = reinterpret_cast<const double2*>(alm);
     int64_t map_stride, row_stride;
@@ -370,24 +492,28 @@ int launch_legendre_synth(const nusht_plan_s* p, const double* alm, void* out, i
         const int groups = left / mb;
         dim3 grid(bx, g.mmax + 1, groups);
         const double2* ab = a + (int64_t)b * nalm;
-#define SYN(MBV, F, OT)                                                                          \
-    hipLaunchKernelGGL((k_legendre_synth<MBV, F, OT>), grid, dim3(threads), 0, s, ab, nalm,       \
-                       g.lmax, p->rec, p->cm_mant, p->cm_exp, g.nrings, g.ntorus,                \
+#define SYN(MBV, RV, F, OT)                                                                      \
+    hipLaunchKernelGGL((k_legendre_synth<MBV, RV, F, OT>), grid, dim3(threads), 0, s, ab, nalm,   \
+                       g.lmax, p->rec, p->cm_mant, p->cm_exp, p->jlive, g.nrings, g.ntorus,      \
                        reinterpret_cast<OT*>(out) + (int64_t)b * map_stride, map_stride,          \
                        row_stride)
+#define SYNR(MBV, F, OT)          \
+    if (R == 2) SYN(MBV, 2, F, OT); \
+    else SYN(MBV, 1, F, OT);
         if (fused && out_f32) {
-            if (mb == 4) SYN(4, true, float2);
-            else if (mb == 2) SYN(2, true, float2);
-            else SYN(1, true, float2);
+            if (mb == 4) { SYNR(4, true, float2) }
+            else if (mb == 2) { SYNR(2, true, float2) }
+            else { SYNR(1, true, float2) }
         } else if (fused) {
-            if (mb == 4) SYN(4, true, double2);
-            else if (mb == 2) SYN(2, true, double2);
-            else SYN(1, true, double2);
+            if (mb == 4) { SYNR(4, true, double2) }
+            else if (mb == 2) { SYNR(2, true, double2) }
+            else { SYNR(1, true, double2) }
         } else {
-            if (mb == 4) SYN(4, false, double2);
-            else if (mb == 2) SYN(2, false, double2);
-            else SYN(1, false, double2);
+            if (mb == 4) { SYNR(4, false, double2) }
+            else if (mb == 2) { SYNR(2, false, double2) }
+            else { SYNR(1, false, double2) }
         }
+#undef SYNR
 #undef SYN
         NUSHT_HIP(hipGetLastError());
         b += groups * mb;
@@ -395,19 +521,29 @@ int launch_legendre_synth(const nusht_plan_s* p, const double* alm, void* out, i
     return NUSHT_OK;
 }
 
+size_t legendre_adjoint_scratch(const nusht_plan_s* p, int nmaps)
+{
+    const int npairs = (p->g.nrings + 1) / 2;
+    const size_t npc = (npairs + kAdjWaves * 64 - 1) / (kAdjWaves * 64);
+    const size_t groups = (nmaps + 3) / 4;
+    return groups * npc * 4 * (size_t)p->g.nalm * 2 * sizeof(double);
+}
+
 int launch_legendre_adjoint(const nusht_plan_s* p, const void* in, double* alm, int nmaps,
-                            int fused, int in_f32, hipStream_t s)
+                            int fused, int in_f32, void* scratch, size_t scratch_bytes,
+                            hipStream_t s)
 {
     const nusht_geometry& g = p->g;
     const int npairs = (g.nrings + 1) / 2;
-    int R = 1;
-    while (R < 16 && R * kAdjMaxThreads < npairs) R *= 2;
-    if (R * kAdjMaxThreads < npairs) {
-        set_last_error("legendre_adjoint", "too many rings for one block");
+    const int npc = (npairs + kAdjWaves * 64 - 1) / (kAdjWaves * 64);
+    int ppb = (npairs + npc - 1) / npc;
+    ppb = ((ppb + 63) / 64) * 64;
+    const int threads = ppb < 128 ? 128 : ppb;
+    const int groups = (nmaps + 3) / 4;
+    if (legendre_adjoint_scratch(p, nmaps) > scratch_bytes) {
+        set_last_error("legendre_adjoint", "partial-sum scratch too small");
         return NUSHT_EINVAL;
     }
-    int threads = (npairs + R - 1) / R;
-    threads = ((threads + 63) / 64) * 64;
     int64_t map_stride, row_stride;
     if (fused) {
         row_stride = g.ntorus;
@@ -416,29 +552,25 @@ int launch_legendre_adjoint(const nusht_plan_s* p, const void* in, double* alm, 
         row_stride = g.nphi / 2 + 1;
         map_stride = (int64_t)g.nrings * row_stride;
     }
-    dim3 grid(g.mmax + 1, nmaps);
-    double2* out = reinterpret_cast<double2*>(alm);
-#define ADJ(RV, F, IT)                                                                          \
-    hipLaunchKernelGGL((k_legendre_adj<RV, F, IT>), grid, dim3(threads), 0, s,                   \
-                       reinterpret_cast<const IT*>(in), map_stride, row_stride, out, g.nalm,      \
-                       g.lmax, p->rec, p->cm_mant, p->cm_exp, g.nrings, g.ntorus)
-#define ADJR(F, IT)                 \
-    switch (R) {                    \
-        case 1: ADJ(1, F, IT); break; \
-        case 2: ADJ(2, F, IT); break; \
-        case 4: ADJ(4, F, IT); break; \
-        case 8: ADJ(8, F, IT); break; \
-        default: ADJ(16, F, IT); break; \
-    }
+    double* part = reinterpret_cast<double*>(scratch);
+    dim3 grid(g.mmax + 1, npc, groups);
+#define ADJ(F, IT)                                                                              \
+    hipLaunchKernelGGL((k_legendre_adj<F, IT>), grid, dim3(threads), 0, s,                       \
+                       reinterpret_cast<const IT*>(in), map_stride, row_stride, nmaps, part, npc, \
+                       g.nalm, g.lmax, p->rec, p->cm_mant, p->cm_exp, p->jlive, g.nrings,        \
+                       g.ntorus, ppb)
     if (fused && in_f32) {
-        ADJR(true, float2);
+        ADJ(true, float2);
     } else if (fused) {
-        ADJR(true, double2);
+        ADJ(true, double2);
     } else {
-        ADJR(false, double2);
+        ADJ(false, double2);
     }
-#undef ADJR
 #undef ADJ
+    NUSHT_HIP(hipGetLastError());
+    dim3 fgrid((unsigned)((g.nalm + 255) / 256), nmaps);
+    hipLaunchKernelGGL(k_adj_finalize, fgrid, dim3(256), 0, s, part, npc, nmaps, g.nalm, g.lmax,
+                       g.mmax, reinterpret_cast<double2*>(alm));
     NUSHT_HIP(hipGetLastError());
     return NUSHT_OK;
 }

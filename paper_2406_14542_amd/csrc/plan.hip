@@ -6,7 +6,9 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <algorithm>
 #include <mutex>
+#include <thread>
 
 #include "internal.h"
 #include "nufft_impl.h"
@@ -266,6 +268,9 @@ int ensure_capacity(nusht_plan_s* p, int nmaps)
     const size_t gfused = (size_t)(g.mmax + 1) * g.ntorus * 2 * 8;  // doubled columns, <= c128
     size_t per = fine_real;
     for (size_t v : {fine_spec, gpaper, ring, torus, tspec, gfused}) per = v > per ? v : per;
+    // the Legendre adjoint keeps its partial sums in whichever region does not hold its input
+    const size_t part = legendre_adjoint_scratch(p, nmaps);
+    if (per * nmaps < part) per = (part + nmaps - 1) / nmaps;
     const int groups = point_groups(nmaps);
     const int P = kTile + g.width - 1;
     const size_t zbytes = (size_t)groups * p->nslots * P * P * 4 * e;
@@ -352,6 +357,47 @@ int bin_points(nusht_plan_s* p, const double* theta, const double* phi, hipStrea
     return rc;
 }
 
+// Smallest ring index j (0 <= j < ceil(N_r/2)) whose pair (j, N_r-1-j) carries any lam_lm,
+// l <= lmax, above 2^-300: rings closer to the poles stay in the evanescent region of every
+// l <= lmax for this m and contribute nothing (the kernels accumulate only above 2^-200).
+// lam grows with sin(theta) there, so the predicate is monotone in j and bisection applies.
+static bool ring_reaches(int lmax, int m, int j, int nr, const std::vector<double>& rec,
+                         int64_t moff, double cm, int ce)
+{
+    const double th = M_PI * (double)j / (double)(nr - 1);
+    const double s = std::sin(th);
+    if (m > 0 && s == 0.0) return false;
+    const double h = std::sin(0.5 * th);
+    const double y = (2 * j == nr - 1) ? 1.0 : 2.0 * h * h;
+    // log2 |lam_mm| = log2|c_m| + m log2(s), tracked as mantissa * 2^e
+    int e = ce;
+    double v = std::fabs(cm);
+    double ls = m > 0 ? m * std::log2(s) : 0.0;
+    const int le = (int)std::floor(ls);
+    v *= std::exp2(ls - le);
+    e += le;
+    if (e > -300) return true;
+    double vp = 0.0, vc = v;
+    for (int l = m + 1; l <= lmax; ++l) {
+        const double a = rec[2 * (moff + l)], b = rec[2 * (moff + l) + 1];
+        const double vn = a * (vc - y * vc) - b * vp;
+        vp = vc;
+        vc = vn;
+        const double big = std::fabs(vc) > std::fabs(vp) ? std::fabs(vc) : std::fabs(vp);
+        if (big > 0x1p200 || (big < 0x1p-200 && big > 0.0)) {
+            int k;
+            std::frexp(big, &k);
+            vc = std::ldexp(vc, -k);
+            vp = std::ldexp(vp, -k);
+            e += k;
+        }
+        int k2;
+        std::frexp(vc, &k2);
+        if (vc != 0.0 && e + k2 > -300) return true;
+    }
+    return false;
+}
+
 static int build_tables(nusht_plan_s* p)
 {
     const nusht_geometry& g = p->g;
@@ -394,6 +440,29 @@ static int build_tables(nusht_plan_s* p)
             ce[m] = e2 / 2 + t;
         }
     }
+    // first live ring pair of every m
+    std::vector<int> jl(M + 1, 0);
+    {
+        const int npairs = (g.nrings + 1) / 2;
+        const unsigned nth = std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
+        std::vector<std::thread> pool;
+        for (unsigned t = 0; t < nth; ++t)
+            pool.emplace_back([&, t] {
+                for (int m = (int)t; m <= M; m += (int)nth) {
+                    const int64_t moff = (int64_t)m * (2 * L + 1 - m) / 2;
+                    int lo = 0, hi = npairs;  // first live index in [lo, hi]
+                    while (lo < hi) {
+                        const int mid = (lo + hi) / 2;
+                        if (ring_reaches(L, m, mid, g.nrings, rec, moff, cm[m], ce[m]))
+                            hi = mid;
+                        else
+                            lo = mid + 1;
+                    }
+                    jl[m] = lo;
+                }
+            });
+        for (auto& th : pool) th.join();
+    }
     // deconvolution: h / psi^(k) = 2 / (w I(k)), with the 1/N_t of the theta transform
     std::vector<double> i1, i2;
     es_fourier(g.beta, g.width * M_PI / g.n1, L, i1);
@@ -415,6 +484,9 @@ static int build_tables(nusht_plan_s* p)
     NUSHT_TRY(dmalloc(&p->dec2, M + 1));
     NUSHT_TRY(dmalloc(&p->dec1f, L + 1));
     NUSHT_TRY(dmalloc(&p->dec2f, M + 1));
+    NUSHT_TRY(dmalloc(&p->jlive, M + 1));
+    NUSHT_HIP(hipMemcpy(p->jlive, jl.data(), jl.size() * sizeof(int), hipMemcpyHostToDevice));
+    p->jlive_host = jl;
     NUSHT_HIP(hipMemcpy(p->rec, rec.data(), rec.size() * sizeof(double), hipMemcpyHostToDevice));
     NUSHT_HIP(hipMemcpy(p->cm_mant, cm.data(), cm.size() * sizeof(double), hipMemcpyHostToDevice));
     NUSHT_HIP(hipMemcpy(p->cm_exp, ce.data(), ce.size() * sizeof(int), hipMemcpyHostToDevice));
@@ -472,7 +544,7 @@ void nusht_destroy(nusht_plan_t p)
     void* bufs[] = {p->rec,  p->cm_mant, p->cm_exp,   p->dec1,      p->dec2,      p->dec1f,
                     p->dec2f, p->sth,    p->sph,      p->perm,      p->slot_off,  p->slot_tile,
                     p->tile_slot, p->dflag, p->X,     p->Y,         p->Z,         p->fftwork,
-                    p->red};
+                    p->red,      p->jlive};
     for (void* b : bufs)
         if (b) hipFree(b);
     for (int i = 0; i < ST_COUNT; ++i) {
