@@ -64,7 +64,8 @@ enum { NUSHT_DFS_FUSED = 0, NUSHT_DFS_PAPER = 1 };
 typedef struct {
     double sigma;        /* fine-grid upsampling factor; 0 -> 2.0 */
     int width;           /* ES kernel width w in grid cells; 0 -> from eps and sigma */
-    double beta_per_w;   /* ES shape beta = beta_per_w * w; 0 -> 0.97 pi (1 - 1/(2 sigma)) */
+    double beta_per_w;   /* ES shape beta = beta_per_w * w; 0 -> 2.30 at sigma = 2, else
+                            0.97 pi (1 - 1/(2 sigma)) */
     int dfs_mode;        /* NUSHT_DFS_FUSED (default) or NUSHT_DFS_PAPER */
     int timing;          /* nonzero: record one hipEvent pair per stage (nusht_stage_times) */
     int reserved[6];     /* must be zero */
@@ -126,6 +127,16 @@ int nusht_adjoint(nusht_plan_t plan, const double* map, double* alm, int nmaps, 
 int nusht_synthesis_deriv(nusht_plan_t plan, const double* alm, double* map, double* dtheta,
                           double* dphi, int nmaps, void* stream);
 
+/* Gradients of a loss L(map) through the synthesis, given g = dL/dmap [nmaps][npts]:
+   nusht_vjp_alm writes dL/dRe a + i dL/dIm a [nmaps][nalm], i.e. the adjoint Y^H g (Eq. 2)
+   scaled by 2 for m > 0 (a_{l,-m} = (-1)^m conj(a_lm) carries the other half) and real for
+   m = 0.  nusht_vjp_points writes grad_theta[i] = sum_b g[b][i] dtheta[b][i] and likewise
+   for phi (dtheta, dphi from nusht_synthesis_deriv); either output may be NULL, not both. */
+int nusht_vjp_alm(nusht_plan_t plan, const double* grad_map, double* grad_alm, int nmaps,
+                  void* stream);
+int nusht_vjp_points(const double* grad_map, const double* dtheta, const double* dphi,
+                     double* grad_theta, double* grad_phi, int nmaps, int64_t npts, void* stream);
+
 /* Iso-latitude parts on their own (the S operator of Eq. 5 and its adjoint) on the plan's
    CC grid: ring[b][j][k] = map at (theta_j = j pi/(N_r-1), phi_k = 2 pi k / N_phi).
    ring: [nmaps][N_r][N_phi] float64.  The adjoint returns sum_jk ring[b][j][k] Y*_lm. */
@@ -134,7 +145,7 @@ int nusht_ring_synthesis(nusht_plan_t plan, const double* alm, double* ring, int
 int nusht_ring_adjoint(nusht_plan_t plan, const double* ring, double* alm, int nmaps,
                        void* stream);
 
-/* Least-squares inverse (spec CG solve; Sec. I: iterative algorithms call the
+/* Least-squares inverse (Sec. I: iterative inverse algorithms call the
    transforms repeatedly).  CGLS on min || W^(1/2) (S a - d) ||_2 in the <.,.>_m geometry:
    each iteration runs one synthesis and one adjoint plus FP64 device reductions.
    map: d [npts] (one map); alm: in = initial iterate x0 [nalm], out = solution;
@@ -144,6 +155,66 @@ int nusht_ring_adjoint(nusht_plan_t plan, const double* ring, double* alm, int n
    Returns NUSHT_ENOCONV after maxiter iterations without convergence.  Synchronises. */
 int nusht_solve(nusht_plan_t plan, const double* map, double* alm, const float* weights,
                 double tol, int maxiter, int* iters, double* relres, void* stream);
+
+/* ---------------------------------------------------------------------------------------
+ * Learned quadrature weights for the weighted least-squares inverse.
+ *
+ * The paper has no such component; it uses the transforms as the inner loop of an
+ * iterative inverse (Sec. I), and these calls build a preconditioner for nusht_solve: a
+ * small network maps density features of each point to a positive weight w_i, trained so
+ * that S^H W d approximates the least-squares solution.  All arrays are device pointers;
+ * FP32 unless stated.  Calls only enqueue work (except nusht_weight_loss_grad).
+ * ------------------------------------------------------------------------------------- */
+
+/* Number of FP32 parameters of the 12 -> 128 -> 128 -> 128 -> 1 network (tanh hidden
+   layers, softplus output).  Layout: for each layer its transposed weight [in][out]
+   row-major, then its bias [out]. */
+int64_t nusht_mlp_param_count(void);
+
+/* density[ntheta][nphi] = (count of points in equal-angle cell) / (npts * cell area / 4 pi),
+   cell (a, b) holding theta in [pi a / ntheta, pi (a+1) / ntheta) and phi mod 2 pi in
+   [2 pi b / nphi, 2 pi (b+1) / nphi), indices clamped.  Uniform points give ~1.
+   theta, phi: FP64 [npts].  ntheta * nphi <= 2^24.  Allocates a stream-ordered count
+   buffer. */
+int nusht_density_map(const double* theta, const double* phi, int64_t npts, int ntheta,
+                      int nphi, float* density, void* stream);
+
+/* features[npts][12]: log density bilinearly interpolated between cell centres at the
+   point; log density of the 3 x 3 cells around the point's cell (theta clamped, phi
+   periodic, row-major); cos theta; sin theta.  log density is floored at log 1e-3. */
+int nusht_point_features(const double* theta, const double* phi, int64_t npts,
+                         const float* density, int ntheta, int nphi, float* features,
+                         void* stream);
+
+/* weights[i] = softplus(net(features[i])) * scale. */
+int nusht_mlp_forward(const float* params, const float* features, int64_t npts, float scale,
+                      float* weights, void* stream);
+
+/* grad_params = d/dparams sum_i grad_weights[i] * weights[i], deterministic for a given npts
+   (fixed per-block partial sums reduced in block order).  Allocates a stream-ordered
+   partial buffer of at most 512 * nusht_mlp_param_count() floats. */
+int nusht_mlp_backward(const float* params, const float* features, const float* grad_weights,
+                       int64_t npts, float scale, float* grad_params, void* stream);
+
+/* One Adam update of params[n] in place with first/second moments m, v (start at 0) and
+   step >= 1 (bias corrections 1 - beta^step). */
+int nusht_adam_step(float* params, const float* grad, float* m, float* v, int64_t n, float lr,
+                    float beta1, float beta2, float eps, int step, void* stream);
+
+/* alm = S^H (W d): the adjoint (Eq. 2) of the weighted map, i.e. the quadrature estimate of
+   the coefficients and the initial iterate of a weighted nusht_solve.  d: FP64 [npts];
+   weights: FP32 [npts]; alm: complex128 [nalm].  Allocates a stream-ordered [npts] buffer. */
+int nusht_weighted_adjoint(nusht_plan_t plan, const double* d, const float* weights,
+                           double* alm, void* stream);
+
+/* Training loss of the weights for one point set: with r = S^H (W d) - astar (Eq. 2 applied
+   to the weighted map), *loss = <r, r>_m / <astar, astar>_m (host double), and, if
+   grad_weights != NULL, grad_weights[i] = 2 d_i (S r)_i / <astar, astar>_m (one synthesis).
+   d: FP64 [npts] in the plan's point order; astar: complex128 [nalm]; weights: FP32 [npts].
+   Synchronises (reads the loss). */
+int nusht_weight_loss_grad(nusht_plan_t plan, const double* d, const double* astar,
+                           const float* weights, float* grad_weights, double* loss,
+                           void* stream);
 
 /* Per-stage device times (ms) of the last execution call when the plan was built with
    opts.timing != 0.  Synchronises on the plan's last event.  Writes up to maxn values to

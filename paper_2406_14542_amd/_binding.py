@@ -80,11 +80,28 @@ def lib():
             "nusht_adjoint": (ctypes.c_int, [_vp, _vp, _vp, ctypes.c_int, _vp]),
             "nusht_synthesis_deriv": (ctypes.c_int, [_vp, _vp, _vp, _vp, _vp, ctypes.c_int,
                                                      _vp]),
+            "nusht_vjp_alm": (ctypes.c_int, [_vp, _vp, _vp, ctypes.c_int, _vp]),
+            "nusht_vjp_points": (ctypes.c_int, [_vp, _vp, _vp, _vp, _vp, ctypes.c_int, _i64,
+                                                _vp]),
             "nusht_ring_synthesis": (ctypes.c_int, [_vp, _vp, _vp, ctypes.c_int, _vp]),
             "nusht_ring_adjoint": (ctypes.c_int, [_vp, _vp, _vp, ctypes.c_int, _vp]),
             "nusht_solve": (ctypes.c_int, [_vp, _vp, _vp, _vp, ctypes.c_double, ctypes.c_int,
                                            ctypes.POINTER(ctypes.c_int),
                                            ctypes.POINTER(ctypes.c_double), _vp]),
+            "nusht_mlp_param_count": (_i64, []),
+            "nusht_density_map": (ctypes.c_int, [_vp, _vp, _i64, ctypes.c_int, ctypes.c_int,
+                                                 _vp, _vp]),
+            "nusht_point_features": (ctypes.c_int, [_vp, _vp, _i64, _vp, ctypes.c_int,
+                                                    ctypes.c_int, _vp, _vp]),
+            "nusht_mlp_forward": (ctypes.c_int, [_vp, _vp, _i64, ctypes.c_float, _vp, _vp]),
+            "nusht_mlp_backward": (ctypes.c_int, [_vp, _vp, _vp, _i64, ctypes.c_float, _vp,
+                                                  _vp]),
+            "nusht_adam_step": (ctypes.c_int, [_vp, _vp, _vp, _vp, _i64, ctypes.c_float,
+                                               ctypes.c_float, ctypes.c_float, ctypes.c_float,
+                                               ctypes.c_int, _vp]),
+            "nusht_weighted_adjoint": (ctypes.c_int, [_vp, _vp, _vp, _vp, _vp]),
+            "nusht_weight_loss_grad": (ctypes.c_int, [_vp, _vp, _vp, _vp, _vp,
+                                                      ctypes.POINTER(ctypes.c_double), _vp]),
             "nusht_stage_times": (ctypes.c_int, [_vp, ctypes.POINTER(ctypes.c_double),
                                                  ctypes.POINTER(ctypes.c_char_p), ctypes.c_int]),
             "nusht_destroy": (None, [_vp]),
@@ -212,6 +229,30 @@ class Plan:
                                            dp.data_ptr(), B, _stream()), "nusht_synthesis_deriv")
         return f, dt, dp
 
+    def vjp_alm(self, grad_map):
+        """dL/dRe a + i dL/dIm a for g = dL/dmap (nusht_vjp_alm)."""
+        import torch
+        g = self._map_in(grad_map)
+        B = g.shape[0]
+        out = torch.empty((B, self.nalm), dtype=torch.complex128, device=g.device)
+        _check(lib().nusht_vjp_alm(self._h, g.data_ptr(), out.data_ptr(), B, _stream()),
+               "nusht_vjp_alm")
+        return out
+
+    def vjp_points(self, grad_map, dtheta, dphi, want_theta=True, want_phi=True):
+        """(sum_b g dmap/dtheta, sum_b g dmap/dphi) per point (nusht_vjp_points)."""
+        import torch
+        g = self._map_in(grad_map)
+        B = g.shape[0]
+        gt = torch.empty(self.npts, dtype=torch.float64, device=g.device) if want_theta else None
+        gp = torch.empty(self.npts, dtype=torch.float64, device=g.device) if want_phi else None
+        _check(lib().nusht_vjp_points(g.data_ptr(), dtheta.contiguous().data_ptr(),
+                                      dphi.contiguous().data_ptr(),
+                                      gt.data_ptr() if gt is not None else None,
+                                      gp.data_ptr() if gp is not None else None, B, self.npts,
+                                      _stream()), "nusht_vjp_points")
+        return gt, gp
+
     def ring_synthesis(self, alm):
         import torch
         a = self._alm_in(alm)
@@ -256,6 +297,35 @@ class Plan:
             _check(st, "nusht_solve")
         return alm, it.value, rr.value, st
 
+    def weighted_adjoint(self, d, weights):
+        """S^H (W d) for one map (nusht_weighted_adjoint): complex128 [1, nalm]."""
+        import torch
+        x = self._map_in(d)
+        if x.shape[0] != 1:
+            raise ValueError("weighted_adjoint takes one map")
+        w = _f32_dev(weights, self.npts, "weights")
+        out = torch.empty((1, self.nalm), dtype=torch.complex128, device=x.device)
+        _check(lib().nusht_weighted_adjoint(self._h, x.data_ptr(), w.data_ptr(), out.data_ptr(),
+                                            _stream()), "nusht_weighted_adjoint")
+        return out
+
+    def weight_loss_grad(self, d, astar, weights, want_grad=True):
+        """Loss <r, r>_m / <a*, a*>_m with r = S^H (W d) - a*, and d loss / d w (float32 [npts])
+        when want_grad (nusht_weight_loss_grad).  Returns (loss, grad or None)."""
+        import torch
+        x = self._map_in(d)
+        a = self._alm_in(astar)
+        if x.shape[0] != 1 or a.shape[0] != 1:
+            raise ValueError("weight_loss_grad takes one map and one coefficient set")
+        w = _f32_dev(weights, self.npts, "weights")
+        g = torch.empty(self.npts, dtype=torch.float32, device=x.device) if want_grad else None
+        loss = ctypes.c_double(0.0)
+        _check(lib().nusht_weight_loss_grad(self._h, x.data_ptr(), a.data_ptr(), w.data_ptr(),
+                                            None if g is None else g.data_ptr(),
+                                            ctypes.byref(loss), _stream()),
+               "nusht_weight_loss_grad")
+        return loss.value, g
+
     def stage_times(self) -> dict:
         ms = (ctypes.c_double * 16)()
         names = (ctypes.c_char_p * 16)()
@@ -278,3 +348,88 @@ class Plan:
             self.close()
         except Exception:
             pass
+
+
+# ---- learned-weight kernels (FP32 network; see include/nusht.h) ----
+
+def _f32_dev(x, n, what):
+    import torch
+    if x.dtype != torch.float32 or not x.is_cuda or x.numel() != n:
+        raise ValueError(f"{what} must be a float32 device tensor with {n} elements")
+    return x.contiguous()
+
+
+def _f64_pts(theta, phi):
+    import torch
+    if theta.dtype != torch.float64 or phi.dtype != torch.float64 or not theta.is_cuda \
+            or theta.shape != phi.shape or theta.dim() != 1:
+        raise ValueError("theta and phi must be 1-D float64 device tensors of equal length")
+    return theta.contiguous(), phi.contiguous()
+
+
+def mlp_param_count() -> int:
+    return int(lib().nusht_mlp_param_count())
+
+
+def density_map(theta, phi, ntheta, nphi):
+    import torch
+    theta, phi = _f64_pts(theta, phi)
+    out = torch.empty((ntheta, nphi), dtype=torch.float32, device=theta.device)
+    _check(lib().nusht_density_map(theta.data_ptr(), phi.data_ptr(), theta.numel(), ntheta,
+                                   nphi, out.data_ptr(), _stream()), "nusht_density_map")
+    return out
+
+
+def point_features(theta, phi, density):
+    import torch
+    theta, phi = _f64_pts(theta, phi)
+    if density.dtype != torch.float32 or density.dim() != 2 or not density.is_cuda:
+        raise ValueError("density must be a float32 [ntheta, nphi] device tensor")
+    density = density.contiguous()
+    out = torch.empty((theta.numel(), 12), dtype=torch.float32, device=theta.device)
+    _check(lib().nusht_point_features(theta.data_ptr(), phi.data_ptr(), theta.numel(),
+                                      density.data_ptr(), density.shape[0], density.shape[1],
+                                      out.data_ptr(), _stream()), "nusht_point_features")
+    return out
+
+
+def _feat_in(features):
+    import torch
+    if features.dtype != torch.float32 or features.dim() != 2 or features.shape[1] != 12 \
+            or not features.is_cuda:
+        raise ValueError("features must be a float32 [npts, 12] device tensor")
+    return features.contiguous()
+
+
+def mlp_forward(params, features, scale):
+    import torch
+    f = _feat_in(features)
+    p = _f32_dev(params, mlp_param_count(), "params")
+    out = torch.empty(f.shape[0], dtype=torch.float32, device=f.device)
+    _check(lib().nusht_mlp_forward(p.data_ptr(), f.data_ptr(), f.shape[0], float(scale),
+                                   out.data_ptr(), _stream()), "nusht_mlp_forward")
+    return out
+
+
+def mlp_backward(params, features, grad_weights, scale):
+    import torch
+    f = _feat_in(features)
+    p = _f32_dev(params, mlp_param_count(), "params")
+    g = _f32_dev(grad_weights, f.shape[0], "grad_weights")
+    out = torch.empty_like(p)
+    _check(lib().nusht_mlp_backward(p.data_ptr(), f.data_ptr(), g.data_ptr(), f.shape[0],
+                                    float(scale), out.data_ptr(), _stream()),
+           "nusht_mlp_backward")
+    return out
+
+
+def adam_step(params, grad, m, v, step, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8):
+    """In-place Adam update of params (and its moments m, v)."""
+    n = params.numel()
+    for t, what in ((params, "params"), (grad, "grad"), (m, "m"), (v, "v")):
+        if not t.is_contiguous():
+            raise ValueError(f"{what} must be contiguous")
+        _f32_dev(t, n, what)
+    _check(lib().nusht_adam_step(params.data_ptr(), grad.data_ptr(), m.data_ptr(), v.data_ptr(),
+                                 n, float(lr), float(beta1), float(beta2), float(eps), int(step),
+                                 _stream()), "nusht_adam_step")

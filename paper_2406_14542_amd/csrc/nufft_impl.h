@@ -9,9 +9,11 @@
 // (kTile + w - 1)^2 cells, which it stages in LDS.
 //  * interpolation: window loaded once from HBM, every point of the tile reads its w x w taps
 //    from LDS, result written straight to the caller's point order;
-//  * spreading: points add their w x w contributions into the LDS window (LDS float atomics),
-//    the window is written once to a per-slot subgrid; a second pass sums, for every fine
-//    cell, the subgrids of the (at most four) windows that cover it.  No global atomics.
+//  * spreading: FP32 output-stationary (threads own cells of the tile window and gather the
+//    contributions of the row-sorted points, taps staged in LDS), FP64 LDS atomics laid
+//    out for the banks; the window is
+//    written once to a per-slot subgrid; a second pass sums, for every fine cell, the
+//    subgrids of the (at most four) windows that cover it.  No atomics of any kind.
 // Offsets are formed in FP64 from FP64 coordinates before any cast to the kernel's type T.
 #pragma once
 
@@ -64,7 +66,14 @@ __device__ inline void es_taps(double d, T beta, T (&psi)[W])
 }
 
 // taps and their derivatives with respect to t (grid units):
-// d psi / dt = psi(z) * beta * (-z / sqrt(1 - z^2)) * 2 / w, set to 0 on the support edge
+// d psi / dt = psi(z) * beta * (-z / sqrt(1 - z^2)) * 2 / w.
+// The derivative is singular at the support edge |z| -> 1, where psi itself is only
+// e^-beta: a tap within 1 - z^2 < 1e-6 of the edge would add a spike of up to
+// e^-beta beta / sqrt(1 - z^2) (and whether 1 - z^2 rounds to 0 or to 1e-16 for a point
+// exactly on a grid line depends on FMA contraction).  Such taps get no derivative; what
+// is dropped is below e^-beta * beta * 1e3 * 2/w times the grid value (5e-11 at w = 14).
+constexpr double kDerivEdgeQ = 1e-6;
+
 template <int W>
 __device__ inline void es_taps_d(double d, double beta, double (&psi)[W], double (&dpsi)[W])
 {
@@ -77,7 +86,7 @@ __device__ inline void es_taps_d(double d, double beta, double (&psi)[W], double
             const double sq = sqrt(q);
             const double v = exp(beta * (sq - 1.0));
             psi[a] = v;
-            dpsi[a] = -v * beta * z / sq * c;
+            dpsi[a] = q > kDerivEdgeQ ? -v * beta * z / sq * c : 0.0;
         } else {
             psi[a] = 0.0;
             dpsi[a] = 0.0;
@@ -213,50 +222,186 @@ __global__ __launch_bounds__(256) void k_interp_deriv(const double* __restrict__
     }
 }
 
+// Spreading, output-stationary (used for FP32).  Points of a slot arrive sorted by their
+// row inside the tile.  Per batch of NB points the block stores, in LDS, each point's row
+// and column in the tile, its values f[b], its row taps psi1[0..W) and its column taps psi2
+// padded with 8 zeros on both sides.  Thread (R, ch) owns window row R and columns
+// 8 ch .. 8 ch + 7 of the tile window in registers and adds, for every point whose rows
+// R - W + 1 .. R touch it, f psi1[R - r] psi2[C - c] to its 8 cells.  No atomics; every
+// cell sums its points in the same (sorted) order on every run.
 template <typename T, int W, int MB>
-__global__ __launch_bounds__(256) void k_spread(const double* __restrict__ in, int64_t npts,
-                                                PointBins pb, T beta, T* __restrict__ sub)
+struct SpreadShape {
+    static constexpr int P = kTile + W - 1;
+    static constexpr int CW = 8;
+    static constexpr int NCH = (P + CW - 1) / CW;
+    static constexpr int NT = ((P * NCH + 63) / 64) * 64;
+    static constexpr int PADW = W + 2 * CW;
+    static constexpr int PER = (W + MB + PADW) * (int)sizeof(T) + 2 * (int)sizeof(int);
+    static constexpr int NB0 = (65536 / PER) / 64 * 64;
+    static constexpr int NB = NB0 < NT ? NB0 : NT;
+    static_assert(NT <= 320 && NB >= 64, "spreading block shape");
+};
+
+template <typename T, int W, int MB>
+__global__ __launch_bounds__(320) void k_spread_rows(
+    const double* __restrict__ in, int64_t npts, PointBins pb, T beta, T* __restrict__ sub)
 {
-    constexpr int P = kTile + W - 1;
-    __shared__ T win[P * P * MB];
+    using S = SpreadShape<T, W, MB>;
+    constexpr int P = S::P, CW = S::CW, NCH = S::NCH, NB = S::NB, PADW = S::PADW;
+    __shared__ T s_p1[NB][W];
+    __shared__ T s_f[NB][MB];
+    __shared__ T s_p2[NB][PADW];
+    __shared__ int s_row[NB], s_col[NB];
+    __shared__ int s_rs[kTile + 1];
+
     const int slot = blockIdx.x;
     const int tile = pb.slot_tile[slot];
     const int r0 = (tile / pb.nt2) * kTile;
     const int c0 = (tile % pb.nt2) * kTile;
-    for (int e = threadIdx.x; e < P * P * MB; e += blockDim.x) win[e] = T(0);
-    __syncthreads();
+    const int t = threadIdx.x;
+    const int R = t / NCH;
+    const int C0 = (t - R * NCH) * CW;
+    const bool owner = R < P;
+    T acc[CW][MB];
+#pragma unroll
+    for (int k = 0; k < CW; ++k)
+#pragma unroll
+        for (int b = 0; b < MB; ++b) acc[k][b] = T(0);
+
     const int p0 = pb.slot_off[slot], p1 = pb.slot_off[slot + 1];
-    for (int p = p0 + threadIdx.x; p < p1; p += blockDim.x) {
+    for (int base = p0; base < p1; base += NB) {
+        const int nb = min(NB, p1 - base);
+        __syncthreads();  // previous batch fully consumed
+        if (t < nb) {
+            const int p = base + t;
+            double d1, d2;
+            const int l1 = first_tap(pb.sth[p], pb.s1, W, d1);
+            const int l2 = first_tap(pb.sph[p], pb.s2, W, d2);
+            int r = wrap_index(l1, pb.n1) - r0;
+            int c = wrap_index(l2, pb.n2) - c0;
+            r = min(max(r, 0), kTile - 1);
+            c = min(max(c, 0), kTile - 1);
+            T a1[W], a2[W];
+            es_taps<T, W>(d1, beta, a1);
+            es_taps<T, W>(d2, beta, a2);
+#pragma unroll
+            for (int a = 0; a < W; ++a) s_p1[t][a] = a1[a];
+#pragma unroll
+            for (int q = 0; q < PADW; ++q) s_p2[t][q] = T(0);
+#pragma unroll
+            for (int q = 0; q < W; ++q) s_p2[t][CW + q] = a2[q];
+            const int64_t src = pb.perm[p];
+#pragma unroll
+            for (int b = 0; b < MB; ++b) s_f[t][b] = (T)in[b * npts + src];
+            s_row[t] = r;
+            s_col[t] = c;
+        }
+        __syncthreads();
+        // first point of each row (points are sorted by row)
+        if (t <= kTile) {
+            int lo = 0, hi = nb;
+            while (lo < hi) {
+                const int mid = (lo + hi) >> 1;
+                if (s_row[mid] < t) lo = mid + 1;
+                else hi = mid;
+            }
+            s_rs[t] = lo;
+        }
+        __syncthreads();
+        if (owner) {
+            const int rlo = max(0, R - W + 1), rhi = min(kTile - 1, R);
+            if (rlo <= rhi) {
+                const int q1 = s_rs[rhi + 1];
+                for (int q = s_rs[rlo]; q < q1; ++q) {
+                    const int c = s_col[q];
+                    const int a = R - s_row[q];
+                    if (c > C0 + CW - 1 || c + W - 1 < C0 || a < 0 || a >= W) continue;
+                    const T pa = s_p1[q][a];
+                    T fa[MB];
+#pragma unroll
+                    for (int b = 0; b < MB; ++b) fa[b] = s_f[q][b] * pa;
+                    const T* p2 = &s_p2[q][CW + C0 - c];
+#pragma unroll
+                    for (int k = 0; k < CW; ++k) {
+                        const T v = p2[k];
+#pragma unroll
+                        for (int b = 0; b < MB; ++b) acc[k][b] += fa[b] * v;
+                    }
+                }
+            }
+        }
+    }
+    if (owner) {
+        T* dst = sub + (int64_t)slot * (P * P * MB) + (R * P) * MB;
+#pragma unroll
+        for (int k = 0; k < CW; ++k) {
+            const int C = C0 + k;
+            if (C < P) {
+#pragma unroll
+                for (int b = 0; b < MB; ++b) dst[C * MB + b] = acc[k][b];
+            }
+        }
+    }
+}
+
+// Spreading with LDS atomics arranged for the LDS banks (used for FP64, where it measured
+// faster than the row-owner kernel): the window is planar (map-major) and a wave works on
+// 4 points at a time, lane = 16 * point + tap column, so the 16 lanes of a point add into
+// 16 consecutive words of one window row.  The order of the additions into a cell is not
+// fixed, so FP64 spreading can differ between runs by rounding (~1e-16 relative).
+template <typename T, int W, int MB>
+__global__ __launch_bounds__(256) void k_spread_atomic(const double* __restrict__ in,
+                                                       int64_t npts, PointBins pb, T beta,
+                                                       T* __restrict__ sub)
+{
+    constexpr int P = kTile + W - 1;
+    __shared__ T win[MB * P * P];
+    const int slot = blockIdx.x;
+    const int tile = pb.slot_tile[slot];
+    const int r0 = (tile / pb.nt2) * kTile;
+    const int c0 = (tile % pb.nt2) * kTile;
+    for (int e = threadIdx.x; e < MB * P * P; e += blockDim.x) win[e] = T(0);
+    __syncthreads();
+    const int lane = threadIdx.x & 63;
+    const int grp = lane >> 4, col = lane & 15;
+    const int gwave = threadIdx.x >> 6, nwaves = blockDim.x >> 6;
+    const int p0 = pb.slot_off[slot], p1 = pb.slot_off[slot + 1];
+    const T cw = T(2) / T(W);
+    for (int pb0 = p0 + 4 * gwave; pb0 < p1; pb0 += 4 * nwaves) {
+        const int p = pb0 + grp;
+        const bool live = p < p1;
+        const int pp = live ? p : p0;
         double d1, d2;
-        const int l1 = first_tap(pb.sth[p], pb.s1, W, d1);
-        const int l2 = first_tap(pb.sph[p], pb.s2, W, d2);
+        const int l1 = first_tap(pb.sth[pp], pb.s1, W, d1);
+        const int l2 = first_tap(pb.sph[pp], pb.s2, W, d2);
         int r = wrap_index(l1, pb.n1) - r0;
         int c = wrap_index(l2, pb.n2) - c0;
         r = min(max(r, 0), kTile - 1);
         c = min(max(c, 0), kTile - 1);
-        T p1v[W], p2v[W];
-        es_taps<T, W>(d1, beta, p1v);
-        es_taps<T, W>(d2, beta, p2v);
-        const int64_t src = pb.perm[p];
+        const bool act = live && col < W;
+        // this lane's column tap and its point's row tap number `col`
+        const T p2 = act ? es_value<T>(((T)d2 - T(col)) * cw, beta) : T(0);
+        const T p1c = col < W ? es_value<T>(((T)d1 - T(col)) * cw, beta) : T(0);
         T f[MB];
+        const int64_t src = pb.perm[pp];
 #pragma unroll
-        for (int b = 0; b < MB; ++b) f[b] = (T)in[b * npts + src];
+        for (int b = 0; b < MB; ++b) f[b] = live ? (T)in[b * npts + src] * p2 : T(0);
+        const int cc = c + (col < W ? col : 0);
 #pragma unroll
         for (int a = 0; a < W; ++a) {
-            T fa[MB];
+            const T pa = __shfl(p1c, (grp << 4) + a, 64);
+            if (act) {
 #pragma unroll
-            for (int b = 0; b < MB; ++b) fa[b] = f[b] * p1v[a];
-            T* wr = win + ((r + a) * P + c) * MB;
-#pragma unroll
-            for (int q = 0; q < W; ++q) {
-#pragma unroll
-                for (int b = 0; b < MB; ++b) atomicAdd(wr + q * MB + b, fa[b] * p2v[q]);
+                for (int b = 0; b < MB; ++b) atomicAdd(&win[(b * P + r + a) * P + cc], f[b] * pa);
             }
         }
     }
     __syncthreads();
     T* dst = sub + (int64_t)slot * (P * P * MB);
-    for (int e = threadIdx.x; e < P * P * MB; e += blockDim.x) dst[e] = win[e];
+    for (int e = threadIdx.x; e < P * P; e += blockDim.x) {
+#pragma unroll
+        for (int b = 0; b < MB; ++b) dst[e * MB + b] = win[b * P * P + e];
+    }
 }
 
 // fine[b][i][j] = sum of the subgrids of the windows covering cell (i, j); zero elsewhere
@@ -365,12 +510,22 @@ int spread_group_impl(const nusht_plan_s* p, const double* in, T* sub, int b, in
     const PointBins pb = make_bins(p);
     const int64_t npts = p->g.npts;
     NUSHT_WIDTH_SWITCH(p->g.width, {
-        if (mb == 4)
-            hipLaunchKernelGGL((k_spread<T, WV, 4>), dim3(p->nslots), dim3(256), 0, s,
-                               in + b * npts, npts, pb, beta, sub);
-        else
-            hipLaunchKernelGGL((k_spread<T, WV, 1>), dim3(p->nslots), dim3(256), 0, s,
-                               in + b * npts, npts, pb, beta, sub);
+        if (sizeof(T) == 8) {
+            if (mb == 4)
+                hipLaunchKernelGGL((k_spread_atomic<T, WV, 4>), dim3(p->nslots), dim3(256), 0, s,
+                                   in + b * npts, npts, pb, beta, sub);
+            else
+                hipLaunchKernelGGL((k_spread_atomic<T, WV, 1>), dim3(p->nslots), dim3(256), 0, s,
+                                   in + b * npts, npts, pb, beta, sub);
+        } else if (mb == 4) {
+            hipLaunchKernelGGL((k_spread_rows<T, WV, 4>), dim3(p->nslots),
+                               dim3(SpreadShape<T, WV, 4>::NT), 0, s, in + b * npts, npts, pb,
+                               beta, sub);
+        } else {
+            hipLaunchKernelGGL((k_spread_rows<T, WV, 1>), dim3(p->nslots),
+                               dim3(SpreadShape<T, WV, 1>::NT), 0, s, in + b * npts, npts, pb,
+                               beta, sub);
+        }
     });
     NUSHT_HIP(hipGetLastError());
     return NUSHT_OK;

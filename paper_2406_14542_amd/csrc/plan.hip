@@ -116,7 +116,8 @@ __global__ void k_bin_keys(const double* __restrict__ theta, const double* __res
     double d;
     const int l1 = wrap_index(first_tap(thc, s1, w, d), n1);
     const int l2 = wrap_index(first_tap(ph, s2, w, d), n2);
-    keys[i] = (l1 / kTile) * nt2 + (l2 / kTile);
+    // tile id, then the row inside the tile: the spreading kernel walks a tile's points by row
+    keys[i] = ((l1 / kTile) * nt2 + (l2 / kTile)) * kTile + (l1 % kTile);
     idx[i] = (int)i;
     phw[i] = ph;
 }
@@ -136,7 +137,7 @@ __global__ void k_mark(const int* __restrict__ keys, int64_t n, int* __restrict_
 {
     const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (k >= n) return;
-    first[k] = (k == 0 || keys[k] != keys[k - 1]) ? 1 : 0;
+    first[k] = (k == 0 || (keys[k] / kTile) != (keys[k - 1] / kTile)) ? 1 : 0;
 }
 
 __global__ void k_slots(const int* __restrict__ keys, const int* __restrict__ first,
@@ -147,9 +148,10 @@ __global__ void k_slots(const int* __restrict__ keys, const int* __restrict__ fi
     if (k >= n) return;
     if (first[k]) {
         const int s = slotidx[k];
+        const int t = keys[k] / kTile;
         slot_off[s] = (int)k;
-        slot_tile[s] = keys[k];
-        tile_slot[keys[k]] = s;
+        slot_tile[s] = t;
+        tile_slot[t] = s;
     }
 }
 
@@ -303,7 +305,11 @@ int bin_points(nusht_plan_s* p, const double* theta, const double* phi, hipStrea
     size_t tbytes = 0, t2 = 0;
     const int blocks = (int)((n + 255) / 256);
     int bits = 1;
-    while ((1LL << bits) < ntiles) ++bits;
+    while ((1LL << bits) < ntiles * kTile) ++bits;
+    if (ntiles * kTile >= (1LL << 31)) {
+        set_last_error("nusht_plan", "fine grid too large for 32-bit bin keys");
+        return NUSHT_EINVAL;
+    }
     do {
         if ((rc = dmalloc(&keys, n)) || (rc = dmalloc(&keys_s, n)) || (rc = dmalloc(&idx, n)) ||
             (rc = dmalloc(&first, n)) || (rc = dmalloc(&sidx, n)) || (rc = dmalloc(&phw, n)) ||

@@ -1,0 +1,85 @@
+"""CGLS inverse (nusht_solve) against a numpy CGLS on the dense oracle matrix, on consistent
+data, with weights, and the non-convergence status."""
+import numpy as np
+import pytest
+
+from paper_2406_14542_amd import inputs
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+def dev(x):
+    return torch.from_numpy(np.ascontiguousarray(x)).cuda()
+
+
+@pytest.fixture(scope="module")
+def P():
+    import paper_2406_14542_amd as P
+    P.lib()
+    return P
+
+
+def mnorm(a, L, M):
+    _, ms = inputs.ell_of_index(L, M)
+    w = np.where(ms == 0, 1.0, 2.0)
+    return float(np.sqrt(np.sum(w * np.abs(a) ** 2)))
+
+
+def test_cgls_matches_dense_twin(P, oracle_mod):
+    """Same iteration count and iterate as CGLS on the dense Y of Eq. (4), unweighted and
+    weighted, at tiny size."""
+    print("[cgls vs twin]", flush=True)
+    rng = np.random.default_rng(40)
+    L = M = 12
+    th, ph = inputs.uniform_points(rng, 400)
+    a_true = inputs.red_alm(rng, L, M, 1)[0]
+    d = oracle_mod.synthesis(L, M, th, ph, a_true[None])[0] + 1e-3 * rng.standard_normal(400)
+    pl = P.Plan(L, M, dev(th), dev(ph), 1e-13)
+    for weights in (None, rng.uniform(0.5, 2.0, 400)):
+        ref, it_ref, hist = oracle_mod.cgls_dense(L, M, th, ph, d, weights=weights, tol=1e-6,
+                                                  maxiter=60)
+        wt = None if weights is None else dev(weights.astype(np.float32))
+        wref = None if weights is None else weights.astype(np.float32).astype(np.float64)
+        if wref is not None:
+            ref, it_ref, hist = oracle_mod.cgls_dense(L, M, th, ph, d, weights=wref, tol=1e-6,
+                                                      maxiter=60)
+        x, it, rr, st = pl.solve(dev(d[None]), weights=wt, tol=1e-6, maxiter=60, check=False)
+        x = x.cpu().numpy()
+        # a slightly noisy inconsistent system: the residual floor is ~1e-3 so both stop at
+        # maxiter and must agree iterate for iterate
+        assert it == it_ref
+        assert mnorm(x - ref, L, M) <= 1e-7 * mnorm(ref, L, M)
+
+
+def test_solve_consistent_data(P, oracle_mod):
+    print("[cg consistent]", flush=True)
+    rng = np.random.default_rng(41)
+    L = 32
+    th, ph = inputs.uniform_points(rng, 4 * (L + 1) ** 2)
+    a_true = inputs.red_alm(rng, L, L, 1)
+    pl = P.Plan(L, L, dev(th), dev(ph), 1e-12)
+    d = pl.synthesis(dev(a_true))
+    x, it, rr, st = pl.solve(d, tol=1e-8, maxiter=500)
+    assert st == P.NUSHT_OK and rr <= 1e-8 and it > 0
+    err = mnorm(x.cpu().numpy() - a_true[0], L, L) / mnorm(a_true[0], L, L)
+    assert err <= 1e-6, err
+    # a weighted solve reaches the same solution
+    w = dev(rng.uniform(0.5, 2.0, th.size).astype(np.float32))
+    x2, it2, rr2, st2 = pl.solve(d, weights=w, tol=1e-8, maxiter=500)
+    assert st2 == P.NUSHT_OK and rr2 <= 1e-8
+    assert mnorm(x2.cpu().numpy() - a_true[0], L, L) / mnorm(a_true[0], L, L) <= 1e-6
+    # starting from the solution: zero iterations
+    x3, it3, rr3, st3 = pl.solve(d, x0=x, tol=1e-6, maxiter=10)
+    assert it3 == 0 and st3 == P.NUSHT_OK
+
+
+def test_solve_reports_nonconvergence(P):
+    rng = np.random.default_rng(42)
+    L = 20
+    th, ph = inputs.uniform_points(rng, 1000)
+    d = dev(rng.standard_normal((1, 1000)))
+    pl = P.Plan(L, L, dev(th), dev(ph), 1e-10)
+    x, it, rr, st = pl.solve(d, tol=1e-12, maxiter=3, check=False)
+    assert st == P.NUSHT_ENOCONV and it == 3 and rr > 1e-12
+    assert np.all(np.isfinite(x.cpu().numpy()))
