@@ -160,11 +160,13 @@ def lambda_column(lmax, m, theta, long_double=False):
     return mant, ex
 
 
-from .twin import (cgls_dense, mlp_backward, mlp_forward, mlp_init, mdot,  # noqa: E402
-                   synthesis_matrix, ylm_dense)
+from .twin import (cgls_dense, density_map, mdot, mlp_backward, mlp_forward,  # noqa: E402
+                   mlp_init, mlp_pack, mlp_unpack, point_features, synthesis_matrix,
+                   weight_loss_dense, ylm_dense)
 
 __all__ = [
     "build", "nalm", "alm_index", "synthesis", "adjoint", "adjoint_columns", "synthesis_grad",
     "lambda_column", "ylm_dense", "synthesis_matrix", "mdot", "cgls_dense", "mlp_init",
-    "mlp_forward", "mlp_backward",
+    "mlp_forward", "mlp_backward", "mlp_pack", "mlp_unpack", "density_map", "point_features",
+    "weight_loss_dense",
 ]

@@ -9,6 +9,8 @@
   Eq. (2) are exact adjoints: <a, b>_m = sum_l [Re(a_l0* b_l0) + 2 sum_{m>0} Re(a_lm* b_lm)].
 * ``cgls_dense``: CGLS for min ||W^(1/2)(S a - d)|| with dense S (least squares on the
   synthesis, the setting in which transforms are called repeatedly, Sec. I).
+* ``density_map``, ``point_features``, ``weight_loss_dense``: the learned-weight inputs and
+  loss for the weighted least-squares inverse, written out plainly.
 * ``mlp_*``: an FP64 multilayer perceptron (tanh hidden layers, softplus output) with its
   backward pass derived by hand; it is the reference for the GPU network kernels.
 """
@@ -160,3 +162,94 @@ def mlp_backward(params, cache, gy, scale=1.0):
         grads[k] = (ga.T @ hs[k], ga.sum(axis=0))
         gh = ga @ W
     return grads
+
+
+# ---------------------------------------------------------------------------------------
+# Learned quadrature weights for the least-squares inverse (not in the paper; the
+# definitions below are the ones the GPU kernels implement, written out plainly).
+# ---------------------------------------------------------------------------------------
+
+def density_map(theta, phi, nt, nph):
+    """rho[a, b] = count of points in equal-angle cell (a, b) / (N * cell area / 4 pi).
+
+    Cell a holds theta in [pi a / nt, pi (a + 1) / nt), cell b holds phi mod 2 pi in
+    [2 pi b / nph, 2 pi (b + 1) / nph); both indices are clamped to the map.  Uniform points
+    give rho ~ 1."""
+    theta = np.asarray(theta, dtype=np.float64)
+    phi = np.asarray(phi, dtype=np.float64)
+    a = np.clip((theta * (nt / np.pi)).astype(np.int64), 0, nt - 1)
+    pw = phi - 2.0 * np.pi * np.floor(phi / (2.0 * np.pi))
+    b = np.clip((pw * (nph / (2.0 * np.pi))).astype(np.int64), 0, nph - 1)
+    cnt = np.zeros((nt, nph))
+    np.add.at(cnt, (a, b), 1.0)
+    rows = np.arange(nt)
+    area = (np.cos(np.pi * rows / nt) - np.cos(np.pi * (rows + 1) / nt)) * (2.0 * np.pi / nph)
+    return cnt / (theta.size * area[:, None] / (4.0 * np.pi))
+
+
+def point_features(theta, phi, rho):
+    """[N, 12] features of each point from the density map rho [nt, nph]:
+    0: log rho bilinearly interpolated between cell centres at the point,
+    1..9: log rho of the 3 x 3 cells around the point's own cell (row-major, theta clamped at
+    the poles, phi periodic), 10: cos theta, 11: sin theta.  log rho is floored at log 1e-3."""
+    theta = np.asarray(theta, dtype=np.float64)
+    phi = np.asarray(phi, dtype=np.float64)
+    nt, nph = rho.shape
+    lr = np.log(np.maximum(rho, 1e-3))
+
+    def cell(a, b):
+        return lr[np.clip(a, 0, nt - 1), np.mod(b, nph)]
+
+    pw = phi - 2.0 * np.pi * np.floor(phi / (2.0 * np.pi))
+    u = theta * (nt / np.pi) - 0.5
+    v = pw * (nph / (2.0 * np.pi)) - 0.5
+    a0 = np.floor(u).astype(np.int64)
+    b0 = np.floor(v).astype(np.int64)
+    fu = u - a0
+    fv = v - b0
+    out = np.empty((theta.size, 12))
+    out[:, 0] = ((1 - fu) * ((1 - fv) * cell(a0, b0) + fv * cell(a0, b0 + 1))
+                 + fu * ((1 - fv) * cell(a0 + 1, b0) + fv * cell(a0 + 1, b0 + 1)))
+    ac = np.clip((theta * (nt / np.pi)).astype(np.int64), 0, nt - 1)
+    bc = np.clip((pw * (nph / (2.0 * np.pi))).astype(np.int64), 0, nph - 1)
+    q = 1
+    for da in (-1, 0, 1):
+        for db in (-1, 0, 1):
+            out[:, q] = cell(ac + da, bc + db)
+            q += 1
+    out[:, 10] = np.cos(theta)
+    out[:, 11] = np.sin(theta)
+    return out
+
+
+def weight_loss_dense(lmax, mmax, theta, phi, d, astar, w):
+    """loss = <r, r>_m / <a*, a*>_m with r = S^H (w d) - a*, and its gradient with respect to
+    the per-point weights: d loss / d w_i = 2 d_i (S r)_i / <a*, a*>_m."""
+    Y = ylm_dense(lmax, mmax, theta, phi)
+    mv = _mvec(lmax, mmax)
+    c = np.conj(Y).T @ (np.asarray(w, dtype=np.float64) * d)
+    c[mv == 0] = c[mv == 0].real
+    r = c - astar
+    den = mdot(astar, astar, lmax, mmax)
+    sr = np.real(Y[:, mv == 0] @ r[mv == 0].real) + 2.0 * np.real(Y[:, mv > 0] @ r[mv > 0])
+    return mdot(r, r, lmax, mmax) / den, 2.0 * d * sr / den
+
+
+def mlp_pack(params):
+    """Flat FP32-ready parameter vector in the layout of the GPU network: for each layer the
+    transposed weight [in][out] row-major, then its bias."""
+    return np.concatenate([np.concatenate([W.T.ravel(), b]) for W, b in params])
+
+
+def mlp_unpack(flat, sizes):
+    params = []
+    o = 0
+    for i in range(len(sizes) - 1):
+        nin, nout = sizes[i], sizes[i + 1]
+        W = np.asarray(flat[o:o + nin * nout], dtype=np.float64).reshape(nin, nout).T.copy()
+        o += nin * nout
+        b = np.asarray(flat[o:o + nout], dtype=np.float64).copy()
+        o += nout
+        params.append((W, b))
+    assert o == len(flat)
+    return params
