@@ -139,7 +139,7 @@ template <typename T>
 __global__ __launch_bounds__(256) void k_deconv_pad_fused(
     const typename cplx<T>::type* __restrict__ cs, typename cplx<T>::type* __restrict__ fs,
     int nt, int n1, int fw, int lmax, int mmax, const T* __restrict__ d1,
-    const T* __restrict__ d2)
+    const T* __restrict__ d2, int ra, int rb)
 {
     using C = typename cplx<T>::type;
     __shared__ C tile[kT][kT + 1];
@@ -151,6 +151,9 @@ __global__ __launch_bounds__(256) void k_deconv_pad_fused(
     const int ilo = i0, ihi = min(i0 + kT, n1) - 1;
     const bool rows_hit = (ilo <= lmax) || (ihi >= n1 - lmax);
     const bool live = rows_hit && mu0 <= mmax;
+    // Columns above mmax are read only by the phi pass, and only in rows [0, ra) and
+    // [n1 - rb, n1); elsewhere the tile is never read and need not be written.
+    if (mu0 > mmax && ilo >= ra && ihi < n1 - rb) return;
     if (live) {
         // load Cs[mu][kappa(i)] with threads along i (coalesced along t)
         for (int r = ty; r < kT; r += blockDim.y) {
@@ -231,6 +234,18 @@ __global__ __launch_bounds__(256) void k_deconv_trunc_fused(
     }
 }
 
+// fs[row_lo + blockIdx.y][0 .. ncol) = 0
+template <typename C>
+__global__ void k_zero_band(C* __restrict__ fs, int row_lo, int fw, int ncol)
+{
+    const int mu = blockIdx.x * blockDim.x + threadIdx.x;
+    if (mu >= ncol) return;
+    C z;
+    z.x = 0;
+    z.y = 0;
+    fs[(int64_t)(row_lo + blockIdx.y) * fw + mu] = z;
+}
+
 }  // namespace
 
 int launch_zero_nyquist_rows(const nusht_plan_s* p, double* G, int nmaps, hipStream_t s)
@@ -241,6 +256,23 @@ int launch_zero_nyquist_rows(const nusht_plan_s* p, double* G, int nmaps, hipStr
     dim3 grid((g.nrings + 255) / 256, nmaps);
     hipLaunchKernelGGL(k_zero_rows, grid, dim3(256), 0, s, reinterpret_cast<double2*>(G),
                        g.nrings, row, g.mmax + 1, (int64_t)g.nrings * row);
+    NUSHT_HIP(hipGetLastError());
+    return NUSHT_OK;
+}
+
+int launch_zero_band_rows(const nusht_plan_s* p, void* fspec, int row_lo, int row_hi,
+                          hipStream_t s)
+{
+    const nusht_geometry& g = p->g;
+    if (row_hi <= row_lo) return NUSHT_OK;
+    const int fw = g.n2 / 2 + 1;
+    dim3 grid((g.mmax + 1 + 255) / 256, row_hi - row_lo);
+    if (g.dtype == NUSHT_MIXED)
+        hipLaunchKernelGGL(k_zero_band<float2>, grid, dim3(256), 0, s,
+                           reinterpret_cast<float2*>(fspec), row_lo, fw, g.mmax + 1);
+    else
+        hipLaunchKernelGGL(k_zero_band<double2>, grid, dim3(256), 0, s,
+                           reinterpret_cast<double2*>(fspec), row_lo, fw, g.mmax + 1);
     NUSHT_HIP(hipGetLastError());
     return NUSHT_OK;
 }
@@ -288,12 +320,12 @@ int launch_deconv_pad(const nusht_plan_s* p, const void* tspec, void* fspec, int
             hipLaunchKernelGGL(k_deconv_pad_fused<float>, grid, block, 0, s,
                                reinterpret_cast<const float2*>(tspec),
                                reinterpret_cast<float2*>(fspec), g.ntorus, g.n1, fw, g.lmax,
-                               g.mmax, p->dec1f, p->dec2f);
+                               g.mmax, p->dec1f, p->dec2f, p->fine_ra, p->fine_rb);
         else
             hipLaunchKernelGGL(k_deconv_pad_fused<double>, grid, block, 0, s,
                                reinterpret_cast<const double2*>(tspec),
                                reinterpret_cast<double2*>(fspec), g.ntorus, g.n1, fw, g.lmax,
-                               g.mmax, p->dec1, p->dec2);
+                               g.mmax, p->dec1, p->dec2, p->fine_ra, p->fine_rb);
     } else {
         const int tw = g.nphi / 2 + 1;
         dim3 grid((fw + 255) / 256, g.n1, nmaps);

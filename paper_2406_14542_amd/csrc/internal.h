@@ -18,6 +18,8 @@ namespace nusht {
 // neighbouring tile, which the halo reduction relies on.
 constexpr int kTile = 32;
 constexpr int kMaxWidth = 16;
+// zero entries after the recurrence table, so that a chunk of l values can be loaded whole
+constexpr int kRecPad = 64;
 constexpr int kMinWidth = 2;
 
 // Status that keeps the first failing HIP/rocFFT call for diagnostics.
@@ -121,7 +123,14 @@ struct nusht_plan_s {
     nusht::FftPlan ring_c2r, ring_r2c;      // 1D over phi, batch N_r, FP64
     nusht::FftPlan torus_r2c, torus_c2r;    // 2D N_t x N_phi (paper mode)
     nusht::FftPlan theta_fwd, theta_bwd;    // 1D C2C over N_t, batch mmax+1 (fused mode)
-    nusht::FftPlan fine_c2r, fine_r2c;      // 2D n1 x n2
+    // Fine grid n1 x n2 (real) <-> n1 x (n2/2+1) (half spectrum), split into its two passes
+    // and pruned: the theta pass runs only over the mmax+1 columns that carry the band
+    // limit, the phi pass only over the rows [0, fine_ra) and [n1 - fine_rb, n1) that the
+    // point windows touch (theta in [0, pi] covers half of the doubled theta circle).
+    nusht::FftPlan fine_col_inv, fine_col_fwd;  // 1D C2C over n1, batch mmax+1, stride n2/2+1
+    nusht::FftPlan fine_rowa_c2r, fine_rowa_r2c;  // 1D over n2, batch fine_ra
+    nusht::FftPlan fine_rowb_c2r, fine_rowb_r2c;  // 1D over n2, batch fine_rb (may be empty)
+    int fine_ra = 0, fine_rb = 0;
 
     // Timing.
     int timing = 0;
@@ -169,6 +178,9 @@ int launch_deconv_pad(const nusht_plan_s* p, const void* tspec, void* fspec, int
                       int f32, hipStream_t s);
 int launch_deconv_trunc(const nusht_plan_s* p, const void* fspec, void* tspec, int nmaps,
                         int fused, int f32, hipStream_t s);
+// zero columns 0..mmax of fine-spectrum rows [row_lo, row_hi) of one map
+int launch_zero_band_rows(const nusht_plan_s* p, void* fspec, int row_lo, int row_hi,
+                          hipStream_t s);
 
 // ---- nonuniform part (nufft_*.hip) ----
 int launch_interp(const nusht_plan_s* p, const void* fine, double* out, int nmaps, int f32,

@@ -104,6 +104,47 @@ __device__ inline void accum(double (&acc)[MB][2], const double2* __restrict__ a
     }
 }
 
+// The coefficient stream of one m (recurrence table and MB coefficient rows) is read through
+// the scalar cache, one l at a time, by every wave of that m; a miss costs a trip to HBM that
+// the few resident waves cannot hide.  Every kPfStep values of l the wave therefore touches
+// the next kPfStep coefficients of each stream, kPfStep steps ahead, with one load per
+// 128-byte line, so that the scalar loads find them in L2.  The touch is an LDS-DMA load
+// (global_load_lds_dword) in inline assembly: it has no register destination, so the
+// compiler never waits for it, and the statement is declared free of memory effects, so the
+// compiler still knows the coefficients are read-only and keeps their loads scalar.  (It
+// does write LDS: a per-wave sink that nothing reads; the wave waits for the DMA once,
+// before its LDS is released.)  M0, the DMA's LDS base, is restored afterwards.  The
+// statement returns the saved M0 so that it stays live; the caller folds it into a value
+// consumed at the end.
+constexpr int kPfStep = 32;
+constexpr int kPfLines = kPfStep * 16 / 128 + 1;  // lines per stream (unaligned start)
+
+__device__ inline unsigned lds_dma_touch(const void* src, unsigned lds_sink)
+{
+    unsigned saved;
+    asm("s_mov_b32 %0, m0\n\t"
+        "s_mov_b32 m0, %2\n\t"
+        "s_nop 0\n\t"
+        "global_load_lds_dword %1, off\n\t"
+        "s_mov_b32 m0, %0"
+        : "=&s"(saved)
+        : "v"(src), "s"(lds_sink));
+    return saved;
+}
+
+template <int MB>
+__device__ inline unsigned prefetch_coeffs(const double2* __restrict__ rec,
+                                           const double2* __restrict__ alm, int64_t nalm,
+                                           int64_t moff, int lmax, int lp, int lane,
+                                           unsigned lds_sink)
+{
+    const int stream = lane / kPfLines, line = lane - stream * kPfLines;
+    if (stream > MB || lp > lmax) return 0u;
+    const int64_t idx = moff + min(lp + 8 * line, lmax);
+    const double2* src = (stream == 0 ? rec : alm + (int64_t)(stream - 1) * nalm) + idx;
+    return lds_dma_touch(src, lds_sink);
+}
+
 // ------------------------------------------------------------------------------------
 // Synthesis.  FUSED: out[b][m][t], t < N_t, the doubled column of Fig. 1 in (theta, m)
 // space: out(t) = G(t) for t < N_r and (-1)^m G(N_t - t) for t >= N_r.  PAPER:
@@ -136,6 +177,7 @@ __global__ __launch_bounds__(256) void k_legendre_synth(
     out += (int64_t)blockIdx.z * MB * out_map_stride;
     const int64_t moff = (int64_t)m * (2 * lmax + 1 - m) / 2;  // index(l, m) = moff + l
     const bool wave_dead = wbase + 64 * R <= jlive[m];
+    __shared__ float pf_sink[4][64];
 
     double E[R][MB][2], O[R][MB][2];
 #pragma unroll
@@ -193,7 +235,16 @@ __global__ __launch_bounds__(256) void k_legendre_synth(
             }
             ++l;
         }
+        int pf_at = l;
+        unsigned pf_keep = 0;
+        const unsigned lds_sink = __builtin_amdgcn_readfirstlane(
+            (unsigned)(uintptr_t)(__attribute__((address_space(3))) float*)pf_sink[wave]);
         for (; l + 1 <= lmax; l += 2) {
+            if (l >= pf_at) {
+                pf_keep ^= prefetch_coeffs<MB>(rec, alm, nalm, moff, lmax, l + kPfStep, lane,
+                                               lds_sink);
+                pf_at = l + kPfStep;
+            }
             const double2 c0 = rec[moff + l], c1 = rec[moff + l + 1];
 #pragma unroll
             for (int r = 0; r < R; ++r) {
@@ -215,6 +266,8 @@ __global__ __launch_bounds__(256) void k_legendre_synth(
                 accum<MB>(E[r], alm, nalm, moff + l, vn);
             }
         }
+        // no LDS-DMA write may be in flight when the workgroup's LDS is released
+        asm volatile("s_waitcnt vmcnt(0)" ::"v"(pf_keep) : "memory");
     }
 
     const double sgn = (m & 1) ? -1.0 : 1.0;
@@ -276,23 +329,6 @@ __device__ inline double2 load_c(const InT* p)
 }
 
 template <bool FUSED, typename InT>
-__device__ inline double2 ring_value(const InT* in_map, int64_t row_stride, int m, int j, int nr,
-                                     int nt, double sgn)
-{
-    if (FUSED) {
-        const InT* col = in_map + (int64_t)m * row_stride;
-        double2 g = load_c(col + j);
-        if (j >= 1 && j <= nr - 2) {
-            const double2 t = load_c(col + (nt - j));
-            g.x += sgn * t.x;
-            g.y += sgn * t.y;
-        }
-        return g;
-    }
-    return load_c(in_map + (int64_t)j * row_stride + m);
-}
-
-template <bool FUSED, typename InT>
 __global__ __launch_bounds__(kAdjWaves * 64) void k_legendre_adj(
     const InT* __restrict__ in, int64_t in_map_stride, int64_t in_row_stride, int nmaps,
     double* __restrict__ part, int npc, int64_t nalm, int lmax,
@@ -302,6 +338,7 @@ __global__ __launch_bounds__(kAdjWaves * 64) void k_legendre_adj(
 {
     __shared__ double stage[kAdjWaves][64 * kLS];
     __shared__ double dsum[kAdjWaves][256];
+    __shared__ float pf_sink[kAdjWaves][64];
     const int m = blockIdx.x;
     const int pc = blockIdx.y;
     const int grp = blockIdx.z;
@@ -332,21 +369,48 @@ __global__ __launch_bounds__(kAdjWaves * 64) void k_legendre_adj(
     }
     const bool wave_dead = pc * pairs_per_block + wave * 64 + 64 <= jl;
 
-    // ring data of this lane's pair: rows 4 b + {N re, N im, S re, S im}
+    // ring data of this lane's pair: rows 4 b + {N re, N im, S re, S im}.  All loads are
+    // issued before any is used (indices clamped into range, unused ones weighted by 0).
     {
+        double2 raw[4][4];
+        double wgt[4];
+        int64_t off[4];
+        if (FUSED) {
+            // G'(j) = Tp(j) + [1 <= j <= N_r - 2] (-1)^m Tp(N_t - j), likewise for js
+            off[0] = j;
+            off[1] = (j >= 1 && j <= nr - 2) ? nt - j : j;
+            off[2] = js;
+            off[3] = (js >= 1 && js <= nr - 2) ? nt - js : js;
+            wgt[0] = 1.0;
+            wgt[1] = (j >= 1 && j <= nr - 2) ? msgn : 0.0;
+            wgt[2] = js != j ? 1.0 : 0.0;
+            wgt[3] = (js != j && js >= 1 && js <= nr - 2) ? msgn : 0.0;
+            for (int q = 0; q < 4; ++q) off[q] += (int64_t)m * in_row_stride;
+        } else {
+            off[0] = (int64_t)j * in_row_stride + m;
+            off[2] = (int64_t)js * in_row_stride + m;
+            off[1] = off[0];
+            off[3] = off[2];
+            wgt[0] = 1.0;
+            wgt[1] = 0.0;
+            wgt[2] = js != j ? 1.0 : 0.0;
+            wgt[3] = 0.0;
+        }
+#pragma unroll
+        for (int b = 0; b < 4; ++b) {
+            const int bb = b < nmb ? b : 0;
+            const InT* im = in + (int64_t)bb * in_map_stride;
+#pragma unroll
+            for (int q = 0; q < 4; ++q) raw[b][q] = load_c(im + off[q]);
+        }
         double hv[16];
 #pragma unroll
         for (int b = 0; b < 4; ++b) {
-            double2 gn = make_double2(0.0, 0.0), gs = make_double2(0.0, 0.0);
-            if (valid && b < nmb) {
-                const InT* im = in + (int64_t)b * in_map_stride;
-                gn = ring_value<FUSED, InT>(im, in_row_stride, m, j, nr, nt, msgn);
-                if (js != j) gs = ring_value<FUSED, InT>(im, in_row_stride, m, js, nr, nt, msgn);
-            }
-            hv[4 * b + 0] = gn.x;
-            hv[4 * b + 1] = gn.y;
-            hv[4 * b + 2] = gs.x;
-            hv[4 * b + 3] = gs.y;
+            const double use = (valid && b < nmb) ? 1.0 : 0.0;
+            hv[4 * b + 0] = use * (wgt[0] * raw[b][0].x + wgt[1] * raw[b][1].x);
+            hv[4 * b + 1] = use * (wgt[0] * raw[b][0].y + wgt[1] * raw[b][1].y);
+            hv[4 * b + 2] = use * (wgt[2] * raw[b][2].x + wgt[3] * raw[b][3].x);
+            hv[4 * b + 3] = use * (wgt[2] * raw[b][2].y + wgt[3] * raw[b][3].y);
         }
 #pragma unroll
         for (int c = 0; c < 16; ++c) st[lane * kLS + c] = hv[c];
@@ -368,10 +432,20 @@ __global__ __launch_bounds__(kAdjWaves * 64) void k_legendre_adj(
         k = 0;
     }
     bool scaled = k > 0;
+    unsigned pf_keep = 0;
+    const unsigned lds_sink = __builtin_amdgcn_readfirstlane(
+        (unsigned)(uintptr_t)(__attribute__((address_space(3))) float*)pf_sink[wave]);
 
     for (int l0 = m; l0 <= lmax; l0 += kLC) {
         d4_t acc = {0.0, 0.0, 0.0, 0.0};
         if (!wave_dead) {
+            // the chunk's recurrence coefficients in one batch of scalar loads (the table is
+            // padded past its end), and the next chunk's lines touched into L2
+            double2 cc[kLC];
+#pragma unroll
+            for (int i = 0; i < kLC; ++i) cc[i] = rec[moff + l0 + i];
+            if (lane < 3 && l0 + kLC <= lmax)
+                pf_keep ^= lds_dma_touch(rec + moff + l0 + kLC + 8 * lane, lds_sink);
             double lam[kLC];
             const bool wscaled = __any(scaled);
 #pragma unroll
@@ -382,7 +456,7 @@ __global__ __launch_bounds__(kAdjWaves * 64) void k_legendre_adj(
                     continue;
                 }
                 if (l > m) {
-                    const double2 c = rec[moff + l];
+                    const double2 c = cc[i];
                     const double vn = rec_step(c, y, vc, vp);
                     vp = vc;
                     vc = vn;
@@ -441,6 +515,8 @@ __global__ __launch_bounds__(kAdjWaves * 64) void k_legendre_adj(
         }
         __syncthreads();
     }
+    // no LDS-DMA write may be in flight when the workgroup's LDS is released
+    asm volatile("s_waitcnt vmcnt(0)" ::"v"(pf_keep) : "memory");
 }
 
 // alm[b][idx] = sum over pair-chunks of the partial sums, in chunk order

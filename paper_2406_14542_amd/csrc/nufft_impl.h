@@ -408,12 +408,13 @@ __global__ __launch_bounds__(256) void k_spread_atomic(const double* __restrict_
 template <typename T, int W, int MB>
 __global__ __launch_bounds__(256) void k_halo(const T* __restrict__ sub,
                                               const int* __restrict__ tile_slot, int nt1, int nt2,
-                                              int n1, int n2, T* __restrict__ fine,
-                                              int64_t map_stride)
+                                              int n1, int n2, int ra, int rb,
+                                              T* __restrict__ fine, int64_t map_stride)
 {
     constexpr int P = kTile + W - 1;
     const int j = blockIdx.x * blockDim.x + threadIdx.x;
-    const int i = blockIdx.y;
+    // rows [0, ra) and [n1 - rb, n1): the only rows any window reaches
+    const int i = (int)blockIdx.y < ra ? (int)blockIdx.y : n1 - rb + ((int)blockIdx.y - ra);
     if (j >= n2) return;
     const int tr = i / kTile, rr = i - tr * kTile;
     const int tc = j / kTile, cc = j - tc * kTile;
@@ -536,14 +537,16 @@ template <typename T>
 int halo_group_impl(const nusht_plan_s* p, const T* sub, T* fine, int b, int mb, hipStream_t s)
 {
     const int64_t ms = (int64_t)p->g.n1 * p->g.n2;
-    dim3 hgrid((p->g.n2 + 255) / 256, p->g.n1);
+    dim3 hgrid((p->g.n2 + 255) / 256, p->fine_ra + p->fine_rb);
     NUSHT_WIDTH_SWITCH(p->g.width, {
         if (mb == 4)
             hipLaunchKernelGGL((k_halo<T, WV, 4>), hgrid, dim3(256), 0, s, sub, p->tile_slot,
-                               p->nt1, p->nt2, p->g.n1, p->g.n2, fine + b * ms, ms);
+                               p->nt1, p->nt2, p->g.n1, p->g.n2, p->fine_ra, p->fine_rb,
+                               fine + b * ms, ms);
         else
             hipLaunchKernelGGL((k_halo<T, WV, 1>), hgrid, dim3(256), 0, s, sub, p->tile_slot,
-                               p->nt1, p->nt2, p->g.n1, p->g.n2, fine + b * ms, ms);
+                               p->nt1, p->nt2, p->g.n1, p->g.n2, p->fine_ra, p->fine_rb,
+                               fine + b * ms, ms);
     });
     NUSHT_HIP(hipGetLastError());
     return NUSHT_OK;

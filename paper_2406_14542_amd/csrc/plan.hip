@@ -409,7 +409,7 @@ static int build_tables(nusht_plan_s* p)
     const nusht_geometry& g = p->g;
     const int L = g.lmax, M = g.mmax;
     // recurrence coefficients (a_lm, a_lm b_lm) in long double, rounded once
-    std::vector<double> rec(2 * (size_t)g.nalm, 0.0);
+    std::vector<double> rec(2 * ((size_t)g.nalm + kRecPad), 0.0);
     for (int m = 0; m <= M; ++m) {
         const int64_t moff = (int64_t)m * (2 * L + 1 - m) / 2;
         for (int l = m + 1; l <= L; ++l) {
@@ -483,7 +483,7 @@ static int build_tables(nusht_plan_s* p)
         d2[k] = 2.0 / (g.width * i2[k]);
         d2f[k] = (float)d2[k];
     }
-    NUSHT_TRY(dmalloc(&p->rec, (size_t)g.nalm));
+    NUSHT_TRY(dmalloc(&p->rec, (size_t)g.nalm + kRecPad));
     NUSHT_TRY(dmalloc(&p->cm_mant, M + 1));
     NUSHT_TRY(dmalloc(&p->cm_exp, M + 1));
     NUSHT_TRY(dmalloc(&p->dec1, L + 1));

@@ -51,6 +51,37 @@ int make_fft(FftPlan& f, rocfft_transform_type type, rocfft_precision prec, size
     return NUSHT_OK;
 }
 
+// 1D batched transform with explicit strides and distances (in elements of the array types)
+int make_fft_1d(FftPlan& f, rocfft_transform_type type, rocfft_precision prec, size_t len,
+                size_t batch, size_t istride, size_t idist, size_t ostride, size_t odist,
+                rocfft_result_placement place)
+{
+    rocfft_array_type in_t, out_t;
+    if (type == rocfft_transform_type_real_forward) {
+        in_t = rocfft_array_type_real;
+        out_t = rocfft_array_type_hermitian_interleaved;
+    } else if (type == rocfft_transform_type_real_inverse) {
+        in_t = rocfft_array_type_hermitian_interleaved;
+        out_t = rocfft_array_type_real;
+    } else {
+        in_t = out_t = rocfft_array_type_complex_interleaved;
+    }
+    rocfft_plan_description desc = nullptr;
+    NUSHT_FFT(rocfft_plan_description_create(&desc));
+    rocfft_status st = rocfft_plan_description_set_data_layout(
+        desc, in_t, out_t, nullptr, nullptr, 1, &istride, idist, 1, &ostride, odist);
+    if (st == rocfft_status_success)
+        st = rocfft_plan_create(&f.plan, place, type, prec, 1, &len, batch, desc);
+    rocfft_plan_description_destroy(desc);
+    if (st != rocfft_status_success) {
+        set_last_error("rocfft_plan_create", "failed (strided 1D)");
+        return NUSHT_EDEVICE;
+    }
+    NUSHT_FFT(rocfft_plan_get_work_buffer_size(f.plan, &f.work_bytes));
+    NUSHT_FFT(rocfft_execution_info_create(&f.info));
+    return NUSHT_OK;
+}
+
 void free_fft(FftPlan& f)
 {
     if (f.info) rocfft_execution_info_destroy(f.info);
@@ -69,11 +100,37 @@ int create_fft_plans(nusht_plan_s* p)
     const nusht_geometry& g = p->g;
     const rocfft_precision prec =
         g.dtype == NUSHT_MIXED ? rocfft_precision_single : rocfft_precision_double;
-    const size_t fine_len[2] = {(size_t)g.n2, (size_t)g.n1};
-    NUSHT_TRY(make_fft(p->fine_c2r, rocfft_transform_type_real_inverse, prec, 2, fine_len, 1,
-                       rocfft_placement_notinplace));
-    NUSHT_TRY(make_fft(p->fine_r2c, rocfft_transform_type_real_forward, prec, 2, fine_len, 1,
-                       rocfft_placement_notinplace));
+    // Rows of the fine grid that any point window touches.  A point at theta has its first
+    // tap in row ceil(theta n1 / (2 pi) - w/2) (mod n1), which for theta in [0, pi] lies in
+    // [n1 - w/2, n1) or [0, floor(n1/2 - w/2) + 1]; a window spans the tile's kTile rows
+    // plus w - 1.  Tile row n1 - kTile wraps into rows below kTile + w - 1.
+    {
+        const int last_tap = (int)std::floor(g.n1 / 2.0 - 0.5 * g.width) + 1;
+        int ra = (last_tap / kTile + 1) * kTile + g.width - 1;
+        int rb = kTile;
+        if (ra + rb >= g.n1) {
+            ra = g.n1;
+            rb = 0;
+        }
+        p->fine_ra = ra;
+        p->fine_rb = rb;
+    }
+    const size_t fw = (size_t)g.n2 / 2 + 1;
+    const size_t ncol = (size_t)g.mmax + 1;
+    NUSHT_TRY(make_fft_1d(p->fine_col_inv, rocfft_transform_type_complex_inverse, prec, g.n1,
+                          ncol, fw, 1, fw, 1, rocfft_placement_inplace));
+    NUSHT_TRY(make_fft_1d(p->fine_col_fwd, rocfft_transform_type_complex_forward, prec, g.n1,
+                          ncol, fw, 1, fw, 1, rocfft_placement_inplace));
+    NUSHT_TRY(make_fft_1d(p->fine_rowa_c2r, rocfft_transform_type_real_inverse, prec, g.n2,
+                          p->fine_ra, 1, fw, 1, g.n2, rocfft_placement_notinplace));
+    NUSHT_TRY(make_fft_1d(p->fine_rowa_r2c, rocfft_transform_type_real_forward, prec, g.n2,
+                          p->fine_ra, 1, g.n2, 1, fw, rocfft_placement_notinplace));
+    if (p->fine_rb > 0) {
+        NUSHT_TRY(make_fft_1d(p->fine_rowb_c2r, rocfft_transform_type_real_inverse, prec, g.n2,
+                              p->fine_rb, 1, fw, 1, g.n2, rocfft_placement_notinplace));
+        NUSHT_TRY(make_fft_1d(p->fine_rowb_r2c, rocfft_transform_type_real_forward, prec, g.n2,
+                              p->fine_rb, 1, g.n2, 1, fw, rocfft_placement_notinplace));
+    }
     if (g.dfs_mode == NUSHT_DFS_FUSED) {
         const size_t len = (size_t)g.ntorus;
         NUSHT_TRY(make_fft(p->theta_fwd, rocfft_transform_type_complex_forward, prec, 1, &len,
@@ -89,8 +146,9 @@ int create_fft_plans(nusht_plan_s* p)
         NUSHT_TRY(ensure_ring_plans(p));
     }
     size_t work = 0;
-    for (FftPlan* f : {&p->fine_c2r, &p->fine_r2c, &p->theta_fwd, &p->theta_bwd, &p->torus_r2c,
-                       &p->torus_c2r, &p->ring_c2r, &p->ring_r2c})
+    for (FftPlan* f : {&p->fine_col_inv, &p->fine_col_fwd, &p->fine_rowa_c2r, &p->fine_rowa_r2c,
+                       &p->fine_rowb_c2r, &p->fine_rowb_r2c, &p->theta_fwd, &p->theta_bwd,
+                       &p->torus_r2c, &p->torus_c2r, &p->ring_c2r, &p->ring_r2c})
         if (f->plan && f->work_bytes > work) work = f->work_bytes;
     if (work > p->fftwork_bytes) {
         if (p->fftwork) hipFree(p->fftwork);
@@ -130,8 +188,9 @@ int ensure_ring_plans(nusht_plan_s* p)
 
 void destroy_fft_plans(nusht_plan_s* p)
 {
-    for (FftPlan* f : {&p->fine_c2r, &p->fine_r2c, &p->theta_fwd, &p->theta_bwd, &p->torus_r2c,
-                       &p->torus_c2r, &p->ring_c2r, &p->ring_r2c})
+    for (FftPlan* f : {&p->fine_col_inv, &p->fine_col_fwd, &p->fine_rowa_c2r, &p->fine_rowa_r2c,
+                       &p->fine_rowb_c2r, &p->fine_rowb_r2c, &p->theta_fwd, &p->theta_bwd,
+                       &p->torus_r2c, &p->torus_c2r, &p->ring_c2r, &p->ring_r2c})
         free_fft(*f);
 }
 
@@ -189,6 +248,41 @@ size_t fine_spec_bytes(const nusht_plan_s* p)
     return (size_t)p->g.n1 * (p->g.n2 / 2 + 1) * 2 * fine_elem_bytes(p);
 }
 
+// Fine half spectrum -> fine grid of one map (N(ii)): theta pass in place over the band
+// columns, then the phi pass into the rows the point windows read.  Columns above mmax of
+// those rows must hold zeros on entry.  Other rows of the grid are left untouched.
+int fine_c2r(nusht_plan_s* p, char* spec, char* real, hipStream_t s)
+{
+    const nusht_geometry& g = p->g;
+    const size_t e = fine_elem_bytes(p);
+    const size_t fw = (size_t)g.n2 / 2 + 1;
+    NUSHT_TRY(fft_exec(p, p->fine_col_inv, spec, nullptr, s));
+    NUSHT_TRY(fft_exec(p, p->fine_rowa_c2r, spec, real, s));
+    if (p->fine_rb > 0) {
+        const size_t r0 = (size_t)g.n1 - p->fine_rb;
+        NUSHT_TRY(fft_exec(p, p->fine_rowb_c2r, spec + r0 * fw * 2 * e, real + r0 * g.n2 * e, s));
+    }
+    return NUSHT_OK;
+}
+
+// Fine grid -> half spectrum of one map (N^H(ii)), reading only the rows the point windows
+// write: phi pass over those rows, zero band columns of the other rows, theta pass in place
+// over the band columns.  Columns above mmax are not produced.
+int fine_r2c(nusht_plan_s* p, char* real, char* spec, hipStream_t s)
+{
+    const nusht_geometry& g = p->g;
+    const size_t e = fine_elem_bytes(p);
+    const size_t fw = (size_t)g.n2 / 2 + 1;
+    NUSHT_TRY(fft_exec(p, p->fine_rowa_r2c, real, spec, s));
+    if (p->fine_rb > 0) {
+        const size_t r0 = (size_t)g.n1 - p->fine_rb;
+        NUSHT_TRY(fft_exec(p, p->fine_rowb_r2c, real + r0 * g.n2 * e, spec + r0 * fw * 2 * e, s));
+    }
+    NUSHT_TRY(launch_zero_band_rows(p, spec, p->fine_ra, g.n1 - p->fine_rb, s));
+    NUSHT_TRY(fft_exec(p, p->fine_col_fwd, spec, nullptr, s));
+    return NUSHT_OK;
+}
+
 // S (Legendre + per-ring phi-FFT) of the paper composition into ring maps [b][N_r][N_phi]
 int ring_synthesis_into(nusht_plan_s* p, const double* alm, double* ring, void* G, int nmaps,
                         hipStream_t s)
@@ -228,7 +322,7 @@ int synthesis_to_fine(nusht_plan_s* p, const double* alm, int nmaps, hipStream_t
         stage_end(p, ST_DECONV, s);
         stage_begin(p, ST_FINE_FFT, s);
         for (int b = 0; b < nmaps; ++b)
-            NUSHT_TRY(fft_exec(p, p->fine_c2r, bytes(p->Y) + b * fine_spec_bytes(p),
+            NUSHT_TRY(fine_c2r(p, bytes(p->Y) + b * fine_spec_bytes(p),
                                bytes(p->X) + b * fine_real_bytes(p), s));
         stage_end(p, ST_FINE_FFT, s);
         *fine_out = p->X;
@@ -249,7 +343,7 @@ int synthesis_to_fine(nusht_plan_s* p, const double* alm, int nmaps, hipStream_t
         stage_end(p, ST_DECONV, s);
         stage_begin(p, ST_FINE_FFT, s);
         for (int b = 0; b < nmaps; ++b)
-            NUSHT_TRY(fft_exec(p, p->fine_c2r, bytes(p->X) + b * fine_spec_bytes(p),
+            NUSHT_TRY(fine_c2r(p, bytes(p->X) + b * fine_spec_bytes(p),
                                bytes(p->Y) + b * fine_real_bytes(p), s));
         stage_end(p, ST_FINE_FFT, s);
         *fine_out = p->Y;
@@ -361,7 +455,7 @@ int nusht_adjoint(nusht_plan_t p, const double* map, double* alm, int nmaps, voi
     // N^H (ii): fine-grid R2C
     stage_begin(p, ST_FINE_FFT, s);
     for (int b = 0; b < nmaps; ++b)
-        NUSHT_TRY(fft_exec(p, p->fine_r2c, bytes(p->X) + b * fine_real_bytes(p),
+        NUSHT_TRY(fine_r2c(p, bytes(p->X) + b * fine_real_bytes(p),
                            bytes(p->Y) + b * fine_spec_bytes(p), s));
     stage_end(p, ST_FINE_FFT, s);
     if (g.dfs_mode == NUSHT_DFS_FUSED) {
