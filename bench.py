@@ -9,6 +9,8 @@ timed beside it and their ratio is reported.  Planning (point binning, tables, F
 excluded, as in the paper (Sec. III).
 
 Prints ONE JSON line.  `--gpus N` with N > 1 exits: this build runs on one GPU.
+`--cg` runs the learned-preconditioner leg instead (CGLS iterations, learned weights vs
+plain; see run_cg).
 """
 from __future__ import annotations
 
@@ -33,10 +35,11 @@ def log(*a):
 
 
 def legendre_flops(g, nmaps):
-    """Algorithmic flops of one Legendre launch: per (l, m, ring pair) one recurrence step
-    (3 flops: a multiply and an FMA) and one complex-by-real FMA per map (4 flops)."""
+    """Algorithmic flops of one Legendre launch: per (l, m, ring pair) one step of the
+    three-term recurrence lam_l = A (x lam_{l-1}) - B lam_{l-2} (two multiplies and an FMA,
+    4 flops) and, per map, one complex-by-real FMA into the parity accumulator (4 flops)."""
     pairs = (g["nrings"] + 1) // 2
-    return float(g["nalm"]) * pairs * (3 + 4 * nmaps)
+    return float(g["nalm"]) * pairs * (4 + 4 * nmaps)
 
 
 def point_bytes(g, nmaps, elem):
@@ -66,22 +69,16 @@ def run_precision(P, torch, cfg, eps, dtype, steps, warmup, alm, d):
     for _ in range(warmup):
         step()
     torch.cuda.synchronize()
+    plan.stage_reset()
     t0 = time.perf_counter()
     for _ in range(steps):
         step()
     torch.cuda.synchronize()
     sec = (time.perf_counter() - t0) / steps
-    # per-stage device times from the library's own HIP events on the call stream
-    syn, adj = {}, {}
-    for _ in range(max(3, min(steps, 5))):
-        plan.synthesis(alm, out=fmap)
-        for k, v in plan.stage_times().items():
-            syn.setdefault(k, []).append(v)
-        plan.adjoint(d, out=calm)
-        for k, v in plan.stage_times().items():
-            adj.setdefault(k, []).append(v)
-    syn = {k: float(np.mean(v)) for k, v in syn.items() if np.mean(v) > 0}
-    adj = {k: float(np.mean(v)) for k, v in adj.items() if np.mean(v) > 0}
+    # per-stage device times over exactly the timed calls, from the HIP events the library
+    # records around each stage on the stream the stage's kernels run on
+    syn = {k: v[0] for k, v in plan.stage_stats("synthesis").items() if v[0] > 0}
+    adj = {k: v[0] for k, v in plan.stage_stats("adjoint").items() if v[0] > 0}
     plan.synthesis(alm, out=fmap)
     f = fmap.cpu().numpy()
     plan.adjoint(d, out=calm)
@@ -107,6 +104,95 @@ def cpu_baseline(cfg, alm_np, d_np, nsample, nmaps):
                 threads=threads, idx=idx, f_sample=fs, sample_s=t2 - t0)
 
 
+def run_cg(args):
+    """Learned-preconditioner leg (`--cg`): CGLS iterations to ||S a - d|| / ||d|| <= tol on
+    holey point sets (lmax = mmax, N = 1.5 (lmax+1)^2 points with density
+    (1 + 0.8 cos^2 theta) and 20 Gaussian holes of 5 degrees, d = S a_true), plain CGLS from
+    zero vs CGLS on W^(1/2) S from S^H W d with the network's weights.  The network is
+    trained on the GPU by the library's kernels on `--cg-train` seeded sets whose targets a*
+    are the method's own plain solves (after at most `--cg-maxiter` iterations), then
+    evaluated on `--cg-test` held-out sets.  Prints ONE JSON line."""
+    import torch
+    import paper_2406_14542_amd as P
+    from paper_2406_14542_amd import inputs
+    from paper_2406_14542_amd.learned import LearnedWeights
+
+    P.lib()
+    L = args.cg_lmax
+    tol, maxit = args.cg_tol, args.cg_maxiter
+    marks = [1e-2, 1e-3, 1e-4, 1e-5, 1e-6, 1e-8]
+
+    def first_below(hist, t):
+        idx = np.nonzero(hist <= t)[0]
+        return int(idx[0]) if idx.size else None
+
+    def make(seed):
+        cfg = inputs.config_c5(seed, lmax=L)
+        th = torch.from_numpy(cfg["theta"]).cuda()
+        ph = torch.from_numpy(cfg["phi"]).cuda()
+        pl = P.Plan(L, L, th, ph, 1e-12)
+        d = pl.synthesis(torch.from_numpy(cfg["alm"]).cuda())
+        return dict(plan=pl, theta=th, phi=ph, d=d)
+
+    lw = LearnedWeights(64, 128, seed=args.cg_seed)
+    t0 = time.perf_counter()
+    train = []
+    for s in range(args.cg_train):
+        ex = make(1000 + s)
+        ex["features"] = lw.features(ex["theta"], ex["phi"])
+        a, it, rr, st = ex["plan"].solve(ex["d"], tol=tol, maxiter=maxit, check=False)
+        ex["astar"] = a
+        log(f"train set {1000 + s}: plain CGLS {it} iterations, residual {rr:.3e}")
+        train.append(ex)
+    t_targets = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    hist = lw.train(train, steps=args.cg_steps, lr=args.cg_lr)
+    torch.cuda.synchronize()
+    t_train = time.perf_counter() - t0
+    log(f"training loss {hist[0] / len(train):.4f} -> {hist[-1] / len(train):.4f} "
+        f"({t_train:.1f} s)")
+    for ex in train:
+        ex["plan"].close()
+    rows = []
+    for s in range(args.cg_test):
+        ex = make(1160 + s)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        _, it0, rr0, st0, h0 = ex["plan"].solve(ex["d"], tol=tol, maxiter=maxit, check=False,
+                                                history=True)
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        w = lw.weights(ex["theta"], ex["phi"])
+        x0 = ex["plan"].weighted_adjoint(ex["d"], w)
+        _, it1, rr1, st1, h1 = ex["plan"].solve(ex["d"], x0=x0, weights=w, tol=tol,
+                                                maxiter=maxit, check=False, history=True)
+        torch.cuda.synchronize()
+        t3 = time.perf_counter()
+        rows.append({"seed": 1160 + s,
+                     "plain": {"iters": it0, "relres": rr0, "s": round(t2 - t1, 3),
+                               "iters_to": {f"{m:g}": first_below(h0, m) for m in marks}},
+                     "learned": {"iters": it1, "relres": rr1, "s": round(t3 - t2, 3),
+                                 "iters_to": {f"{m:g}": first_below(h1, m) for m in marks}}})
+        log(f"held-out {1160 + s}: plain {it0} ({rr0:.2e}), learned {it1} ({rr1:.2e})")
+        ex["plan"].close()
+    out = {"metric": f"CGLS iterations to relative residual {tol:g} at lmax={L} "
+                     "(learned weights vs plain)",
+           "value": float(np.mean([r["learned"]["iters"] for r in rows])),
+           "unit": "iterations", "n_gpus": 1, "higher_is_better": False,
+           "vs_baseline": None, "dtype": "f64 transforms, f32 network", "data": "synthetic",
+           "config": {"workload": f"holey point sets: lmax=mmax={L}, "
+                                  f"N={int(1.5 * (L + 1) ** 2)}, 20 holes of 5 deg, "
+                                  "density 1 + 0.8 cos^2 theta",
+                      "tol": tol, "maxiter": maxit, "train_sets": args.cg_train,
+                      "test_sets": args.cg_test, "adam_steps": args.cg_steps, "lr": args.cg_lr,
+                      "density_map": [64, 128]},
+           "plain_mean_iters": float(np.mean([r["plain"]["iters"] for r in rows])),
+           "targets_s": round(t_targets, 2), "train_s": round(t_train, 2),
+           "train_loss": [hist[0] / len(train), hist[-1] / len(train)],
+           "held_out": rows}
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -116,11 +202,24 @@ def main():
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--cpu-sample", type=int, default=256)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cg", action="store_true",
+                    help="run the learned-preconditioner CGLS leg instead of the transform step")
+    ap.add_argument("--cg-lmax", type=int, default=2047)
+    ap.add_argument("--cg-tol", type=float, default=1e-8)
+    ap.add_argument("--cg-maxiter", type=int, default=3000)
+    ap.add_argument("--cg-train", type=int, default=8)
+    ap.add_argument("--cg-test", type=int, default=2)
+    ap.add_argument("--cg-steps", type=int, default=200)
+    ap.add_argument("--cg-lr", type=float, default=1e-3)
+    ap.add_argument("--cg-seed", type=int, default=7)
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported",
               file=sys.stderr)
         sys.exit(2)
+    if args.cg:
+        run_cg(args)
+        return
 
     import torch
     import paper_2406_14542_amd as P

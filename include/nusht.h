@@ -156,6 +156,14 @@ int nusht_ring_adjoint(nusht_plan_t plan, const double* ring, double* alm, int n
 int nusht_solve(nusht_plan_t plan, const double* map, double* alm, const float* weights,
                 double tol, int maxiter, int* iters, double* relres, void* stream);
 
+/* nusht_solve that also records the recurred relative residual ||d - S a_k|| / ||d|| after
+   each iteration k = 0..iters into `history`, a HOST array of at least maxiter + 1 doubles
+   (NULL: not recorded).  The values are the ones the stopping test reads, so recording
+   costs nothing extra. */
+int nusht_solve_ex(nusht_plan_t plan, const double* map, double* alm, const float* weights,
+                   double tol, int maxiter, int* iters, double* relres, double* history,
+                   void* stream);
+
 /* ---------------------------------------------------------------------------------------
  * Learned quadrature weights for the weighted least-squares inverse.
  *
@@ -217,9 +225,24 @@ int nusht_weight_loss_grad(nusht_plan_t plan, const double* d, const double* ast
                            void* stream);
 
 /* Per-stage device times (ms) of the last execution call when the plan was built with
-   opts.timing != 0.  Synchronises on the plan's last event.  Writes up to maxn values to
-   ms and the stage names (static strings) to names (may be NULL); returns the count. */
+   opts.timing != 0 (HIP events recorded on the call's stream around each stage).
+   Synchronises on the plan's last event.  Writes up to maxn values to ms and the stage
+   names (static strings) to names (may be NULL); returns the count. */
 int nusht_stage_times(nusht_plan_t plan, double* ms, const char** names, int maxn);
+
+/* Kinds of execution call, for nusht_stage_stats. */
+enum { NUSHT_CALL_SYNTHESIS = 0, NUSHT_CALL_ADJOINT = 1, NUSHT_CALL_SYNTHESIS_DERIV = 2,
+       NUSHT_CALL_RING = 3 };
+
+/* Mean per-stage device time (ms) over the calls of one kind made since the plan was built
+   or since nusht_stage_reset (the most recent 64 calls of the plan count at most); ncalls
+   (may be NULL) receives the number of calls averaged per stage.  Same output convention as
+   nusht_stage_times; returns the number of stages written.  Synchronises. */
+int nusht_stage_stats(nusht_plan_t plan, int kind, double* ms, int* ncalls, const char** names,
+                      int maxn);
+
+/* Forget the recorded calls (timing plans only; the events themselves are reused). */
+void nusht_stage_reset(nusht_plan_t plan);
 
 /* Frees everything the plan owns.  NULL is a no-op. */
 void nusht_destroy(nusht_plan_t plan);

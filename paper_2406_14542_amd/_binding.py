@@ -102,8 +102,16 @@ def lib():
             "nusht_weighted_adjoint": (ctypes.c_int, [_vp, _vp, _vp, _vp, _vp]),
             "nusht_weight_loss_grad": (ctypes.c_int, [_vp, _vp, _vp, _vp, _vp,
                                                       ctypes.POINTER(ctypes.c_double), _vp]),
+            "nusht_solve_ex": (ctypes.c_int, [_vp, _vp, _vp, _vp, ctypes.c_double, ctypes.c_int,
+                                              ctypes.POINTER(ctypes.c_int),
+                                              ctypes.POINTER(ctypes.c_double),
+                                              ctypes.POINTER(ctypes.c_double), _vp]),
             "nusht_stage_times": (ctypes.c_int, [_vp, ctypes.POINTER(ctypes.c_double),
                                                  ctypes.POINTER(ctypes.c_char_p), ctypes.c_int]),
+            "nusht_stage_stats": (ctypes.c_int, [_vp, ctypes.c_int, ctypes.POINTER(ctypes.c_double),
+                                                 ctypes.POINTER(ctypes.c_int),
+                                                 ctypes.POINTER(ctypes.c_char_p), ctypes.c_int]),
+            "nusht_stage_reset": (None, [_vp]),
             "nusht_destroy": (None, [_vp]),
             "nusht_strerror": (ctypes.c_char_p, [ctypes.c_int]),
             "nusht_last_error": (ctypes.c_char_p, []),
@@ -275,8 +283,10 @@ class Plan:
                "nusht_ring_adjoint")
         return out
 
-    def solve(self, d, x0=None, weights=None, tol=1e-8, maxiter=1000, check=True):
-        """CGLS inverse (nusht_solve).  Returns (alm, iterations, true relative residual)."""
+    def solve(self, d, x0=None, weights=None, tol=1e-8, maxiter=1000, check=True,
+              history=False):
+        """CGLS inverse (nusht_solve_ex).  Returns (alm, iterations, true relative residual,
+        status), plus the per-iteration recurred relative residuals (numpy) if history."""
         import torch
         x = self._map_in(d)
         if x.shape[0] != 1:
@@ -291,10 +301,15 @@ class Plan:
             wptr = weights.data_ptr()
         it = ctypes.c_int(0)
         rr = ctypes.c_double(0.0)
-        st = lib().nusht_solve(self._h, x.data_ptr(), alm.data_ptr(), wptr, float(tol),
-                               int(maxiter), ctypes.byref(it), ctypes.byref(rr), _stream())
+        hist = (ctypes.c_double * (int(maxiter) + 1))() if history else None
+        st = lib().nusht_solve_ex(self._h, x.data_ptr(), alm.data_ptr(), wptr, float(tol),
+                                  int(maxiter), ctypes.byref(it), ctypes.byref(rr), hist,
+                                  _stream())
         if st not in (NUSHT_OK, NUSHT_ENOCONV) or (check and st != NUSHT_OK):
             _check(st, "nusht_solve")
+        if history:
+            import numpy as np
+            return alm, it.value, rr.value, st, np.array(hist[:it.value + 1])
         return alm, it.value, rr.value, st
 
     def weighted_adjoint(self, d, weights):
@@ -333,6 +348,22 @@ class Plan:
         if n < 0:
             _check(n, "nusht_stage_times")
         return {names[i].decode(): ms[i] for i in range(n)}
+
+    CALL_KINDS = {"synthesis": 0, "adjoint": 1, "synthesis_deriv": 2, "ring": 3}
+
+    def stage_stats(self, kind: str) -> dict:
+        """Mean per-stage device ms over the recorded calls of one kind (timing plans):
+        {stage: (mean_ms, ncalls)}."""
+        ms = (ctypes.c_double * 16)()
+        cnt = (ctypes.c_int * 16)()
+        names = (ctypes.c_char_p * 16)()
+        n = lib().nusht_stage_stats(self._h, self.CALL_KINDS[kind], ms, cnt, names, 16)
+        if n < 0:
+            _check(n, "nusht_stage_stats")
+        return {names[i].decode(): (ms[i], cnt[i]) for i in range(n) if cnt[i] > 0}
+
+    def stage_reset(self):
+        lib().nusht_stage_reset(self._h)
 
     @property
     def handle(self):

@@ -6,9 +6,11 @@
 //   N step (i)   b(kappa, mu) = C(kappa, mu) h1 h2 / (psi1^(kappa) psi2^(mu)), zero-padded to the
 //                fine grid;
 //   N^H step (iii) the same factor after truncating the fine spectrum to |kappa| <= L, mu <= M.
-// All of these are memory-bound; each thread touches each element once and consecutive
-// threads touch consecutive addresses (the fused-mode deconvolutions also transpose
-// between the (m, t) and (kappa, mu) layouts through a 32 x 32 LDS tile).
+// The fine spectrum is kept in two layouts: the band spectrum [mu][i] (mu <= M, all n1 rows
+// i = kappa mod n1, the input/output of the theta pass) and the row spectrum [i][mu]
+// (mu < n2/2+1, window rows only, the input/output of the phi pass); 32 x 32 LDS-tiled
+// transposes link them.  All of these are memory-bound; each thread touches each element
+// once and consecutive threads touch consecutive addresses.
 #include "internal.h"
 
 namespace nusht {
@@ -74,53 +76,57 @@ __global__ void k_fold(const TI* __restrict__ torus, double* __restrict__ ring, 
     ring[(int64_t)b * nr * nphi + (int64_t)j * nphi + k] = v;
 }
 
-// torus spectrum [N_t][N_phi/2+1] -> fine spectrum [n1][n2/2+1]
+// fine row of kappa and back
+__device__ inline int kappa_of_row(int i, int n) { return i <= n / 2 ? i : i - n; }
+
+// torus spectrum ts[b][t][mu] (rows of tw) -> band spectrum [b][mu][i], deconvolved and
+// zero-padded (paper mode)
 template <typename T>
 __global__ void k_deconv_pad_paper(const typename cplx<T>::type* __restrict__ ts,
-                                   typename cplx<T>::type* __restrict__ fs, int nt, int tw,
-                                   int n1, int fw, int lmax, int mmax,
-                                   const T* __restrict__ d1, const T* __restrict__ d2, T scale)
+                                   typename cplx<T>::type* __restrict__ band, int nt, int tw,
+                                   int n1, int lmax, int mmax, const T* __restrict__ d1,
+                                   const T* __restrict__ d2, T scale)
 {
     using C = typename cplx<T>::type;
-    const int mu = blockIdx.x * blockDim.x + threadIdx.x;
-    const int i = blockIdx.y;
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int mu = blockIdx.y;
     const int b = blockIdx.z;
-    if (mu >= fw) return;
-    const int kap = (i <= n1 / 2) ? i : i - n1;
+    if (i >= n1) return;
+    const int kap = kappa_of_row(i, n1);
     const int ak = kap < 0 ? -kap : kap;
     C v;
     v.x = 0;
     v.y = 0;
-    if (ak <= lmax && mu <= mmax) {
+    if (ak <= lmax) {
         const int t = kap < 0 ? kap + nt : kap;
         const C c = ts[(int64_t)b * nt * tw + (int64_t)t * tw + mu];
         const T f = d1[ak] * d2[mu] * scale;
         v.x = c.x * f;
         v.y = c.y * f;
     }
-    fs[(int64_t)b * n1 * fw + (int64_t)i * fw + mu] = v;
+    band[((int64_t)b * (mmax + 1) + mu) * n1 + i] = v;
 }
 
-// fine spectrum [n1][n2/2+1] -> torus spectrum [N_t][N_phi/2+1]
+// band spectrum [b][mu][i] -> torus spectrum ts[b][t][mu] (zero for mu > M or |kappa| > L)
 template <typename T>
-__global__ void k_deconv_trunc_paper(const typename cplx<T>::type* __restrict__ fs,
+__global__ void k_deconv_trunc_paper(const typename cplx<T>::type* __restrict__ band,
                                      typename cplx<T>::type* __restrict__ ts, int nt, int tw,
-                                     int n1, int fw, int lmax, int mmax,
-                                     const T* __restrict__ d1, const T* __restrict__ d2, T scale)
+                                     int n1, int lmax, int mmax, const T* __restrict__ d1,
+                                     const T* __restrict__ d2, T scale)
 {
     using C = typename cplx<T>::type;
     const int mu = blockIdx.x * blockDim.x + threadIdx.x;
     const int t = blockIdx.y;
     const int b = blockIdx.z;
     if (mu >= tw) return;
-    const int kap = (t <= nt / 2) ? t : t - nt;
+    const int kap = kappa_of_row(t, nt);
     const int ak = kap < 0 ? -kap : kap;
     C v;
     v.x = 0;
     v.y = 0;
     if (ak <= lmax && mu <= mmax) {
         const int i = kap < 0 ? kap + n1 : kap;
-        const C c = fs[(int64_t)b * n1 * fw + (int64_t)i * fw + mu];
+        const C c = band[((int64_t)b * (mmax + 1) + mu) * n1 + i];
         const T f = d1[ak] * d2[mu] * scale;
         v.x = c.x * f;
         v.y = c.y * f;
@@ -128,59 +134,94 @@ __global__ void k_deconv_trunc_paper(const typename cplx<T>::type* __restrict__ 
     ts[(int64_t)b * nt * tw + (int64_t)t * tw + mu] = v;
 }
 
-// ---- fused mode: (m, t) <-> (kappa, mu) transposes --------------------------------------
+// fused mode: column spectrum Cs[b][m][t] (t < N_t) <-> band spectrum [b][m][i]; both are
+// contiguous along the theta frequency, so these are plain gathers
+template <typename T>
+__global__ void k_deconv_pad_fused(const typename cplx<T>::type* __restrict__ cs,
+                                   typename cplx<T>::type* __restrict__ band, int nt, int n1,
+                                   int lmax, int mmax, const T* __restrict__ d1,
+                                   const T* __restrict__ d2)
+{
+    using C = typename cplx<T>::type;
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int m = blockIdx.y;
+    const int b = blockIdx.z;
+    if (i >= n1) return;
+    const int kap = kappa_of_row(i, n1);
+    const int ak = kap < 0 ? -kap : kap;
+    C v;
+    v.x = 0;
+    v.y = 0;
+    if (ak <= lmax) {
+        const int t = kap < 0 ? kap + nt : kap;
+        const C c = cs[((int64_t)b * (mmax + 1) + m) * nt + t];
+        const T f = d1[ak] * d2[m];
+        v.x = c.x * f;
+        v.y = c.y * f;
+    }
+    band[((int64_t)b * (mmax + 1) + m) * n1 + i] = v;
+}
+
+template <typename T>
+__global__ void k_deconv_trunc_fused(const typename cplx<T>::type* __restrict__ band,
+                                     typename cplx<T>::type* __restrict__ cs, int nt, int n1,
+                                     int lmax, int mmax, const T* __restrict__ d1,
+                                     const T* __restrict__ d2)
+{
+    using C = typename cplx<T>::type;
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    const int m = blockIdx.y;
+    const int b = blockIdx.z;
+    if (t >= nt) return;
+    const int kap = kappa_of_row(t, nt);
+    const int ak = kap < 0 ? -kap : kap;
+    C v;
+    v.x = 0;
+    v.y = 0;
+    if (ak <= lmax) {
+        const int i = kap < 0 ? kap + n1 : kap;
+        const C c = band[((int64_t)b * (mmax + 1) + m) * n1 + i];
+        const T f = d1[ak] * d2[m];
+        v.x = c.x * f;
+        v.y = c.y * f;
+    }
+    cs[((int64_t)b * (mmax + 1) + m) * nt + t] = v;
+}
+
+// ---- band <-> row spectrum transposes (one map) -----------------------------------------
 
 constexpr int kT = 32;
 
-// column spectrum Cs[b][m][t] (t < N_t, the theta-FFT of the doubled column) -> fine
-// spectrum [n1][n2/2+1].  Block (32 x 8 threads) covers fine rows i0..i0+31, columns
-// mu0..mu0+31.
-template <typename T>
-__global__ __launch_bounds__(256) void k_deconv_pad_fused(
-    const typename cplx<T>::type* __restrict__ cs, typename cplx<T>::type* __restrict__ fs,
-    int nt, int n1, int fw, int lmax, int mmax, const T* __restrict__ d1,
-    const T* __restrict__ d2, int ra, int rb)
+// window row of compact index q: rows [0, ra) then [n1 - rb, n1)
+__device__ inline int window_row(int q, int ra, int rb, int n1) { return q < ra ? q : n1 - rb + (q - ra); }
+
+// rows[i][mu] = band[mu][i] for mu <= M, 0 for mu in (M, fw); window rows only.
+// Block 32 x 8 threads: tile of 32 compact rows x 32 columns.
+template <typename C>
+__global__ __launch_bounds__(256) void k_band_to_rows(const C* __restrict__ band,
+                                                      C* __restrict__ rows, int n1, int fw,
+                                                      int ncol, int ra, int rb)
 {
-    using C = typename cplx<T>::type;
     __shared__ C tile[kT][kT + 1];
-    const int i0 = blockIdx.y * kT, mu0 = blockIdx.x * kT;
-    const int b = blockIdx.z;
+    const int q0 = blockIdx.y * kT, mu0 = blockIdx.x * kT;
+    const int nq = ra + rb;
     const int tx = threadIdx.x, ty = threadIdx.y;
-    const C* cb = cs + (int64_t)b * (mmax + 1) * nt;
-    // block-level test: does the tile meet |kappa| <= L and mu <= M at all?
-    const int ilo = i0, ihi = min(i0 + kT, n1) - 1;
-    const bool rows_hit = (ilo <= lmax) || (ihi >= n1 - lmax);
-    const bool live = rows_hit && mu0 <= mmax;
-    // Columns above mmax are read only by the phi pass, and only in rows [0, ra) and
-    // [n1 - rb, n1); elsewhere the tile is never read and need not be written.
-    if (mu0 > mmax && ilo >= ra && ihi < n1 - rb) return;
+    const bool live = mu0 < ncol;
     if (live) {
-        // load Cs[mu][kappa(i)] with threads along i (coalesced along t)
+        // read along i (contiguous in the band spectrum)
         for (int r = ty; r < kT; r += blockDim.y) {
-            const int mu = mu0 + r;
-            const int i = i0 + tx;
+            const int mu = mu0 + r, q = q0 + tx;
             C v;
             v.x = 0;
             v.y = 0;
-            if (mu <= mmax && i < n1) {
-                const int kap = (i <= n1 / 2) ? i : i - n1;
-                const int ak = kap < 0 ? -kap : kap;
-                if (ak <= lmax) {
-                    const int t = kap < 0 ? kap + nt : kap;
-                    const C c = cb[(int64_t)mu * nt + t];
-                    const T f = d1[ak] * d2[mu];
-                    v.x = c.x * f;
-                    v.y = c.y * f;
-                }
-            }
+            if (mu < ncol && q < nq) v = band[(int64_t)mu * n1 + window_row(q, ra, rb, n1)];
             tile[r][tx] = v;
         }
         __syncthreads();
     }
     for (int r = ty; r < kT; r += blockDim.y) {
-        const int i = i0 + r;
-        const int mu = mu0 + tx;
-        if (i >= n1 || mu >= fw) continue;
+        const int q = q0 + r, mu = mu0 + tx;
+        if (q >= nq || mu >= fw) continue;
         C v;
         if (live) {
             v = tile[tx][r];
@@ -188,62 +229,34 @@ __global__ __launch_bounds__(256) void k_deconv_pad_fused(
             v.x = 0;
             v.y = 0;
         }
-        fs[(int64_t)b * n1 * fw + (int64_t)i * fw + mu] = v;
+        rows[(int64_t)window_row(q, ra, rb, n1) * fw + mu] = v;
     }
 }
 
-// fine spectrum [n1][n2/2+1] -> column spectrum Cs[b][m][t] for m <= M, t < N_t
-template <typename T>
-__global__ __launch_bounds__(256) void k_deconv_trunc_fused(
-    const typename cplx<T>::type* __restrict__ fs, typename cplx<T>::type* __restrict__ cs,
-    int nt, int n1, int fw, int lmax, int mmax, const T* __restrict__ d1,
-    const T* __restrict__ d2)
+// band[mu][i] = rows[i][mu] for window rows, 0 for the other rows; mu <= M.
+template <typename C>
+__global__ __launch_bounds__(256) void k_rows_to_band(const C* __restrict__ rows,
+                                                      C* __restrict__ band, int n1, int fw,
+                                                      int ncol, int ra, int rb)
 {
-    using C = typename cplx<T>::type;
     __shared__ C tile[kT][kT + 1];
-    const int t0 = blockIdx.x * kT, m0 = blockIdx.y * kT;
-    const int b = blockIdx.z;
+    const int i0 = blockIdx.y * kT, mu0 = blockIdx.x * kT;
     const int tx = threadIdx.x, ty = threadIdx.y;
-    const C* fb = fs + (int64_t)b * n1 * fw;
-    // load fine[i(t)][m] with threads along m
+    // read along mu (contiguous in the row spectrum)
     for (int r = ty; r < kT; r += blockDim.y) {
-        const int t = t0 + r;
-        const int m = m0 + tx;
+        const int i = i0 + r, mu = mu0 + tx;
         C v;
         v.x = 0;
         v.y = 0;
-        if (t < nt && m <= mmax) {
-            const int kap = (t <= nt / 2) ? t : t - nt;
-            const int ak = kap < 0 ? -kap : kap;
-            if (ak <= lmax) {
-                const int i = kap < 0 ? kap + n1 : kap;
-                const C c = fb[(int64_t)i * fw + m];
-                const T f = d1[ak] * d2[m];
-                v.x = c.x * f;
-                v.y = c.y * f;
-            }
-        }
+        if (i < n1 && mu < ncol && (i < ra || i >= n1 - rb)) v = rows[(int64_t)i * fw + mu];
         tile[r][tx] = v;
     }
     __syncthreads();
     for (int r = ty; r < kT; r += blockDim.y) {
-        const int m = m0 + r;
-        const int t = t0 + tx;
-        if (m > mmax || t >= nt) continue;
-        cs[(int64_t)b * (mmax + 1) * nt + (int64_t)m * nt + t] = tile[tx][r];
+        const int mu = mu0 + r, i = i0 + tx;
+        if (mu >= ncol || i >= n1) continue;
+        band[(int64_t)mu * n1 + i] = tile[tx][r];
     }
-}
-
-// fs[row_lo + blockIdx.y][0 .. ncol) = 0
-template <typename C>
-__global__ void k_zero_band(C* __restrict__ fs, int row_lo, int fw, int ncol)
-{
-    const int mu = blockIdx.x * blockDim.x + threadIdx.x;
-    if (mu >= ncol) return;
-    C z;
-    z.x = 0;
-    z.y = 0;
-    fs[(int64_t)(row_lo + blockIdx.y) * fw + mu] = z;
 }
 
 }  // namespace
@@ -260,19 +273,40 @@ int launch_zero_nyquist_rows(const nusht_plan_s* p, double* G, int nmaps, hipStr
     return NUSHT_OK;
 }
 
-int launch_zero_band_rows(const nusht_plan_s* p, void* fspec, int row_lo, int row_hi,
-                          hipStream_t s)
+int launch_band_to_rows(const nusht_plan_s* p, const void* band, void* rows, hipStream_t s)
 {
     const nusht_geometry& g = p->g;
-    if (row_hi <= row_lo) return NUSHT_OK;
-    const int fw = g.n2 / 2 + 1;
-    dim3 grid((g.mmax + 1 + 255) / 256, row_hi - row_lo);
+    const int fw = g.n2 / 2 + 1, nq = p->fine_ra + p->fine_rb;
+    dim3 grid((fw + kT - 1) / kT, (nq + kT - 1) / kT);
+    dim3 block(kT, 8);
     if (g.dtype == NUSHT_MIXED)
-        hipLaunchKernelGGL(k_zero_band<float2>, grid, dim3(256), 0, s,
-                           reinterpret_cast<float2*>(fspec), row_lo, fw, g.mmax + 1);
+        hipLaunchKernelGGL(k_band_to_rows<float2>, grid, block, 0, s,
+                           reinterpret_cast<const float2*>(band), reinterpret_cast<float2*>(rows),
+                           g.n1, fw, g.mmax + 1, p->fine_ra, p->fine_rb);
     else
-        hipLaunchKernelGGL(k_zero_band<double2>, grid, dim3(256), 0, s,
-                           reinterpret_cast<double2*>(fspec), row_lo, fw, g.mmax + 1);
+        hipLaunchKernelGGL(k_band_to_rows<double2>, grid, block, 0, s,
+                           reinterpret_cast<const double2*>(band),
+                           reinterpret_cast<double2*>(rows), g.n1, fw, g.mmax + 1, p->fine_ra,
+                           p->fine_rb);
+    NUSHT_HIP(hipGetLastError());
+    return NUSHT_OK;
+}
+
+int launch_rows_to_band(const nusht_plan_s* p, const void* rows, void* band, hipStream_t s)
+{
+    const nusht_geometry& g = p->g;
+    const int fw = g.n2 / 2 + 1;
+    dim3 grid((g.mmax + 1 + kT - 1) / kT, (g.n1 + kT - 1) / kT);
+    dim3 block(kT, 8);
+    if (g.dtype == NUSHT_MIXED)
+        hipLaunchKernelGGL(k_rows_to_band<float2>, grid, block, 0, s,
+                           reinterpret_cast<const float2*>(rows), reinterpret_cast<float2*>(band),
+                           g.n1, fw, g.mmax + 1, p->fine_ra, p->fine_rb);
+    else
+        hipLaunchKernelGGL(k_rows_to_band<double2>, grid, block, 0, s,
+                           reinterpret_cast<const double2*>(rows),
+                           reinterpret_cast<double2*>(band), g.n1, fw, g.mmax + 1, p->fine_ra,
+                           p->fine_rb);
     NUSHT_HIP(hipGetLastError());
     return NUSHT_OK;
 }
@@ -308,74 +342,69 @@ int launch_fold(const nusht_plan_s* p, const void* torus, double* ring, int nmap
     return NUSHT_OK;
 }
 
-int launch_deconv_pad(const nusht_plan_s* p, const void* tspec, void* fspec, int nmaps, int fused,
+int launch_deconv_pad(const nusht_plan_s* p, const void* tspec, void* band, int nmaps, int fused,
                       int f32, hipStream_t s)
 {
     const nusht_geometry& g = p->g;
-    const int fw = g.n2 / 2 + 1;
+    dim3 grid((g.n1 + 255) / 256, g.mmax + 1, nmaps);
     if (fused) {
-        dim3 grid((fw + kT - 1) / kT, (g.n1 + kT - 1) / kT, nmaps);
-        dim3 block(kT, 8);
         if (f32)
-            hipLaunchKernelGGL(k_deconv_pad_fused<float>, grid, block, 0, s,
+            hipLaunchKernelGGL(k_deconv_pad_fused<float>, grid, dim3(256), 0, s,
                                reinterpret_cast<const float2*>(tspec),
-                               reinterpret_cast<float2*>(fspec), g.ntorus, g.n1, fw, g.lmax,
-                               g.mmax, p->dec1f, p->dec2f, p->fine_ra, p->fine_rb);
+                               reinterpret_cast<float2*>(band), g.ntorus, g.n1, g.lmax, g.mmax,
+                               p->dec1f, p->dec2f);
         else
-            hipLaunchKernelGGL(k_deconv_pad_fused<double>, grid, block, 0, s,
+            hipLaunchKernelGGL(k_deconv_pad_fused<double>, grid, dim3(256), 0, s,
                                reinterpret_cast<const double2*>(tspec),
-                               reinterpret_cast<double2*>(fspec), g.ntorus, g.n1, fw, g.lmax,
-                               g.mmax, p->dec1, p->dec2, p->fine_ra, p->fine_rb);
+                               reinterpret_cast<double2*>(band), g.ntorus, g.n1, g.lmax, g.mmax,
+                               p->dec1, p->dec2);
     } else {
         const int tw = g.nphi / 2 + 1;
-        dim3 grid((fw + 255) / 256, g.n1, nmaps);
         const double sc = 1.0 / g.nphi;
         if (f32)
             hipLaunchKernelGGL(k_deconv_pad_paper<float>, grid, dim3(256), 0, s,
                                reinterpret_cast<const float2*>(tspec),
-                               reinterpret_cast<float2*>(fspec), g.ntorus, tw, g.n1, fw, g.lmax,
+                               reinterpret_cast<float2*>(band), g.ntorus, tw, g.n1, g.lmax,
                                g.mmax, p->dec1f, p->dec2f, (float)sc);
         else
             hipLaunchKernelGGL(k_deconv_pad_paper<double>, grid, dim3(256), 0, s,
                                reinterpret_cast<const double2*>(tspec),
-                               reinterpret_cast<double2*>(fspec), g.ntorus, tw, g.n1, fw, g.lmax,
+                               reinterpret_cast<double2*>(band), g.ntorus, tw, g.n1, g.lmax,
                                g.mmax, p->dec1, p->dec2, sc);
     }
     NUSHT_HIP(hipGetLastError());
     return NUSHT_OK;
 }
 
-int launch_deconv_trunc(const nusht_plan_s* p, const void* fspec, void* tspec, int nmaps,
+int launch_deconv_trunc(const nusht_plan_s* p, const void* band, void* tspec, int nmaps,
                         int fused, int f32, hipStream_t s)
 {
     const nusht_geometry& g = p->g;
-    const int fw = g.n2 / 2 + 1;
     if (fused) {
-        dim3 grid((g.ntorus + kT - 1) / kT, (g.mmax + 1 + kT - 1) / kT, nmaps);
-        dim3 block(kT, 8);
+        dim3 grid((g.ntorus + 255) / 256, g.mmax + 1, nmaps);
         if (f32)
-            hipLaunchKernelGGL(k_deconv_trunc_fused<float>, grid, block, 0, s,
-                               reinterpret_cast<const float2*>(fspec),
-                               reinterpret_cast<float2*>(tspec), g.ntorus, g.n1, fw, g.lmax,
-                               g.mmax, p->dec1f, p->dec2f);
+            hipLaunchKernelGGL(k_deconv_trunc_fused<float>, grid, dim3(256), 0, s,
+                               reinterpret_cast<const float2*>(band),
+                               reinterpret_cast<float2*>(tspec), g.ntorus, g.n1, g.lmax, g.mmax,
+                               p->dec1f, p->dec2f);
         else
-            hipLaunchKernelGGL(k_deconv_trunc_fused<double>, grid, block, 0, s,
-                               reinterpret_cast<const double2*>(fspec),
-                               reinterpret_cast<double2*>(tspec), g.ntorus, g.n1, fw, g.lmax,
-                               g.mmax, p->dec1, p->dec2);
+            hipLaunchKernelGGL(k_deconv_trunc_fused<double>, grid, dim3(256), 0, s,
+                               reinterpret_cast<const double2*>(band),
+                               reinterpret_cast<double2*>(tspec), g.ntorus, g.n1, g.lmax, g.mmax,
+                               p->dec1, p->dec2);
     } else {
         const int tw = g.nphi / 2 + 1;
         dim3 grid((tw + 255) / 256, g.ntorus, nmaps);
         const double sc = 1.0 / g.nphi;
         if (f32)
             hipLaunchKernelGGL(k_deconv_trunc_paper<float>, grid, dim3(256), 0, s,
-                               reinterpret_cast<const float2*>(fspec),
-                               reinterpret_cast<float2*>(tspec), g.ntorus, tw, g.n1, fw, g.lmax,
+                               reinterpret_cast<const float2*>(band),
+                               reinterpret_cast<float2*>(tspec), g.ntorus, tw, g.n1, g.lmax,
                                g.mmax, p->dec1f, p->dec2f, (float)sc);
         else
             hipLaunchKernelGGL(k_deconv_trunc_paper<double>, grid, dim3(256), 0, s,
-                               reinterpret_cast<const double2*>(fspec),
-                               reinterpret_cast<double2*>(tspec), g.ntorus, tw, g.n1, fw, g.lmax,
+                               reinterpret_cast<const double2*>(band),
+                               reinterpret_cast<double2*>(tspec), g.ntorus, tw, g.n1, g.lmax,
                                g.mmax, p->dec1, p->dec2, sc);
     }
     NUSHT_HIP(hipGetLastError());

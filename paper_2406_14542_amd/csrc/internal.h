@@ -112,6 +112,8 @@ struct nusht_plan_s {
     size_t Xbytes = 0;
     void* Y = nullptr;
     size_t Ybytes = 0;
+    void* W = nullptr;           // one map's fine row spectrum [n1][n2/2+1]
+    size_t Wbytes = 0;
     void* Z = nullptr;           // spreading subgrids
     size_t Zbytes = 0;
     void* fftwork = nullptr;
@@ -126,16 +128,24 @@ struct nusht_plan_s {
     // Fine grid n1 x n2 (real) <-> n1 x (n2/2+1) (half spectrum), split into its two passes
     // and pruned: the theta pass runs only over the mmax+1 columns that carry the band
     // limit, the phi pass only over the rows [0, fine_ra) and [n1 - fine_rb, n1) that the
-    // point windows touch (theta in [0, pi] covers half of the doubled theta circle).
-    nusht::FftPlan fine_col_inv, fine_col_fwd;  // 1D C2C over n1, batch mmax+1, stride n2/2+1
+    // point windows touch (theta in [0, pi] covers half of the doubled theta circle).  The
+    // band columns are stored transposed, [mu][i] ("band spectrum"), so that the theta pass
+    // is a contiguous batched FFT; an LDS-tiled transpose links them to the row spectrum.
+    nusht::FftPlan fine_col_inv, fine_col_fwd;  // 1D C2C over n1, batch mmax+1, contiguous
     nusht::FftPlan fine_rowa_c2r, fine_rowa_r2c;  // 1D over n2, batch fine_ra
     nusht::FftPlan fine_rowb_c2r, fine_rowb_r2c;  // 1D over n2, batch fine_rb (may be empty)
     int fine_ra = 0, fine_rb = 0;
 
     // Timing.
+    // Timing: every execution call takes the next slot of a ring of kTimingSlots slots, each
+    // with one event pair per stage; nusht_stage_stats averages the calls of one kind.
+    static constexpr int kTimingSlots = 64;
     int timing = 0;
-    hipEvent_t ev[nusht::ST_COUNT][2]{};
-    int ev_used[nusht::ST_COUNT]{};
+    hipEvent_t ev[kTimingSlots][nusht::ST_COUNT][2]{};
+    unsigned char ev_used[kTimingSlots][nusht::ST_COUNT]{};
+    int slot_kind[kTimingSlots]{};
+    int64_t ncalls = 0;   // calls since the last reset
+    int cur = 0;          // slot of the current call
 };
 
 namespace nusht {
@@ -178,9 +188,11 @@ int launch_deconv_pad(const nusht_plan_s* p, const void* tspec, void* fspec, int
                       int f32, hipStream_t s);
 int launch_deconv_trunc(const nusht_plan_s* p, const void* fspec, void* tspec, int nmaps,
                         int fused, int f32, hipStream_t s);
-// zero columns 0..mmax of fine-spectrum rows [row_lo, row_hi) of one map
-int launch_zero_band_rows(const nusht_plan_s* p, void* fspec, int row_lo, int row_hi,
-                          hipStream_t s);
+// band spectrum [mmax+1][n1] <-> row spectrum [n1][n2/2+1] of one map, rows [0, fine_ra)
+// and [n1 - fine_rb, n1) only.  band_to_rows zero-fills the columns above mmax;
+// rows_to_band writes zeros for the rows no window reaches.
+int launch_band_to_rows(const nusht_plan_s* p, const void* band, void* rows, hipStream_t s);
+int launch_rows_to_band(const nusht_plan_s* p, const void* rows, void* band, hipStream_t s);
 
 // ---- nonuniform part (nufft_*.hip) ----
 int launch_interp(const nusht_plan_s* p, const void* fine, double* out, int nmaps, int f32,

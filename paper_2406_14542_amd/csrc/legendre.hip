@@ -302,21 +302,20 @@ __global__ __launch_bounds__(256) void k_legendre_synth(
 // Adjoint.  c_lm = sum_j lam_lm(x_j) G'_m(theta_j) is, for one m, a product of the
 // (L - m + 1) x N_r matrix of lam values (generated by the recurrence) with the N_r x
 // (2 B) matrix of ring data, reduced over rings.  gfx950 mapping:
-//  * one lane = one ring pair (j, N_r-1-j); it runs the recurrence for 16 consecutive l
-//    and parks the 16 values in LDS;
-//  * the reduction over ring pairs is done by v_mfma_f64_16x16x4: per MFMA, A (16 x 4) holds
-//    the ring data of 4 pairs -- rows = {north re, north im, south re, south im} x 4 maps --
-//    and B (4 x 16) the lam values of those 4 pairs for the 16 l of the chunk, so 16 MFMAs
-//    reduce the wave's 64 pairs into D (16 x 16); the south rows enter with the parity sign
-//    lam_lm(-x) = (-1)^(l+m) lam_lm(x), applied once per l when the rows are combined;
+//  * one lane = one ring pair (j, N_r-1-j): lam_lm(-x) = (-1)^(l+m) lam_lm(x), so the pair
+//    enters through its even (N + S) and odd (N - S) combinations, chosen by the parity of
+//    l - m; the lane runs the recurrence for 16 consecutive l and parks the values in LDS;
+//  * the reduction over ring pairs runs on v_mfma_f64_4x4x4_4b: four 4x4x4 products per
+//    instruction, one for each (parity, real/imaginary) pair, with rows = the 4 maps,
+//    K = 4 ring pairs and columns = 4 values of l of that parity -- every product term is
+//    used (the 16x16x4 shape would spend half of its work on the wrong parity) and this
+//    shape sustains close to the FP64 peak on gfx950, the 16x16 one about 60 % of it;
 //  * the waves of a block (one pair-chunk) are summed through LDS; pair-chunks write
 //    partial sums that k_adj_finalize adds in a fixed order (deterministic, no atomics).
 // Input: FUSED Tp[b][m][t] (t < N_t), folded here:
 //   G'_m(j) = Tp(j) + [1 <= j <= N_r - 2] (-1)^m Tp(N_t - j)      (D^H of Eq. 6)
 // PAPER G'[b][j][m] rows of length (N_phi/2 + 1) (output of the per-ring R2C).
 // ------------------------------------------------------------------------------------
-typedef double d4_t __attribute__((ext_vector_type(4)));
-
 constexpr int kAdjWaves = 4;     // waves per block: one block reduces up to 256 ring pairs
 constexpr int kLC = 16;          // l values per chunk = the MFMA N dimension
 constexpr int kLS = kLC + 1;     // padded row of the lam staging area
@@ -337,7 +336,7 @@ __global__ __launch_bounds__(kAdjWaves * 64) void k_legendre_adj(
     int pairs_per_block)
 {
     __shared__ double stage[kAdjWaves][64 * kLS];
-    __shared__ double dsum[kAdjWaves][256];
+    __shared__ double dsum[kAdjWaves][128];
     __shared__ float pf_sink[kAdjWaves][64];
     const int m = blockIdx.x;
     const int pc = blockIdx.y;
@@ -403,14 +402,20 @@ __global__ __launch_bounds__(kAdjWaves * 64) void k_legendre_adj(
 #pragma unroll
             for (int q = 0; q < 4; ++q) raw[b][q] = load_c(im + off[q]);
         }
+        // hv[(2 h + c) * 4 + map]: h = 0 the even combination N + S, h = 1 the odd one
+        // N - S (lam_lm(-x) = (-1)^(l+m) lam_lm(x)); c = 0 real, 1 imaginary part
         double hv[16];
 #pragma unroll
         for (int b = 0; b < 4; ++b) {
             const double use = (valid && b < nmb) ? 1.0 : 0.0;
-            hv[4 * b + 0] = use * (wgt[0] * raw[b][0].x + wgt[1] * raw[b][1].x);
-            hv[4 * b + 1] = use * (wgt[0] * raw[b][0].y + wgt[1] * raw[b][1].y);
-            hv[4 * b + 2] = use * (wgt[2] * raw[b][2].x + wgt[3] * raw[b][3].x);
-            hv[4 * b + 3] = use * (wgt[2] * raw[b][2].y + wgt[3] * raw[b][3].y);
+            const double nre = use * (wgt[0] * raw[b][0].x + wgt[1] * raw[b][1].x);
+            const double nim = use * (wgt[0] * raw[b][0].y + wgt[1] * raw[b][1].y);
+            const double sre = use * (wgt[2] * raw[b][2].x + wgt[3] * raw[b][3].x);
+            const double sim = use * (wgt[2] * raw[b][2].y + wgt[3] * raw[b][3].y);
+            hv[0 * 4 + b] = nre + sre;
+            hv[1 * 4 + b] = nim + sim;
+            hv[2 * 4 + b] = nre - sre;
+            hv[3 * 4 + b] = nim - sim;
         }
 #pragma unroll
         for (int c = 0; c < 16; ++c) st[lane * kLS + c] = hv[c];
@@ -437,7 +442,12 @@ __global__ __launch_bounds__(kAdjWaves * 64) void k_legendre_adj(
         (unsigned)(uintptr_t)(__attribute__((address_space(3))) float*)pf_sink[wave]);
 
     for (int l0 = m; l0 <= lmax; l0 += kLC) {
-        d4_t acc = {0.0, 0.0, 0.0, 0.0};
+        // D of v_mfma_f64_4x4x4_4b (measured layout: A_b[i][k] in lane i + 4 b + 16 k,
+        // B_b[k][j] in lane j + 4 b + 16 k, D_b[i][j] in lane j + 4 b + 16 i).  Here
+        // i = map, k = ring pair of the group, block b = 2 h + c (h: l parity relative to
+        // l0, c: real/imaginary part), j: l = l0 + 8 s + 2 j + h for half-chunk s.  Two
+        // accumulators per half-chunk (even/odd pair groups) keep four chains in flight.
+        double acc0 = 0.0, acc1 = 0.0, acc2 = 0.0, acc3 = 0.0;
         if (!wave_dead) {
             // the chunk's recurrence coefficients in one batch of scalar loads (the table is
             // padded past its end), and the next chunk's lines touched into L2
@@ -477,41 +487,33 @@ __global__ __launch_bounds__(kAdjWaves * 64) void k_legendre_adj(
             __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
             __builtin_amdgcn_wave_barrier();
             __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-            // B[k][j] = lam_{l0 + j}(pair 4q + k); lane = j + 16 k.  Four independent
-            // accumulator chains keep the matrix pipe busy.
-            d4_t a1 = {0.0, 0.0, 0.0, 0.0}, a2 = a1, a3 = a1;
+            {
+                const int kk = lane >> 4, bb = (lane >> 2) & 3, jj = lane & 3;
+                const int lo0 = 2 * jj + (bb >> 1), lo1 = lo0 + 8;
 #pragma unroll
-            for (int q = 0; q < 16; q += 4) {
-                const double b0 = st[(4 * q + (lane >> 4)) * kLS + (lane & 15)];
-                const double b1 = st[(4 * (q + 1) + (lane >> 4)) * kLS + (lane & 15)];
-                const double b2 = st[(4 * (q + 2) + (lane >> 4)) * kLS + (lane & 15)];
-                const double b3 = st[(4 * (q + 3) + (lane >> 4)) * kLS + (lane & 15)];
-                acc = __builtin_amdgcn_mfma_f64_16x16x4f64(aop[q], b0, acc, 0, 0, 0);
-                a1 = __builtin_amdgcn_mfma_f64_16x16x4f64(aop[q + 1], b1, a1, 0, 0, 0);
-                a2 = __builtin_amdgcn_mfma_f64_16x16x4f64(aop[q + 2], b2, a2, 0, 0, 0);
-                a3 = __builtin_amdgcn_mfma_f64_16x16x4f64(aop[q + 3], b3, a3, 0, 0, 0);
+                for (int q = 0; q < 16; q += 2) {
+                    const double* r0 = st + (4 * q + kk) * kLS;
+                    const double* r1 = st + (4 * (q + 1) + kk) * kLS;
+                    acc0 = __builtin_amdgcn_mfma_f64_4x4x4f64(aop[q], r0[lo0], acc0, 0, 0, 0);
+                    acc2 = __builtin_amdgcn_mfma_f64_4x4x4f64(aop[q], r0[lo1], acc2, 0, 0, 0);
+                    acc1 = __builtin_amdgcn_mfma_f64_4x4x4f64(aop[q + 1], r1[lo0], acc1, 0, 0, 0);
+                    acc3 = __builtin_amdgcn_mfma_f64_4x4x4f64(aop[q + 1], r1[lo1], acc3, 0, 0, 0);
+                }
             }
-            acc = acc + a1 + a2 + a3;
         }
-        // gfx950 f64 16x16 accumulator layout (measured): D[i][j] sits in lane j + 16 (i % 4),
-        // register i / 4, i.e. i = lane / 16 + 4 r, j = lane % 16
-#pragma unroll
-        for (int r = 0; r < 4; ++r) dsum[wave][((lane >> 4) + 4 * r) * 16 + (lane & 15)] = acc[r];
+        dsum[wave][lane] = acc0 + acc1;
+        dsum[wave][64 + lane] = acc2 + acc3;
         __syncthreads();
-        // combine: c_l = D[N] + (-1)^(l+m) D[S], summed over the block's waves
+        // sum over the block's waves; thread t -> half-chunk t / 64, D lane t % 64
         for (int t = threadIdx.x; t < 128; t += blockDim.x) {
-            const int jj = t & 15;
-            const int comp = (t >> 4) & 1;
-            const int b = t >> 5;
-            const int l = l0 + jj;
+            const int d = t & 63;
+            const int b = d >> 4;              // map
+            const int blk = (d >> 2) & 3;      // 2 h + c
+            const int l = l0 + 8 * (t >> 6) + 2 * (d & 3) + (blk >> 1);
             if (l > lmax || b >= nmb) continue;
-            double n = 0.0, so = 0.0;
-            for (int w = 0; w < nwaves; ++w) {
-                n += dsum[w][(4 * b + comp) * 16 + jj];
-                so += dsum[w][(4 * b + 2 + comp) * 16 + jj];
-            }
-            const double v = ((l - m) & 1) ? n - so : n + so;
-            part[(((int64_t)(grp * npc + pc) * 4 + b) * nalm + moff + l) * 2 + comp] = v;
+            double v = 0.0;
+            for (int w = 0; w < nwaves; ++w) v += dsum[w][t];
+            part[(((int64_t)(grp * npc + pc) * 4 + b) * nalm + moff + l) * 2 + (blk & 1)] = v;
         }
         __syncthreads();
     }

@@ -287,6 +287,10 @@ int ensure_capacity(nusht_plan_s* p, int nmaps)
     NUSHT_TRY(dmalloc((char**)&p->Z, zbytes > 0 ? zbytes : 256));
     p->Xbytes = p->Ybytes = per * nmaps;
     p->Zbytes = zbytes;
+    if (!p->W) {
+        NUSHT_TRY(dmalloc((char**)&p->W, fine_spec));
+        p->Wbytes = fine_spec;
+    }
     p->bcap = nmaps;
     return NUSHT_OK;
 }
@@ -549,14 +553,16 @@ void nusht_destroy(nusht_plan_t p)
     destroy_fft_plans(p);
     void* bufs[] = {p->rec,  p->cm_mant, p->cm_exp,   p->dec1,      p->dec2,      p->dec1f,
                     p->dec2f, p->sth,    p->sph,      p->perm,      p->slot_off,  p->slot_tile,
-                    p->tile_slot, p->dflag, p->X,     p->Y,         p->Z,         p->fftwork,
+                    p->tile_slot, p->dflag, p->X,     p->Y,         p->Z,         p->W,
+                    p->fftwork,
                     p->red,      p->jlive};
     for (void* b : bufs)
         if (b) hipFree(b);
-    for (int i = 0; i < ST_COUNT; ++i) {
-        if (p->ev[i][0]) hipEventDestroy(p->ev[i][0]);
-        if (p->ev[i][1]) hipEventDestroy(p->ev[i][1]);
-    }
+    for (int c = 0; c < nusht_plan_s::kTimingSlots; ++c)
+        for (int i = 0; i < ST_COUNT; ++i) {
+            if (p->ev[c][i][0]) hipEventDestroy(p->ev[c][i][0]);
+            if (p->ev[c][i][1]) hipEventDestroy(p->ev[c][i][1]);
+        }
     hipSetDevice(cur);
     delete p;
 }
@@ -588,10 +594,15 @@ int nusht_plan_ex(int lmax, int mmax, int64_t npts, const double* theta, const d
         p->g.ntiles_used = p->nslots;
         if ((rc = create_fft_plans(p))) break;
         if (p->timing) {
-            for (int i = 0; i < ST_COUNT; ++i) {
-                if (hipEventCreate(&p->ev[i][0]) != hipSuccess ||
-                    hipEventCreate(&p->ev[i][1]) != hipSuccess) { rc = NUSHT_EDEVICE; break; }
-            }
+            for (int c = 0; c < nusht_plan_s::kTimingSlots && rc == NUSHT_OK; ++c)
+                for (int i = 0; i < ST_COUNT; ++i) {
+                    if (hipEventCreate(&p->ev[c][i][0]) != hipSuccess ||
+                        hipEventCreate(&p->ev[c][i][1]) != hipSuccess) {
+                        rc = NUSHT_EDEVICE;
+                        break;
+                    }
+                }
+            if (rc != NUSHT_OK) break;
         }
     } while (0);
     if (rc != NUSHT_OK) {

@@ -166,6 +166,13 @@ extern "C" {
 int nusht_solve(nusht_plan_t p, const double* map, double* alm, const float* weights, double tol,
                 int maxiter, int* iters, double* relres, void* stream)
 {
+    return nusht_solve_ex(p, map, alm, weights, tol, maxiter, iters, relres, nullptr, stream);
+}
+
+int nusht_solve_ex(nusht_plan_t p, const double* map, double* alm, const float* weights,
+                   double tol, int maxiter, int* iters, double* relres, double* history,
+                   void* stream)
+{
     if (!p || !map || !alm || !(tol > 0.0) || maxiter < 0) {
         set_last_error("nusht_solve", "null plan/buffer, tol <= 0 or maxiter < 0");
         return NUSHT_EINVAL;
@@ -233,6 +240,7 @@ int nusht_solve(nusht_plan_t p, const double* map, double* alm, const float* wei
     NUSHT_TRY(read_scalar(SC_RR, &rr));
     if (dn2 == 0.0) dn2 = 1.0;  // d = 0: report the absolute residual
     int it = 0;
+    if (history) history[0] = std::sqrt(rr / dn2);
     const double tol2 = tol * tol;
     while (rr > tol2 * dn2 && it < maxiter) {
         NUSHT_TRY(nusht_synthesis(p, reinterpret_cast<const double*>(b.p), b.q, 1, stream));
@@ -249,6 +257,7 @@ int nusht_solve(nusht_plan_t p, const double* map, double* alm, const float* wei
         NUSHT_HIP(hipGetLastError());
         NUSHT_TRY(read_scalar(SC_RR, &rr));
         ++it;
+        if (history) history[it] = std::sqrt(rr / dn2);
     }
     // true residual of the final iterate
     NUSHT_TRY(nusht_synthesis(p, alm, b.q, 1, stream));

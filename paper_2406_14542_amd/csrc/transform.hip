@@ -118,9 +118,9 @@ int create_fft_plans(nusht_plan_s* p)
     const size_t fw = (size_t)g.n2 / 2 + 1;
     const size_t ncol = (size_t)g.mmax + 1;
     NUSHT_TRY(make_fft_1d(p->fine_col_inv, rocfft_transform_type_complex_inverse, prec, g.n1,
-                          ncol, fw, 1, fw, 1, rocfft_placement_inplace));
+                          ncol, 1, g.n1, 1, g.n1, rocfft_placement_inplace));
     NUSHT_TRY(make_fft_1d(p->fine_col_fwd, rocfft_transform_type_complex_forward, prec, g.n1,
-                          ncol, fw, 1, fw, 1, rocfft_placement_inplace));
+                          ncol, 1, g.n1, 1, g.n1, rocfft_placement_inplace));
     NUSHT_TRY(make_fft_1d(p->fine_rowa_c2r, rocfft_transform_type_real_inverse, prec, g.n2,
                           p->fine_ra, 1, fw, 1, g.n2, rocfft_placement_notinplace));
     NUSHT_TRY(make_fft_1d(p->fine_rowa_r2c, rocfft_transform_type_real_forward, prec, g.n2,
@@ -207,14 +207,14 @@ int fft_exec(nusht_plan_s* p, FftPlan& f, void* in, void* out, hipStream_t s)
 void stage_begin(nusht_plan_s* p, Stage st, hipStream_t s)
 {
     if (!p->timing) return;
-    hipEventRecord(p->ev[st][0], s);
-    p->ev_used[st] = 1;
+    hipEventRecord(p->ev[p->cur][st][0], s);
+    p->ev_used[p->cur][st] = 1;
 }
 
 void stage_end(nusht_plan_s* p, Stage st, hipStream_t s)
 {
     if (!p->timing) return;
-    hipEventRecord(p->ev[st][1], s);
+    hipEventRecord(p->ev[p->cur][st][1], s);
 }
 
 namespace {
@@ -234,52 +234,61 @@ struct DeviceGuard {
     }
 };
 
-void reset_timing(nusht_plan_s* p)
+// start of an execution call of the given kind: take the next timing slot
+void begin_call(nusht_plan_s* p, int kind)
 {
-    for (int i = 0; i < ST_COUNT; ++i) p->ev_used[i] = 0;
+    if (!p->timing) return;
+    p->cur = (int)(p->ncalls % nusht_plan_s::kTimingSlots);
+    ++p->ncalls;
+    p->slot_kind[p->cur] = kind;
+    for (int i = 0; i < ST_COUNT; ++i) p->ev_used[p->cur][i] = 0;
 }
 
 inline char* bytes(void* v) { return reinterpret_cast<char*>(v); }
 
 // fine grid (real) of map b and its half spectrum, in elements of the plan's precision
 size_t fine_real_bytes(const nusht_plan_s* p) { return (size_t)p->g.n1 * p->g.n2 * fine_elem_bytes(p); }
-size_t fine_spec_bytes(const nusht_plan_s* p)
+// band spectrum [mmax+1][n1] of one map
+size_t fine_band_bytes(const nusht_plan_s* p)
 {
-    return (size_t)p->g.n1 * (p->g.n2 / 2 + 1) * 2 * fine_elem_bytes(p);
+    return (size_t)(p->g.mmax + 1) * p->g.n1 * 2 * fine_elem_bytes(p);
 }
 
-// Fine half spectrum -> fine grid of one map (N(ii)): theta pass in place over the band
-// columns, then the phi pass into the rows the point windows read.  Columns above mmax of
-// those rows must hold zeros on entry.  Other rows of the grid are left untouched.
-int fine_c2r(nusht_plan_s* p, char* spec, char* real, hipStream_t s)
+// Band spectrum -> fine grid of one map (N(ii)): theta pass in place over the band, transpose
+// into the row spectrum of the window rows (p->W), phi pass into those rows of the grid.
+// Other rows of the grid are left untouched (no window reads them).
+int fine_c2r(nusht_plan_s* p, char* band, char* real, hipStream_t s)
 {
     const nusht_geometry& g = p->g;
     const size_t e = fine_elem_bytes(p);
     const size_t fw = (size_t)g.n2 / 2 + 1;
-    NUSHT_TRY(fft_exec(p, p->fine_col_inv, spec, nullptr, s));
-    NUSHT_TRY(fft_exec(p, p->fine_rowa_c2r, spec, real, s));
+    char* rows = bytes(p->W);
+    NUSHT_TRY(fft_exec(p, p->fine_col_inv, band, nullptr, s));
+    NUSHT_TRY(launch_band_to_rows(p, band, rows, s));
+    NUSHT_TRY(fft_exec(p, p->fine_rowa_c2r, rows, real, s));
     if (p->fine_rb > 0) {
         const size_t r0 = (size_t)g.n1 - p->fine_rb;
-        NUSHT_TRY(fft_exec(p, p->fine_rowb_c2r, spec + r0 * fw * 2 * e, real + r0 * g.n2 * e, s));
+        NUSHT_TRY(fft_exec(p, p->fine_rowb_c2r, rows + r0 * fw * 2 * e, real + r0 * g.n2 * e, s));
     }
     return NUSHT_OK;
 }
 
-// Fine grid -> half spectrum of one map (N^H(ii)), reading only the rows the point windows
-// write: phi pass over those rows, zero band columns of the other rows, theta pass in place
-// over the band columns.  Columns above mmax are not produced.
-int fine_r2c(nusht_plan_s* p, char* real, char* spec, hipStream_t s)
+// Fine grid -> band spectrum of one map (N^H(ii)), reading only the window rows: phi pass
+// over those rows into p->W, transpose into the band (zeros for the other rows), theta pass
+// in place.
+int fine_r2c(nusht_plan_s* p, char* real, char* band, hipStream_t s)
 {
     const nusht_geometry& g = p->g;
     const size_t e = fine_elem_bytes(p);
     const size_t fw = (size_t)g.n2 / 2 + 1;
-    NUSHT_TRY(fft_exec(p, p->fine_rowa_r2c, real, spec, s));
+    char* rows = bytes(p->W);
+    NUSHT_TRY(fft_exec(p, p->fine_rowa_r2c, real, rows, s));
     if (p->fine_rb > 0) {
         const size_t r0 = (size_t)g.n1 - p->fine_rb;
-        NUSHT_TRY(fft_exec(p, p->fine_rowb_r2c, real + r0 * g.n2 * e, spec + r0 * fw * 2 * e, s));
+        NUSHT_TRY(fft_exec(p, p->fine_rowb_r2c, real + r0 * g.n2 * e, rows + r0 * fw * 2 * e, s));
     }
-    NUSHT_TRY(launch_zero_band_rows(p, spec, p->fine_ra, g.n1 - p->fine_rb, s));
-    NUSHT_TRY(fft_exec(p, p->fine_col_fwd, spec, nullptr, s));
+    NUSHT_TRY(launch_rows_to_band(p, rows, band, s));
+    NUSHT_TRY(fft_exec(p, p->fine_col_fwd, band, nullptr, s));
     return NUSHT_OK;
 }
 
@@ -322,7 +331,7 @@ int synthesis_to_fine(nusht_plan_s* p, const double* alm, int nmaps, hipStream_t
         stage_end(p, ST_DECONV, s);
         stage_begin(p, ST_FINE_FFT, s);
         for (int b = 0; b < nmaps; ++b)
-            NUSHT_TRY(fine_c2r(p, bytes(p->Y) + b * fine_spec_bytes(p),
+            NUSHT_TRY(fine_c2r(p, bytes(p->Y) + b * fine_band_bytes(p),
                                bytes(p->X) + b * fine_real_bytes(p), s));
         stage_end(p, ST_FINE_FFT, s);
         *fine_out = p->X;
@@ -343,7 +352,7 @@ int synthesis_to_fine(nusht_plan_s* p, const double* alm, int nmaps, hipStream_t
         stage_end(p, ST_DECONV, s);
         stage_begin(p, ST_FINE_FFT, s);
         for (int b = 0; b < nmaps; ++b)
-            NUSHT_TRY(fine_c2r(p, bytes(p->X) + b * fine_spec_bytes(p),
+            NUSHT_TRY(fine_c2r(p, bytes(p->X) + b * fine_band_bytes(p),
                                bytes(p->Y) + b * fine_real_bytes(p), s));
         stage_end(p, ST_FINE_FFT, s);
         *fine_out = p->Y;
@@ -377,7 +386,7 @@ int nusht_synthesis(nusht_plan_t p, const double* alm, double* map, int nmaps, v
     DeviceGuard dg(p->device);
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
     NUSHT_TRY(ensure_capacity(p, nmaps));
-    reset_timing(p);
+    begin_call(p, NUSHT_CALL_SYNTHESIS);
     void* fine = nullptr;
     NUSHT_TRY(synthesis_to_fine(p, alm, nmaps, s, &fine));
     stage_begin(p, ST_POINTS, s);
@@ -401,7 +410,7 @@ int nusht_synthesis_deriv(nusht_plan_t p, const double* alm, double* map, double
     DeviceGuard dg(p->device);
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
     NUSHT_TRY(ensure_capacity(p, nmaps));
-    reset_timing(p);
+    begin_call(p, NUSHT_CALL_SYNTHESIS_DERIV);
     void* fine = nullptr;
     NUSHT_TRY(synthesis_to_fine(p, alm, nmaps, s, &fine));
     stage_begin(p, ST_POINTS, s);
@@ -417,7 +426,7 @@ int nusht_adjoint(nusht_plan_t p, const double* map, double* alm, int nmaps, voi
     DeviceGuard dg(p->device);
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
     NUSHT_TRY(ensure_capacity(p, nmaps));
-    reset_timing(p);
+    begin_call(p, NUSHT_CALL_ADJOINT);
     const nusht_geometry& g = p->g;
     const int f32 = g.dtype == NUSHT_MIXED;
     const size_t e = fine_elem_bytes(p);
@@ -456,7 +465,7 @@ int nusht_adjoint(nusht_plan_t p, const double* map, double* alm, int nmaps, voi
     stage_begin(p, ST_FINE_FFT, s);
     for (int b = 0; b < nmaps; ++b)
         NUSHT_TRY(fine_r2c(p, bytes(p->X) + b * fine_real_bytes(p),
-                           bytes(p->Y) + b * fine_spec_bytes(p), s));
+                           bytes(p->Y) + b * fine_band_bytes(p), s));
     stage_end(p, ST_FINE_FFT, s);
     if (g.dfs_mode == NUSHT_DFS_FUSED) {
         stage_begin(p, ST_DECONV, s);
@@ -505,7 +514,7 @@ int nusht_ring_synthesis(nusht_plan_t p, const double* alm, double* ring, int nm
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
     NUSHT_TRY(ensure_ring_plans(p));
     NUSHT_TRY(ensure_capacity(p, nmaps));
-    reset_timing(p);
+    begin_call(p, NUSHT_CALL_RING);
     return ring_synthesis_into(p, alm, ring, p->X, nmaps, s);
 }
 
@@ -516,7 +525,7 @@ int nusht_ring_adjoint(nusht_plan_t p, const double* ring, double* alm, int nmap
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
     NUSHT_TRY(ensure_ring_plans(p));
     NUSHT_TRY(ensure_capacity(p, nmaps));
-    reset_timing(p);
+    begin_call(p, NUSHT_CALL_RING);
     const nusht_geometry& g = p->g;
     const size_t rstride = (size_t)g.nrings * g.nphi * 8;
     const size_t gstride = (size_t)g.nrings * (g.nphi / 2 + 1) * 16;
@@ -532,25 +541,62 @@ int nusht_ring_adjoint(nusht_plan_t p, const double* ring, double* alm, int nmap
     return NUSHT_OK;
 }
 
+static const char* kStageNames[ST_COUNT] = {"legendre", "ring_fft", "double_fold", "torus_fft",
+                                            "deconv", "fine_fft", "points", "halo"};
+
 int nusht_stage_times(nusht_plan_t p, double* ms, const char** names, int maxn)
 {
-    static const char* kNames[ST_COUNT] = {"legendre", "ring_fft", "double_fold", "torus_fft",
-                                           "deconv", "fine_fft", "points", "halo"};
     if (!p || !ms || maxn < 0) return NUSHT_EINVAL;
-    if (!p->timing) return 0;
+    if (!p->timing || p->ncalls == 0) return 0;
+    const int c = p->cur;
     int n = 0;
     for (int i = 0; i < ST_COUNT && n < maxn; ++i) {
         float t = 0.0f;
-        if (p->ev_used[i]) {
-            if (hipEventSynchronize(p->ev[i][1]) != hipSuccess ||
-                hipEventElapsedTime(&t, p->ev[i][0], p->ev[i][1]) != hipSuccess)
+        if (p->ev_used[c][i]) {
+            if (hipEventSynchronize(p->ev[c][i][1]) != hipSuccess ||
+                hipEventElapsedTime(&t, p->ev[c][i][0], p->ev[c][i][1]) != hipSuccess)
                 t = -1.0f;
         }
-        ms[n] = p->ev_used[i] ? (double)t : 0.0;
-        if (names) names[n] = kNames[i];
+        ms[n] = p->ev_used[c][i] ? (double)t : 0.0;
+        if (names) names[n] = kStageNames[i];
         ++n;
     }
     return n;
+}
+
+int nusht_stage_stats(nusht_plan_t p, int kind, double* ms, int* ncalls, const char** names,
+                      int maxn)
+{
+    if (!p || !ms || maxn < 0) return NUSHT_EINVAL;
+    if (!p->timing) return 0;
+    const int nslot = (int)(p->ncalls < nusht_plan_s::kTimingSlots ? p->ncalls
+                                                                   : nusht_plan_s::kTimingSlots);
+    int n = 0;
+    for (int i = 0; i < ST_COUNT && n < maxn; ++i) {
+        double sum = 0.0;
+        int cnt = 0;
+        for (int c = 0; c < nslot; ++c) {
+            if (p->slot_kind[c] != kind || !p->ev_used[c][i]) continue;
+            float t = 0.0f;
+            if (hipEventSynchronize(p->ev[c][i][1]) != hipSuccess ||
+                hipEventElapsedTime(&t, p->ev[c][i][0], p->ev[c][i][1]) != hipSuccess) {
+                set_last_error("nusht_stage_stats", "event query failed");
+                return NUSHT_EDEVICE;
+            }
+            sum += t;
+            ++cnt;
+        }
+        ms[n] = cnt ? sum / cnt : 0.0;
+        if (ncalls) ncalls[n] = cnt;
+        if (names) names[n] = kStageNames[i];
+        ++n;
+    }
+    return n;
+}
+
+void nusht_stage_reset(nusht_plan_t p)
+{
+    if (p) p->ncalls = 0;
 }
 
 }  // extern "C"

@@ -182,3 +182,28 @@ def test_plan_rejects_bad_points(P):
     ph = np.array([0.0, np.nan])
     with pytest.raises(P.NushtError):
         P.Plan(10, 10, dev(th), dev(ph), 1e-8)
+
+
+def test_stage_timing_ring(P):
+    """Per-call stage events: averages per call kind over exactly the calls since reset,
+    and results unchanged by timing."""
+    rng = np.random.default_rng(77)
+    L = 40
+    th, ph = inputs.uniform_points(rng, 5000)
+    a = dev(inputs.red_alm(rng, L, L, 2))
+    pl = P.Plan(L, L, dev(th), dev(ph), 1e-10, timing=True)
+    ref = P.Plan(L, L, dev(th), dev(ph), 1e-10)
+    f = pl.synthesis(a)
+    pl.stage_reset()
+    for _ in range(3):
+        f = pl.synthesis(a)
+    for _ in range(2):
+        c = pl.adjoint(f)
+    syn = pl.stage_stats("synthesis")
+    adj = pl.stage_stats("adjoint")
+    assert syn["legendre"][1] == 3 and syn["points"][1] == 3 and syn["fine_fft"][1] == 3
+    assert adj["legendre"][1] == 2 and adj["halo"][1] == 2 and "halo" not in syn
+    assert all(v[0] > 0 for v in syn.values()) and all(v[0] > 0 for v in adj.values())
+    assert np.array_equal(f.cpu().numpy(), ref.synthesis(a).cpu().numpy())
+    last = pl.stage_times()
+    assert last["legendre"] > 0 and last["halo"] > 0
