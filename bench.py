@@ -212,7 +212,20 @@ def main():
     ap.add_argument("--cg-steps", type=int, default=200)
     ap.add_argument("--cg-lr", type=float, default=1e-3)
     ap.add_argument("--cg-seed", type=int, default=7)
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
+                    help="only run one elementwise device copy of BYTES bytes (the reference "
+                         "kernel that scales HBM byte counters)")
     args = ap.parse_args()
+    if args.copy_calibration:
+        import torch
+        n = args.copy_calibration // 4
+        x = torch.ones(n, dtype=torch.float32, device="cuda")
+        y = torch.empty_like(x)
+        torch.cuda.synchronize()
+        torch.add(x, 0.0, out=y)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_read": 4 * n, "copy_bytes_written": 4 * n}), flush=True)
+        return
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported",
               file=sys.stderr)
@@ -265,9 +278,18 @@ def main():
                               achieved=by / (st["points"] * 1e-3) / 1e9, peak=HBM_PEAK_GBS,
                               unit="GB/s"))
     dom = max(cands, key=lambda c: c["ms"])
+    # measured HBM bytes per launch of that kernel (rocprofv3 FETCH_SIZE / WRITE_SIZE runs,
+    # scaled by a copy kernel; see profiles/c3_pmc_counters.md), when they are on record
+    # for the kernel as it stands
+    traffic = None
+    tfile = os.path.join(ROOT, "profiles", "c3_traffic.json")
+    if args.workload == "c3" and os.path.exists(tfile):
+        rec = json.load(open(tfile)).get("kernels", {}).get(dom["kernel"])
+        if rec:
+            traffic = round(rec["hbm_bytes"], -6)
     roofline = {"bound": dom["bound"], "achieved": round(dom["achieved"], 3),
                 "peak": dom["peak"], "unit": dom["unit"],
-                "frac": round(dom["achieved"] / dom["peak"], 4), "traffic": None,
+                "frac": round(dom["achieved"] / dom["peak"], 4), "traffic": traffic,
                 "kernel": dom["kernel"], "ms_per_launch": round(dom["ms"], 4),
                 "algorithmic_work_per_launch": dom["work"]}
     others = {c["kernel"]: {"ms": round(c["ms"], 4), "achieved": round(c["achieved"], 3),
