@@ -86,6 +86,7 @@ struct nusht_plan_s {
     double* cm_mant = nullptr;   // [mmax+1]: lam_mm prefactor mantissa, sign (-1)^m included
     int* cm_exp = nullptr;       // [mmax+1]: its power-of-two exponent
     int* jlive = nullptr;        // [mmax+1]: first ring pair with any lam_lm above 2^-300
+    int* jscale = nullptr;       // [mmax+1]: first ring pair with lam_mm above 2^-190
     std::vector<int> jlive_host;
 
     // Deconvolution factors (include the FFT normalisation of the torus transform).
@@ -98,6 +99,7 @@ struct nusht_plan_s {
     double* sth = nullptr;       // [npts] theta, sorted by tile
     double* sph = nullptr;       // [npts] phi mod 2 pi, sorted by tile
     int* perm = nullptr;         // [npts] user index of each sorted point
+    int* iperm = nullptr;        // [npts] sorted position of each user index
     int* slot_off = nullptr;     // [nslots+1] first sorted point of each slot
     int* slot_tile = nullptr;    // [nslots] tile id of each slot
     int* tile_slot = nullptr;    // [ntiles] slot of each tile or -1
@@ -114,6 +116,7 @@ struct nusht_plan_s {
     size_t Ybytes = 0;
     void* W = nullptr;           // one map's fine row spectrum [n1][n2/2+1]
     size_t Wbytes = 0;
+    double* V = nullptr;         // FP64 adjoint input of one point group, sorted [npts][4]
     void* Z = nullptr;           // spreading subgrids
     size_t Zbytes = 0;
     void* fftwork = nullptr;

@@ -159,22 +159,44 @@ __device__ inline OutT make_out(double re, double im)
     return o;
 }
 
+// XCD-aware placement: workgroups are handed to the 8 XCDs round-robin by linear id, and
+// every XCD has its own L2.  Block id b = 8 q + x goes to XCD x; the q-th block of XCD x
+// gets (m, ring block) = (8 (q / nbx) + x, q % nbx), so all nbx ring blocks of one m run
+// on the same XCD at about the same time and fetch that m's coefficient stream into one
+// L2 once.  The grid is (nbx * mpad, groups) with mpad = mmax + 1 rounded up to 8.
+__device__ inline void xcd_block(int b, int nbx, int& m, int& rb)
+{
+    const int x = b & 7, q = b >> 3;
+    m = 8 * (q / nbx) + x;
+    rb = q % nbx;
+}
+
 // Each lane owns R ring pairs j = base + lane + 64 r; a wave therefore covers 64 R
 // consecutive pairs and loads every coefficient once for all of them.
-template <int MB, int R, bool FUSED, typename OutT>
+//
+// The kernel comes in two instances over the same grid.  Ring pairs j >= jscale[m] have
+// lam_mm above 2^-190, so none of their lam_lm ever needs the power-of-two scale; a wave
+// made only of such pairs runs the SCALED = false instance, which has no scaled step at
+// all (the scaled step's extra live registers would otherwise cost the whole kernel almost
+// half of its occupancy).  Every other live wave runs SCALED = true.
+template <int MB, int R, bool FUSED, typename OutT, bool SCALED>
 __global__ __launch_bounds__(256) void k_legendre_synth(
-    const double2* __restrict__ alm, int64_t nalm, int lmax,
+    const double2* __restrict__ alm, int64_t nalm, int lmax, int mmax, int nbx,
     const double2* __restrict__ rec, const double* __restrict__ cm_mant,
-    const int* __restrict__ cm_exp, const int* __restrict__ jlive, int nr, int nt,
-    OutT* __restrict__ out, int64_t out_map_stride, int64_t out_row_stride)
+    const int* __restrict__ cm_exp, const int* __restrict__ jlive,
+    const int* __restrict__ jscale, int nr, int nt, OutT* __restrict__ out,
+    int64_t out_map_stride, int64_t out_row_stride)
 {
-    const int m = blockIdx.y;
+    int m, rb;
+    xcd_block(blockIdx.x, nbx, m, rb);
+    if (m > mmax) return;
     const int npairs = (nr + 1) / 2;
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const int wbase = (blockIdx.x * (blockDim.x >> 6) + wave) * 64 * R;
+    const int wbase = (rb * (blockDim.x >> 6) + wave) * 64 * R;
     if (wbase >= npairs) return;
-    alm += (int64_t)blockIdx.z * MB * nalm;
-    out += (int64_t)blockIdx.z * MB * out_map_stride;
+    if (SCALED != (wbase < jscale[m])) return;  // the other instance owns this wave
+    alm += (int64_t)blockIdx.y * MB * nalm;
+    out += (int64_t)blockIdx.y * MB * out_map_stride;
     const int64_t moff = (int64_t)m * (2 * lmax + 1 - m) / 2;  // index(l, m) = moff + l
     const bool wave_dead = wbase + 64 * R <= jlive[m];
     __shared__ float pf_sink[4][64];
@@ -196,13 +218,19 @@ __global__ __launch_bounds__(256) void k_legendre_synth(
             ring_geom(j, nr, s, y[r]);
             vp[r] = 0.0;
             lambda_mm_scaled(cm_mant[m], cm_exp[m], s, m, vc[r], k[r]);
+            if (!SCALED && k[r] != 0) {
+                // cannot happen above jscale (10 bits of margin); drop rather than misuse
+                vc[r] = 0.0;
+                k[r] = 0;
+            }
             if (k[r] == 0) accum<MB>(E[r], alm, nalm, moff + m, vc[r]);
             any_scaled |= k[r] > 0;
         }
-        int l = m + 1;
-        // scaled phase: some lane of the wave still carries a 2^256 factor
-        while (l <= lmax && __any(any_scaled)) {
-            const double2 c = rec[moff + l];
+        // Steps run in (even, odd) pairs of l - m after the first (odd) one, so that the
+        // accumulator of every step is static.  While some lane of the wave still carries a
+        // 2^256 factor the wave takes the scaled step; the branch is wave-uniform and both
+        // sides update the same accumulators in place.
+        auto scaled_step = [&](const double2 c, int64_t idx, double (&A)[R][MB][2]) {
             any_scaled = false;
 #pragma unroll
             for (int r = 0; r < R; ++r) {
@@ -215,24 +243,24 @@ __global__ __launch_bounds__(256) void k_legendre_synth(
                 vp[r] *= sc;
                 k[r] -= big ? 1 : 0;
                 any_scaled |= k[r] > 0;
-                const double lam = (k[r] == 0) ? vc[r] : 0.0;
-                if ((l - m) & 1)
-                    accum<MB>(O[r], alm, nalm, moff + l, lam);
-                else
-                    accum<MB>(E[r], alm, nalm, moff + l, lam);
+                accum<MB>(A[r], alm, nalm, idx, (k[r] == 0) ? vc[r] : 0.0);
             }
-            ++l;
-        }
-        // plain phase, two steps at a time so that the parity of l - m is static
-        if (l <= lmax && ((l - m) & 1)) {
-            const double2 c = rec[moff + l];
+        };
+        auto plain_step = [&](const double2 c, int64_t idx, double (&A)[R][MB][2]) {
 #pragma unroll
             for (int r = 0; r < R; ++r) {
                 const double vn = rec_step(c, y[r], vc[r], vp[r]);
                 vp[r] = vc[r];
                 vc[r] = vn;
-                accum<MB>(O[r], alm, nalm, moff + l, vc[r]);
+                accum<MB>(A[r], alm, nalm, idx, vc[r]);
             }
+        };
+        int l = m + 1;
+        if (l <= lmax) {
+            if (SCALED && __any(any_scaled))
+                scaled_step(rec[moff + l], moff + l, O);
+            else
+                plain_step(rec[moff + l], moff + l, O);
             ++l;
         }
         int pf_at = l;
@@ -246,25 +274,19 @@ __global__ __launch_bounds__(256) void k_legendre_synth(
                 pf_at = l + kPfStep;
             }
             const double2 c0 = rec[moff + l], c1 = rec[moff + l + 1];
-#pragma unroll
-            for (int r = 0; r < R; ++r) {
-                double vn = rec_step(c0, y[r], vc[r], vp[r]);
-                vp[r] = vc[r];
-                vc[r] = vn;
-                accum<MB>(E[r], alm, nalm, moff + l, vc[r]);
-                vn = rec_step(c1, y[r], vc[r], vp[r]);
-                vp[r] = vc[r];
-                vc[r] = vn;
-                accum<MB>(O[r], alm, nalm, moff + l + 1, vc[r]);
+            if (SCALED && __any(any_scaled)) {
+                scaled_step(c0, moff + l, E);
+                scaled_step(c1, moff + l + 1, O);
+            } else {
+                plain_step(c0, moff + l, E);
+                plain_step(c1, moff + l + 1, O);
             }
         }
         if (l <= lmax) {
-            const double2 c = rec[moff + l];
-#pragma unroll
-            for (int r = 0; r < R; ++r) {
-                const double vn = rec_step(c, y[r], vc[r], vp[r]);
-                accum<MB>(E[r], alm, nalm, moff + l, vn);
-            }
+            if (SCALED && __any(any_scaled))
+                scaled_step(rec[moff + l], moff + l, E);
+            else
+                plain_step(rec[moff + l], moff + l, E);
         }
         // no LDS-DMA write may be in flight when the workgroup's LDS is released
         asm volatile("s_waitcnt vmcnt(0)" ::"v"(pf_keep) : "memory");
@@ -319,6 +341,7 @@ __global__ __launch_bounds__(256) void k_legendre_synth(
 constexpr int kAdjWaves = 4;     // waves per block: one block reduces up to 256 ring pairs
 constexpr int kLC = 16;          // l values per chunk = the MFMA N dimension
 constexpr int kLS = kLC + 1;     // padded row of the lam staging area
+constexpr int kAdjGroup = 4;     // chunks whose D values are summed over waves together
 
 template <typename InT>
 __device__ inline double2 load_c(const InT* p)
@@ -328,16 +351,18 @@ __device__ inline double2 load_c(const InT* p)
 }
 
 template <bool FUSED, typename InT>
-__global__ __launch_bounds__(kAdjWaves * 64) void k_legendre_adj(
+__global__ __launch_bounds__(kAdjWaves * 64, 4) void k_legendre_adj(
     const InT* __restrict__ in, int64_t in_map_stride, int64_t in_row_stride, int nmaps,
     double* __restrict__ part, int npc, int64_t nalm, int lmax,
     const double2* __restrict__ rec, const double* __restrict__ cm_mant,
     const int* __restrict__ cm_exp, const int* __restrict__ jlive, int nr, int nt,
     int pairs_per_block)
 {
+    // per wave: the lam values of one chunk (64 pairs x 16 l), and after the MFMAs of a
+    // group of kAdjGroup chunks the wave's D values of those chunks (kAdjGroup x 128)
     __shared__ double stage[kAdjWaves][64 * kLS];
-    __shared__ double dsum[kAdjWaves][128];
     __shared__ float pf_sink[kAdjWaves][64];
+    static_assert(kAdjGroup * 128 <= 64 * kLS, "D values of a chunk group fit the staging area");
     const int m = blockIdx.x;
     const int pc = blockIdx.y;
     const int grp = blockIdx.z;
@@ -366,7 +391,9 @@ __global__ __launch_bounds__(kAdjWaves * 64) void k_legendre_adj(
             }
         return;
     }
-    const bool wave_dead = pc * pairs_per_block + wave * 64 + 64 <= jl;
+    // a wave is dead when all its pairs lie below the live-ring bound or beyond the pairs
+    const int wfirst = pc * pairs_per_block + wave * 64;
+    const bool wave_dead = wfirst + 64 <= jl || wave * 64 >= pairs_per_block || wfirst >= npairs;
 
     // ring data of this lane's pair: rows 4 b + {N re, N im, S re, S im}.  All loads are
     // issued before any is used (indices clamped into range, unused ones weighted by 0).
@@ -441,78 +468,106 @@ __global__ __launch_bounds__(kAdjWaves * 64) void k_legendre_adj(
     const unsigned lds_sink = __builtin_amdgcn_readfirstlane(
         (unsigned)(uintptr_t)(__attribute__((address_space(3))) float*)pf_sink[wave]);
 
-    for (int l0 = m; l0 <= lmax; l0 += kLC) {
-        // D of v_mfma_f64_4x4x4_4b (measured layout: A_b[i][k] in lane i + 4 b + 16 k,
-        // B_b[k][j] in lane j + 4 b + 16 k, D_b[i][j] in lane j + 4 b + 16 i).  Here
-        // i = map, k = ring pair of the group, block b = 2 h + c (h: l parity relative to
-        // l0, c: real/imaginary part), j: l = l0 + 8 s + 2 j + h for half-chunk s.  Two
-        // accumulators per half-chunk (even/odd pair groups) keep four chains in flight.
-        double acc0 = 0.0, acc1 = 0.0, acc2 = 0.0, acc3 = 0.0;
-        if (!wave_dead) {
-            // the chunk's recurrence coefficients in one batch of scalar loads (the table is
-            // padded past its end), and the next chunk's lines touched into L2
-            double2 cc[kLC];
+    // D of v_mfma_f64_4x4x4_4b (measured layout: A_b[i][k] in lane i + 4 b + 16 k,
+    // B_b[k][j] in lane j + 4 b + 16 k, D_b[i][j] in lane j + 4 b + 16 i).  Here i = map,
+    // k = ring pair of the group, block b = 2 h + c (h: l parity relative to l0, c: real or
+    // imaginary part), j: l = l0 + 8 s + 2 j + h for half-chunk s.  Two accumulators per
+    // half-chunk (even/odd pair groups) keep four chains in flight.
+    const int kk = lane >> 4, bb = (lane >> 2) & 3, jj = lane & 3;
+    const int lo0 = 2 * jj + (bb >> 1), lo1 = lo0 + 8;
+    const int nchunks = (lmax - m) / kLC + 1;
+    for (int c0 = 0; c0 < nchunks; c0 += kAdjGroup) {
+        double dv[kAdjGroup][2];
 #pragma unroll
-            for (int i = 0; i < kLC; ++i) cc[i] = rec[moff + l0 + i];
-            if (lane < 3 && l0 + kLC <= lmax)
-                pf_keep ^= lds_dma_touch(rec + moff + l0 + kLC + 8 * lane, lds_sink);
-            double lam[kLC];
-            const bool wscaled = __any(scaled);
+        for (int g = 0; g < kAdjGroup; ++g) {
+            double acc0 = 0.0, acc1 = 0.0, acc2 = 0.0, acc3 = 0.0;
+            const int l0 = m + (c0 + g) * kLC;
+            if (!wave_dead && l0 <= lmax) {
+                // the chunk's recurrence coefficients in one batch of scalar loads (the table
+                // is padded past its end), and the next chunk's lines touched into L2
+                double2 cc[kLC];
 #pragma unroll
-            for (int i = 0; i < kLC; ++i) {
-                const int l = l0 + i;
-                if (l > lmax) {
-                    lam[i] = 0.0;
-                    continue;
-                }
-                if (l > m) {
-                    const double2 c = cc[i];
-                    const double vn = rec_step(c, y, vc, vp);
-                    vp = vc;
-                    vc = vn;
-                    if (wscaled) {
-                        const bool big = (k > 0) && (fabs(vc) >= kBig);
-                        const double sc = big ? kUnit : 1.0;
-                        vc *= sc;
-                        vp *= sc;
-                        k -= big ? 1 : 0;
+                for (int i = 0; i < kLC; ++i) cc[i] = rec[moff + l0 + i];
+                if (lane < 3 && l0 + kLC <= lmax)
+                    pf_keep ^= lds_dma_touch(rec + moff + l0 + kLC + 8 * lane, lds_sink);
+                double lam[kLC];
+                if (!__any(scaled) && l0 > m && l0 + kLC - 1 <= lmax) {
+                    // common case: a full chunk past lam_mm with no lane scaled
+#pragma unroll
+                    for (int i = 0; i < kLC; ++i) {
+                        const double vn = rec_step(cc[i], y, vc, vp);
+                        vp = vc;
+                        vc = vn;
+                        lam[i] = vc;
                     }
-                }
-                lam[i] = (k == 0) ? vc : 0.0;
-            }
-            scaled = k > 0;
+                } else {
+                    const bool wscaled = __any(scaled);
 #pragma unroll
-            for (int i = 0; i < kLC; ++i) st[lane * kLS + i] = lam[i];
-            // the wave reads back only its own staging rows
-            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-            __builtin_amdgcn_wave_barrier();
-            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-            {
-                const int kk = lane >> 4, bb = (lane >> 2) & 3, jj = lane & 3;
-                const int lo0 = 2 * jj + (bb >> 1), lo1 = lo0 + 8;
+                    for (int i = 0; i < kLC; ++i) {
+                        const int l = l0 + i;
+                        if (l > lmax) {
+                            lam[i] = 0.0;
+                            continue;
+                        }
+                        if (l > m) {
+                            const double vn = rec_step(cc[i], y, vc, vp);
+                            vp = vc;
+                            vc = vn;
+                            if (wscaled) {
+                                const bool big = (k > 0) && (fabs(vc) >= kBig);
+                                const double sc = big ? kUnit : 1.0;
+                                vc *= sc;
+                                vp *= sc;
+                                k -= big ? 1 : 0;
+                            }
+                        }
+                        lam[i] = (k == 0) ? vc : 0.0;
+                    }
+                    scaled = k > 0;
+                }
+#pragma unroll
+                for (int i = 0; i < kLC; ++i) st[lane * kLS + i] = lam[i];
+                // the wave reads back only its own staging rows
+                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+                __builtin_amdgcn_wave_barrier();
+                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 #pragma unroll
                 for (int q = 0; q < 16; q += 2) {
                     const double* r0 = st + (4 * q + kk) * kLS;
                     const double* r1 = st + (4 * (q + 1) + kk) * kLS;
                     acc0 = __builtin_amdgcn_mfma_f64_4x4x4f64(aop[q], r0[lo0], acc0, 0, 0, 0);
                     acc2 = __builtin_amdgcn_mfma_f64_4x4x4f64(aop[q], r0[lo1], acc2, 0, 0, 0);
-                    acc1 = __builtin_amdgcn_mfma_f64_4x4x4f64(aop[q + 1], r1[lo0], acc1, 0, 0, 0);
-                    acc3 = __builtin_amdgcn_mfma_f64_4x4x4f64(aop[q + 1], r1[lo1], acc3, 0, 0, 0);
+                    acc1 = __builtin_amdgcn_mfma_f64_4x4x4f64(aop[q + 1], r1[lo0], acc1, 0, 0,
+                                                              0);
+                    acc3 = __builtin_amdgcn_mfma_f64_4x4x4f64(aop[q + 1], r1[lo1], acc3, 0, 0,
+                                                              0);
                 }
+                // the next chunk rewrites the staging rows: all lanes' reads come first
+                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+                __builtin_amdgcn_wave_barrier();
+                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
             }
+            dv[g][0] = acc0 + acc1;
+            dv[g][1] = acc2 + acc3;
         }
-        dsum[wave][lane] = acc0 + acc1;
-        dsum[wave][64 + lane] = acc2 + acc3;
+        // the group's D values go into this wave's staging area (its lam values are consumed)
+#pragma unroll
+        for (int g = 0; g < kAdjGroup; ++g) {
+            st[(2 * g) * 64 + lane] = dv[g][0];
+            st[(2 * g + 1) * 64 + lane] = dv[g][1];
+        }
         __syncthreads();
-        // sum over the block's waves; thread t -> half-chunk t / 64, D lane t % 64
-        for (int t = threadIdx.x; t < 128; t += blockDim.x) {
+        // sum over the block's waves; value t -> chunk t / 128, half-chunk (t / 64) % 2,
+        // D lane t % 64
+        for (int t = threadIdx.x; t < kAdjGroup * 128; t += blockDim.x) {
             const int d = t & 63;
             const int b = d >> 4;              // map
             const int blk = (d >> 2) & 3;      // 2 h + c
-            const int l = l0 + 8 * (t >> 6) + 2 * (d & 3) + (blk >> 1);
+            const int l = m + (c0 + (t >> 7)) * kLC + 8 * ((t >> 6) & 1) + 2 * (d & 3) +
+                          (blk >> 1);
             if (l > lmax || b >= nmb) continue;
             double v = 0.0;
-            for (int w = 0; w < nwaves; ++w) v += dsum[w][t];
+            for (int w = 0; w < nwaves; ++w) v += stage[w][t];
             part[(((int64_t)(grp * npc + pc) * 4 + b) * nalm + moff + l) * 2 + (blk & 1)] = v;
         }
         __syncthreads();
@@ -568,16 +623,24 @@ int launch_legendre_synth(const nusht_plan_s* p, const double* alm, void* out, i
         const int left = nmaps - b;
         const int mb = left >= 4 ? 4 : (left >= 2 ? 2 : 1);
         const int groups = left / mb;
-        dim3 grid(bx, g.mmax + 1, groups);
+        const int mpad = (g.mmax + 1 + 7) / 8 * 8;
+        dim3 grid(bx * mpad, groups);
         const double2* ab = a + (int64_t)b * nalm;
-#define SYN(MBV, RV, F, OT)                                                                      \
-    hipLaunchKernelGGL((k_legendre_synth<MBV, RV, F, OT>), grid, dim3(threads), 0, s, ab, nalm,   \
-                       g.lmax, p->rec, p->cm_mant, p->cm_exp, p->jlive, g.nrings, g.ntorus,      \
+#define SYN1(MBV, RV, F, OT, SC)                                                                 \
+    hipLaunchKernelGGL((k_legendre_synth<MBV, RV, F, OT, SC>), grid, dim3(threads), 0, s, ab,     \
+                       nalm, g.lmax, g.mmax, bx, p->rec, p->cm_mant, p->cm_exp, p->jlive,        \
+                       p->jscale, g.nrings, g.ntorus,                                             \
                        reinterpret_cast<OT*>(out) + (int64_t)b * map_stride, map_stride,          \
                        row_stride)
-#define SYNR(MBV, F, OT)          \
-    if (R == 2) SYN(MBV, 2, F, OT); \
-    else SYN(MBV, 1, F, OT);
+#define SYN(MBV, RV, F, OT)        \
+    SYN1(MBV, RV, F, OT, false);   \
+    SYN1(MBV, RV, F, OT, true)
+#define SYNR(MBV, F, OT)   \
+    if (R == 2) {            \
+        SYN(MBV, 2, F, OT);  \
+    } else {                 \
+        SYN(MBV, 1, F, OT);  \
+    }
         if (fused && out_f32) {
             if (mb == 4) { SYNR(4, true, float2) }
             else if (mb == 2) { SYNR(2, true, float2) }
@@ -593,6 +656,7 @@ int launch_legendre_synth(const nusht_plan_s* p, const double* alm, void* out, i
         }
 #undef SYNR
 #undef SYN
+#undef SYN1
         NUSHT_HIP(hipGetLastError());
         b += groups * mb;
     }

@@ -9,10 +9,10 @@ int interp_f64(const nusht_plan_s* p, const double* fine, double* out, int nmaps
     return dispatch_interp_impl<double>(p, fine, out, nmaps, p->g.beta, s);
 }
 
-int spread_group_f64(const nusht_plan_s* p, const double* in, double* sub, int b, int mb,
+int spread_group_f64(const nusht_plan_s* p, const double* vals, double* sub, int mb,
                      hipStream_t s)
 {
-    return spread_group_impl<double>(p, in, sub, b, mb, p->g.beta, s);
+    return spread_group_impl<double>(p, vals, sub, mb, p->g.beta, s);
 }
 
 int halo_group_f64(const nusht_plan_s* p, const double* sub, double* fine, int b, int mb,

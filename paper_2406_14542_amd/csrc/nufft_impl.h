@@ -350,8 +350,8 @@ __global__ __launch_bounds__(320) void k_spread_rows(
 // 16 consecutive words of one window row.  The order of the additions into a cell is not
 // fixed, so FP64 spreading can differ between runs by rounding (~1e-16 relative).
 template <typename T, int W, int MB>
-__global__ __launch_bounds__(256) void k_spread_atomic(const double* __restrict__ in,
-                                                       int64_t npts, PointBins pb, T beta,
+__global__ __launch_bounds__(256) void k_spread_atomic(const double* __restrict__ vals,
+                                                       PointBins pb, T beta,
                                                        T* __restrict__ sub)
 {
     constexpr int P = kTile + W - 1;
@@ -383,9 +383,8 @@ __global__ __launch_bounds__(256) void k_spread_atomic(const double* __restrict_
         const T p2 = act ? es_value<T>(((T)d2 - T(col)) * cw, beta) : T(0);
         const T p1c = col < W ? es_value<T>(((T)d1 - T(col)) * cw, beta) : T(0);
         T f[MB];
-        const int64_t src = pb.perm[pp];
 #pragma unroll
-        for (int b = 0; b < MB; ++b) f[b] = live ? (T)in[b * npts + src] * p2 : T(0);
+        for (int b = 0; b < MB; ++b) f[b] = live ? (T)vals[(int64_t)pp * MB + b] * p2 : T(0);
         const int cc = c + (col < W ? col : 0);
 #pragma unroll
         for (int a = 0; a < W; ++a) {
@@ -503,8 +502,12 @@ int dispatch_interp_impl(const nusht_plan_s* p, const T* fine, double* out, int 
 }
 
 // spreading of maps [b, b + mb) into the slot subgrids (mb = 1 or 4)
+// FP64 (LDS atomics): `vals` holds the group's values in tile-sorted order, [npts][mb]
+// (k_sort_values); gathering them inside the atomic loop stalls it.  FP32 (output-
+// stationary): `vals` is the caller's map block [mb][npts], gathered through the
+// permutation while the block stages its points -- cheaper there than a separate pass.
 template <typename T>
-int spread_group_impl(const nusht_plan_s* p, const double* in, T* sub, int b, int mb, T beta,
+int spread_group_impl(const nusht_plan_s* p, const double* vals, T* sub, int mb, T beta,
                       hipStream_t s)
 {
     if (p->nslots == 0) return NUSHT_OK;
@@ -514,18 +517,16 @@ int spread_group_impl(const nusht_plan_s* p, const double* in, T* sub, int b, in
         if (sizeof(T) == 8) {
             if (mb == 4)
                 hipLaunchKernelGGL((k_spread_atomic<T, WV, 4>), dim3(p->nslots), dim3(256), 0, s,
-                                   in + b * npts, npts, pb, beta, sub);
+                                   vals, pb, beta, sub);
             else
                 hipLaunchKernelGGL((k_spread_atomic<T, WV, 1>), dim3(p->nslots), dim3(256), 0, s,
-                                   in + b * npts, npts, pb, beta, sub);
+                                   vals, pb, beta, sub);
         } else if (mb == 4) {
             hipLaunchKernelGGL((k_spread_rows<T, WV, 4>), dim3(p->nslots),
-                               dim3(SpreadShape<T, WV, 4>::NT), 0, s, in + b * npts, npts, pb,
-                               beta, sub);
+                               dim3(SpreadShape<T, WV, 4>::NT), 0, s, vals, npts, pb, beta, sub);
         } else {
             hipLaunchKernelGGL((k_spread_rows<T, WV, 1>), dim3(p->nslots),
-                               dim3(SpreadShape<T, WV, 1>::NT), 0, s, in + b * npts, npts, pb,
-                               beta, sub);
+                               dim3(SpreadShape<T, WV, 1>::NT), 0, s, vals, npts, pb, beta, sub);
         }
     });
     NUSHT_HIP(hipGetLastError());

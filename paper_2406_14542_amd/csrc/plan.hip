@@ -133,6 +133,12 @@ __global__ void k_gather_sorted(const double* __restrict__ theta, const double* 
     sph[k] = phw[i];
 }
 
+__global__ void k_invert(const int* __restrict__ perm, int64_t n, int* __restrict__ iperm)
+{
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k < n) iperm[perm[k]] = (int)k;
+}
+
 __global__ void k_mark(const int* __restrict__ keys, int64_t n, int* __restrict__ first)
 {
     const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -291,6 +297,7 @@ int ensure_capacity(nusht_plan_s* p, int nmaps)
         NUSHT_TRY(dmalloc((char**)&p->W, fine_spec));
         p->Wbytes = fine_spec;
     }
+    if (!p->V && g.dtype == NUSHT_F64) NUSHT_TRY(dmalloc(&p->V, (size_t)g.npts * 4));
     p->bcap = nmaps;
     return NUSHT_OK;
 }
@@ -317,7 +324,8 @@ int bin_points(nusht_plan_s* p, const double* theta, const double* phi, hipStrea
     do {
         if ((rc = dmalloc(&keys, n)) || (rc = dmalloc(&keys_s, n)) || (rc = dmalloc(&idx, n)) ||
             (rc = dmalloc(&first, n)) || (rc = dmalloc(&sidx, n)) || (rc = dmalloc(&phw, n)) ||
-            (rc = dmalloc(&p->perm, n)) || (rc = dmalloc(&p->sth, n)) ||
+            (rc = dmalloc(&p->perm, n)) || (rc = dmalloc(&p->iperm, n)) ||
+            (rc = dmalloc(&p->sth, n)) ||
             (rc = dmalloc(&p->sph, n)) || (rc = dmalloc(&p->tile_slot, ntiles)) ||
             (rc = dmalloc(&p->dflag, 1)))
             break;
@@ -334,6 +342,7 @@ int bin_points(nusht_plan_s* p, const double* theta, const double* phi, hipStrea
                                                bits, s) != hipSuccess) { rc = NUSHT_EDEVICE; break; }
         hipLaunchKernelGGL(k_gather_sorted, dim3(blocks), dim3(256), 0, s, theta, phw, p->perm, n,
                            p->sth, p->sph);
+        hipLaunchKernelGGL(k_invert, dim3(blocks), dim3(256), 0, s, p->perm, n, p->iperm);
         hipLaunchKernelGGL(k_mark, dim3(blocks), dim3(256), 0, s, keys_s, n, first);
         if (hipcub::DeviceScan::ExclusiveSum(tmp, tbytes, first, sidx, (int)n, s) != hipSuccess) { rc = NUSHT_EDEVICE; break; }
         int last_first = 0, last_idx = 0, flag = 0;
@@ -473,6 +482,31 @@ static int build_tables(nusht_plan_s* p)
             });
         for (auto& th : pool) th.join();
     }
+    // first ring pair whose lam_mm = c_m sin^m(theta_j) is at least 2^-190 (sin theta_j grows
+    // with j up to the equator); no lam_lm of such a pair needs the power-of-two scale
+    std::vector<int> jsc(M + 1, 0);
+    {
+        const int npairs = (g.nrings + 1) / 2;
+        for (int m = 0; m <= M; ++m) {
+            const double lc = (double)ce[m] + std::log2(std::fabs(cm[m]));
+            int j = 0;
+            if (m > 0) {
+                // bisection on the monotone log2 lam_mm(theta_j) >= -190
+                int lo = 0, hi = npairs;
+                while (lo < hi) {
+                    const int mid = (lo + hi) / 2;
+                    const double sth = std::sin(M_PI * (double)mid / (double)(g.nrings - 1));
+                    const bool ok = sth > 0.0 && lc + m * std::log2(sth) >= -190.0;
+                    if (ok)
+                        hi = mid;
+                    else
+                        lo = mid + 1;
+                }
+                j = lo;
+            }
+            jsc[m] = j < jl[m] ? jl[m] : j;
+        }
+    }
     // deconvolution: h / psi^(k) = 2 / (w I(k)), with the 1/N_t of the theta transform
     std::vector<double> i1, i2;
     es_fourier(g.beta, g.width * M_PI / g.n1, L, i1);
@@ -495,6 +529,8 @@ static int build_tables(nusht_plan_s* p)
     NUSHT_TRY(dmalloc(&p->dec1f, L + 1));
     NUSHT_TRY(dmalloc(&p->dec2f, M + 1));
     NUSHT_TRY(dmalloc(&p->jlive, M + 1));
+    NUSHT_TRY(dmalloc(&p->jscale, M + 1));
+    NUSHT_HIP(hipMemcpy(p->jscale, jsc.data(), jsc.size() * sizeof(int), hipMemcpyHostToDevice));
     NUSHT_HIP(hipMemcpy(p->jlive, jl.data(), jl.size() * sizeof(int), hipMemcpyHostToDevice));
     p->jlive_host = jl;
     NUSHT_HIP(hipMemcpy(p->rec, rec.data(), rec.size() * sizeof(double), hipMemcpyHostToDevice));
@@ -552,10 +588,11 @@ void nusht_destroy(nusht_plan_t p)
     hipDeviceSynchronize();
     destroy_fft_plans(p);
     void* bufs[] = {p->rec,  p->cm_mant, p->cm_exp,   p->dec1,      p->dec2,      p->dec1f,
-                    p->dec2f, p->sth,    p->sph,      p->perm,      p->slot_off,  p->slot_tile,
+                    p->dec2f, p->sth,    p->sph,      p->perm,      p->iperm,     p->V,
+                    p->slot_off,  p->slot_tile,
                     p->tile_slot, p->dflag, p->X,     p->Y,         p->Z,         p->W,
                     p->fftwork,
-                    p->red,      p->jlive};
+                    p->red,      p->jlive,  p->jscale};
     for (void* b : bufs)
         if (b) hipFree(b);
     for (int c = 0; c < nusht_plan_s::kTimingSlots; ++c)

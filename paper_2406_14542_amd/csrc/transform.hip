@@ -11,9 +11,9 @@ namespace nusht {
 
 int interp_f64(const nusht_plan_s* p, const double* fine, double* out, int nmaps, hipStream_t s);
 int interp_f32(const nusht_plan_s* p, const float* fine, double* out, int nmaps, hipStream_t s);
-int spread_group_f64(const nusht_plan_s* p, const double* in, double* sub, int b, int mb,
+int spread_group_f64(const nusht_plan_s* p, const double* vals, double* sub, int mb,
                      hipStream_t s);
-int spread_group_f32(const nusht_plan_s* p, const double* in, float* sub, int b, int mb,
+int spread_group_f32(const nusht_plan_s* p, const double* vals, float* sub, int mb,
                      hipStream_t s);
 int halo_group_f64(const nusht_plan_s* p, const double* sub, double* fine, int b, int mb,
                    hipStream_t s);
@@ -246,6 +246,23 @@ void begin_call(nusht_plan_s* p, int kind)
 
 inline char* bytes(void* v) { return reinterpret_cast<char*>(v); }
 
+// Adjoint input of maps [b, b + MB) into tile-sorted order, the MB values of a point
+// contiguous: reads are coalesced in the caller's order and each point is one MB * 8-byte
+// write, instead of MB separate 8-byte gathers per point in the spreading kernel.
+template <int MB>
+__global__ void k_sort_values(const double* __restrict__ map, int64_t npts,
+                              const int* __restrict__ iperm, double* __restrict__ vals)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= npts) return;
+    double v[MB];
+#pragma unroll
+    for (int b = 0; b < MB; ++b) v[b] = map[b * npts + i];
+    double* dst = vals + (int64_t)iperm[i] * MB;
+#pragma unroll
+    for (int b = 0; b < MB; ++b) dst[b] = v[b];
+}
+
 // fine grid (real) of map b and its half spectrum, in elements of the plan's precision
 size_t fine_real_bytes(const nusht_plan_s* p) { return (size_t)p->g.n1 * p->g.n2 * fine_elem_bytes(p); }
 // band spectrum [mmax+1][n1] of one map
@@ -438,13 +455,22 @@ int nusht_adjoint(nusht_plan_t p, const double* map, double* alm, int nmaps, voi
         return NUSHT_EINVAL;
     }
     stage_begin(p, ST_POINTS, s);
+    const unsigned vblocks = (unsigned)((g.npts + 255) / 256);
     for (int b = 0, grp = 0; b < nmaps; ++grp) {
         const int mb = group_width(nmaps, b);
         void* sub = bytes(p->Z) + grp * zgroup;
-        if (f32)
-            NUSHT_TRY(spread_group_f32(p, map, reinterpret_cast<float*>(sub), b, mb, s));
-        else
-            NUSHT_TRY(spread_group_f64(p, map, reinterpret_cast<double*>(sub), b, mb, s));
+        if (f32) {
+            NUSHT_TRY(spread_group_f32(p, map + b * g.npts, reinterpret_cast<float*>(sub), mb, s));
+        } else {
+            if (mb == 4)
+                hipLaunchKernelGGL(k_sort_values<4>, dim3(vblocks), dim3(256), 0, s,
+                                   map + b * g.npts, g.npts, p->iperm, p->V);
+            else
+                hipLaunchKernelGGL(k_sort_values<1>, dim3(vblocks), dim3(256), 0, s,
+                                   map + b * g.npts, g.npts, p->iperm, p->V);
+            NUSHT_HIP(hipGetLastError());
+            NUSHT_TRY(spread_group_f64(p, p->V, reinterpret_cast<double*>(sub), mb, s));
+        }
         b += mb;
     }
     stage_end(p, ST_POINTS, s);
