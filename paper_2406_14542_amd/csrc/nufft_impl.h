@@ -94,6 +94,39 @@ __device__ inline void es_taps_d(double d, double beta, double (&psi)[W], double
     }
 }
 
+// Stage the tile's P x P window of MB maps into LDS (256 threads).  Each thread issues all
+// of its loads before its first LDS write, so the block waits for HBM once rather than once
+// per element it stages.
+template <typename T, int P, int MB>
+__device__ inline void stage_window(const T* __restrict__ fine, int64_t map_stride,
+                                    const PointBins& pb, int r0, int c0, T* win)
+{
+    constexpr int NE = (P * P + 255) / 256;
+    T v[NE][MB];
+#pragma unroll
+    for (int i = 0; i < NE; ++i) {
+        const int e = (int)threadIdx.x + 256 * i;
+        if (e < P * P) {
+            const int r = e / P, c = e - r * P;
+            int gr = r0 + r;
+            if (gr >= pb.n1) gr -= pb.n1;
+            int gc = c0 + c;
+            if (gc >= pb.n2) gc -= pb.n2;
+            const int64_t off = (int64_t)gr * pb.n2 + gc;
+#pragma unroll
+            for (int b = 0; b < MB; ++b) v[i][b] = fine[b * map_stride + off];
+        }
+    }
+#pragma unroll
+    for (int i = 0; i < NE; ++i) {
+        const int e = (int)threadIdx.x + 256 * i;
+        if (e < P * P) {
+#pragma unroll
+            for (int b = 0; b < MB; ++b) win[e * MB + b] = v[i][b];
+        }
+    }
+}
+
 template <typename T, int W, int MB>
 __global__ __launch_bounds__(256) void k_interp(const T* __restrict__ fine, int64_t map_stride,
                                                 PointBins pb, T beta, double* __restrict__ out,
@@ -105,22 +138,30 @@ __global__ __launch_bounds__(256) void k_interp(const T* __restrict__ fine, int6
     const int tile = pb.slot_tile[slot];
     const int r0 = (tile / pb.nt2) * kTile;
     const int c0 = (tile % pb.nt2) * kTile;
-    for (int e = threadIdx.x; e < P * P; e += blockDim.x) {
-        const int r = e / P, c = e - (e / P) * P;
-        int gr = r0 + r;
-        if (gr >= pb.n1) gr -= pb.n1;
-        int gc = c0 + c;
-        if (gc >= pb.n2) gc -= pb.n2;
-        const int64_t off = (int64_t)gr * pb.n2 + gc;
-#pragma unroll
-        for (int b = 0; b < MB; ++b) win[e * MB + b] = fine[b * map_stride + off];
-    }
-    __syncthreads();
+    // the first point's coordinates and destination, then the whole window: every load of
+    // the thread is in flight before the first one is waited for
     const int p0 = pb.slot_off[slot], p1 = pb.slot_off[slot + 1];
-    for (int p = p0 + threadIdx.x; p < p1; p += blockDim.x) {
+    int p = p0 + threadIdx.x;
+    double thn = 0.0, phn = 0.0;
+    int dstn = 0;
+    if (p < p1) {
+        thn = pb.sth[p];
+        phn = pb.sph[p];
+        dstn = pb.perm[p];
+    }
+    stage_window<T, P, MB>(fine, map_stride, pb, r0, c0, win);
+    __syncthreads();
+    for (; p < p1; p += 256) {
+        const double th = thn, ph = phn;
+        const int64_t dst = dstn;
+        if (p + 256 < p1) {  // the next point's data, loaded under this point's work
+            thn = pb.sth[p + 256];
+            phn = pb.sph[p + 256];
+            dstn = pb.perm[p + 256];
+        }
         double d1, d2;
-        const int l1 = first_tap(pb.sth[p], pb.s1, W, d1);
-        const int l2 = first_tap(pb.sph[p], pb.s2, W, d2);
+        const int l1 = first_tap(th, pb.s1, W, d1);
+        const int l2 = first_tap(ph, pb.s2, W, d2);
         int r = wrap_index(l1, pb.n1) - r0;
         int c = wrap_index(l2, pb.n2) - c0;
         r = min(max(r, 0), kTile - 1);
@@ -145,7 +186,6 @@ __global__ __launch_bounds__(256) void k_interp(const T* __restrict__ fine, int6
 #pragma unroll
             for (int b = 0; b < MB; ++b) acc[b] += p1v[a] * row[b];
         }
-        const int64_t dst = pb.perm[p];
 #pragma unroll
         for (int b = 0; b < MB; ++b) out[b * npts + dst] = (double)acc[b];
     }
@@ -164,22 +204,30 @@ __global__ __launch_bounds__(256) void k_interp_deriv(const double* __restrict__
     const int tile = pb.slot_tile[slot];
     const int r0 = (tile / pb.nt2) * kTile;
     const int c0 = (tile % pb.nt2) * kTile;
-    for (int e = threadIdx.x; e < P * P; e += blockDim.x) {
-        const int r = e / P, c = e - (e / P) * P;
-        int gr = r0 + r;
-        if (gr >= pb.n1) gr -= pb.n1;
-        int gc = c0 + c;
-        if (gc >= pb.n2) gc -= pb.n2;
-        const int64_t off = (int64_t)gr * pb.n2 + gc;
-#pragma unroll
-        for (int b = 0; b < MB; ++b) win[e * MB + b] = fine[b * map_stride + off];
-    }
-    __syncthreads();
+    // the first point's coordinates and destination, then the whole window: every load of
+    // the thread is in flight before the first one is waited for
     const int p0 = pb.slot_off[slot], p1 = pb.slot_off[slot + 1];
-    for (int p = p0 + threadIdx.x; p < p1; p += blockDim.x) {
+    int p = p0 + threadIdx.x;
+    double thn = 0.0, phn = 0.0;
+    int dstn = 0;
+    if (p < p1) {
+        thn = pb.sth[p];
+        phn = pb.sph[p];
+        dstn = pb.perm[p];
+    }
+    stage_window<double, P, MB>(fine, map_stride, pb, r0, c0, win);
+    __syncthreads();
+    for (; p < p1; p += 256) {
+        const double th = thn, ph = phn;
+        const int64_t dst = dstn;
+        if (p + 256 < p1) {  // the next point's data, loaded under this point's work
+            thn = pb.sth[p + 256];
+            phn = pb.sph[p + 256];
+            dstn = pb.perm[p + 256];
+        }
         double d1, d2;
-        const int l1 = first_tap(pb.sth[p], pb.s1, W, d1);
-        const int l2 = first_tap(pb.sph[p], pb.s2, W, d2);
+        const int l1 = first_tap(th, pb.s1, W, d1);
+        const int l2 = first_tap(ph, pb.s2, W, d2);
         int r = wrap_index(l1, pb.n1) - r0;
         int c = wrap_index(l2, pb.n2) - c0;
         r = min(max(r, 0), kTile - 1);
@@ -212,7 +260,6 @@ __global__ __launch_bounds__(256) void k_interp_deriv(const double* __restrict__
                 a2[b] = fma(p1v[a], rowd[b], a2[b]);
             }
         }
-        const int64_t dst = pb.perm[p];
 #pragma unroll
         for (int b = 0; b < MB; ++b) {
             out[b * npts + dst] = acc[b];
