@@ -174,11 +174,12 @@ __device__ inline void xcd_block(int b, int nbx, int& m, int& rb)
 // Each lane owns R ring pairs j = base + lane + 64 r; a wave therefore covers 64 R
 // consecutive pairs and loads every coefficient once for all of them.
 //
-// The kernel comes in two instances over the same grid.  Ring pairs j >= jscale[m] have
-// lam_mm above 2^-190, so none of their lam_lm ever needs the power-of-two scale; a wave
-// made only of such pairs runs the SCALED = false instance, which has no scaled step at
-// all (the scaled step's extra live registers would otherwise cost the whole kernel almost
-// half of its occupancy).  Every other live wave runs SCALED = true.
+// The kernel comes in two instances.  Ring pairs j >= jscale[m] have lam_mm above 2^-190,
+// so none of their lam_lm ever needs the power-of-two scale; their waves run the
+// SCALED = false instance, which has no scaled step at all (the scaled step's extra live
+// registers would otherwise cost the whole kernel almost half of its occupancy).  The pairs
+// below jscale[m] (a multiple of 64 R of the plain instance, so that the two instances'
+// waves partition the pairs) run SCALED = true with one pair per lane.
 template <int MB, int R, bool FUSED, typename OutT, bool SCALED>
 __global__ __launch_bounds__(256) void k_legendre_synth(
     const double2* __restrict__ alm, int64_t nalm, int lmax, int mmax, int nbx,
@@ -597,17 +598,26 @@ __global__ void k_adj_finalize(const double* __restrict__ part, int npc, int nma
 
 }  // namespace
 
+int synth_pairs_per_lane(int npairs) { return npairs >= 1024 ? 2 : 1; }
+
 int launch_legendre_synth(const nusht_plan_s* p, const double* alm, void* out, int nmaps,
                           int fused, int out_f32, hipStream_t s)
 {
     const nusht_geometry& g = p->g;
     const int npairs = (g.nrings + 1) / 2;
-    // two ring pairs per lane once there are enough pairs to fill the waves
-    const int R = npairs >= 1024 ? 2 : 1;
-    const int waves_needed = (npairs + 64 * R - 1) / (64 * R);
-    const int wpb = waves_needed >= 4 ? 4 : waves_needed;
-    const int threads = 64 * wpb;
-    const int bx = (waves_needed + wpb - 1) / wpb;
+    // the plain instance takes two ring pairs per lane once there are enough pairs to fill
+    // the waves; the scaled instance always one, which halves the spread of the scaled
+    // phase's length across the lanes of a wave and keeps its occupancy higher
+    const int R = synth_pairs_per_lane(npairs);
+    auto shape = [&](int r, int& bx, int& threads) {
+        const int waves_needed = (npairs + 64 * r - 1) / (64 * r);
+        const int wpb = waves_needed >= 4 ? 4 : waves_needed;
+        threads = 64 * wpb;
+        bx = (waves_needed + wpb - 1) / wpb;
+    };
+    int bxp, thp, bxs, ths;
+    shape(R, bxp, thp);
+    shape(1, bxs, ths);
     const int64_t nalm = g.nalm;
     const double2* a = reinterpret_cast<const double2*>(alm);
     int64_t map_stride, row_stride;
@@ -618,29 +628,26 @@ int launch_legendre_synth(const nusht_plan_s* p, const double* alm, void* out, i
         row_stride = g.nphi / 2 + 1;
         map_stride = (int64_t)g.nrings * row_stride;
     }
+    const int mpad = (g.mmax + 1 + 7) / 8 * 8;
     int b = 0;
     while (b < nmaps) {
         const int left = nmaps - b;
         const int mb = left >= 4 ? 4 : (left >= 2 ? 2 : 1);
         const int groups = left / mb;
-        const int mpad = (g.mmax + 1 + 7) / 8 * 8;
-        dim3 grid(bx * mpad, groups);
         const double2* ab = a + (int64_t)b * nalm;
-#define SYN1(MBV, RV, F, OT, SC)                                                                 \
-    hipLaunchKernelGGL((k_legendre_synth<MBV, RV, F, OT, SC>), grid, dim3(threads), 0, s, ab,     \
-                       nalm, g.lmax, g.mmax, bx, p->rec, p->cm_mant, p->cm_exp, p->jlive,        \
-                       p->jscale, g.nrings, g.ntorus,                                             \
+#define SYN1(MBV, RV, F, OT, SC, BX, TH)                                                         \
+    hipLaunchKernelGGL((k_legendre_synth<MBV, RV, F, OT, SC>), dim3(BX * mpad, groups),          \
+                       dim3(TH), 0, s, ab, nalm, g.lmax, g.mmax, BX, p->rec, p->cm_mant,          \
+                       p->cm_exp, p->jlive, p->jscale, g.nrings, g.ntorus,                        \
                        reinterpret_cast<OT*>(out) + (int64_t)b * map_stride, map_stride,          \
                        row_stride)
-#define SYN(MBV, RV, F, OT)        \
-    SYN1(MBV, RV, F, OT, false);   \
-    SYN1(MBV, RV, F, OT, true)
-#define SYNR(MBV, F, OT)   \
-    if (R == 2) {            \
-        SYN(MBV, 2, F, OT);  \
-    } else {                 \
-        SYN(MBV, 1, F, OT);  \
-    }
+#define SYNR(MBV, F, OT)                              \
+    if (R == 2) {                                     \
+        SYN1(MBV, 2, F, OT, false, bxp, thp);         \
+    } else {                                          \
+        SYN1(MBV, 1, F, OT, false, bxp, thp);         \
+    }                                                 \
+    SYN1(MBV, 1, F, OT, true, bxs, ths);
         if (fused && out_f32) {
             if (mb == 4) { SYNR(4, true, float2) }
             else if (mb == 2) { SYNR(2, true, float2) }
@@ -655,7 +662,6 @@ int launch_legendre_synth(const nusht_plan_s* p, const double* alm, void* out, i
             else { SYNR(1, false, double2) }
         }
 #undef SYNR
-#undef SYN
 #undef SYN1
         NUSHT_HIP(hipGetLastError());
         b += groups * mb;

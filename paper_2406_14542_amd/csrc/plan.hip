@@ -504,7 +504,10 @@ static int build_tables(nusht_plan_s* p)
                 }
                 j = lo;
             }
-            jsc[m] = j < jl[m] ? jl[m] : j;
+            if (j < jl[m]) j = jl[m];
+            // the synthesis splits its waves at jsc: a multiple of its plain waves' span
+            const int span = 64 * synth_pairs_per_lane(npairs);
+            jsc[m] = (j + span - 1) / span * span;
         }
     }
     // deconvolution: h / psi^(k) = 2 / (w I(k)), with the 1/N_t of the theta transform
