@@ -177,6 +177,7 @@ int launch_legendre_synth(const nusht_plan_s* p, const double* alm, void* out, i
                           int fused, int out_f32, hipStream_t s);
 // ring pairs per lane of the synthesis' plain instance
 int synth_pairs_per_lane(int npairs);
+int synth_scaled_pairs_per_lane(int npairs);
 int launch_legendre_adjoint(const nusht_plan_s* p, const void* in, double* alm, int nmaps,
                             int fused, int in_f32, void* scratch, size_t scratch_bytes,
                             hipStream_t s);

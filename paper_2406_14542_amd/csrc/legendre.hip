@@ -268,20 +268,68 @@ __global__ __launch_bounds__(256) void k_legendre_synth(
         unsigned pf_keep = 0;
         const unsigned lds_sink = __builtin_amdgcn_readfirstlane(
             (unsigned)(uintptr_t)(__attribute__((address_space(3))) float*)pf_sink[wave]);
-        for (; l + 1 <= lmax; l += 2) {
+        auto prefetch = [&]() {
             if (l >= pf_at) {
                 pf_keep ^= prefetch_coeffs<MB>(rec, alm, nalm, moff, lmax, l + kPfStep, lane,
                                                lds_sink);
                 pf_at = l + kPfStep;
             }
-            const double2 c0 = rec[moff + l], c1 = rec[moff + l + 1];
-            if (SCALED && __any(any_scaled)) {
+        };
+        if (SCALED) {
+            // Phase 1: no lane has reached the accumulation range (every accumulator is still
+            // zero), so the steps run the recurrence and its rescaling only.  The rescale test
+            // is made once per pair: one step grows a value by less than 2^7, far from the
+            // FP64 range above kBig.  The pair in which some lane reaches k = 0 accumulates
+            // both of its values for those lanes (a value one step before k reached 0 is
+            // below 2^-200 times its coefficient: kept, not dropped).
+            bool reached = false;
+#pragma unroll
+            for (int r = 0; r < R; ++r) reached |= k[r] == 0;
+            if (!__any(reached)) {
+                for (; l + 1 <= lmax; l += 2) {
+                    const double2 c0 = rec[moff + l], c1 = rec[moff + l + 1];
+                    reached = false;
+#pragma unroll
+                    for (int r = 0; r < R; ++r) {
+                        const double v0 = rec_step(c0, y[r], vc[r], vp[r]);
+                        const double v1 = rec_step(c1, y[r], v0, vc[r]);
+                        const bool big = fmax(fabs(v0), fabs(v1)) >= kBig;
+                        const double sc = big ? kUnit : 1.0;
+                        vp[r] = v0 * sc;
+                        vc[r] = v1 * sc;
+                        k[r] -= big ? 1 : 0;
+                        reached |= k[r] == 0;
+                    }
+                    if (__any(reached)) {
+                        prefetch();
+                        any_scaled = false;
+#pragma unroll
+                        for (int r = 0; r < R; ++r) {
+                            const bool live = k[r] == 0;
+                            any_scaled |= !live;
+                            accum<MB>(E[r], alm, nalm, moff + l, live ? vp[r] : 0.0);
+                            accum<MB>(O[r], alm, nalm, moff + l + 1, live ? vc[r] : 0.0);
+                        }
+                        l += 2;
+                        break;
+                    }
+                }
+            }
+            // Phase 2: some lane still carries a scale factor: per-step rescaling and masked
+            // accumulation.
+            for (; l + 1 <= lmax && __any(any_scaled); l += 2) {
+                prefetch();
+                const double2 c0 = rec[moff + l], c1 = rec[moff + l + 1];
                 scaled_step(c0, moff + l, E);
                 scaled_step(c1, moff + l + 1, O);
-            } else {
-                plain_step(c0, moff + l, E);
-                plain_step(c1, moff + l + 1, O);
             }
+        }
+        // Phase 3: every lane is in plain FP64 range.
+        for (; l + 1 <= lmax; l += 2) {
+            prefetch();
+            const double2 c0 = rec[moff + l], c1 = rec[moff + l + 1];
+            plain_step(c0, moff + l, E);
+            plain_step(c1, moff + l + 1, O);
         }
         if (l <= lmax) {
             if (SCALED && __any(any_scaled))
@@ -342,7 +390,7 @@ __global__ __launch_bounds__(256) void k_legendre_synth(
 constexpr int kAdjWaves = 4;     // waves per block: one block reduces up to 256 ring pairs
 constexpr int kLC = 16;          // l values per chunk = the MFMA N dimension
 constexpr int kLS = kLC + 1;     // padded row of the lam staging area
-constexpr int kAdjGroup = 4;     // chunks whose D values are summed over waves together
+constexpr int kAdjGroup = 2;     // chunks whose D values are summed over waves together
 
 template <typename InT>
 __device__ inline double2 load_c(const InT* p)
@@ -449,10 +497,22 @@ __global__ __launch_bounds__(kAdjWaves * 64, 4) void k_legendre_adj(
         for (int c = 0; c < 16; ++c) st[lane * kLS + c] = hv[c];
     }
     __syncthreads();
-    // A operand of MFMA q: A[i][k] = ring data of pair 4q + k, row i; lane = i + 16 k
-    double aop[16];
+    // D of v_mfma_f64_4x4x4_4b (measured layout: A_b[i][k] in lane i + 4 b + 16 k,
+    // B_b[k][j] in lane j + 4 b + 16 k, D_b[i][j] in lane j + 4 b + 16 i).  Here k = ring
+    // pair of the group of four, block b = 2 s + h selects l = l0 + 8 s + 2 j + h of the
+    // chunk (s: half-chunk, h: parity of l - l0), so that the four blocks of one B operand
+    // hold 16 distinct lam values and every lam value is read from LDS once; i = map, and
+    // the real and imaginary parts (c) are two MFMAs on the same B.
+    const int kk = lane >> 4, bb = (lane >> 2) & 3, jj = lane & 3;
+    const int lidx = 8 * (bb >> 1) + 2 * jj + (bb & 1);  // this lane's l - l0 in B
+    // A operand of MFMA (q, c): ring data of pair 4 q + k, part c of the combination of
+    // parity h, map i
+    double aop[2][16];
 #pragma unroll
-    for (int q = 0; q < 16; ++q) aop[q] = st[(4 * q + (lane >> 4)) * kLS + (lane & 15)];
+    for (int c = 0; c < 2; ++c)
+#pragma unroll
+        for (int q = 0; q < 16; ++q)
+            aop[c][q] = st[(4 * q + kk) * kLS + (2 * (bb & 1) + c) * 4 + jj];
     __syncthreads();
 
     double s, y;
@@ -469,13 +529,6 @@ __global__ __launch_bounds__(kAdjWaves * 64, 4) void k_legendre_adj(
     const unsigned lds_sink = __builtin_amdgcn_readfirstlane(
         (unsigned)(uintptr_t)(__attribute__((address_space(3))) float*)pf_sink[wave]);
 
-    // D of v_mfma_f64_4x4x4_4b (measured layout: A_b[i][k] in lane i + 4 b + 16 k,
-    // B_b[k][j] in lane j + 4 b + 16 k, D_b[i][j] in lane j + 4 b + 16 i).  Here i = map,
-    // k = ring pair of the group, block b = 2 h + c (h: l parity relative to l0, c: real or
-    // imaginary part), j: l = l0 + 8 s + 2 j + h for half-chunk s.  Two accumulators per
-    // half-chunk (even/odd pair groups) keep four chains in flight.
-    const int kk = lane >> 4, bb = (lane >> 2) & 3, jj = lane & 3;
-    const int lo0 = 2 * jj + (bb >> 1), lo1 = lo0 + 8;
     const int nchunks = (lmax - m) / kLC + 1;
     for (int c0 = 0; c0 < nchunks; c0 += kAdjGroup) {
         double dv[kAdjGroup][2];
@@ -526,27 +579,31 @@ __global__ __launch_bounds__(kAdjWaves * 64, 4) void k_legendre_adj(
                     }
                     scaled = k > 0;
                 }
+                // a chunk after which every lane still carries a scale factor has only zero
+                // lam values (k never increases): it adds nothing
+                if (!__all(scaled)) {
 #pragma unroll
-                for (int i = 0; i < kLC; ++i) st[lane * kLS + i] = lam[i];
-                // the wave reads back only its own staging rows
-                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-                __builtin_amdgcn_wave_barrier();
-                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+                    for (int i = 0; i < kLC; ++i) st[lane * kLS + i] = lam[i];
+                    // the wave reads back only its own staging rows
+                    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+                    __builtin_amdgcn_wave_barrier();
+                    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 #pragma unroll
-                for (int q = 0; q < 16; q += 2) {
-                    const double* r0 = st + (4 * q + kk) * kLS;
-                    const double* r1 = st + (4 * (q + 1) + kk) * kLS;
-                    acc0 = __builtin_amdgcn_mfma_f64_4x4x4f64(aop[q], r0[lo0], acc0, 0, 0, 0);
-                    acc2 = __builtin_amdgcn_mfma_f64_4x4x4f64(aop[q], r0[lo1], acc2, 0, 0, 0);
-                    acc1 = __builtin_amdgcn_mfma_f64_4x4x4f64(aop[q + 1], r1[lo0], acc1, 0, 0,
-                                                              0);
-                    acc3 = __builtin_amdgcn_mfma_f64_4x4x4f64(aop[q + 1], r1[lo1], acc3, 0, 0,
-                                                              0);
+                    for (int q = 0; q < 16; q += 2) {
+                        const double b0 = st[(4 * q + kk) * kLS + lidx];
+                        const double b1 = st[(4 * (q + 1) + kk) * kLS + lidx];
+                        acc0 = __builtin_amdgcn_mfma_f64_4x4x4f64(aop[0][q], b0, acc0, 0, 0, 0);
+                        acc2 = __builtin_amdgcn_mfma_f64_4x4x4f64(aop[1][q], b0, acc2, 0, 0, 0);
+                        acc1 = __builtin_amdgcn_mfma_f64_4x4x4f64(aop[0][q + 1], b1, acc1, 0, 0,
+                                                                  0);
+                        acc3 = __builtin_amdgcn_mfma_f64_4x4x4f64(aop[1][q + 1], b1, acc3, 0, 0,
+                                                                  0);
+                    }
+                    // the next chunk rewrites the staging rows: all lanes' reads come first
+                    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+                    __builtin_amdgcn_wave_barrier();
+                    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
                 }
-                // the next chunk rewrites the staging rows: all lanes' reads come first
-                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-                __builtin_amdgcn_wave_barrier();
-                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
             }
             dv[g][0] = acc0 + acc1;
             dv[g][1] = acc2 + acc3;
@@ -558,18 +615,18 @@ __global__ __launch_bounds__(kAdjWaves * 64, 4) void k_legendre_adj(
             st[(2 * g + 1) * 64 + lane] = dv[g][1];
         }
         __syncthreads();
-        // sum over the block's waves; value t -> chunk t / 128, half-chunk (t / 64) % 2,
+        // sum over the block's waves; value t -> chunk t / 128, part c = (t / 64) % 2,
         // D lane t % 64
         for (int t = threadIdx.x; t < kAdjGroup * 128; t += blockDim.x) {
             const int d = t & 63;
             const int b = d >> 4;              // map
-            const int blk = (d >> 2) & 3;      // 2 h + c
-            const int l = m + (c0 + (t >> 7)) * kLC + 8 * ((t >> 6) & 1) + 2 * (d & 3) +
-                          (blk >> 1);
+            const int blk = (d >> 2) & 3;      // 2 s + h
+            const int l = m + (c0 + (t >> 7)) * kLC + 8 * (blk >> 1) + 2 * (d & 3) + (blk & 1);
             if (l > lmax || b >= nmb) continue;
             double v = 0.0;
             for (int w = 0; w < nwaves; ++w) v += stage[w][t];
-            part[(((int64_t)(grp * npc + pc) * 4 + b) * nalm + moff + l) * 2 + (blk & 1)] = v;
+            part[(((int64_t)(grp * npc + pc) * 4 + b) * nalm + moff + l) * 2 + ((t >> 6) & 1)] =
+                v;
         }
         __syncthreads();
     }
@@ -599,6 +656,7 @@ __global__ void k_adj_finalize(const double* __restrict__ part, int npc, int nma
 }  // namespace
 
 int synth_pairs_per_lane(int npairs) { return npairs >= 1024 ? 2 : 1; }
+int synth_scaled_pairs_per_lane(int npairs) { return synth_pairs_per_lane(npairs); }
 
 int launch_legendre_synth(const nusht_plan_s* p, const double* alm, void* out, int nmaps,
                           int fused, int out_f32, hipStream_t s)
@@ -606,9 +664,10 @@ int launch_legendre_synth(const nusht_plan_s* p, const double* alm, void* out, i
     const nusht_geometry& g = p->g;
     const int npairs = (g.nrings + 1) / 2;
     // the plain instance takes two ring pairs per lane once there are enough pairs to fill
-    // the waves; the scaled instance always one, which halves the spread of the scaled
-    // phase's length across the lanes of a wave and keeps its occupancy higher
+    // the waves; the scaled instance one, which halves the spread of the scaled phases'
+    // lengths across the lanes of a wave and keeps its occupancy higher
     const int R = synth_pairs_per_lane(npairs);
+    const int RS = synth_scaled_pairs_per_lane(npairs);
     auto shape = [&](int r, int& bx, int& threads) {
         const int waves_needed = (npairs + 64 * r - 1) / (64 * r);
         const int wpb = waves_needed >= 4 ? 4 : waves_needed;
@@ -617,7 +676,7 @@ int launch_legendre_synth(const nusht_plan_s* p, const double* alm, void* out, i
     };
     int bxp, thp, bxs, ths;
     shape(R, bxp, thp);
-    shape(1, bxs, ths);
+    shape(RS, bxs, ths);
     const int64_t nalm = g.nalm;
     const double2* a = reinterpret_cast<const double2*>(alm);
     int64_t map_stride, row_stride;
@@ -647,7 +706,11 @@ int launch_legendre_synth(const nusht_plan_s* p, const double* alm, void* out, i
     } else {                                          \
         SYN1(MBV, 1, F, OT, false, bxp, thp);         \
     }                                                 \
-    SYN1(MBV, 1, F, OT, true, bxs, ths);
+    if (RS == 2) {                                    \
+        SYN1(MBV, 2, F, OT, true, bxs, ths);          \
+    } else {                                          \
+        SYN1(MBV, 1, F, OT, true, bxs, ths);          \
+    }
         if (fused && out_f32) {
             if (mb == 4) { SYNR(4, true, float2) }
             else if (mb == 2) { SYNR(2, true, float2) }

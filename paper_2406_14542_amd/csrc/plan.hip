@@ -505,8 +505,10 @@ static int build_tables(nusht_plan_s* p)
                 j = lo;
             }
             if (j < jl[m]) j = jl[m];
-            // the synthesis splits its waves at jsc: a multiple of its plain waves' span
-            const int span = 64 * synth_pairs_per_lane(npairs);
+            // the synthesis splits its waves at jsc: a multiple of the spans of both of its
+            // instances' waves (powers of two)
+            const int span = 64 * std::max(synth_pairs_per_lane(npairs),
+                                            synth_scaled_pairs_per_lane(npairs));
             jsc[m] = (j + span - 1) / span * span;
         }
     }
