@@ -195,7 +195,8 @@ constexpr int kT = 32;
 // window row of compact index q: rows [0, ra) then [n1 - rb, n1)
 __device__ inline int window_row(int q, int ra, int rb, int n1) { return q < ra ? q : n1 - rb + (q - ra); }
 
-// rows[i][mu] = band[mu][i] for mu <= M, 0 for mu in (M, fw); window rows only.
+// rows[i][mu] = band[mu][i] for mu <= M, 0 for mu in (M, fw) (fw = the row width); window
+// rows only.
 // Block 32 x 8 threads: tile of 32 compact rows x 32 columns.
 template <typename C>
 __global__ __launch_bounds__(256) void k_band_to_rows(const C* __restrict__ band,
@@ -273,10 +274,11 @@ int launch_zero_nyquist_rows(const nusht_plan_s* p, double* G, int nmaps, hipStr
     return NUSHT_OK;
 }
 
-int launch_band_to_rows(const nusht_plan_s* p, const void* band, void* rows, hipStream_t s)
+int launch_band_to_rows(const nusht_plan_s* p, const void* band, void* rows, int rw,
+                        hipStream_t s)
 {
     const nusht_geometry& g = p->g;
-    const int fw = g.n2 / 2 + 1, nq = p->fine_ra + p->fine_rb;
+    const int fw = rw, nq = p->fine_ra + p->fine_rb;
     dim3 grid((fw + kT - 1) / kT, (nq + kT - 1) / kT);
     dim3 block(kT, 8);
     if (g.dtype == NUSHT_MIXED)
@@ -292,10 +294,11 @@ int launch_band_to_rows(const nusht_plan_s* p, const void* band, void* rows, hip
     return NUSHT_OK;
 }
 
-int launch_rows_to_band(const nusht_plan_s* p, const void* rows, void* band, hipStream_t s)
+int launch_rows_to_band(const nusht_plan_s* p, const void* rows, int rw, void* band,
+                        hipStream_t s)
 {
     const nusht_geometry& g = p->g;
-    const int fw = g.n2 / 2 + 1;
+    const int fw = rw;
     dim3 grid((g.mmax + 1 + kT - 1) / kT, (g.n1 + kT - 1) / kT);
     dim3 block(kT, 8);
     if (g.dtype == NUSHT_MIXED)

@@ -99,7 +99,6 @@ struct nusht_plan_s {
     double* sth = nullptr;       // [npts] theta, sorted by tile
     double* sph = nullptr;       // [npts] phi mod 2 pi, sorted by tile
     int* perm = nullptr;         // [npts] user index of each sorted point
-    int* iperm = nullptr;        // [npts] sorted position of each user index
     int* slot_off = nullptr;     // [nslots+1] first sorted point of each slot
     int* slot_tile = nullptr;    // [nslots] tile id of each slot
     int* tile_slot = nullptr;    // [ntiles] slot of each tile or -1
@@ -116,7 +115,7 @@ struct nusht_plan_s {
     size_t Ybytes = 0;
     void* W = nullptr;           // one map's fine row spectrum [n1][n2/2+1]
     size_t Wbytes = 0;
-    double* V = nullptr;         // FP64 adjoint input of one point group, sorted [npts][4]
+    double* V = nullptr;         // point scratch [npts][4]: packed point values of one group
     void* Z = nullptr;           // spreading subgrids
     size_t Zbytes = 0;
     void* fftwork = nullptr;
@@ -138,6 +137,10 @@ struct nusht_plan_s {
     nusht::FftPlan fine_rowa_c2r, fine_rowa_r2c;  // 1D over n2, batch fine_ra
     nusht::FftPlan fine_rowb_c2r, fine_rowb_r2c;  // 1D over n2, batch fine_rb (may be empty)
     int fine_ra = 0, fine_rb = 0;
+    // Power-of-two n2: the phi pass runs in the library's own row kernels (rowfft.hip), on
+    // row spectra of width mmax + 1 (no zero columns), instead of the rocFFT row plans.
+    bool row_custom = false;
+    void* rowtw = nullptr;  // [n2] e^{2 pi i k / n2} in the plan's FFT precision
 
     // Timing.
     // Timing: every execution call takes the next slot of a ring of kTimingSlots slots, each
@@ -194,11 +197,20 @@ int launch_deconv_pad(const nusht_plan_s* p, const void* tspec, void* fspec, int
                       int f32, hipStream_t s);
 int launch_deconv_trunc(const nusht_plan_s* p, const void* fspec, void* tspec, int nmaps,
                         int fused, int f32, hipStream_t s);
-// band spectrum [mmax+1][n1] <-> row spectrum [n1][n2/2+1] of one map, rows [0, fine_ra)
-// and [n1 - fine_rb, n1) only.  band_to_rows zero-fills the columns above mmax;
-// rows_to_band writes zeros for the rows no window reaches.
-int launch_band_to_rows(const nusht_plan_s* p, const void* band, void* rows, hipStream_t s);
-int launch_rows_to_band(const nusht_plan_s* p, const void* rows, void* band, hipStream_t s);
+// band spectrum [mmax+1][n1] <-> row spectrum [n1][rw] of one map, rows [0, fine_ra) and
+// [n1 - fine_rb, n1) only (rw = n2/2+1 for the rocFFT row plans, mmax+1 for the row kernels).
+// band_to_rows zero-fills the columns mmax+1 .. rw-1; rows_to_band writes zeros for the rows
+// no window reaches.
+int launch_band_to_rows(const nusht_plan_s* p, const void* band, void* rows, int rw,
+                        hipStream_t s);
+int launch_rows_to_band(const nusht_plan_s* p, const void* rows, int rw, void* band,
+                        hipStream_t s);
+
+// ---- fine-grid row transforms for power-of-two n2 (rowfft.hip) ----
+bool rowfft_supported(const nusht_geometry& g);
+// window rows of one map: rows [n1][rw] (columns 0 .. mmax) <-> real fine grid [n1][n2]
+int launch_row_c2r(const nusht_plan_s* p, const void* rows, int64_t rw, void* fine, hipStream_t s);
+int launch_row_r2c(const nusht_plan_s* p, const void* fine, void* rows, int64_t rw, hipStream_t s);
 
 // ---- nonuniform part (nufft_*.hip) ----
 int launch_interp(const nusht_plan_s* p, const void* fine, double* out, int nmaps, int f32,

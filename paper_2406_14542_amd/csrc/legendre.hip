@@ -391,6 +391,7 @@ constexpr int kAdjWaves = 4;     // waves per block: one block reduces up to 256
 constexpr int kLC = 16;          // l values per chunk = the MFMA N dimension
 constexpr int kLS = kLC + 1;     // padded row of the lam staging area
 constexpr int kAdjGroup = 2;     // chunks whose D values are summed over waves together
+constexpr int kAdjPfAhead = 4;   // chunks between a coefficient line's L2 touch and its use
 
 template <typename InT>
 __device__ inline double2 load_c(const InT* p)
@@ -405,16 +406,19 @@ __global__ __launch_bounds__(kAdjWaves * 64, 4) void k_legendre_adj(
     double* __restrict__ part, int npc, int64_t nalm, int lmax,
     const double2* __restrict__ rec, const double* __restrict__ cm_mant,
     const int* __restrict__ cm_exp, const int* __restrict__ jlive, int nr, int nt,
-    int pairs_per_block)
+    int pairs_per_block, int mmax)
 {
     // per wave: the lam values of one chunk (64 pairs x 16 l), and after the MFMAs of a
     // group of kAdjGroup chunks the wave's D values of those chunks (kAdjGroup x 128)
     __shared__ double stage[kAdjWaves][64 * kLS];
     __shared__ float pf_sink[kAdjWaves][64];
     static_assert(kAdjGroup * 128 <= 64 * kLS, "D values of a chunk group fit the staging area");
-    const int m = blockIdx.x;
-    const int pc = blockIdx.y;
-    const int grp = blockIdx.z;
+    // all pair-chunks of one m on one XCD, one after the other: they share the m's
+    // coefficient stream in that XCD's L2
+    int m, pc;
+    xcd_block(blockIdx.x, npc, m, pc);
+    if (m > mmax) return;
+    const int grp = blockIdx.y;
     const int nmb = min(4, nmaps - 4 * grp);
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int nwaves = blockDim.x >> 6;
@@ -529,6 +533,10 @@ __global__ __launch_bounds__(kAdjWaves * 64, 4) void k_legendre_adj(
     const unsigned lds_sink = __builtin_amdgcn_readfirstlane(
         (unsigned)(uintptr_t)(__attribute__((address_space(3))) float*)pf_sink[wave]);
 
+    // the coefficient lines of chunks 1 .. kAdjPfAhead (later chunks are touched kAdjPfAhead
+    // chunks ahead of their use inside the loop)
+    if (!wave_dead && lane < 2 * kAdjPfAhead && m + kLC + 8 * lane <= lmax)
+        pf_keep ^= lds_dma_touch(rec + moff + m + kLC + 8 * lane, lds_sink);
     const int nchunks = (lmax - m) / kLC + 1;
     for (int c0 = 0; c0 < nchunks; c0 += kAdjGroup) {
         double dv[kAdjGroup][2];
@@ -538,12 +546,14 @@ __global__ __launch_bounds__(kAdjWaves * 64, 4) void k_legendre_adj(
             const int l0 = m + (c0 + g) * kLC;
             if (!wave_dead && l0 <= lmax) {
                 // the chunk's recurrence coefficients in one batch of scalar loads (the table
-                // is padded past its end), and the next chunk's lines touched into L2
+                // is padded past its end), and the lines of the chunk kAdjPfAhead ahead
+                // touched into L2
                 double2 cc[kLC];
 #pragma unroll
                 for (int i = 0; i < kLC; ++i) cc[i] = rec[moff + l0 + i];
-                if (lane < 3 && l0 + kLC <= lmax)
-                    pf_keep ^= lds_dma_touch(rec + moff + l0 + kLC + 8 * lane, lds_sink);
+                if (lane < 3 && l0 + kAdjPfAhead * kLC <= lmax)
+                    pf_keep ^= lds_dma_touch(rec + moff + l0 + kAdjPfAhead * kLC + 8 * lane,
+                                             lds_sink);
                 double lam[kLC];
                 if (!__any(scaled) && l0 > m && l0 + kLC - 1 <= lmax) {
                     // common case: a full chunk past lam_mm with no lane scaled
@@ -764,12 +774,13 @@ int launch_legendre_adjoint(const nusht_plan_s* p, const void* in, double* alm, 
         map_stride = (int64_t)g.nrings * row_stride;
     }
     double* part = reinterpret_cast<double*>(scratch);
-    dim3 grid(g.mmax + 1, npc, groups);
+    const int mpad = (g.mmax + 1 + 7) / 8 * 8;
+    dim3 grid(npc * mpad, groups);
 #define ADJ(F, IT)                                                                              \
     hipLaunchKernelGGL((k_legendre_adj<F, IT>), grid, dim3(threads), 0, s,                       \
                        reinterpret_cast<const IT*>(in), map_stride, row_stride, nmaps, part, npc, \
                        g.nalm, g.lmax, p->rec, p->cm_mant, p->cm_exp, p->jlive, g.nrings,        \
-                       g.ntorus, ppb)
+                       g.ntorus, ppb, g.mmax)
     if (fused && in_f32) {
         ADJ(true, float2);
     } else if (fused) {

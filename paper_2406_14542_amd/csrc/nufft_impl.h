@@ -8,12 +8,11 @@
 // workgroup owns one non-empty tile ("slot") and the tile's window of
 // (kTile + w - 1)^2 cells, which it stages in LDS.
 //  * interpolation: window loaded once from HBM, every point of the tile reads its w x w taps
-//    from LDS, result written straight to the caller's point order;
-//  * spreading: FP32 output-stationary (threads own cells of the tile window and gather the
-//    contributions of the row-sorted points, taps staged in LDS), FP64 LDS atomics laid
-//    out for the banks; the window is
-//    written once to a per-slot subgrid; a second pass sums, for every fine cell, the
-//    subgrids of the (at most four) windows that cover it.  No atomics of any kind.
+//    from LDS, results written packed per point in the caller's point order;
+//  * spreading: the tile's points (values packed per point, fetched through the permutation)
+//    are added into an FP64 LDS copy of the window with LDS atomics; the window is written
+//    once to a per-slot subgrid, and a second pass sums, for every fine cell, the subgrids of
+//    the (at most four) windows that cover it (no global atomics).
 // Offsets are formed in FP64 from FP64 coordinates before any cast to the kernel's type T.
 #pragma once
 
@@ -127,7 +126,9 @@ __device__ inline void stage_window(const T* __restrict__ fine, int64_t map_stri
     }
 }
 
-template <typename T, int W, int MB>
+// PACKED: out[dst][MB] (one MB * 8-byte store per point, unpacked afterwards by
+// k_unpack_points); otherwise out[b][dst] (MB scattered 8-byte stores).
+template <typename T, int W, int MB, bool PACKED>
 __global__ __launch_bounds__(256) void k_interp(const T* __restrict__ fine, int64_t map_stride,
                                                 PointBins pb, T beta, double* __restrict__ out,
                                                 int64_t npts)
@@ -186,9 +187,42 @@ __global__ __launch_bounds__(256) void k_interp(const T* __restrict__ fine, int6
 #pragma unroll
             for (int b = 0; b < MB; ++b) acc[b] += p1v[a] * row[b];
         }
+        if (PACKED) {
+            double* o = out + dst * MB;
 #pragma unroll
-        for (int b = 0; b < MB; ++b) out[b * npts + dst] = (double)acc[b];
+            for (int b = 0; b < MB; ++b) o[b] = (double)acc[b];
+        } else {
+#pragma unroll
+            for (int b = 0; b < MB; ++b) out[b * npts + dst] = (double)acc[b];
+        }
     }
+}
+
+// out[b][i] = packed[i][b]: both sides coalesced
+template <int MB>
+__global__ void k_unpack_points(const double* __restrict__ packed, int64_t npts,
+                                double* __restrict__ out)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= npts) return;
+    double v[MB];
+#pragma unroll
+    for (int b = 0; b < MB; ++b) v[b] = packed[i * MB + b];
+#pragma unroll
+    for (int b = 0; b < MB; ++b) out[b * npts + i] = v[b];
+}
+
+// packed[i][b] = (T) in[b][i], the caller's point order kept: both sides coalesced
+template <typename T, int MB>
+__global__ void k_pack_values(const double* __restrict__ in, int64_t npts, T* __restrict__ packed)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= npts) return;
+    T v[MB];
+#pragma unroll
+    for (int b = 0; b < MB; ++b) v[b] = (T)in[b * npts + i];
+#pragma unroll
+    for (int b = 0; b < MB; ++b) packed[i * MB + b] = v[b];
 }
 
 template <int W, int MB>
@@ -269,56 +303,50 @@ __global__ __launch_bounds__(256) void k_interp_deriv(const double* __restrict__
     }
 }
 
-// Spreading, output-stationary (used for FP32).  Points of a slot arrive sorted by their
-// row inside the tile.  Per batch of NB points the block stores, in LDS, each point's row
-// and column in the tile, its values f[b], its row taps psi1[0..W) and its column taps psi2
-// padded with 8 zeros on both sides.  Thread (R, ch) owns window row R and columns
-// 8 ch .. 8 ch + 7 of the tile window in registers and adds, for every point whose rows
-// R - W + 1 .. R touch it, f psi1[R - r] psi2[C - c] to its 8 cells.  No atomics; every
-// cell sums its points in the same (sorted) order on every run.
-template <typename T, int W, int MB>
-struct SpreadShape {
-    static constexpr int P = kTile + W - 1;
-    static constexpr int CW = 8;
-    static constexpr int NCH = (P + CW - 1) / CW;
-    static constexpr int NT = ((P * NCH + 63) / 64) * 64;
-    static constexpr int PADW = W + 2 * CW;
-    static constexpr int PER = (W + MB + PADW) * (int)sizeof(T) + 2 * (int)sizeof(int);
-    static constexpr int NB0 = (65536 / PER) / 64 * 64;
-    static constexpr int NB = NB0 < NT ? NB0 : NT;
-    static_assert(NT <= 320 && NB >= 64, "spreading block shape");
+// Spreading with LDS atomics, batched.  The block stages up to NB of the slot's points (tap
+// offsets, first cells relative to the tile, values) in LDS, then every wave takes
+// PPW = 64 / LPP points at a time with LPP lanes per point, lane = column tap: each lane forms
+// its column tap psi2[col] and the row tap psi1[col], the row taps of the point are exchanged
+// through a per-wave LDS row, and lane (point, col) adds f psi1[a] psi2[col] into window
+// rows r + a, a < W, of its column.  The window is planar (map-major), so the lanes of one
+// point add into consecutive words of one row.  Values come in packed, [point][MB], in the
+// caller's order, and are fetched through the permutation.  The window sums in FP64; the order of the additions into a cell is not fixed, so results can
+// differ between runs by FP64 rounding (~1e-16 relative) before the cast to T.
+template <typename T, int MB>
+struct SpreadPoint {
+    T d1, d2;  // offsets of the first taps, grid units
+    int r, c;  // first tap cell relative to the tile
+    T f[MB];
 };
 
 template <typename T, int W, int MB>
-__global__ __launch_bounds__(320) void k_spread_rows(
-    const double* __restrict__ in, int64_t npts, PointBins pb, T beta, T* __restrict__ sub)
+__global__ __launch_bounds__(256) void k_spread_lds(const T* __restrict__ vals, PointBins pb,
+                                                    T beta, T* __restrict__ sub)
 {
-    using S = SpreadShape<T, W, MB>;
-    constexpr int P = S::P, CW = S::CW, NCH = S::NCH, NB = S::NB, PADW = S::PADW;
-    __shared__ T s_p1[NB][W];
-    __shared__ T s_f[NB][MB];
-    __shared__ T s_p2[NB][PADW];
-    __shared__ int s_row[NB], s_col[NB];
-    __shared__ int s_rs[kTile + 1];
-
+    constexpr int P = kTile + W - 1;
+    constexpr int LPP = W <= 8 ? 8 : 16;
+    constexpr int PPW = 64 / LPP;
+    constexpr int NB = sizeof(T) == 4 ? 128 : 64;
+    static_assert(W <= 16, "one lane per column tap");
+    // the window accumulates in FP64 for either T: LDS atomic adds of FP64 measured fast on
+    // gfx950, those of FP32 an order of magnitude slower than the whole kernel
+    __shared__ double win[MB * P * P];
+    __shared__ SpreadPoint<T, MB> s_pt[NB];
+    __shared__ T s_p1[4][PPW][LPP];
     const int slot = blockIdx.x;
     const int tile = pb.slot_tile[slot];
     const int r0 = (tile / pb.nt2) * kTile;
     const int c0 = (tile % pb.nt2) * kTile;
     const int t = threadIdx.x;
-    const int R = t / NCH;
-    const int C0 = (t - R * NCH) * CW;
-    const bool owner = R < P;
-    T acc[CW][MB];
-#pragma unroll
-    for (int k = 0; k < CW; ++k)
-#pragma unroll
-        for (int b = 0; b < MB; ++b) acc[k][b] = T(0);
-
+    for (int e = t; e < MB * P * P; e += blockDim.x) win[e] = 0.0;
+    const int wave = t >> 6, lane = t & 63;
+    const int grp = lane / LPP, col = lane - grp * LPP;
     const int p0 = pb.slot_off[slot], p1 = pb.slot_off[slot + 1];
+    const T cw = T(2) / T(W);
+    T* p1row = s_p1[wave][grp];
     for (int base = p0; base < p1; base += NB) {
         const int nb = min(NB, p1 - base);
-        __syncthreads();  // previous batch fully consumed
+        __syncthreads();  // window cleared, or the previous batch consumed
         if (t < nb) {
             const int p = base + t;
             double d1, d2;
@@ -326,127 +354,56 @@ __global__ __launch_bounds__(320) void k_spread_rows(
             const int l2 = first_tap(pb.sph[p], pb.s2, W, d2);
             int r = wrap_index(l1, pb.n1) - r0;
             int c = wrap_index(l2, pb.n2) - c0;
-            r = min(max(r, 0), kTile - 1);
-            c = min(max(c, 0), kTile - 1);
-            T a1[W], a2[W];
-            es_taps<T, W>(d1, beta, a1);
-            es_taps<T, W>(d2, beta, a2);
-#pragma unroll
-            for (int a = 0; a < W; ++a) s_p1[t][a] = a1[a];
-#pragma unroll
-            for (int q = 0; q < PADW; ++q) s_p2[t][q] = T(0);
-#pragma unroll
-            for (int q = 0; q < W; ++q) s_p2[t][CW + q] = a2[q];
             const int64_t src = pb.perm[p];
+            SpreadPoint<T, MB> sp;
+            sp.d1 = (T)d1;
+            sp.d2 = (T)d2;
+            sp.r = min(max(r, 0), kTile - 1);
+            sp.c = min(max(c, 0), kTile - 1);
 #pragma unroll
-            for (int b = 0; b < MB; ++b) s_f[t][b] = (T)in[b * npts + src];
-            s_row[t] = r;
-            s_col[t] = c;
+            for (int b = 0; b < MB; ++b) sp.f[b] = vals[src * MB + b];
+            s_pt[t] = sp;
         }
         __syncthreads();
-        // first point of each row (points are sorted by row)
-        if (t <= kTile) {
-            int lo = 0, hi = nb;
-            while (lo < hi) {
-                const int mid = (lo + hi) >> 1;
-                if (s_row[mid] < t) lo = mid + 1;
-                else hi = mid;
-            }
-            s_rs[t] = lo;
-        }
-        __syncthreads();
-        if (owner) {
-            const int rlo = max(0, R - W + 1), rhi = min(kTile - 1, R);
-            if (rlo <= rhi) {
-                const int q1 = s_rs[rhi + 1];
-                for (int q = s_rs[rlo]; q < q1; ++q) {
-                    const int c = s_col[q];
-                    const int a = R - s_row[q];
-                    if (c > C0 + CW - 1 || c + W - 1 < C0 || a < 0 || a >= W) continue;
-                    const T pa = s_p1[q][a];
-                    T fa[MB];
+        // lane group g takes the points g S + i of the row-sorted batch: the PPW points of one
+        // step lie S apart, in different rows, so no two lanes of an atomic add address the
+        // same cell (a point adds into rows r + a for the step's common a)
+        const int S = (nb + PPW - 1) / PPW;
+        for (int i = wave; i < S; i += 4) {
+            const int q = grp * S + i;
+            const bool live = q < nb;
+            const SpreadPoint<T, MB> sp = s_pt[live ? q : 0];
+            const bool act = live && col < W;
+            const T p2 = act ? es_value<T>((sp.d2 - T(col)) * cw, beta) : T(0);
+            p1row[col] = col < W ? es_value<T>((sp.d1 - T(col)) * cw, beta) : T(0);
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+            T pr[W];
 #pragma unroll
-                    for (int b = 0; b < MB; ++b) fa[b] = s_f[q][b] * pa;
-                    const T* p2 = &s_p2[q][CW + C0 - c];
-#pragma unroll
-                    for (int k = 0; k < CW; ++k) {
-                        const T v = p2[k];
-#pragma unroll
-                        for (int b = 0; b < MB; ++b) acc[k][b] += fa[b] * v;
-                    }
-                }
-            }
-        }
-    }
-    if (owner) {
-        T* dst = sub + (int64_t)slot * (P * P * MB) + (R * P) * MB;
-#pragma unroll
-        for (int k = 0; k < CW; ++k) {
-            const int C = C0 + k;
-            if (C < P) {
-#pragma unroll
-                for (int b = 0; b < MB; ++b) dst[C * MB + b] = acc[k][b];
-            }
-        }
-    }
-}
-
-// Spreading with LDS atomics arranged for the LDS banks (used for FP64, where it measured
-// faster than the row-owner kernel): the window is planar (map-major) and a wave works on
-// 4 points at a time, lane = 16 * point + tap column, so the 16 lanes of a point add into
-// 16 consecutive words of one window row.  The order of the additions into a cell is not
-// fixed, so FP64 spreading can differ between runs by rounding (~1e-16 relative).
-template <typename T, int W, int MB>
-__global__ __launch_bounds__(256) void k_spread_atomic(const double* __restrict__ vals,
-                                                       PointBins pb, T beta,
-                                                       T* __restrict__ sub)
-{
-    constexpr int P = kTile + W - 1;
-    __shared__ T win[MB * P * P];
-    const int slot = blockIdx.x;
-    const int tile = pb.slot_tile[slot];
-    const int r0 = (tile / pb.nt2) * kTile;
-    const int c0 = (tile % pb.nt2) * kTile;
-    for (int e = threadIdx.x; e < MB * P * P; e += blockDim.x) win[e] = T(0);
-    __syncthreads();
-    const int lane = threadIdx.x & 63;
-    const int grp = lane >> 4, col = lane & 15;
-    const int gwave = threadIdx.x >> 6, nwaves = blockDim.x >> 6;
-    const int p0 = pb.slot_off[slot], p1 = pb.slot_off[slot + 1];
-    const T cw = T(2) / T(W);
-    for (int pb0 = p0 + 4 * gwave; pb0 < p1; pb0 += 4 * nwaves) {
-        const int p = pb0 + grp;
-        const bool live = p < p1;
-        const int pp = live ? p : p0;
-        double d1, d2;
-        const int l1 = first_tap(pb.sth[pp], pb.s1, W, d1);
-        const int l2 = first_tap(pb.sph[pp], pb.s2, W, d2);
-        int r = wrap_index(l1, pb.n1) - r0;
-        int c = wrap_index(l2, pb.n2) - c0;
-        r = min(max(r, 0), kTile - 1);
-        c = min(max(c, 0), kTile - 1);
-        const bool act = live && col < W;
-        // this lane's column tap and its point's row tap number `col`
-        const T p2 = act ? es_value<T>(((T)d2 - T(col)) * cw, beta) : T(0);
-        const T p1c = col < W ? es_value<T>(((T)d1 - T(col)) * cw, beta) : T(0);
-        T f[MB];
-#pragma unroll
-        for (int b = 0; b < MB; ++b) f[b] = live ? (T)vals[(int64_t)pp * MB + b] * p2 : T(0);
-        const int cc = c + (col < W ? col : 0);
-#pragma unroll
-        for (int a = 0; a < W; ++a) {
-            const T pa = __shfl(p1c, (grp << 4) + a, 64);
+            for (int a = 0; a < W; ++a) pr[a] = p1row[a];
+            // the next step rewrites the row: every lane's reads come first
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
             if (act) {
+                T fb[MB];
 #pragma unroll
-                for (int b = 0; b < MB; ++b) atomicAdd(&win[(b * P + r + a) * P + cc], f[b] * pa);
+                for (int b = 0; b < MB; ++b) fb[b] = sp.f[b] * p2;
+                double* w0 = win + sp.r * P + sp.c + col;
+#pragma unroll
+                for (int a = 0; a < W; ++a)
+#pragma unroll
+                    for (int b = 0; b < MB; ++b)
+                        atomicAdd(w0 + (b * P + a) * P, (double)(fb[b] * pr[a]));
             }
         }
     }
     __syncthreads();
     T* dst = sub + (int64_t)slot * (P * P * MB);
-    for (int e = threadIdx.x; e < P * P; e += blockDim.x) {
+    for (int e = t; e < P * P; e += blockDim.x) {
 #pragma unroll
-        for (int b = 0; b < MB; ++b) dst[e * MB + b] = win[b * P * P + e];
+        for (int b = 0; b < MB; ++b) dst[e * MB + b] = (T)win[b * P * P + e];
     }
 }
 
@@ -523,6 +480,10 @@ inline PointBins make_bins(const nusht_plan_s* p)
         default: set_last_error("nufft", "unsupported kernel width"); return NUSHT_EINVAL; \
     }
 
+// Interpolation of maps [0, nmaps): groups of four write packed rows [point][4] into the plan's
+// point scratch (one 32-byte store per point instead of four scattered 8-byte ones), unpacked
+// into out afterwards; a single map writes straight to out.
+
 template <typename T>
 int dispatch_interp_impl(const nusht_plan_s* p, const T* fine, double* out, int nmaps, T beta,
                          hipStream_t s)
@@ -531,16 +492,20 @@ int dispatch_interp_impl(const nusht_plan_s* p, const T* fine, double* out, int 
     const PointBins pb = make_bins(p);
     const int64_t ms = (int64_t)p->g.n1 * p->g.n2;
     const int64_t npts = p->g.npts;
+    const unsigned pblocks = (unsigned)((npts + 255) / 256);
     int b = 0;
     while (b < nmaps) {
         const int mb = group_width(nmaps, b);
         NUSHT_WIDTH_SWITCH(p->g.width, {
-            if (mb == 4)
-                hipLaunchKernelGGL((k_interp<T, WV, 4>), dim3(p->nslots), dim3(256), 0, s,
-                                   fine + b * ms, ms, pb, beta, out + b * npts, npts);
-            else
-                hipLaunchKernelGGL((k_interp<T, WV, 1>), dim3(p->nslots), dim3(256), 0, s,
-                                   fine + b * ms, ms, pb, beta, out + b * npts, npts);
+            if (mb == 4) {
+                hipLaunchKernelGGL((k_interp<T, WV, 4, true>), dim3(p->nslots), dim3(256), 0, s,
+                                   fine + b * ms, ms, pb, beta, p->V, npts);
+                hipLaunchKernelGGL(k_unpack_points<4>, dim3(pblocks), dim3(256), 0, s, p->V,
+                                   npts, out + b * npts);
+            } else {
+                hipLaunchKernelGGL((k_interp<T, WV, 1, false>), dim3(p->nslots), dim3(256), 0,
+                                   s, fine + b * ms, ms, pb, beta, out + b * npts, npts);
+            }
         });
         NUSHT_HIP(hipGetLastError());
         b += mb;
@@ -548,11 +513,10 @@ int dispatch_interp_impl(const nusht_plan_s* p, const T* fine, double* out, int 
     return NUSHT_OK;
 }
 
-// spreading of maps [b, b + mb) into the slot subgrids (mb = 1 or 4)
-// FP64 (LDS atomics): `vals` holds the group's values in tile-sorted order, [npts][mb]
-// (k_sort_values); gathering them inside the atomic loop stalls it.  FP32 (output-
-// stationary): `vals` is the caller's map block [mb][npts], gathered through the
-// permutation while the block stages its points -- cheaper there than a separate pass.
+// Spreading of the caller's maps [b, b + mb) (`vals` = its map block [mb][npts]) into the
+// slot subgrids: the values are first packed [point][mb] in the caller's order into the
+// plan's point scratch, and the spreading kernel fetches a point's mb values with one load
+// through the permutation.
 template <typename T>
 int spread_group_impl(const nusht_plan_s* p, const double* vals, T* sub, int mb, T beta,
                       hipStream_t s)
@@ -560,21 +524,22 @@ int spread_group_impl(const nusht_plan_s* p, const double* vals, T* sub, int mb,
     if (p->nslots == 0) return NUSHT_OK;
     const PointBins pb = make_bins(p);
     const int64_t npts = p->g.npts;
+    const unsigned pblocks = (unsigned)((npts + 255) / 256);
+    T* packed = reinterpret_cast<T*>(p->V);
+    if (mb == 4)
+        hipLaunchKernelGGL((k_pack_values<T, 4>), dim3(pblocks), dim3(256), 0, s, vals, npts,
+                           packed);
+    else
+        hipLaunchKernelGGL((k_pack_values<T, 1>), dim3(pblocks), dim3(256), 0, s, vals, npts,
+                           packed);
+    NUSHT_HIP(hipGetLastError());
     NUSHT_WIDTH_SWITCH(p->g.width, {
-        if (sizeof(T) == 8) {
-            if (mb == 4)
-                hipLaunchKernelGGL((k_spread_atomic<T, WV, 4>), dim3(p->nslots), dim3(256), 0, s,
-                                   vals, pb, beta, sub);
-            else
-                hipLaunchKernelGGL((k_spread_atomic<T, WV, 1>), dim3(p->nslots), dim3(256), 0, s,
-                                   vals, pb, beta, sub);
-        } else if (mb == 4) {
-            hipLaunchKernelGGL((k_spread_rows<T, WV, 4>), dim3(p->nslots),
-                               dim3(SpreadShape<T, WV, 4>::NT), 0, s, vals, npts, pb, beta, sub);
-        } else {
-            hipLaunchKernelGGL((k_spread_rows<T, WV, 1>), dim3(p->nslots),
-                               dim3(SpreadShape<T, WV, 1>::NT), 0, s, vals, npts, pb, beta, sub);
-        }
+        if (mb == 4)
+            hipLaunchKernelGGL((k_spread_lds<T, WV, 4>), dim3(p->nslots), dim3(256), 0, s,
+                               packed, pb, beta, sub);
+        else
+            hipLaunchKernelGGL((k_spread_lds<T, WV, 1>), dim3(p->nslots), dim3(256), 0, s,
+                               packed, pb, beta, sub);
     });
     NUSHT_HIP(hipGetLastError());
     return NUSHT_OK;

@@ -133,12 +133,6 @@ __global__ void k_gather_sorted(const double* __restrict__ theta, const double* 
     sph[k] = phw[i];
 }
 
-__global__ void k_invert(const int* __restrict__ perm, int64_t n, int* __restrict__ iperm)
-{
-    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (k < n) iperm[perm[k]] = (int)k;
-}
-
 __global__ void k_mark(const int* __restrict__ keys, int64_t n, int* __restrict__ first)
 {
     const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -297,7 +291,7 @@ int ensure_capacity(nusht_plan_s* p, int nmaps)
         NUSHT_TRY(dmalloc((char**)&p->W, fine_spec));
         p->Wbytes = fine_spec;
     }
-    if (!p->V && g.dtype == NUSHT_F64) NUSHT_TRY(dmalloc(&p->V, (size_t)g.npts * 4));
+    if (!p->V) NUSHT_TRY(dmalloc(&p->V, (size_t)g.npts * 4));
     p->bcap = nmaps;
     return NUSHT_OK;
 }
@@ -324,8 +318,7 @@ int bin_points(nusht_plan_s* p, const double* theta, const double* phi, hipStrea
     do {
         if ((rc = dmalloc(&keys, n)) || (rc = dmalloc(&keys_s, n)) || (rc = dmalloc(&idx, n)) ||
             (rc = dmalloc(&first, n)) || (rc = dmalloc(&sidx, n)) || (rc = dmalloc(&phw, n)) ||
-            (rc = dmalloc(&p->perm, n)) || (rc = dmalloc(&p->iperm, n)) ||
-            (rc = dmalloc(&p->sth, n)) ||
+            (rc = dmalloc(&p->perm, n)) || (rc = dmalloc(&p->sth, n)) ||
             (rc = dmalloc(&p->sph, n)) || (rc = dmalloc(&p->tile_slot, ntiles)) ||
             (rc = dmalloc(&p->dflag, 1)))
             break;
@@ -342,7 +335,6 @@ int bin_points(nusht_plan_s* p, const double* theta, const double* phi, hipStrea
                                                bits, s) != hipSuccess) { rc = NUSHT_EDEVICE; break; }
         hipLaunchKernelGGL(k_gather_sorted, dim3(blocks), dim3(256), 0, s, theta, phw, p->perm, n,
                            p->sth, p->sph);
-        hipLaunchKernelGGL(k_invert, dim3(blocks), dim3(256), 0, s, p->perm, n, p->iperm);
         hipLaunchKernelGGL(k_mark, dim3(blocks), dim3(256), 0, s, keys_s, n, first);
         if (hipcub::DeviceScan::ExclusiveSum(tmp, tbytes, first, sidx, (int)n, s) != hipSuccess) { rc = NUSHT_EDEVICE; break; }
         int last_first = 0, last_idx = 0, flag = 0;
@@ -593,10 +585,10 @@ void nusht_destroy(nusht_plan_t p)
     hipDeviceSynchronize();
     destroy_fft_plans(p);
     void* bufs[] = {p->rec,  p->cm_mant, p->cm_exp,   p->dec1,      p->dec2,      p->dec1f,
-                    p->dec2f, p->sth,    p->sph,      p->perm,      p->iperm,     p->V,
+                    p->dec2f, p->sth,    p->sph,      p->perm,      p->V,
                     p->slot_off,  p->slot_tile,
                     p->tile_slot, p->dflag, p->X,     p->Y,         p->Z,         p->W,
-                    p->fftwork,
+                    p->fftwork,   p->rowtw,
                     p->red,      p->jlive,  p->jscale};
     for (void* b : bufs)
         if (b) hipFree(b);

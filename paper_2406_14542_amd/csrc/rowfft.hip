@@ -1,0 +1,355 @@
+// Row transforms of the fine grid (the phi direction of N's 2-D FFT, arXiv:2406.14542
+// Sec. III) for power-of-two row lengths n2, one workgroup per window row:
+//   C2R  x[n] = sum_{k=0}^{n2-1} X[k] e^{+2 pi i k n / n2},  X[n2 - k] = conj X[k],
+//        X[k] = 0 for M < k < n2 - M (the band limit), Im X[0] ignored;
+//   R2C  X[k] = sum_n x[n] e^{-2 pi i k n / n2}, k = 0 .. M only.
+// Both take the half-length route: with N = n2 / 2 and z[n] = x[2n] + i x[2n+1],
+//   z = IDFT_N(Z),  Z[k] = E[k] + i O[k],  E[k] = X[k] + X[k + N],
+//   O[k] = (X[k] - X[k + N]) e^{2 pi i k / n2},  X[k + N] = conj X[N - k];
+// and backwards E = (Z[k] + conj Z[N-k]) / 2, O = (Z[k] - conj Z[N-k]) / (2i),
+//   X[k] = E + e^{-2 pi i k / n2} O.
+// The N-point transform runs in LDS as Stockham radix passes (a first pass of radix
+// 2^(log2 N mod 4) when needed, then radix 16), reading the row straight from HBM in the
+// first pass and writing it in the last: one read and one write of each row, and only the
+// M + 1 band columns of the spectrum are read (C2R) or written (R2C).
+#include "internal.h"
+
+namespace nusht {
+namespace {
+
+template <typename T>
+struct Cx;
+template <>
+struct Cx<float> {
+    using type = float2;
+};
+template <>
+struct Cx<double> {
+    using type = double2;
+};
+
+template <typename C>
+__device__ inline C cmk(decltype(C::x) re, decltype(C::x) im)
+{
+    C r;
+    r.x = re;
+    r.y = im;
+    return r;
+}
+template <typename C>
+__device__ inline C cadd(C a, C b)
+{
+    return cmk<C>(a.x + b.x, a.y + b.y);
+}
+template <typename C>
+__device__ inline C csub(C a, C b)
+{
+    return cmk<C>(a.x - b.x, a.y - b.y);
+}
+template <typename C>
+__device__ inline C cmul(C a, C b)
+{
+    return cmk<C>(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+// a * (DIR i)
+template <int DIR, typename C>
+__device__ inline C cmul_i(C a)
+{
+    return DIR > 0 ? cmk<C>(-a.y, a.x) : cmk<C>(a.y, -a.x);
+}
+
+// cos and sin of 2 pi e / 16
+__device__ constexpr double kCos16[16] = {
+    1.0, 0.92387953251128675613, 0.70710678118654752440, 0.38268343236508977173,
+    0.0, -0.38268343236508977173, -0.70710678118654752440, -0.92387953251128675613,
+    -1.0, -0.92387953251128675613, -0.70710678118654752440, -0.38268343236508977173,
+    0.0, 0.38268343236508977173, 0.70710678118654752440, 0.92387953251128675613};
+__device__ constexpr double kSin16[16] = {
+    0.0, 0.38268343236508977173, 0.70710678118654752440, 0.92387953251128675613,
+    1.0, 0.92387953251128675613, 0.70710678118654752440, 0.38268343236508977173,
+    0.0, -0.38268343236508977173, -0.70710678118654752440, -0.92387953251128675613,
+    -1.0, -0.92387953251128675613, -0.70710678118654752440, -0.38268343236508977173};
+
+// a * e^{DIR 2 pi i e / 16}; e is a constant once the callers' loops are unrolled, so the
+// branches and the table lookups fold away
+template <int DIR, typename C>
+__device__ __forceinline__ C rot16(C a, int e)
+{
+    using T = decltype(C::x);
+    e &= 15;
+    if (e == 0) return a;
+    if (e == 4) return cmul_i<DIR>(a);
+    if (e == 8) return cmk<C>(-a.x, -a.y);
+    if (e == 12) return cmul_i<-DIR>(a);
+    return cmul(a, cmk<C>((T)kCos16[e], (T)(DIR * kSin16[e])));
+}
+
+// in-place DFT of R = 1, 2, 4, 8 or 16 values, natural order in and out:
+// V[k] = sum_n v[n] e^{DIR 2 pi i n k / R}
+template <int R, int DIR, typename C>
+__device__ inline void dft(C (&v)[R])
+{
+    if constexpr (R == 2) {
+        const C a = v[0];
+        v[0] = cadd(a, v[1]);
+        v[1] = csub(a, v[1]);
+    } else if constexpr (R == 4) {
+        const C a0 = cadd(v[0], v[2]), a1 = csub(v[0], v[2]);
+        const C a2 = cadd(v[1], v[3]), a3 = cmul_i<DIR>(csub(v[1], v[3]));
+        v[0] = cadd(a0, a2);
+        v[2] = csub(a0, a2);
+        v[1] = cadd(a1, a3);
+        v[3] = csub(a1, a3);
+    } else if constexpr (R == 8 || R == 16) {
+        // R = 4 Q: n = Q n1 + n2, k = k1 + 4 k2; DFT_4 over n1, twiddle e^{DIR 2 pi i n2 k1 / R},
+        // DFT_Q over n2
+        constexpr int Q = R / 4;
+        C u[4][Q];
+#pragma unroll
+        for (int n2 = 0; n2 < Q; ++n2) {
+            C w[4] = {v[n2], v[Q + n2], v[2 * Q + n2], v[3 * Q + n2]};
+            dft<4, DIR>(w);
+#pragma unroll
+            for (int k1 = 0; k1 < 4; ++k1) u[k1][n2] = rot16<DIR>(w[k1], n2 * k1 * (16 / R));
+        }
+#pragma unroll
+        for (int k1 = 0; k1 < 4; ++k1) {
+            dft<Q, DIR>(u[k1]);
+#pragma unroll
+            for (int k2 = 0; k2 < Q; ++k2) v[k1 + 4 * k2] = u[k1][k2];
+        }
+    }
+}
+
+// LDS index with one pad slot per 16 entries (stride-16 accesses stay off one bank)
+__device__ inline int pad16(int i) { return i + (i >> 4); }
+
+template <int K>
+struct RowShape {
+    static constexpr int N = 1 << K;                          // complex points
+    static constexpr int NB16 = N / 16;                       // radix-16 butterflies per pass
+    static constexpr int NT = NB16 < 64 ? 64 : NB16;          // threads
+    static constexpr int R0 = (K % 4) ? (1 << (K % 4)) : 16;  // first pass radix
+    static constexpr int NPASS16 = (K % 4) ? K / 4 : K / 4 - 1;  // radix-16 passes after it
+};
+
+// One Stockham pass (radix R, span Ns) over LDS, in place: every thread loads the inputs of
+// its butterflies, the block synchronises, then the outputs are written.
+//   butterfly idx: inputs in[idx + r N / R], twiddle e^{DIR 2 pi i j r / (Ns R)} (j = idx mod
+//   Ns), DFT_R, outputs out[(idx - j) R + j + r Ns].
+// tw[m] = e^{2 pi i m / n2} (n2 = 2 N), so e^{2 pi i a / N} = tw[2 a].
+template <int R, int DIR, typename C>
+__device__ inline void twiddle(C (&v)[R], int j, int Ns, int N, const C* __restrict__ tw)
+{
+    if (Ns == 1) return;
+    const int step = 2 * j * (N / (Ns * R));
+#pragma unroll
+    for (int r = 1; r < R; ++r) {
+        C w = tw[r * step];
+        if (DIR < 0) w.y = -w.y;
+        v[r] = cmul(v[r], w);
+    }
+}
+
+template <int K, int DIR, typename C>
+__device__ inline void middle_passes(C* buf, int t, const C* __restrict__ tw)
+{
+    using S = RowShape<K>;
+    constexpr int N = S::N;
+    int Ns = S::R0;
+    for (int p = 0; p < S::NPASS16 - 1; ++p) {
+        C v[16];
+        const bool act = t < S::NB16;
+        if (act) {
+#pragma unroll
+            for (int r = 0; r < 16; ++r) v[r] = buf[pad16(t + r * (N / 16))];
+        }
+        __syncthreads();
+        if (act) {
+            const int j = t & (Ns - 1);
+            twiddle<16, DIR>(v, j, Ns, N, tw);
+            dft<16, DIR>(v);
+            const int base = (t - j) * 16 + j;
+#pragma unroll
+            for (int r = 0; r < 16; ++r) buf[pad16(base + r * Ns)] = v[r];
+        }
+        __syncthreads();
+        Ns *= 16;
+    }
+}
+
+// C2R of window rows: blockIdx.x = compact window row q, fine row i = q for q < ra, else
+// n1 - rb + (q - ra).  rows: [i][rw] spectrum columns 0 .. ncol-1 (ncol = M + 1 <= N);
+// fine: real [n1][n2].
+template <typename T, int K>
+__global__ __launch_bounds__(RowShape<K>::NT) void k_row_c2r(
+    const typename Cx<T>::type* __restrict__ rows, int64_t rw, int ncol,
+    T* __restrict__ fine, int n1, int ra, int rb, const typename Cx<T>::type* __restrict__ tw)
+{
+    using C = typename Cx<T>::type;
+    using S = RowShape<K>;
+    constexpr int N = S::N, R0 = S::R0;
+    __shared__ C buf[N + N / 16];
+    const int q = blockIdx.x, t = threadIdx.x;
+    const int i = q < ra ? q : n1 - rb + (q - ra);
+    const C* X = rows + (int64_t)i * rw;
+    const int M = ncol - 1;
+    // first pass (span 1) from HBM: Z[k] built from X[k] and X[N - k]
+    for (int idx = t; idx < N / R0; idx += S::NT) {
+        C v[R0];
+#pragma unroll
+        for (int r = 0; r < R0; ++r) {
+            const int k = idx + r * (N / R0);
+            C xk = k <= M ? X[k] : cmk<C>(0, 0);
+            if (k == 0) xk.y = 0;
+            const C xm = (k > 0 && N - k <= M) ? X[N - k] : cmk<C>(0, 0);
+            const C xc = cmk<C>(xm.x, -xm.y);
+            const C e = cadd(xk, xc);
+            const C o = cmul(csub(xk, xc), tw[k]);
+            v[r] = cmk<C>(e.x - o.y, e.y + o.x);
+        }
+        dft<R0, +1>(v);
+#pragma unroll
+        for (int r = 0; r < R0; ++r) buf[pad16(idx * R0 + r)] = v[r];
+    }
+    __syncthreads();
+    middle_passes<K, +1>(buf, t, tw);
+    // last pass (radix 16, span N / 16) into the fine row: z[n] = x[2n] + i x[2n+1]
+    if (t < S::NB16) {
+        C v[16];
+#pragma unroll
+        for (int r = 0; r < 16; ++r) v[r] = buf[pad16(t + r * (N / 16))];
+        twiddle<16, +1>(v, t, N / 16, N, tw);
+        dft<16, +1>(v);
+        C* z = reinterpret_cast<C*>(fine + (int64_t)i * (2 * N));
+#pragma unroll
+        for (int r = 0; r < 16; ++r) z[t + r * (N / 16)] = v[r];
+    }
+}
+
+// R2C of window rows, columns 0 .. ncol-1 of each row's spectrum into rows[i][.]
+template <typename T, int K>
+__global__ __launch_bounds__(RowShape<K>::NT) void k_row_r2c(
+    const T* __restrict__ fine, int n1, int ra, int rb, typename Cx<T>::type* __restrict__ rows,
+    int64_t rw, int ncol, const typename Cx<T>::type* __restrict__ tw)
+{
+    using C = typename Cx<T>::type;
+    using S = RowShape<K>;
+    constexpr int N = S::N, R0 = S::R0;
+    __shared__ C buf[N + N / 16];
+    const int q = blockIdx.x, t = threadIdx.x;
+    const int i = q < ra ? q : n1 - rb + (q - ra);
+    const C* z = reinterpret_cast<const C*>(fine + (int64_t)i * (2 * N));
+    for (int idx = t; idx < N / R0; idx += S::NT) {
+        C v[R0];
+#pragma unroll
+        for (int r = 0; r < R0; ++r) v[r] = z[idx + r * (N / R0)];
+        dft<R0, -1>(v);
+#pragma unroll
+        for (int r = 0; r < R0; ++r) buf[pad16(idx * R0 + r)] = v[r];
+    }
+    __syncthreads();
+    middle_passes<K, -1>(buf, t, tw);
+    {
+        C v[16];
+        const bool act = t < S::NB16;
+        if (act) {
+#pragma unroll
+            for (int r = 0; r < 16; ++r) v[r] = buf[pad16(t + r * (N / 16))];
+            twiddle<16, -1>(v, t, N / 16, N, tw);
+            dft<16, -1>(v);
+        }
+        __syncthreads();  // every thread has read its inputs
+        if (act) {
+#pragma unroll
+            for (int r = 0; r < 16; ++r) buf[pad16(t + r * (N / 16))] = v[r];
+        }
+        __syncthreads();
+    }
+    C* X = rows + (int64_t)i * rw;
+    for (int k = t; k < ncol; k += S::NT) {
+        const C zk = buf[pad16(k)];
+        const C zm = buf[pad16((N - k) & (N - 1))];
+        const C e = cmk<C>((zk.x + zm.x) / 2, (zk.y - zm.y) / 2);
+        // O = (Z[k] - conj Z[N-k]) / (2 i)
+        const C d = cmk<C>((zk.x - zm.x) / 2, (zk.y + zm.y) / 2);
+        const C o = cmk<C>(d.y, -d.x);
+        C w = tw[k];
+        w.y = -w.y;
+        X[k] = cadd(e, cmul(o, w));
+    }
+}
+
+}  // namespace
+
+bool rowfft_supported(const nusht_geometry& g)
+{
+    const int n2 = g.n2;
+    if (n2 < 64 || n2 > 16384 || (n2 & (n2 - 1))) return false;
+    return g.mmax + 1 <= n2 / 2;
+}
+
+#define NUSHT_ROWK_SWITCH(K_, BODY)                    \
+    switch (K_) {                                      \
+        case 5: { constexpr int KV = 5; BODY; } break;   \
+        case 6: { constexpr int KV = 6; BODY; } break;   \
+        case 7: { constexpr int KV = 7; BODY; } break;   \
+        case 8: { constexpr int KV = 8; BODY; } break;   \
+        case 9: { constexpr int KV = 9; BODY; } break;   \
+        case 10: { constexpr int KV = 10; BODY; } break; \
+        case 11: { constexpr int KV = 11; BODY; } break; \
+        case 12: { constexpr int KV = 12; BODY; } break; \
+        case 13: { constexpr int KV = 13; BODY; } break; \
+        default: set_last_error("rowfft", "unsupported row length"); return NUSHT_EINVAL; \
+    }
+
+static int row_log2(int n2)
+{
+    int k = 0;
+    while ((2 << k) < n2) ++k;
+    return k;  // n2 / 2 = 2^k
+}
+
+int launch_row_c2r(const nusht_plan_s* p, const void* rows, int64_t rw, void* fine, hipStream_t s)
+{
+    const nusht_geometry& g = p->g;
+    const int nq = p->fine_ra + p->fine_rb;
+    const int K = row_log2(g.n2);
+    NUSHT_ROWK_SWITCH(K, {
+        if (g.dtype == NUSHT_MIXED)
+            hipLaunchKernelGGL((k_row_c2r<float, KV>), dim3(nq), dim3(RowShape<KV>::NT), 0, s,
+                               reinterpret_cast<const float2*>(rows), rw, g.mmax + 1,
+                               reinterpret_cast<float*>(fine), g.n1, p->fine_ra, p->fine_rb,
+                               reinterpret_cast<const float2*>(p->rowtw));
+        else
+            hipLaunchKernelGGL((k_row_c2r<double, KV>), dim3(nq), dim3(RowShape<KV>::NT), 0, s,
+                               reinterpret_cast<const double2*>(rows), rw, g.mmax + 1,
+                               reinterpret_cast<double*>(fine), g.n1, p->fine_ra, p->fine_rb,
+                               reinterpret_cast<const double2*>(p->rowtw));
+    });
+    NUSHT_HIP(hipGetLastError());
+    return NUSHT_OK;
+}
+
+int launch_row_r2c(const nusht_plan_s* p, const void* fine, void* rows, int64_t rw, hipStream_t s)
+{
+    const nusht_geometry& g = p->g;
+    const int nq = p->fine_ra + p->fine_rb;
+    const int K = row_log2(g.n2);
+    NUSHT_ROWK_SWITCH(K, {
+        if (g.dtype == NUSHT_MIXED)
+            hipLaunchKernelGGL((k_row_r2c<float, KV>), dim3(nq), dim3(RowShape<KV>::NT), 0, s,
+                               reinterpret_cast<const float*>(fine), g.n1, p->fine_ra, p->fine_rb,
+                               reinterpret_cast<float2*>(rows), rw, g.mmax + 1,
+                               reinterpret_cast<const float2*>(p->rowtw));
+        else
+            hipLaunchKernelGGL((k_row_r2c<double, KV>), dim3(nq), dim3(RowShape<KV>::NT), 0, s,
+                               reinterpret_cast<const double*>(fine), g.n1, p->fine_ra,
+                               p->fine_rb, reinterpret_cast<double2*>(rows), rw, g.mmax + 1,
+                               reinterpret_cast<const double2*>(p->rowtw));
+    });
+    NUSHT_HIP(hipGetLastError());
+    return NUSHT_OK;
+}
+
+}  // namespace nusht

@@ -2,8 +2,10 @@
 // (Eq. 6) of arXiv:2406.14542 on one HIP stream, with rocFFT for the uniform FFTs.
 // Everything is enqueued asynchronously; intermediates live in two ping-pong scratch
 // regions X and Y (and Z for the spreading subgrids) that the plan owns.
+#include <cmath>
 #include <cstring>
 #include <mutex>
+#include <vector>
 
 #include "internal.h"
 
@@ -121,11 +123,34 @@ int create_fft_plans(nusht_plan_s* p)
                           ncol, 1, g.n1, 1, g.n1, rocfft_placement_inplace));
     NUSHT_TRY(make_fft_1d(p->fine_col_fwd, rocfft_transform_type_complex_forward, prec, g.n1,
                           ncol, 1, g.n1, 1, g.n1, rocfft_placement_inplace));
-    NUSHT_TRY(make_fft_1d(p->fine_rowa_c2r, rocfft_transform_type_real_inverse, prec, g.n2,
-                          p->fine_ra, 1, fw, 1, g.n2, rocfft_placement_notinplace));
-    NUSHT_TRY(make_fft_1d(p->fine_rowa_r2c, rocfft_transform_type_real_forward, prec, g.n2,
-                          p->fine_ra, 1, g.n2, 1, fw, rocfft_placement_notinplace));
-    if (p->fine_rb > 0) {
+    p->row_custom = rowfft_supported(g);
+    if (p->row_custom) {
+        // twiddle table of the row kernels, rounded once from long double
+        const int n2 = g.n2;
+        const bool f32 = g.dtype == NUSHT_MIXED;
+        std::vector<double> tw(2 * (size_t)n2);
+        std::vector<float> twf(2 * (size_t)n2);
+        for (int k = 0; k < n2; ++k) {
+            const long double a = 2.0L * 3.14159265358979323846264338327950288L * k / n2;
+            tw[2 * k] = (double)cosl(a);
+            tw[2 * k + 1] = (double)sinl(a);
+            twf[2 * k] = (float)cosl(a);
+            twf[2 * k + 1] = (float)sinl(a);
+        }
+        const size_t tb = 2 * (size_t)n2 * (f32 ? sizeof(float) : sizeof(double));
+        if (hipMalloc(&p->rowtw, tb) != hipSuccess) {
+            set_last_error("nusht_plan", "device allocation failed");
+            return NUSHT_ENOMEM;
+        }
+        NUSHT_HIP(hipMemcpy(p->rowtw, f32 ? (const void*)twf.data() : (const void*)tw.data(), tb,
+                            hipMemcpyHostToDevice));
+    } else {
+        NUSHT_TRY(make_fft_1d(p->fine_rowa_c2r, rocfft_transform_type_real_inverse, prec, g.n2,
+                              p->fine_ra, 1, fw, 1, g.n2, rocfft_placement_notinplace));
+        NUSHT_TRY(make_fft_1d(p->fine_rowa_r2c, rocfft_transform_type_real_forward, prec, g.n2,
+                              p->fine_ra, 1, g.n2, 1, fw, rocfft_placement_notinplace));
+    }
+    if (p->fine_rb > 0 && !p->row_custom) {
         NUSHT_TRY(make_fft_1d(p->fine_rowb_c2r, rocfft_transform_type_real_inverse, prec, g.n2,
                               p->fine_rb, 1, fw, 1, g.n2, rocfft_placement_notinplace));
         NUSHT_TRY(make_fft_1d(p->fine_rowb_r2c, rocfft_transform_type_real_forward, prec, g.n2,
@@ -246,23 +271,6 @@ void begin_call(nusht_plan_s* p, int kind)
 
 inline char* bytes(void* v) { return reinterpret_cast<char*>(v); }
 
-// Adjoint input of maps [b, b + MB) into tile-sorted order, the MB values of a point
-// contiguous: reads are coalesced in the caller's order and each point is one MB * 8-byte
-// write, instead of MB separate 8-byte gathers per point in the spreading kernel.
-template <int MB>
-__global__ void k_sort_values(const double* __restrict__ map, int64_t npts,
-                              const int* __restrict__ iperm, double* __restrict__ vals)
-{
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= npts) return;
-    double v[MB];
-#pragma unroll
-    for (int b = 0; b < MB; ++b) v[b] = map[b * npts + i];
-    double* dst = vals + (int64_t)iperm[i] * MB;
-#pragma unroll
-    for (int b = 0; b < MB; ++b) dst[b] = v[b];
-}
-
 // fine grid (real) of map b and its half spectrum, in elements of the plan's precision
 size_t fine_real_bytes(const nusht_plan_s* p) { return (size_t)p->g.n1 * p->g.n2 * fine_elem_bytes(p); }
 // band spectrum [mmax+1][n1] of one map
@@ -281,7 +289,11 @@ int fine_c2r(nusht_plan_s* p, char* band, char* real, hipStream_t s)
     const size_t fw = (size_t)g.n2 / 2 + 1;
     char* rows = bytes(p->W);
     NUSHT_TRY(fft_exec(p, p->fine_col_inv, band, nullptr, s));
-    NUSHT_TRY(launch_band_to_rows(p, band, rows, s));
+    if (p->row_custom) {
+        NUSHT_TRY(launch_band_to_rows(p, band, rows, g.mmax + 1, s));
+        return launch_row_c2r(p, rows, g.mmax + 1, real, s);
+    }
+    NUSHT_TRY(launch_band_to_rows(p, band, rows, (int)fw, s));
     NUSHT_TRY(fft_exec(p, p->fine_rowa_c2r, rows, real, s));
     if (p->fine_rb > 0) {
         const size_t r0 = (size_t)g.n1 - p->fine_rb;
@@ -299,12 +311,17 @@ int fine_r2c(nusht_plan_s* p, char* real, char* band, hipStream_t s)
     const size_t e = fine_elem_bytes(p);
     const size_t fw = (size_t)g.n2 / 2 + 1;
     char* rows = bytes(p->W);
+    if (p->row_custom) {
+        NUSHT_TRY(launch_row_r2c(p, real, rows, g.mmax + 1, s));
+        NUSHT_TRY(launch_rows_to_band(p, rows, g.mmax + 1, band, s));
+        return fft_exec(p, p->fine_col_fwd, band, nullptr, s);
+    }
     NUSHT_TRY(fft_exec(p, p->fine_rowa_r2c, real, rows, s));
     if (p->fine_rb > 0) {
         const size_t r0 = (size_t)g.n1 - p->fine_rb;
         NUSHT_TRY(fft_exec(p, p->fine_rowb_r2c, real + r0 * g.n2 * e, rows + r0 * fw * 2 * e, s));
     }
-    NUSHT_TRY(launch_rows_to_band(p, rows, band, s));
+    NUSHT_TRY(launch_rows_to_band(p, rows, (int)fw, band, s));
     NUSHT_TRY(fft_exec(p, p->fine_col_fwd, band, nullptr, s));
     return NUSHT_OK;
 }
@@ -455,22 +472,13 @@ int nusht_adjoint(nusht_plan_t p, const double* map, double* alm, int nmaps, voi
         return NUSHT_EINVAL;
     }
     stage_begin(p, ST_POINTS, s);
-    const unsigned vblocks = (unsigned)((g.npts + 255) / 256);
     for (int b = 0, grp = 0; b < nmaps; ++grp) {
         const int mb = group_width(nmaps, b);
         void* sub = bytes(p->Z) + grp * zgroup;
-        if (f32) {
+        if (f32)
             NUSHT_TRY(spread_group_f32(p, map + b * g.npts, reinterpret_cast<float*>(sub), mb, s));
-        } else {
-            if (mb == 4)
-                hipLaunchKernelGGL(k_sort_values<4>, dim3(vblocks), dim3(256), 0, s,
-                                   map + b * g.npts, g.npts, p->iperm, p->V);
-            else
-                hipLaunchKernelGGL(k_sort_values<1>, dim3(vblocks), dim3(256), 0, s,
-                                   map + b * g.npts, g.npts, p->iperm, p->V);
-            NUSHT_HIP(hipGetLastError());
-            NUSHT_TRY(spread_group_f64(p, p->V, reinterpret_cast<double*>(sub), mb, s));
-        }
+        else
+            NUSHT_TRY(spread_group_f64(p, map + b * g.npts, reinterpret_cast<double*>(sub), mb, s));
         b += mb;
     }
     stage_end(p, ST_POINTS, s);
