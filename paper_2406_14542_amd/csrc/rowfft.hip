@@ -138,17 +138,24 @@ struct RowShape {
 //   butterfly idx: inputs in[idx + r N / R], twiddle e^{DIR 2 pi i j r / (Ns R)} (j = idx mod
 //   Ns), DFT_R, outputs out[(idx - j) R + j + r Ns].
 // tw[m] = e^{2 pi i m / n2} (n2 = 2 N), so e^{2 pi i a / N} = tw[2 a].
+// The twiddles of a butterfly are fetched (global loads, L2-resident table) before the
+// pass's LDS reads and barrier, so that their latency overlaps the wait.
 template <int R, int DIR, typename C>
-__device__ inline void twiddle(C (&v)[R], int j, int Ns, int N, const C* __restrict__ tw)
+__device__ inline void load_twiddles(C (&w)[R], int j, int Ns, int N, const C* __restrict__ tw)
 {
-    if (Ns == 1) return;
     const int step = 2 * j * (N / (Ns * R));
 #pragma unroll
     for (int r = 1; r < R; ++r) {
-        C w = tw[r * step];
-        if (DIR < 0) w.y = -w.y;
-        v[r] = cmul(v[r], w);
+        w[r] = tw[r * step];
+        if (DIR < 0) w[r].y = -w[r].y;
     }
+}
+
+template <int R, typename C>
+__device__ inline void apply_twiddles(C (&v)[R], const C (&w)[R])
+{
+#pragma unroll
+    for (int r = 1; r < R; ++r) v[r] = cmul(v[r], w[r]);
 }
 
 template <int K, int DIR, typename C>
@@ -156,25 +163,27 @@ __device__ inline void middle_passes(C* buf, int t, const C* __restrict__ tw)
 {
     using S = RowShape<K>;
     constexpr int N = S::N;
-    int Ns = S::R0;
+    const bool act = t < S::NB16;
+#pragma unroll
     for (int p = 0; p < S::NPASS16 - 1; ++p) {
-        C v[16];
-        const bool act = t < S::NB16;
+        int Ns = S::R0;
+        for (int e = 0; e < p; ++e) Ns *= 16;
+        const int j = t & (Ns - 1);
+        C v[16], w[16];
         if (act) {
+            load_twiddles<16, DIR>(w, j, Ns, N, tw);
 #pragma unroll
             for (int r = 0; r < 16; ++r) v[r] = buf[pad16(t + r * (N / 16))];
         }
         __syncthreads();
         if (act) {
-            const int j = t & (Ns - 1);
-            twiddle<16, DIR>(v, j, Ns, N, tw);
+            apply_twiddles(v, w);
             dft<16, DIR>(v);
             const int base = (t - j) * 16 + j;
 #pragma unroll
             for (int r = 0; r < 16; ++r) buf[pad16(base + r * Ns)] = v[r];
         }
         __syncthreads();
-        Ns *= 16;
     }
 }
 
@@ -194,32 +203,49 @@ __global__ __launch_bounds__(RowShape<K>::NT) void k_row_c2r(
     const int i = q < ra ? q : n1 - rb + (q - ra);
     const C* X = rows + (int64_t)i * rw;
     const int M = ncol - 1;
-    // first pass (span 1) from HBM: Z[k] built from X[k] and X[N - k]
-    for (int idx = t; idx < N / R0; idx += S::NT) {
-        C v[R0];
+    // first pass (span 1) from HBM: Z[k] built from X[k] and X[N - k].  All of the thread's
+    // loads are issued first (indices clamped into the band, unused values masked after),
+    // then the butterflies are formed.
+    constexpr int NU = (N / R0 + S::NT - 1) / S::NT;
+    C xa[NU][R0], xb[NU][R0];
+#pragma unroll
+    for (int u = 0; u < NU; ++u)
 #pragma unroll
         for (int r = 0; r < R0; ++r) {
-            const int k = idx + r * (N / R0);
-            C xk = k <= M ? X[k] : cmk<C>(0, 0);
-            if (k == 0) xk.y = 0;
-            const C xm = (k > 0 && N - k <= M) ? X[N - k] : cmk<C>(0, 0);
-            const C xc = cmk<C>(xm.x, -xm.y);
-            const C e = cadd(xk, xc);
-            const C o = cmul(csub(xk, xc), tw[k]);
-            v[r] = cmk<C>(e.x - o.y, e.y + o.x);
+            const int k = t + u * S::NT + r * (N / R0);
+            xa[u][r] = X[min(k, M)];
+            xb[u][r] = X[max(0, min(N - k, M))];
         }
-        dft<R0, +1>(v);
 #pragma unroll
-        for (int r = 0; r < R0; ++r) buf[pad16(idx * R0 + r)] = v[r];
+    for (int u = 0; u < NU; ++u) {
+        const int idx = t + u * S::NT;
+        if (idx < N / R0) {
+            C v[R0];
+#pragma unroll
+            for (int r = 0; r < R0; ++r) {
+                const int k = idx + r * (N / R0);
+                C xk = k <= M ? xa[u][r] : cmk<C>(0, 0);
+                if (k == 0) xk.y = 0;
+                const C xm = (k > 0 && N - k <= M) ? xb[u][r] : cmk<C>(0, 0);
+                const C xc = cmk<C>(xm.x, -xm.y);
+                const C e = cadd(xk, xc);
+                const C o = cmul(csub(xk, xc), tw[k]);
+                v[r] = cmk<C>(e.x - o.y, e.y + o.x);
+            }
+            dft<R0, +1>(v);
+#pragma unroll
+            for (int r = 0; r < R0; ++r) buf[pad16(idx * R0 + r)] = v[r];
+        }
     }
     __syncthreads();
     middle_passes<K, +1>(buf, t, tw);
     // last pass (radix 16, span N / 16) into the fine row: z[n] = x[2n] + i x[2n+1]
     if (t < S::NB16) {
-        C v[16];
+        C v[16], w[16];
+        load_twiddles<16, +1>(w, t, N / 16, N, tw);
 #pragma unroll
         for (int r = 0; r < 16; ++r) v[r] = buf[pad16(t + r * (N / 16))];
-        twiddle<16, +1>(v, t, N / 16, N, tw);
+        apply_twiddles(v, w);
         dft<16, +1>(v);
         C* z = reinterpret_cast<C*>(fine + (int64_t)i * (2 * N));
 #pragma unroll
@@ -240,23 +266,31 @@ __global__ __launch_bounds__(RowShape<K>::NT) void k_row_r2c(
     const int q = blockIdx.x, t = threadIdx.x;
     const int i = q < ra ? q : n1 - rb + (q - ra);
     const C* z = reinterpret_cast<const C*>(fine + (int64_t)i * (2 * N));
-    for (int idx = t; idx < N / R0; idx += S::NT) {
-        C v[R0];
+    constexpr int NU = (N / R0 + S::NT - 1) / S::NT;
+    C za[NU][R0];
 #pragma unroll
-        for (int r = 0; r < R0; ++r) v[r] = z[idx + r * (N / R0)];
-        dft<R0, -1>(v);
+    for (int u = 0; u < NU; ++u)
 #pragma unroll
-        for (int r = 0; r < R0; ++r) buf[pad16(idx * R0 + r)] = v[r];
+        for (int r = 0; r < R0; ++r) za[u][r] = z[min(t + u * S::NT + r * (N / R0), N - 1)];
+#pragma unroll
+    for (int u = 0; u < NU; ++u) {
+        const int idx = t + u * S::NT;
+        if (idx < N / R0) {
+            dft<R0, -1>(za[u]);
+#pragma unroll
+            for (int r = 0; r < R0; ++r) buf[pad16(idx * R0 + r)] = za[u][r];
+        }
     }
     __syncthreads();
     middle_passes<K, -1>(buf, t, tw);
     {
-        C v[16];
+        C v[16], w[16];
         const bool act = t < S::NB16;
         if (act) {
+            load_twiddles<16, -1>(w, t, N / 16, N, tw);
 #pragma unroll
             for (int r = 0; r < 16; ++r) v[r] = buf[pad16(t + r * (N / 16))];
-            twiddle<16, -1>(v, t, N / 16, N, tw);
+            apply_twiddles(v, w);
             dft<16, -1>(v);
         }
         __syncthreads();  // every thread has read its inputs
