@@ -181,11 +181,9 @@ int launch_legendre_synth(const nusht_plan_s* p, const double* alm, void* out, i
 // ring pairs per lane of the synthesis' plain instance
 int synth_pairs_per_lane(int npairs);
 int synth_scaled_pairs_per_lane(int npairs);
+// adjoint into alm [nmaps][nalm] (complex128), which it zeroes and then accumulates into
 int launch_legendre_adjoint(const nusht_plan_s* p, const void* in, double* alm, int nmaps,
-                            int fused, int in_f32, void* scratch, size_t scratch_bytes,
-                            hipStream_t s);
-// bytes of partial sums the adjoint needs (one slice per chunk of ring pairs)
-size_t legendre_adjoint_scratch(const nusht_plan_s* p, int nmaps);
+                            int fused, int in_f32, hipStream_t s);
 
 // ---- DFS glue (dfs.hip) ----
 int launch_zero_nyquist_rows(const nusht_plan_s* p, double* G, int nmaps, hipStream_t s);

@@ -381,8 +381,10 @@ __global__ __launch_bounds__(256) void k_legendre_synth(
 //    K = 4 ring pairs and columns = 4 values of l of that parity -- every product term is
 //    used (the 16x16x4 shape would spend half of its work on the wrong parity) and this
 //    shape sustains close to the FP64 peak on gfx950, the 16x16 one about 60 % of it;
-//  * the waves of a block (one pair-chunk) are summed through LDS; pair-chunks write
-//    partial sums that k_adj_finalize adds in a fixed order (deterministic, no atomics).
+//  * the waves of a block (one pair-chunk) are summed through LDS; the pair-chunks of one m
+//    run on one XCD and add their sums into the zeroed output with FP64 atomics that
+//    resolve in that XCD's L2 (the order of the additions is not fixed: results can differ
+//    between runs by FP64 rounding).
 // Input: FUSED Tp[b][m][t] (t < N_t), folded here:
 //   G'_m(j) = Tp(j) + [1 <= j <= N_r - 2] (-1)^m Tp(N_t - j)      (D^H of Eq. 6)
 // PAPER G'[b][j][m] rows of length (N_phi/2 + 1) (output of the per-ring R2C).
@@ -392,6 +394,7 @@ constexpr int kLC = 16;          // l values per chunk = the MFMA N dimension
 constexpr int kLS = kLC + 1;     // padded row of the lam staging area
 constexpr int kAdjGroup = 2;     // chunks whose D values are summed over waves together
 constexpr int kAdjPfAhead = 4;   // chunks between a coefficient line's L2 touch and its use
+
 
 template <typename InT>
 __device__ inline double2 load_c(const InT* p)
@@ -403,7 +406,7 @@ __device__ inline double2 load_c(const InT* p)
 template <bool FUSED, typename InT>
 __global__ __launch_bounds__(kAdjWaves * 64, 4) void k_legendre_adj(
     const InT* __restrict__ in, int64_t in_map_stride, int64_t in_row_stride, int nmaps,
-    double* __restrict__ part, int npc, int64_t nalm, int lmax,
+    double* __restrict__ alm, int npc, int64_t nalm, int lmax,
     const double2* __restrict__ rec, const double* __restrict__ cm_mant,
     const int* __restrict__ cm_exp, const int* __restrict__ jlive, int nr, int nt,
     int pairs_per_block, int mmax)
@@ -435,15 +438,7 @@ __global__ __launch_bounds__(kAdjWaves * 64, 4) void k_legendre_adj(
     const int jl = jlive[m];
     // pairs below jl never carry lam above 2^-300 for l <= lmax: a block made only of them
     // writes zero partial sums, a wave made only of them skips its recurrence and MFMAs
-    if (pc * pairs_per_block + pairs_per_block <= jl) {
-        for (int l = m + threadIdx.x; l <= lmax; l += blockDim.x)
-            for (int b = 0; b < nmb; ++b) {
-                double* dst = part + (((int64_t)(grp * npc + pc) * 4 + b) * nalm + moff + l) * 2;
-                dst[0] = 0.0;
-                dst[1] = 0.0;
-            }
-        return;
-    }
+    if (pc * pairs_per_block + pairs_per_block <= jl) return;
     // a wave is dead when all its pairs lie below the live-ring bound or beyond the pairs
     const int wfirst = pc * pairs_per_block + wave * 64;
     const bool wave_dead = wfirst + 64 <= jl || wave * 64 >= pairs_per_block || wfirst >= npairs;
@@ -555,7 +550,8 @@ __global__ __launch_bounds__(kAdjWaves * 64, 4) void k_legendre_adj(
                     pf_keep ^= lds_dma_touch(rec + moff + l0 + kAdjPfAhead * kLC + 8 * lane,
                                              lds_sink);
                 double lam[kLC];
-                if (!__any(scaled) && l0 > m && l0 + kLC - 1 <= lmax) {
+                const bool full = l0 > m && l0 + kLC - 1 <= lmax;
+                if (full && !__any(scaled)) {
                     // common case: a full chunk past lam_mm with no lane scaled
 #pragma unroll
                     for (int i = 0; i < kLC; ++i) {
@@ -564,7 +560,25 @@ __global__ __launch_bounds__(kAdjWaves * 64, 4) void k_legendre_adj(
                         vc = vn;
                         lam[i] = vc;
                     }
+                } else if (full) {
+                    // a full chunk with some lane still scaled: the rescale test once per
+                    // pair of steps (a step grows a value by less than 2^7, far from the
+                    // FP64 range above kBig); a pair's values count once its lane is in range
+#pragma unroll
+                    for (int i = 0; i < kLC; i += 2) {
+                        const double v0 = rec_step(cc[i], y, vc, vp);
+                        const double v1 = rec_step(cc[i + 1], y, v0, vc);
+                        const bool big = (k > 0) && fmax(fabs(v0), fabs(v1)) >= kBig;
+                        const double sc = big ? kUnit : 1.0;
+                        vp = v0 * sc;
+                        vc = v1 * sc;
+                        k -= big ? 1 : 0;
+                        lam[i] = (k == 0) ? vp : 0.0;
+                        lam[i + 1] = (k == 0) ? vc : 0.0;
+                    }
+                    scaled = k > 0;
                 } else {
+                    // the first chunk (lam_mm) and a partial last one: per-step tests
                     const bool wscaled = __any(scaled);
 #pragma unroll
                     for (int i = 0; i < kLC; ++i) {
@@ -589,9 +603,9 @@ __global__ __launch_bounds__(kAdjWaves * 64, 4) void k_legendre_adj(
                     }
                     scaled = k > 0;
                 }
-                // a chunk after which every lane still carries a scale factor has only zero
-                // lam values (k never increases): it adds nothing
-                if (!__all(scaled)) {
+                // a chunk after which every live lane still carries a scale factor has only
+                // zero lam values (k never increases): it adds nothing
+                if (!__all(scaled || !valid)) {
 #pragma unroll
                     for (int i = 0; i < kLC; ++i) st[lane * kLS + i] = lam[i];
                     // the wave reads back only its own staging rows
@@ -634,9 +648,12 @@ __global__ __launch_bounds__(kAdjWaves * 64, 4) void k_legendre_adj(
             const int l = m + (c0 + (t >> 7)) * kLC + 8 * (blk >> 1) + 2 * (d & 3) + (blk & 1);
             if (l > lmax || b >= nmb) continue;
             double v = 0.0;
-            for (int w = 0; w < nwaves; ++w) v += stage[w][t];
-            part[(((int64_t)(grp * npc + pc) * 4 + b) * nalm + moff + l) * 2 + ((t >> 6) & 1)] =
-                v;
+#pragma unroll
+            for (int w = 0; w < kAdjWaves; ++w)
+                if (w < nwaves) v += stage[w][t];
+            const int c = (t >> 6) & 1;
+            if (m > 0 || c == 0)  // c_l0 is real
+                unsafeAtomicAdd(alm + ((int64_t)(4 * grp + b) * nalm + moff + l) * 2 + c, v);
         }
         __syncthreads();
     }
@@ -644,23 +661,10 @@ __global__ __launch_bounds__(kAdjWaves * 64, 4) void k_legendre_adj(
     asm volatile("s_waitcnt vmcnt(0)" ::"v"(pf_keep) : "memory");
 }
 
-// alm[b][idx] = sum over pair-chunks of the partial sums, in chunk order
-__global__ void k_adj_finalize(const double* __restrict__ part, int npc, int nmaps, int64_t nalm,
-                               int lmax, int mmax, double2* __restrict__ alm)
+__global__ void k_fill_zero(double* __restrict__ a, int64_t n)
 {
-    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const int b = blockIdx.y;
-    if (idx >= nalm) return;
-    const int grp = b >> 2, bb = b & 3;
-    double re = 0.0, im = 0.0;
-    for (int pc = 0; pc < npc; ++pc) {
-        const double* src = part + (((int64_t)(grp * npc + pc) * 4 + bb) * nalm + idx) * 2;
-        re += src[0];
-        im += src[1];
-    }
-    // m = 0 occupies idx 0..lmax: c_l0 is real
-    if (idx <= lmax) im = 0.0;
-    alm[(int64_t)b * nalm + idx] = make_double2(re, im);
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) a[i] = 0.0;
 }
 
 }  // namespace
@@ -742,17 +746,8 @@ int launch_legendre_synth(const nusht_plan_s* p, const double* alm, void* out, i
     return NUSHT_OK;
 }
 
-size_t legendre_adjoint_scratch(const nusht_plan_s* p, int nmaps)
-{
-    const int npairs = (p->g.nrings + 1) / 2;
-    const size_t npc = (npairs + kAdjWaves * 64 - 1) / (kAdjWaves * 64);
-    const size_t groups = (nmaps + 3) / 4;
-    return groups * npc * 4 * (size_t)p->g.nalm * 2 * sizeof(double);
-}
-
 int launch_legendre_adjoint(const nusht_plan_s* p, const void* in, double* alm, int nmaps,
-                            int fused, int in_f32, void* scratch, size_t scratch_bytes,
-                            hipStream_t s)
+                            int fused, int in_f32, hipStream_t s)
 {
     const nusht_geometry& g = p->g;
     const int npairs = (g.nrings + 1) / 2;
@@ -761,10 +756,6 @@ int launch_legendre_adjoint(const nusht_plan_s* p, const void* in, double* alm, 
     ppb = ((ppb + 63) / 64) * 64;
     const int threads = ppb < 128 ? 128 : ppb;
     const int groups = (nmaps + 3) / 4;
-    if (legendre_adjoint_scratch(p, nmaps) > scratch_bytes) {
-        set_last_error("legendre_adjoint", "partial-sum scratch too small");
-        return NUSHT_EINVAL;
-    }
     int64_t map_stride, row_stride;
     if (fused) {
         row_stride = g.ntorus;
@@ -773,12 +764,15 @@ int launch_legendre_adjoint(const nusht_plan_s* p, const void* in, double* alm, 
         row_stride = g.nphi / 2 + 1;
         map_stride = (int64_t)g.nrings * row_stride;
     }
-    double* part = reinterpret_cast<double*>(scratch);
+    // the pair-chunk workgroups of one m add their sums into the zeroed output with FP64
+    // atomics, which resolve in the L2 of the XCD those workgroups share
+    const int64_t nz = (int64_t)nmaps * g.nalm * 2;
+    hipLaunchKernelGGL(k_fill_zero, dim3((unsigned)((nz + 255) / 256)), dim3(256), 0, s, alm, nz);
     const int mpad = (g.mmax + 1 + 7) / 8 * 8;
     dim3 grid(npc * mpad, groups);
 #define ADJ(F, IT)                                                                              \
     hipLaunchKernelGGL((k_legendre_adj<F, IT>), grid, dim3(threads), 0, s,                       \
-                       reinterpret_cast<const IT*>(in), map_stride, row_stride, nmaps, part, npc, \
+                       reinterpret_cast<const IT*>(in), map_stride, row_stride, nmaps, alm, npc,  \
                        g.nalm, g.lmax, p->rec, p->cm_mant, p->cm_exp, p->jlive, g.nrings,        \
                        g.ntorus, ppb, g.mmax)
     if (fused && in_f32) {
@@ -789,10 +783,6 @@ int launch_legendre_adjoint(const nusht_plan_s* p, const void* in, double* alm, 
         ADJ(false, double2);
     }
 #undef ADJ
-    NUSHT_HIP(hipGetLastError());
-    dim3 fgrid((unsigned)((g.nalm + 255) / 256), nmaps);
-    hipLaunchKernelGGL(k_adj_finalize, fgrid, dim3(256), 0, s, part, npc, nmaps, g.nalm, g.lmax,
-                       g.mmax, reinterpret_cast<double2*>(alm));
     NUSHT_HIP(hipGetLastError());
     return NUSHT_OK;
 }

@@ -270,9 +270,6 @@ int ensure_capacity(nusht_plan_s* p, int nmaps)
     const size_t gfused = (size_t)(g.mmax + 1) * g.ntorus * 2 * 8;  // doubled columns, <= c128
     size_t per = fine_real;
     for (size_t v : {fine_spec, gpaper, ring, torus, tspec, gfused}) per = v > per ? v : per;
-    // the Legendre adjoint keeps its partial sums in whichever region does not hold its input
-    const size_t part = legendre_adjoint_scratch(p, nmaps);
-    if (per * nmaps < part) per = (part + nmaps - 1) / nmaps;
     const int groups = point_groups(nmaps);
     const int P = kTile + g.width - 1;
     const size_t zbytes = (size_t)groups * p->nslots * P * P * 4 * e;

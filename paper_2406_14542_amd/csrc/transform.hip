@@ -511,7 +511,7 @@ int nusht_adjoint(nusht_plan_t p, const double* map, double* alm, int nmaps, voi
             NUSHT_TRY(fft_exec(p, p->theta_bwd, bytes(p->X) + b * cstride, nullptr, s));
         stage_end(p, ST_TORUS_FFT, s);
         stage_begin(p, ST_LEGENDRE, s);
-        NUSHT_TRY(launch_legendre_adjoint(p, p->X, alm, nmaps, 1, f32, p->Y, p->Ybytes, s));
+        NUSHT_TRY(launch_legendre_adjoint(p, p->X, alm, nmaps, 1, f32, s));
         stage_end(p, ST_LEGENDRE, s);
     } else {
         stage_begin(p, ST_DECONV, s);
@@ -535,7 +535,7 @@ int nusht_adjoint(nusht_plan_t p, const double* map, double* alm, int nmaps, voi
                                bytes(p->Y) + b * gstride, s));
         stage_end(p, ST_RING_FFT, s);
         stage_begin(p, ST_LEGENDRE, s);
-        NUSHT_TRY(launch_legendre_adjoint(p, p->Y, alm, nmaps, 0, 0, p->X, p->Xbytes, s));
+        NUSHT_TRY(launch_legendre_adjoint(p, p->Y, alm, nmaps, 0, 0, s));
         stage_end(p, ST_LEGENDRE, s);
     }
     return NUSHT_OK;
@@ -570,7 +570,7 @@ int nusht_ring_adjoint(nusht_plan_t p, const double* ring, double* alm, int nmap
         NUSHT_TRY(fft_exec(p, p->ring_r2c, bytes(p->X) + b * rstride, bytes(p->Y) + b * gstride, s));
     stage_end(p, ST_RING_FFT, s);
     stage_begin(p, ST_LEGENDRE, s);
-    NUSHT_TRY(launch_legendre_adjoint(p, p->Y, alm, nmaps, 0, 0, p->X, p->Xbytes, s));
+    NUSHT_TRY(launch_legendre_adjoint(p, p->Y, alm, nmaps, 0, 0, s));
     stage_end(p, ST_LEGENDRE, s);
     return NUSHT_OK;
 }
