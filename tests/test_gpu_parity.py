@@ -171,6 +171,28 @@ def test_edge_points_and_small_bands(P, oracle_mod):
     assert mrel(c[0], oracle_mod.adjoint(L, L, tc, pc, d)[0], L, L) <= 1e-11
 
 
+@pytest.mark.parametrize("L", [31, 255, 511, 1023])
+def test_row_kernel_sizes(P, oracle_mod, L):
+    """Band limits whose power-of-two fine rows (n2 = 128, 1024, 2048, 4096) run the library's
+    row kernels through each of their pass plans (first radix 4, 2, 4 and 8), in FP64 and in
+    mixed precision."""
+    print(f"[row kernels L={L}]", flush=True)
+    rng = np.random.default_rng(30 + L)
+    th, ph = inputs.uniform_points(rng, 300)
+    a = inputs.red_alm(rng, L, L, 1)
+    d = rng.standard_normal((1, th.size))
+    fref = oracle_mod.synthesis(L, L, th, ph, a)
+    cref = oracle_mod.adjoint(L, L, th, ph, d)
+    for eps, dtype, tol in ((1e-12, "f64", 1e-11), (1e-5, "mixed", 1e-5)):
+        pl = P.Plan(L, L, dev(th), dev(ph), eps, dtype=dtype)
+        n2 = pl.geometry["n2"]
+        assert n2 & (n2 - 1) == 0, n2
+        f = pl.synthesis(dev(a)).cpu().numpy()
+        assert rel(f, fref) <= tol, (L, dtype, rel(f, fref))
+        c = pl.adjoint(dev(d)).cpu().numpy()
+        assert mrel(c[0], cref[0], L, L) <= tol, (L, dtype, mrel(c[0], cref[0], L, L))
+
+
 def test_plan_rejects_bad_points(P):
     print("[bad points]", flush=True)
     th = np.array([0.1, 3.5, 0.2])
