@@ -146,7 +146,12 @@ def run_cg(args):
         train.append(ex)
     t_targets = time.perf_counter() - t0
     t0 = time.perf_counter()
-    hist = lw.train(train, steps=args.cg_steps, lr=args.cg_lr)
+    def train_log(step, total):
+        if step == 1 or step % 10 == 0:
+            log(f"training step {step}: loss {total / len(train):.4f} "
+                f"({time.perf_counter() - t0:.1f} s)")
+
+    hist = lw.train(train, steps=args.cg_steps, lr=args.cg_lr, log=train_log)
     torch.cuda.synchronize()
     t_train = time.perf_counter() - t0
     log(f"training loss {hist[0] / len(train):.4f} -> {hist[-1] / len(train):.4f} "
