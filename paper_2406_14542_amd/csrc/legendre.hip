@@ -381,10 +381,15 @@ __global__ __launch_bounds__(256) void k_legendre_synth(
 //    K = 4 ring pairs and columns = 4 values of l of that parity -- every product term is
 //    used (the 16x16x4 shape would spend half of its work on the wrong parity) and this
 //    shape sustains close to the FP64 peak on gfx950, the 16x16 one about 60 % of it;
-//  * the waves of a block (one pair-chunk) are summed through LDS; the pair-chunks of one m
-//    run on one XCD and add their sums into the zeroed output with FP64 atomics that
-//    resolve in that XCD's L2 (the order of the additions is not fixed: results can differ
-//    between runs by FP64 rounding).
+//  * the waves of a block (one pair-chunk) are summed without workgroup barriers: each wave
+//    adds its D values of a round of kAdjGroup chunks into one of kAdjSlots LDS slots (LDS
+//    FP64 atomics) and counts itself in; the last of the block's live waves to arrive adds
+//    the slot into the output, clears it and hands it on to the round kAdjSlots later.  The
+//    waves therefore run at their own pace (scaled and unscaled lanes, dead waves) instead of
+//    meeting at two barriers after every round;
+//  * the pair-chunks of one m run on one XCD and add their sums into the zeroed output with
+//    FP64 atomics that resolve in that XCD's L2 (the order of the additions is not fixed:
+//    results can differ between runs by FP64 rounding).
 // Input: FUSED Tp[b][m][t] (t < N_t), folded here:
 //   G'_m(j) = Tp(j) + [1 <= j <= N_r - 2] (-1)^m Tp(N_t - j)      (D^H of Eq. 6)
 // PAPER G'[b][j][m] rows of length (N_phi/2 + 1) (output of the per-ring R2C).
@@ -392,7 +397,8 @@ __global__ __launch_bounds__(256) void k_legendre_synth(
 constexpr int kAdjWaves = 4;     // waves per block: one block reduces up to 256 ring pairs
 constexpr int kLC = 16;          // l values per chunk = the MFMA N dimension
 constexpr int kLS = kLC + 1;     // padded row of the lam staging area
-constexpr int kAdjGroup = 2;     // chunks whose D values are summed over waves together
+constexpr int kAdjGroup = 2;     // chunks whose sums go through one slot together
+constexpr int kAdjSlots = 2;     // slots in flight per block (power of two)
 constexpr int kAdjPfAhead = 4;   // chunks between a coefficient line's L2 touch and its use
 
 
@@ -411,11 +417,14 @@ __global__ __launch_bounds__(kAdjWaves * 64, 4) void k_legendre_adj(
     const int* __restrict__ cm_exp, const int* __restrict__ jlive, int nr, int nt,
     int pairs_per_block, int mmax)
 {
-    // per wave: the lam values of one chunk (64 pairs x 16 l), and after the MFMAs of a
-    // group of kAdjGroup chunks the wave's D values of those chunks (kAdjGroup x 128)
+    // per wave: the lam values of one chunk (64 pairs x 16 l); per block: the chunk-sum slots
+    // (128 D values: 64 lanes x real/imaginary), their arrival counts and hand-on counts
     __shared__ double stage[kAdjWaves][64 * kLS];
     __shared__ float pf_sink[kAdjWaves][64];
-    static_assert(kAdjGroup * 128 <= 64 * kLS, "D values of a chunk group fit the staging area");
+    __shared__ double slot[kAdjSlots][kAdjGroup * 128];
+    __shared__ unsigned scnt[kAdjSlots], sgen[kAdjSlots];
+    static_assert((kAdjSlots & (kAdjSlots - 1)) == 0 && kAdjSlots * kAdjGroup * 128 <= 2 * 256,
+                  "slot count a power of two, cleared by the block's threads in two stores");
     // all pair-chunks of one m on one XCD, one after the other: they share the m's
     // coefficient stream in that XCD's L2
     int m, pc;
@@ -423,7 +432,9 @@ __global__ __launch_bounds__(kAdjWaves * 64, 4) void k_legendre_adj(
     if (m > mmax) return;
     const int grp = blockIdx.y;
     const int nmb = min(4, nmaps - 4 * grp);
-    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    // the wave index read through a scalar register: everything derived from it (dead waves,
+    // the slot protocol) is then known to be wave-uniform
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
     const int nwaves = blockDim.x >> 6;
     const int npairs = (nr + 1) / 2;
     const int local = wave * 64 + lane;
@@ -495,6 +506,12 @@ __global__ __launch_bounds__(kAdjWaves * 64, 4) void k_legendre_adj(
 #pragma unroll
         for (int c = 0; c < 16; ++c) st[lane * kLS + c] = hv[c];
     }
+    for (int e = threadIdx.x; e < kAdjSlots * kAdjGroup * 128; e += blockDim.x)
+        (&slot[0][0])[e] = 0.0;
+    if (threadIdx.x < kAdjSlots) {
+        scnt[threadIdx.x] = 0;
+        sgen[threadIdx.x] = 0;
+    }
     __syncthreads();
     // D of v_mfma_f64_4x4x4_4b (measured layout: A_b[i][k] in lane i + 4 b + 16 k,
     // B_b[k][j] in lane j + 4 b + 16 k, D_b[i][j] in lane j + 4 b + 16 i).  Here k = ring
@@ -533,19 +550,35 @@ __global__ __launch_bounds__(kAdjWaves * 64, 4) void k_legendre_adj(
     if (!wave_dead && lane < 2 * kAdjPfAhead && m + kLC + 8 * lane <= lmax)
         pf_keep ^= lds_dma_touch(rec + moff + m + kLC + 8 * lane, lds_sink);
     const int nchunks = (lmax - m) / kLC + 1;
+    // the table is read through the constant address space: it is never written while the
+    // kernel runs, so its wave-uniform reads stay scalar loads next to the atomics below
+    const __attribute__((address_space(4))) double* crec =
+        (const __attribute__((address_space(4))) double*)rec;
+    // the block's live waves take part in the chunk sums; the dead ones leave (they issued no
+    // LDS-DMA touches)
+    int nlive = 0;
+    for (int w = 0; w < nwaves; ++w) {
+        const int wf = pc * pairs_per_block + w * 64;
+        nlive += (wf + 64 <= jl || w * 64 >= pairs_per_block || wf >= npairs) ? 0 : 1;
+    }
+    if (wave_dead) return;
+    // Cross-wave sums: the wave adds its D values of round r (chunks kAdjGroup r ..) into slot
+    // r % kAdjSlots and counts itself in; the wave that completes the count adds the slot into
+    // the output, clears it and hands it on to round r + kAdjSlots.
     for (int c0 = 0; c0 < nchunks; c0 += kAdjGroup) {
         double dv[kAdjGroup][2];
 #pragma unroll
         for (int g = 0; g < kAdjGroup; ++g) {
             double acc0 = 0.0, acc1 = 0.0, acc2 = 0.0, acc3 = 0.0;
             const int l0 = m + (c0 + g) * kLC;
-            if (!wave_dead && l0 <= lmax) {
+            if (c0 + g < nchunks) {
                 // the chunk's recurrence coefficients in one batch of scalar loads (the table
                 // is padded past its end), and the lines of the chunk kAdjPfAhead ahead
                 // touched into L2
                 double2 cc[kLC];
 #pragma unroll
-                for (int i = 0; i < kLC; ++i) cc[i] = rec[moff + l0 + i];
+                for (int i = 0; i < kLC; ++i)
+                    cc[i] = make_double2(crec[2 * (moff + l0 + i)], crec[2 * (moff + l0 + i) + 1]);
                 if (lane < 3 && l0 + kAdjPfAhead * kLC <= lmax)
                     pf_keep ^= lds_dma_touch(rec + moff + l0 + kAdjPfAhead * kLC + 8 * lane,
                                              lds_sink);
@@ -632,30 +665,70 @@ __global__ __launch_bounds__(kAdjWaves * 64, 4) void k_legendre_adj(
             dv[g][0] = acc0 + acc1;
             dv[g][1] = acc2 + acc3;
         }
-        // the group's D values go into this wave's staging area (its lam values are consumed)
+        // this wave's share of the round into slot r % kAdjSlots, once the round kAdjSlots
+        // earlier has been taken out of it.  A slot is handed on as soon as the slowest live
+        // wave has added into it, so the slowest wave never waits here and every wait ends; the
+        // bound only keeps a broken invariant from hanging the device.
+        const int rnd = c0 / kAdjGroup;
+        const int sl = rnd & (kAdjSlots - 1);
+        const unsigned use = (unsigned)(rnd / kAdjSlots);
+        for (int it = 0; it < (1 << 22); ++it) {
+            if (__hip_atomic_load(&sgen[sl], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP) ==
+                use)
+                break;
+            __builtin_amdgcn_s_sleep(1);
+        }
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
 #pragma unroll
         for (int g = 0; g < kAdjGroup; ++g) {
-            st[(2 * g) * 64 + lane] = dv[g][0];
-            st[(2 * g + 1) * 64 + lane] = dv[g][1];
+            __hip_atomic_fetch_add(&slot[sl][g * 128 + lane], dv[g][0], __ATOMIC_RELAXED,
+                                   __HIP_MEMORY_SCOPE_WORKGROUP);
+            __hip_atomic_fetch_add(&slot[sl][g * 128 + 64 + lane], dv[g][1], __ATOMIC_RELAXED,
+                                   __HIP_MEMORY_SCOPE_WORKGROUP);
         }
-        __syncthreads();
-        // sum over the block's waves; value t -> chunk t / 128, part c = (t / 64) % 2,
-        // D lane t % 64
-        for (int t = threadIdx.x; t < kAdjGroup * 128; t += blockDim.x) {
-            const int d = t & 63;
-            const int b = d >> 4;              // map
-            const int blk = (d >> 2) & 3;      // 2 s + h
-            const int l = m + (c0 + (t >> 7)) * kLC + 8 * (blk >> 1) + 2 * (d & 3) + (blk & 1);
-            if (l > lmax || b >= nmb) continue;
-            double v = 0.0;
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+        unsigned arrived = 0;
+        if (lane == 0)
+            arrived = __hip_atomic_fetch_add(&scnt[sl], 1u, __ATOMIC_RELAXED,
+                                             __HIP_MEMORY_SCOPE_WORKGROUP);
+        arrived = __builtin_amdgcn_readfirstlane(arrived);
+        if ((int)arrived == nlive - 1) {
+            // last arrival: the slot holds the block's sums of this round
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+            double v[kAdjGroup][2];
 #pragma unroll
-            for (int w = 0; w < kAdjWaves; ++w)
-                if (w < nwaves) v += stage[w][t];
-            const int c = (t >> 6) & 1;
-            if (m > 0 || c == 0)  // c_l0 is real
-                unsafeAtomicAdd(alm + ((int64_t)(4 * grp + b) * nalm + moff + l) * 2 + c, v);
+            for (int g = 0; g < kAdjGroup; ++g) {
+                v[g][0] = slot[sl][g * 128 + lane];
+                v[g][1] = slot[sl][g * 128 + 64 + lane];
+                slot[sl][g * 128 + lane] = 0.0;
+                slot[sl][g * 128 + 64 + lane] = 0.0;
+            }
+            // the lane index re-read here (opaque to the compiler), so that the lane's output
+            // offset is formed in this branch instead of being held in registers throughout
+            unsigned ln;
+            asm volatile("v_mbcnt_lo_u32_b32 %0, -1, 0\n\tv_mbcnt_hi_u32_b32 %0, -1, %0"
+                         : "=v"(ln));
+            const int b = ln >> 4;                // map
+            const int blk = (ln >> 2) & 3;        // 2 s + h
+            const int dl = 8 * (blk >> 1) + 2 * (ln & 3) + (blk & 1);
+#pragma unroll
+            for (int g = 0; g < kAdjGroup; ++g) {
+                const int l = m + (c0 + g) * kLC + dl;
+                if (l <= lmax && b < nmb) {
+                    // the lane's map offset in 32 bits (b nalm 2 < 2^32), the rest uniform
+                    double* o = alm + ((int64_t)(4 * grp) * nalm + moff + m + (c0 + g) * kLC) * 2 +
+                                (unsigned)(b * (unsigned)nalm * 2u + (unsigned)dl * 2u);
+                    if (v[g][0] != 0.0) unsafeAtomicAdd(o, v[g][0]);
+                    if (m > 0 && v[g][1] != 0.0) unsafeAtomicAdd(o + 1, v[g][1]);  // c_l0 is real
+                }
+            }
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+            if (lane == 0) {
+                scnt[sl] = 0;
+                __hip_atomic_store(&sgen[sl], use + 1, __ATOMIC_RELAXED,
+                                   __HIP_MEMORY_SCOPE_WORKGROUP);
+            }
         }
-        __syncthreads();
     }
     // no LDS-DMA write may be in flight when the workgroup's LDS is released
     asm volatile("s_waitcnt vmcnt(0)" ::"v"(pf_keep) : "memory");
