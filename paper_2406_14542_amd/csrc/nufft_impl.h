@@ -48,6 +48,21 @@ __device__ inline int wrap_index(int i, int n)
     return i < 0 ? i + n : i;
 }
 
+// Slot of a tile workgroup: runs of kSlotRun consecutive slots (neighbouring tiles of a tile
+// row) go to one XCD (workgroups go to the 8 XCDs round-robin by linear id), so that the
+// 128-byte line a window shares with the next tile of its row comes from that XCD's L2
+// instead of a second HBM fetch; the runs themselves alternate over the XCDs, which keeps the
+// point load of the XCDs even (points per tile follow sin theta).  The last partial group of
+// 8 runs keeps the identity order.
+constexpr int kSlotRun = 8;
+__device__ inline int xcd_slot(int b, int n)
+{
+    const int full = n / (8 * kSlotRun) * (8 * kSlotRun);
+    if (b >= full) return b;
+    const int x = b & 7, i = b >> 3;
+    return ((i / kSlotRun) * 8 + x) * kSlotRun + i % kSlotRun;
+}
+
 template <typename T>
 __device__ inline T es_value(T z, T beta)
 {
@@ -135,7 +150,7 @@ __global__ __launch_bounds__(256) void k_interp(const T* __restrict__ fine, int6
 {
     constexpr int P = kTile + W - 1;
     __shared__ T win[P * P * MB];
-    const int slot = blockIdx.x;
+    const int slot = xcd_slot(blockIdx.x, gridDim.x);
     const int tile = pb.slot_tile[slot];
     const int r0 = (tile / pb.nt2) * kTile;
     const int c0 = (tile % pb.nt2) * kTile;
@@ -234,7 +249,7 @@ __global__ __launch_bounds__(256) void k_interp_deriv(const double* __restrict__
 {
     constexpr int P = kTile + W - 1;
     __shared__ double win[P * P * MB];
-    const int slot = blockIdx.x;
+    const int slot = xcd_slot(blockIdx.x, gridDim.x);
     const int tile = pb.slot_tile[slot];
     const int r0 = (tile / pb.nt2) * kTile;
     const int c0 = (tile % pb.nt2) * kTile;
