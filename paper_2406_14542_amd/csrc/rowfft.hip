@@ -139,16 +139,40 @@ struct RowShape {
 //   Ns), DFT_R, outputs out[(idx - j) R + j + r Ns].
 // tw[m] = e^{2 pi i m / n2} (n2 = 2 N), so e^{2 pi i a / N} = tw[2 a].
 // The twiddles of a butterfly are fetched (global loads, L2-resident table) before the
-// pass's LDS reads and barrier, so that their latency overlaps the wait.
+// pass's LDS reads and barrier, so that their latency overlaps the wait.  A radix-16
+// butterfly loads w, w^2, w^4 and w^8 and forms the other powers by at most three complex
+// products (the table loads, not the arithmetic, set the time of these passes).
 template <int R, int DIR, typename C>
 __device__ inline void load_twiddles(C (&w)[R], int j, int Ns, int N, const C* __restrict__ tw)
 {
     const int step = 2 * j * (N / (Ns * R));
+    if constexpr (R == 16) {
+        w[1] = tw[step];
+        w[2] = tw[2 * step];
+        w[4] = tw[4 * step];
+        w[8] = tw[8 * step];
+        w[3] = cmul(w[1], w[2]);
+        w[5] = cmul(w[4], w[1]);
+        w[6] = cmul(w[4], w[2]);
+        w[7] = cmul(w[4], w[3]);
 #pragma unroll
-    for (int r = 1; r < R; ++r) {
-        w[r] = tw[r * step];
-        if (DIR < 0) w[r].y = -w[r].y;
+        for (int r = 9; r < 16; ++r) w[r] = cmul(w[8], w[r - 8]);
+    } else {
+#pragma unroll
+        for (int r = 1; r < R; ++r) w[r] = tw[r * step];
     }
+    if (DIR < 0) {
+#pragma unroll
+        for (int r = 1; r < R; ++r) w[r].y = -w[r].y;
+    }
+}
+
+// tw[k] read through the constant address space: for a wave-uniform k this is a scalar load
+template <typename T>
+__device__ inline typename Cx<T>::type tw_uniform(const typename Cx<T>::type* tw, int k)
+{
+    const __attribute__((address_space(4))) T* p = (const __attribute__((address_space(4))) T*)tw;
+    return cmk<typename Cx<T>::type>(p[2 * k], p[2 * k + 1]);
 }
 
 template <int R, typename C>
@@ -207,6 +231,9 @@ __global__ __launch_bounds__(RowShape<K>::NT) void k_row_c2r(
     // loads are issued first (indices clamped into the band, unused values masked after),
     // then the butterflies are formed.
     constexpr int NU = (N / R0 + S::NT - 1) / S::NT;
+    // split twiddles e^{2 pi i k / n2}, k = t + u NT + r N / R0: the thread's tw[t] times a
+    // wave-uniform factor
+    const C wt = tw[t];
     C xa[NU][R0], xb[NU][R0];
 #pragma unroll
     for (int u = 0; u < NU; ++u)
@@ -229,7 +256,8 @@ __global__ __launch_bounds__(RowShape<K>::NT) void k_row_c2r(
                 const C xm = (k > 0 && N - k <= M) ? xb[u][r] : cmk<C>(0, 0);
                 const C xc = cmk<C>(xm.x, -xm.y);
                 const C e = cadd(xk, xc);
-                const C o = cmul(csub(xk, xc), tw[k]);
+                const C o = cmul(csub(xk, xc),
+                                 cmul(wt, tw_uniform<T>(tw, u * S::NT + r * (N / R0))));
                 v[r] = cmk<C>(e.x - o.y, e.y + o.x);
             }
             dft<R0, +1>(v);
@@ -301,6 +329,7 @@ __global__ __launch_bounds__(RowShape<K>::NT) void k_row_r2c(
         __syncthreads();
     }
     C* X = rows + (int64_t)i * rw;
+    const C wt = tw[t];  // e^{-2 pi i k / n2} = conj(tw[t] tw[k - t]), k - t wave-uniform
     for (int k = t; k < ncol; k += S::NT) {
         const C zk = buf[pad16(k)];
         const C zm = buf[pad16((N - k) & (N - 1))];
@@ -308,7 +337,7 @@ __global__ __launch_bounds__(RowShape<K>::NT) void k_row_r2c(
         // O = (Z[k] - conj Z[N-k]) / (2 i)
         const C d = cmk<C>((zk.x - zm.x) / 2, (zk.y + zm.y) / 2);
         const C o = cmk<C>(d.y, -d.x);
-        C w = tw[k];
+        C w = cmul(wt, tw_uniform<T>(tw, k - t));
         w.y = -w.y;
         X[k] = cadd(e, cmul(o, w));
     }
