@@ -99,6 +99,7 @@ struct nusht_plan_s {
     double* sth = nullptr;       // [npts] theta, sorted by tile
     double* sph = nullptr;       // [npts] phi mod 2 pi, sorted by tile
     int* perm = nullptr;         // [npts] user index of each sorted point
+    int* iperm = nullptr;        // [npts] sorted index of each user point (inverse of perm)
     int* slot_off = nullptr;     // [nslots+1] first sorted point of each slot
     int* slot_tile = nullptr;    // [nslots] tile id of each slot
     int* tile_slot = nullptr;    // [ntiles] slot of each tile or -1

@@ -141,14 +141,18 @@ __device__ inline void stage_window(const T* __restrict__ fine, int64_t map_stri
     }
 }
 
-// PACKED: out[dst][MB] (one MB * 8-byte store per point, unpacked afterwards by
-// k_unpack_points); otherwise out[b][dst] (MB scattered 8-byte stores).
+// PACKED: one MB * 8-byte row per point, unpacked afterwards by k_unpack_points.  FP32
+// windows write the rows in the sorted (tile) order p, coalesced, and the unpack gathers each
+// caller point's row through the inverse permutation; FP64 windows (whose taps hide the
+// scattered stores) write the rows in the caller's order, out[dst].  Not PACKED:
+// out[b][dst] (MB scattered 8-byte stores).
 template <typename T, int W, int MB, bool PACKED>
 __global__ __launch_bounds__(256) void k_interp(const T* __restrict__ fine, int64_t map_stride,
                                                 PointBins pb, T beta, double* __restrict__ out,
                                                 int64_t npts)
 {
     constexpr int P = kTile + W - 1;
+    constexpr bool kUserRows = !PACKED || sizeof(T) == 8;  // results addressed by caller index
     __shared__ T win[P * P * MB];
     const int slot = xcd_slot(blockIdx.x, gridDim.x);
     const int tile = pb.slot_tile[slot];
@@ -163,7 +167,7 @@ __global__ __launch_bounds__(256) void k_interp(const T* __restrict__ fine, int6
     if (p < p1) {
         thn = pb.sth[p];
         phn = pb.sph[p];
-        dstn = pb.perm[p];
+        if (kUserRows) dstn = pb.perm[p];
     }
     stage_window<T, P, MB>(fine, map_stride, pb, r0, c0, win);
     __syncthreads();
@@ -173,7 +177,7 @@ __global__ __launch_bounds__(256) void k_interp(const T* __restrict__ fine, int6
         if (p + 256 < p1) {  // the next point's data, loaded under this point's work
             thn = pb.sth[p + 256];
             phn = pb.sph[p + 256];
-            dstn = pb.perm[p + 256];
+            if (kUserRows) dstn = pb.perm[p + 256];
         }
         double d1, d2;
         const int l1 = first_tap(th, pb.s1, W, d1);
@@ -203,7 +207,7 @@ __global__ __launch_bounds__(256) void k_interp(const T* __restrict__ fine, int6
             for (int b = 0; b < MB; ++b) acc[b] += p1v[a] * row[b];
         }
         if (PACKED) {
-            double* o = out + dst * MB;
+            double* o = out + (kUserRows ? dst : (int64_t)p) * MB;
 #pragma unroll
             for (int b = 0; b < MB; ++b) o[b] = (double)acc[b];
         } else {
@@ -213,16 +217,20 @@ __global__ __launch_bounds__(256) void k_interp(const T* __restrict__ fine, int6
     }
 }
 
-// out[b][i] = packed[i][b]: both sides coalesced
-template <int MB>
-__global__ void k_unpack_points(const double* __restrict__ packed, int64_t npts,
+// out[b][i] = packed[src][b] with src = iperm[i] (GATHER: rows in tile order; one 8 MB-byte
+// gather per caller point, writes coalesced; scattered 32-byte row writes had cost the FP32
+// interpolation kernel 1.1 ms at 33.5 M points) or src = i (rows in caller order)
+template <int MB, bool GATHER>
+__global__ void k_unpack_points(const double* __restrict__ packed,
+                                const int* __restrict__ iperm, int64_t npts,
                                 double* __restrict__ out)
 {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= npts) return;
+    const int64_t src = GATHER ? (int64_t)iperm[i] : i;
     double v[MB];
 #pragma unroll
-    for (int b = 0; b < MB; ++b) v[b] = packed[i * MB + b];
+    for (int b = 0; b < MB; ++b) v[b] = packed[src * MB + b];
 #pragma unroll
     for (int b = 0; b < MB; ++b) out[b * npts + i] = v[b];
 }
@@ -515,8 +523,8 @@ int dispatch_interp_impl(const nusht_plan_s* p, const T* fine, double* out, int 
             if (mb == 4) {
                 hipLaunchKernelGGL((k_interp<T, WV, 4, true>), dim3(p->nslots), dim3(256), 0, s,
                                    fine + b * ms, ms, pb, beta, p->V, npts);
-                hipLaunchKernelGGL(k_unpack_points<4>, dim3(pblocks), dim3(256), 0, s, p->V,
-                                   npts, out + b * npts);
+                hipLaunchKernelGGL((k_unpack_points<4, sizeof(T) == 4>), dim3(pblocks), dim3(256),
+                                   0, s, p->V, p->iperm, npts, out + b * npts);
             } else {
                 hipLaunchKernelGGL((k_interp<T, WV, 1, false>), dim3(p->nslots), dim3(256), 0,
                                    s, fine + b * ms, ms, pb, beta, out + b * npts, npts);

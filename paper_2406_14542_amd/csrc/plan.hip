@@ -124,13 +124,14 @@ __global__ void k_bin_keys(const double* __restrict__ theta, const double* __res
 
 __global__ void k_gather_sorted(const double* __restrict__ theta, const double* __restrict__ phw,
                                 const int* __restrict__ perm, int64_t n, double* __restrict__ sth,
-                                double* __restrict__ sph)
+                                double* __restrict__ sph, int* __restrict__ iperm)
 {
     const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (k >= n) return;
     const int i = perm[k];
     sth[k] = theta[i];
     sph[k] = phw[i];
+    iperm[i] = (int)k;
 }
 
 __global__ void k_mark(const int* __restrict__ keys, int64_t n, int* __restrict__ first)
@@ -315,7 +316,8 @@ int bin_points(nusht_plan_s* p, const double* theta, const double* phi, hipStrea
     do {
         if ((rc = dmalloc(&keys, n)) || (rc = dmalloc(&keys_s, n)) || (rc = dmalloc(&idx, n)) ||
             (rc = dmalloc(&first, n)) || (rc = dmalloc(&sidx, n)) || (rc = dmalloc(&phw, n)) ||
-            (rc = dmalloc(&p->perm, n)) || (rc = dmalloc(&p->sth, n)) ||
+            (rc = dmalloc(&p->perm, n)) || (rc = dmalloc(&p->iperm, n)) ||
+            (rc = dmalloc(&p->sth, n)) ||
             (rc = dmalloc(&p->sph, n)) || (rc = dmalloc(&p->tile_slot, ntiles)) ||
             (rc = dmalloc(&p->dflag, 1)))
             break;
@@ -331,7 +333,7 @@ int bin_points(nusht_plan_s* p, const double* theta, const double* phi, hipStrea
         if (hipcub::DeviceRadixSort::SortPairs(tmp, tbytes, keys, keys_s, idx, p->perm, (int)n, 0,
                                                bits, s) != hipSuccess) { rc = NUSHT_EDEVICE; break; }
         hipLaunchKernelGGL(k_gather_sorted, dim3(blocks), dim3(256), 0, s, theta, phw, p->perm, n,
-                           p->sth, p->sph);
+                           p->sth, p->sph, p->iperm);
         hipLaunchKernelGGL(k_mark, dim3(blocks), dim3(256), 0, s, keys_s, n, first);
         if (hipcub::DeviceScan::ExclusiveSum(tmp, tbytes, first, sidx, (int)n, s) != hipSuccess) { rc = NUSHT_EDEVICE; break; }
         int last_first = 0, last_idx = 0, flag = 0;
@@ -582,7 +584,7 @@ void nusht_destroy(nusht_plan_t p)
     hipDeviceSynchronize();
     destroy_fft_plans(p);
     void* bufs[] = {p->rec,  p->cm_mant, p->cm_exp,   p->dec1,      p->dec2,      p->dec1f,
-                    p->dec2f, p->sth,    p->sph,      p->perm,      p->V,
+                    p->dec2f, p->sth,    p->sph,      p->perm,      p->iperm,     p->V,
                     p->slot_off,  p->slot_tile,
                     p->tile_slot, p->dflag, p->X,     p->Y,         p->Z,         p->W,
                     p->fftwork,   p->rowtw,
