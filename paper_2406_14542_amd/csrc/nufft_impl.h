@@ -206,8 +206,13 @@ __global__ __launch_bounds__(256) void k_interp(const T* __restrict__ fine, int6
 #pragma unroll
             for (int b = 0; b < MB; ++b) acc[b] += p1v[a] * row[b];
         }
-        if (PACKED) {
-            double* o = out + (kUserRows ? dst : (int64_t)p) * MB;
+        if (PACKED && !kUserRows) {
+            // FP32 rows (the values are FP32 sums): 16 bytes per point
+            float* o = reinterpret_cast<float*>(out) + (int64_t)p * MB;
+#pragma unroll
+            for (int b = 0; b < MB; ++b) o[b] = (float)acc[b];
+        } else if (PACKED) {
+            double* o = out + dst * MB;
 #pragma unroll
             for (int b = 0; b < MB; ++b) o[b] = (double)acc[b];
         } else {
@@ -217,9 +222,9 @@ __global__ __launch_bounds__(256) void k_interp(const T* __restrict__ fine, int6
     }
 }
 
-// out[b][i] = packed[src][b] with src = iperm[i] (GATHER: rows in tile order; one 8 MB-byte
-// gather per caller point, writes coalesced; scattered 32-byte row writes had cost the FP32
-// interpolation kernel 1.1 ms at 33.5 M points) or src = i (rows in caller order)
+// out[b][i] = packed[src][b].  GATHER: FP32 rows in tile order, src = iperm[i] (one 4 MB-byte
+// gather per caller point, writes coalesced; scattered row writes had cost the FP32
+// interpolation kernel 1.1 ms at 33.5 M points).  Otherwise FP64 rows in caller order, src = i.
 template <int MB, bool GATHER>
 __global__ void k_unpack_points(const double* __restrict__ packed,
                                 const int* __restrict__ iperm, int64_t npts,
@@ -227,10 +232,15 @@ __global__ void k_unpack_points(const double* __restrict__ packed,
 {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= npts) return;
-    const int64_t src = GATHER ? (int64_t)iperm[i] : i;
     double v[MB];
+    if (GATHER) {
+        const float* pf = reinterpret_cast<const float*>(packed) + (int64_t)iperm[i] * MB;
 #pragma unroll
-    for (int b = 0; b < MB; ++b) v[b] = packed[src * MB + b];
+        for (int b = 0; b < MB; ++b) v[b] = (double)pf[b];
+    } else {
+#pragma unroll
+        for (int b = 0; b < MB; ++b) v[b] = packed[i * MB + b];
+    }
 #pragma unroll
     for (int b = 0; b < MB; ++b) out[b * npts + i] = v[b];
 }
