@@ -144,22 +144,45 @@ static void lam_mm_step(int m, double s, double* mant, int* ex)
     *ex += k;
 }
 
-/* lam[l - m] = lam_lm(cos theta) for l = m..lmax, given lam_mm = pm * 2^pe. */
-static void lambda_column(int lmax, int m, const angle_t* ang, double pm, int pe, double* lam)
+/* The scaled column: lam_lm(cos theta) = mant[l - m] * 2^ex[l - m] for l = m..lmax, given
+   lam_mm = pm * 2^pe.  Every function of this file that needs lam_lm goes through here, and
+   so do the pins (oracle_lambda_column). */
+static void column_scaled(int lmax, int m, const angle_t* ang, double pm, int pe, double* mant,
+                          int* ex)
 {
     double v0 = pm, v1;
     int e = pe;
-    lam[0] = ldexp(v0, e);
+    mant[0] = v0;
+    ex[0] = e;
     if (m + 1 > lmax) return;
     v1 = sqrt(2.0 * m + 3.0) * xmul(ang, v0);
-    lam[1] = ldexp(v1, e);
+    mant[1] = v1;
+    ex[1] = e;
     for (int l = m + 2; l <= lmax; ++l) {
         double v2 = coef_a(l, m) * (xmul(ang, v1) - coef_b(l, m) * v0);
         v0 = v1;
         v1 = v2;
         renorm2(&v0, &v1, &e);
-        lam[l - m] = ldexp(v1, e);
+        mant[l - m] = v1;
+        ex[l - m] = e;
     }
+}
+
+/* lam[l - m] = lam_lm(cos theta) as plain doubles (rounded to 0 or a subnormal when that
+   small); mant and ex are caller scratch of lmax + 1 entries. */
+static void lambda_column(int lmax, int m, const angle_t* ang, double pm, int pe, double* lam,
+                          double* mant, int* ex)
+{
+    column_scaled(lmax, m, ang, pm, pe, mant, ex);
+    for (int l = m; l <= lmax; ++l) lam[l - m] = ldexp(mant[l - m], ex[l - m]);
+}
+
+/* lam_00 = 1/sqrt(4 pi) as mantissa * 2^exponent */
+static void lam_00(double* pm, int* pe)
+{
+    int k;
+    *pm = frexp(1.0 / sqrt(4.0 * PI_D), &k);
+    *pe = k;
 }
 
 /* Same column and its theta-derivative.  With x = cos(theta), s = sin(theta):
@@ -217,28 +240,11 @@ static int pick_threads(int nthreads)
 void oracle_lambda_column(int lmax, int m, double theta, double* mant, int* ex)
 {
     angle_t ang = make_angle(theta);
-    double s = ang.s;
-    double pm = 1.0 / sqrt(4.0 * PI_D);
-    int pe = 0, k;
-    pm = frexp(pm, &k);
-    pe += k;
-    for (int j = 1; j <= m; ++j) lam_mm_step(j, s, &pm, &pe);
-    double v0 = pm, v1;
-    int e = pe;
-    mant[0] = v0;
-    ex[0] = e;
-    if (m + 1 > lmax) return;
-    v1 = sqrt(2.0 * m + 3.0) * xmul(&ang, v0);
-    mant[1] = v1;
-    ex[1] = e;
-    for (int l = m + 2; l <= lmax; ++l) {
-        double v2 = coef_a(l, m) * (xmul(&ang, v1) - coef_b(l, m) * v0);
-        v0 = v1;
-        v1 = v2;
-        renorm2(&v0, &v1, &e);
-        mant[l - m] = v1;
-        ex[l - m] = e;
-    }
+    double pm;
+    int pe;
+    lam_00(&pm, &pe);
+    for (int j = 1; j <= m; ++j) lam_mm_step(j, ang.s, &pm, &pe);
+    column_scaled(lmax, m, &ang, pm, pe, mant, ex);
 }
 
 /* The same column in x87 80-bit long double (range about 1e+-4932), with no exponent
@@ -278,18 +284,19 @@ void oracle_synthesis(int lmax, int mmax, int64_t npts, const double* theta, con
 #pragma omp parallel num_threads(nt)
     {
         double* lam = (double*)malloc(sizeof(double) * (lmax + 1));
+        double* mant = (double*)malloc(sizeof(double) * (lmax + 1));
+        int* ex = (int*)malloc(sizeof(int) * (lmax + 1));
         double* acc = (double*)malloc(sizeof(double) * 2 * nmaps);
 #pragma omp for schedule(static)
         for (int64_t i = 0; i < npts; ++i) {
             angle_t ang = make_angle(theta[i]);
-            double pm = 1.0 / sqrt(4.0 * PI_D);
-            int pe = 0, k;
-            pm = frexp(pm, &k);
-            pe += k;
+            double pm;
+            int pe;
+            lam_00(&pm, &pe);
             for (int b = 0; b < nmaps; ++b) out[(int64_t)b * npts + i] = 0.0;
             for (int m = 0; m <= mmax; ++m) {
                 if (m > 0) lam_mm_step(m, ang.s, &pm, &pe);
-                lambda_column(lmax, m, &ang, pm, pe, lam);
+                lambda_column(lmax, m, &ang, pm, pe, lam, mant, ex);
                 for (int b = 0; b < 2 * nmaps; ++b) acc[b] = 0.0;
                 for (int l = m; l <= lmax; ++l) {
                     const double* a = alm + 2 * alm_index(lmax, l, m);
@@ -310,6 +317,8 @@ void oracle_synthesis(int lmax, int mmax, int64_t npts, const double* theta, con
             }
         }
         free(lam);
+        free(mant);
+        free(ex);
         free(acc);
     }
 }
@@ -340,13 +349,14 @@ void oracle_adjoint_columns(int lmax, int64_t npts, const double* theta, const d
 #endif
         double* mine = part + per * tid;
         double* lam = (double*)malloc(sizeof(double) * (lmax + 1));
+        double* mant = (double*)malloc(sizeof(double) * (lmax + 1));
+        int* ex = (int*)malloc(sizeof(int) * (lmax + 1));
 #pragma omp for schedule(static)
         for (int64_t i = 0; i < npts; ++i) {
             angle_t ang = make_angle(theta[i]);
-            double pm = 1.0 / sqrt(4.0 * PI_D);
-            int pe = 0, k;
-            pm = frexp(pm, &k);
-            pe += k;
+            double pm;
+            int pe;
+            lam_00(&pm, &pe);
             int mcur = 0;
             /* visit the columns in increasing m so lam_mm can be advanced incrementally */
             for (int m = 0; m <= maxm; ++m) {
@@ -356,7 +366,7 @@ void oracle_adjoint_columns(int lmax, int64_t npts, const double* theta, const d
                 }
                 int c = slot[m];
                 if (c < 0) continue;
-                lambda_column(lmax, m, &ang, pm, pe, lam);
+                lambda_column(lmax, m, &ang, pm, pe, lam, mant, ex);
                 double cr = cos(m * phi[i]), ci = -sin(m * phi[i]);
                 for (int b = 0; b < nmaps; ++b) {
                     double fv = f[(int64_t)b * npts + i];
@@ -369,6 +379,8 @@ void oracle_adjoint_columns(int lmax, int64_t npts, const double* theta, const d
             }
         }
         free(lam);
+        free(mant);
+        free(ex);
     }
     memset(out, 0, sizeof(double) * per);
     for (int t = 0; t < nt; ++t)
@@ -410,16 +422,18 @@ void oracle_synthesis_grad(int lmax, int mmax, int64_t npts, const double* theta
 #pragma omp parallel num_threads(nt)
     {
         double* lam = (double*)malloc(sizeof(double) * (lmax + 1));
+        double* lam_d = (double*)malloc(sizeof(double) * (lmax + 1));
         double* dlam = (double*)malloc(sizeof(double) * (lmax + 1));
+        double* mant = (double*)malloc(sizeof(double) * (lmax + 1));
+        int* ex = (int*)malloc(sizeof(int) * (lmax + 1));
         double* acc = (double*)malloc(sizeof(double) * 4 * nmaps);
 #pragma omp for schedule(static)
         for (int64_t i = 0; i < npts; ++i) {
             angle_t ang = make_angle(theta[i]);
             /* pm*2^pe = c_m s^m ; pm1*2^pe1 = c_m s^(m-1) */
-            double pm = 1.0 / sqrt(4.0 * PI_D), pm1 = 0.0;
-            int pe = 0, pe1 = 0, k;
-            pm = frexp(pm, &k);
-            pe += k;
+            double pm, pm1 = 0.0;
+            int pe, pe1 = 0, k;
+            lam_00(&pm, &pe);
             for (int b = 0; b < nmaps; ++b) {
                 f[(int64_t)b * npts + i] = 0.0;
                 dth[(int64_t)b * npts + i] = 0.0;
@@ -436,7 +450,10 @@ void oracle_synthesis_grad(int lmax, int mmax, int64_t npts, const double* theta
                     }
                     lam_mm_step(m, ang.s, &pm, &pe);
                 }
-                lambda_column_d(lmax, m, &ang, pm, pe, pm1, pe1, lam, dlam);
+                /* lam from the shared scaled column; the forward-mode recurrence is used
+                   for the derivative only */
+                lambda_column(lmax, m, &ang, pm, pe, lam, mant, ex);
+                lambda_column_d(lmax, m, &ang, pm, pe, pm1, pe1, lam_d, dlam);
                 for (int b = 0; b < 4 * nmaps; ++b) acc[b] = 0.0;
                 for (int l = m; l <= lmax; ++l) {
                     const double* a = alm + 2 * alm_index(lmax, l, m);
@@ -466,7 +483,10 @@ void oracle_synthesis_grad(int lmax, int mmax, int64_t npts, const double* theta
             }
         }
         free(lam);
+        free(lam_d);
         free(dlam);
+        free(mant);
+        free(ex);
         free(acc);
     }
 }

@@ -296,3 +296,73 @@ def test_oracle_is_deterministic_across_thread_counts(oracle_mod):
     a1 = oracle_mod.synthesis(L, L, th, ph, alm, nthreads=1)
     a4 = oracle_mod.synthesis(L, L, th, ph, alm, nthreads=4)
     assert np.array_equal(a1, a4)
+
+
+# ---- pins through the transform entry points at lmax = 4095 --------------------------------
+# The functions the parity tests call (synthesis, adjoint, adjoint_columns, synthesis_grad)
+# run the same scaled column as lambda_column, but then round every value to a plain double
+# and sum; these pins go through those entry points themselves, so a slip in the exponent
+# bookkeeping or the final ldexp shows up where the parity tests look.
+
+def _mp_lambda(L, m, th):
+    """lam_Lm(cos th) from mpmath at 60 digits (legenp carries the Condon-Shortley phase)."""
+    mpmath.mp.dps = 60
+    norm = mpmath.sqrt((2 * L + 1) / (4 * mpmath.pi) * mpmath.factorial(L - m)
+                       / mpmath.factorial(L + m))
+    return norm * mpmath.legenp(L, m, mpmath.cos(mpmath.mpf(th)), type=2)
+
+
+@pytest.mark.parametrize("th", [1e-6, 0.02, 0.7, math.pi - 0.3])
+def test_single_point_adjoint_addition_theorem_4095(oracle_mod, th):
+    """Adjoint (Eq. 2) of a unit value at one point: c_lm = lam_lm(x) e^{-i m phi}, so
+    sum_m w_m |c_lm|^2 = (2l+1)/4pi for every l <= 4095 (addition theorem), with w_0 = 1 and
+    w_m = 2.  Terms below the double range are dropped by the entry point; they are far below
+    the tolerance.  The phase factor is checked to be a pure rotation: |c_lm| = |lam_lm|."""
+    L = 4095
+    ph = 1.1
+    c = oracle_mod.adjoint(L, L, np.array([th]), np.array([ph]), np.ones((1, 1)),
+                           nthreads=1)[0]
+    ls, ms = inputs.ell_of_index(L, L)
+    w = np.where(ms == 0, 1.0, 2.0)
+    tot = np.zeros(L + 1)
+    np.add.at(tot, ls, w * np.abs(c) ** 2)
+    want = (2 * np.arange(L + 1) + 1) / (4 * math.pi)
+    growth = np.sqrt(np.arange(L + 1) + 1.0) * np.minimum(np.arange(L + 1) + 1.0,
+                                                          1.0 / math.sin(th))
+    rtol = np.maximum(2e-13, 4.0 * 2.2e-16 * growth)
+    r = np.abs(tot / want - 1.0)
+    assert np.all(r <= rtol), (th, float(r.max()), int(np.argmax(r / rtol)))
+    # phase: c_lm e^{i m phi} is real (= lam_lm)
+    rot = c * np.exp(1j * ms * ph)
+    assert np.all(np.abs(rot.imag) <= 1e-12 * np.abs(c) + 1e-300)
+
+
+@pytest.mark.parametrize("m,th", [(0, 0.3), (1500, 0.8), (3000, 1.2), (4000, 1.5),
+                                  (2500, 0.75)])
+def test_unit_coefficient_entry_points_vs_mpmath_4095(oracle_mod, m, th):
+    """Unit coefficient a_{4095,m} through synthesis (f = w_m lam cos(m phi)), through the
+    adjoint column of a unit value (c = lam e^{-i m phi}) and through synthesis_grad (its f,
+    and d f/d theta against sin(th) dlam/dth = l cos(th) lam_l - sqrt((2l+1)(l^2-m^2)/(2l-1))
+    lam_{l-1}, both lam from mpmath).  (2500, 0.75) lies just inside the oscillatory region,
+    where lam_mm is ~1e-300 and the recurrence crosses the rescale threshold many times."""
+    L = 4095
+    ph = 0.37
+    want = _mp_lambda(L, m, th)
+    wm = 1.0 if m == 0 else 2.0
+    thv, phv = np.array([th]), np.array([ph])
+    f = oracle_mod.synthesis(L, L, thv, phv, unit_alm(L, L, L, m))[0, 0]
+    fw = float(wm * want * mpmath.cos(m * mpmath.mpf(ph)))
+    assert abs(f - fw) <= 1e-11 * abs(float(want)) * wm, (m, th, f, fw)
+    col = oracle_mod.adjoint_columns(L, thv, phv, np.ones((1, 1)), [m], nthreads=1)[0, 0, L]
+    cw = complex(want * mpmath.exp(-1j * m * mpmath.mpf(ph)))
+    assert abs(col - cw) <= 1e-11 * abs(float(want)), (m, th, col, cw)
+    fg, dt, _ = oracle_mod.synthesis_grad(L, L, thv, phv, unit_alm(L, L, L, m))
+    assert abs(fg[0, 0] - fw) <= 1e-11 * abs(float(want)) * wm
+    lm1 = _mp_lambda(L - 1, m, th) if m < L else mpmath.mpf(0)
+    x = mpmath.cos(mpmath.mpf(th))
+    dlam = (L * x * want - mpmath.sqrt(mpmath.mpf((2 * L + 1) * (L * L - m * m)) / (2 * L - 1))
+            * lm1) / mpmath.sin(mpmath.mpf(th))
+    dw = float(wm * dlam * mpmath.cos(m * mpmath.mpf(ph)))
+    # d lam / d theta is ~ l lam: the same relative tolerance against its own scale
+    scale = max(abs(float(dlam)), L * abs(float(want)))
+    assert abs(dt[0, 0] - dw) <= 2e-11 * scale * wm, (m, th, dt[0, 0], dw)
