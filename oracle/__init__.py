@@ -4,13 +4,15 @@ TEST INFRASTRUCTURE, NOT THE PRODUCT.  Only ``tests/``, ``__graft_entry__.smoke(
 the CPU-baseline leg of ``bench.py`` may import this package.  It shares no code with the
 GPU library and never imports it.
 
-Two implementations live here:
+Three parts live here:
 
 * ``liboracle.so`` (``nusht_oracle.c``): plain C direct sums in FP64 -- synthesis (type 2,
   Eq. 3), adjoint (type 1, Eq. 2) and the synthesis gradient with respect to the point
   coordinates -- with an explicit power-of-two exponent on the Legendre recurrence.
 * a numpy twin (``twin.py``) for tiny sizes: the dense matrix Y of Eq. (4), CGLS on it,
   and an FP64 multilayer perceptron with its hand-derived backward pass.
+* the lensing pointing of Appendix C (``pointing.py``): Eq. (C2) through the direct-sum
+  synthesis gradient, then Eq. (C1) written out in numpy.
 
 Coefficient layout everywhere: complex128 ``[nmaps, nalm]``, m-major triangle with
 ``index(l, m) = m (2 lmax + 1 - m) / 2 + l``.
@@ -160,6 +162,7 @@ def lambda_column(lmax, m, theta, long_double=False):
     return mant, ex
 
 
+from .pointing import alpha_from_potential, deflect_by_alpha, pointing  # noqa: E402
 from .twin import (cgls_dense, density_map, mdot, mlp_backward, mlp_forward,  # noqa: E402
                    mlp_init, mlp_pack, mlp_unpack, point_features, synthesis_matrix,
                    weight_loss_dense, ylm_dense)
@@ -168,5 +171,5 @@ __all__ = [
     "build", "nalm", "alm_index", "synthesis", "adjoint", "adjoint_columns", "synthesis_grad",
     "lambda_column", "ylm_dense", "synthesis_matrix", "mdot", "cgls_dense", "mlp_init",
     "mlp_forward", "mlp_backward", "mlp_pack", "mlp_unpack", "density_map", "point_features",
-    "weight_loss_dense",
+    "weight_loss_dense", "pointing", "deflect_by_alpha", "alpha_from_potential",
 ]
