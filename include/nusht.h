@@ -49,7 +49,7 @@ enum {
     NUSHT_EINVAL = -1,     /* bad argument (host check) or bad point (device check in plan) */
     NUSHT_ENOMEM = -2,     /* device allocation failed */
     NUSHT_EDEVICE = -3,    /* HIP or rocFFT call failed */
-    NUSHT_ENOCONV = -4,    /* nusht_solve reached maxiter; iterate and residual still written */
+    NUSHT_ENOCONV = -4,    /* nusht_solve: true residual above tol; iterate, residual written */
     NUSHT_EPRECISION = -5  /* NUSHT_MIXED requested with eps < 1e-6 */
 };
 
@@ -112,6 +112,14 @@ int nusht_plan_ex(int lmax, int mmax, int64_t npts, const double* theta, const d
 /* Fills *out with the plan's sizes. */
 int nusht_plan_info(nusht_plan_t plan, nusht_geometry* out);
 
+/* Device-side status of the plan's execution calls so far: waits for the plan's device to
+   finish its work, then returns NUSHT_EDEVICE (with nusht_last_error naming the kernel) if a
+   kernel has flagged a failure it could not report through its own return value -- the
+   bounded cross-wave wait of the Legendre adjoint (Eq. 6, S^H) giving up -- and NUSHT_OK
+   otherwise.  The flag stays set until nusht_destroy.  nusht_solve and nusht_stage_stats
+   check it as well. */
+int nusht_plan_status(nusht_plan_t plan);
+
 /* Type 2 (synthesis), Eq. (3): map[b][i] = sum_lm a_lm Y_lm(theta_i, phi_i), to accuracy eps.
    alm: [nmaps][nalm] complex128, map: [nmaps][npts] float64, nmaps >= 1.
    Scratch grows on the first call with a larger nmaps than before (that call allocates). */
@@ -149,10 +157,13 @@ int nusht_ring_adjoint(nusht_plan_t plan, const double* ring, double* alm, int n
    transforms repeatedly).  CGLS on min || W^(1/2) (S a - d) ||_2 in the <.,.>_m geometry:
    each iteration runs one synthesis and one adjoint plus FP64 device reductions.
    map: d [npts] (one map); alm: in = initial iterate x0 [nalm], out = solution;
-   weights: [npts] float32 row weights W (NULL = all ones).  Stops when the recurred
-   ||d - S a|| / ||d|| <= tol, checked every iteration through one 8-byte device-to-host read,
-   and then recomputes the true residual once.  *iters, *relres (true residual) are written.
-   Returns NUSHT_ENOCONV after maxiter iterations without convergence.  Synchronises. */
+   weights: [npts] float32 row weights W (NULL = all ones).  Iterates while the recurred
+   ||d - S a|| / ||d|| is above tol, checked every iteration through one 8-byte device-to-host
+   read; it then recomputes the true residual, and if that is still above tol restarts CGLS
+   from the current iterate with the true residual (at most 4 restarts, within maxiter).
+   *iters (iterations in total) and *relres (true residual of the returned iterate) are
+   written.  Returns NUSHT_OK only when the true residual is <= tol, NUSHT_ENOCONV otherwise
+   (the iterate is still written).  Synchronises. */
 int nusht_solve(nusht_plan_t plan, const double* map, double* alm, const float* weights,
                 double tol, int maxiter, int* iters, double* relres, void* stream);
 

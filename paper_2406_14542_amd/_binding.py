@@ -76,6 +76,7 @@ def lib():
                                              ctypes.c_double, ctypes.c_int,
                                              ctypes.POINTER(PlanOpts), _vp, ctypes.POINTER(_vp)]),
             "nusht_plan_info": (ctypes.c_int, [_vp, ctypes.POINTER(Geometry)]),
+            "nusht_plan_status": (ctypes.c_int, [_vp]),
             "nusht_synthesis": (ctypes.c_int, [_vp, _vp, _vp, ctypes.c_int, _vp]),
             "nusht_adjoint": (ctypes.c_int, [_vp, _vp, _vp, ctypes.c_int, _vp]),
             "nusht_synthesis_deriv": (ctypes.c_int, [_vp, _vp, _vp, _vp, _vp, ctypes.c_int,
@@ -188,11 +189,18 @@ class Plan:
         self.geometry = g.as_dict()
         self.nalm = int(self.geometry["nalm"])
 
+    def status(self):
+        """Raise NushtError if a kernel of this plan flagged a device-side failure (waits for
+        the device)."""
+        _check(lib().nusht_plan_status(self._h), "nusht_plan_status")
+
     # ---- helpers ----
     def _alm_in(self, alm):
         import torch
         if alm.dtype != torch.complex128 or not alm.is_cuda:
             raise TypeError("alm must be a complex128 device tensor")
+        if alm.device != self.device:
+            raise TypeError(f"alm must live on {self.device}")
         a = alm.reshape(-1, self.nalm) if alm.dim() == 1 else alm
         if a.dim() != 2 or a.shape[1] != self.nalm:
             raise ValueError(f"alm must have shape [B, {self.nalm}]")
@@ -202,17 +210,36 @@ class Plan:
         import torch
         if m.dtype != torch.float64 or not m.is_cuda:
             raise TypeError("maps must be float64 device tensors")
+        if m.device != self.device:
+            raise TypeError(f"maps must live on {self.device}")
         x = m.reshape(1, -1) if m.dim() == 1 else m
         if x.dim() != 2 or x.shape[1] != self.npts:
             raise ValueError(f"map must have shape [B, {self.npts}]")
         return x.contiguous()
+
+    @staticmethod
+    def _out(out, shape, dtype, like):
+        """A fresh output tensor, or the caller's `out` checked to be exactly what the
+        library will write: dtype, device, shape and a contiguous layout."""
+        import torch
+        if out is None:
+            return torch.empty(shape, dtype=dtype, device=like.device)
+        if not isinstance(out, torch.Tensor) or out.dtype != dtype:
+            raise TypeError(f"out must be a {dtype} tensor")
+        if not out.is_cuda or out.device != like.device:
+            raise TypeError(f"out must live on {like.device}")
+        if tuple(out.shape) != tuple(shape):
+            raise ValueError(f"out must have shape {list(shape)}, got {list(out.shape)}")
+        if not out.is_contiguous():
+            raise ValueError("out must be contiguous")
+        return out
 
     # ---- transforms ----
     def synthesis(self, alm, out=None):
         import torch
         a = self._alm_in(alm)
         B = a.shape[0]
-        out = torch.empty((B, self.npts), dtype=torch.float64, device=a.device) if out is None else out
+        out = self._out(out, (B, self.npts), torch.float64, a)
         _check(lib().nusht_synthesis(self._h, a.data_ptr(), out.data_ptr(), B, _stream()),
                "nusht_synthesis")
         return out
@@ -221,7 +248,7 @@ class Plan:
         import torch
         x = self._map_in(m)
         B = x.shape[0]
-        out = torch.empty((B, self.nalm), dtype=torch.complex128, device=x.device) if out is None else out
+        out = self._out(out, (B, self.nalm), torch.complex128, x)
         _check(lib().nusht_adjoint(self._h, x.data_ptr(), out.data_ptr(), B, _stream()),
                "nusht_adjoint")
         return out

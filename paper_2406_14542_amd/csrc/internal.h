@@ -21,6 +21,12 @@ constexpr int kMaxWidth = 16;
 // zero entries after the recurrence table, so that a chunk of l values can be loaded whole
 constexpr int kRecPad = 64;
 constexpr int kMinWidth = 2;
+// bits of a plan's device error word
+constexpr int kErrAdjWait = 1;  // a Legendre-adjoint slot wait reached its bound
+
+// Reads the plan's device error word (synchronises the plan's device); NUSHT_EDEVICE if any
+// kernel has set it.
+int check_device_status(nusht_plan_s* p);
 
 // Status that keeps the first failing HIP/rocFFT call for diagnostics.
 struct Err {
@@ -106,6 +112,8 @@ struct nusht_plan_s {
     int nslots = 0;
     int nt1 = 0, nt2 = 0;        // tiles per fine-grid axis
     int* dflag = nullptr;        // device error flag used by plan validation
+    int* dstatus = nullptr;      // device error word of the execution kernels (kErr* bits),
+                                 // sticky until the plan is destroyed
 
     // Scratch, grown to the largest batch seen.  Two ping-pong regions and one for the
     // spread subgrids.

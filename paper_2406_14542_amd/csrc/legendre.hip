@@ -400,6 +400,7 @@ constexpr int kLS = kLC + 1;     // padded row of the lam staging area
 constexpr int kAdjGroup = 2;     // chunks whose sums go through one slot together
 constexpr int kAdjSlots = 2;     // slots in flight per block (power of two)
 constexpr int kAdjPfAhead = 4;   // chunks between a coefficient line's L2 touch and its use
+constexpr int kAdjSpinLimit = 1 << 22;  // sleeps before a slot wait gives up (never reached)
 
 
 template <typename InT>
@@ -415,7 +416,7 @@ __global__ __launch_bounds__(kAdjWaves * 64, 4) void k_legendre_adj(
     double* __restrict__ alm, int npc, int64_t nalm, int lmax,
     const double2* __restrict__ rec, const double* __restrict__ cm_mant,
     const int* __restrict__ cm_exp, const int* __restrict__ jlive, int nr, int nt,
-    int pairs_per_block, int mmax)
+    int pairs_per_block, int mmax, int* __restrict__ err)
 {
     // per wave: the lam values of one chunk (64 pairs x 16 l); per block: the chunk-sum slots
     // (128 D values: 64 lanes x real/imaginary), their arrival counts and hand-on counts
@@ -668,16 +669,22 @@ __global__ __launch_bounds__(kAdjWaves * 64, 4) void k_legendre_adj(
         // this wave's share of the round into slot r % kAdjSlots, once the round kAdjSlots
         // earlier has been taken out of it.  A slot is handed on as soon as the slowest live
         // wave has added into it, so the slowest wave never waits here and every wait ends; the
-        // bound only keeps a broken invariant from hanging the device.
+        // bound only keeps a broken invariant from hanging the device, and a wave that reaches
+        // it sets the error word (the host reports NUSHT_EDEVICE: the sums may be wrong).
         const int rnd = c0 / kAdjGroup;
         const int sl = rnd & (kAdjSlots - 1);
         const unsigned use = (unsigned)(rnd / kAdjSlots);
-        for (int it = 0; it < (1 << 22); ++it) {
+        bool ready = false;
+        for (int it = 0; it < kAdjSpinLimit; ++it) {
             if (__hip_atomic_load(&sgen[sl], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP) ==
-                use)
+                use) {
+                ready = true;
                 break;
+            }
             __builtin_amdgcn_s_sleep(1);
         }
+        if (!ready && lane == 0)
+            __hip_atomic_fetch_or(err, kErrAdjWait, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
 #pragma unroll
         for (int g = 0; g < kAdjGroup; ++g) {
@@ -724,8 +731,10 @@ __global__ __launch_bounds__(kAdjWaves * 64, 4) void k_legendre_adj(
             }
             __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
             if (lane == 0) {
+                // the count is reset before the hand-on becomes visible: a wave that sees the
+                // new hand-on count also sees the zero count (release store)
                 scnt[sl] = 0;
-                __hip_atomic_store(&sgen[sl], use + 1, __ATOMIC_RELAXED,
+                __hip_atomic_store(&sgen[sl], use + 1, __ATOMIC_RELEASE,
                                    __HIP_MEMORY_SCOPE_WORKGROUP);
             }
         }
@@ -847,7 +856,7 @@ int launch_legendre_adjoint(const nusht_plan_s* p, const void* in, double* alm, 
     hipLaunchKernelGGL((k_legendre_adj<F, IT>), grid, dim3(threads), 0, s,                       \
                        reinterpret_cast<const IT*>(in), map_stride, row_stride, nmaps, alm, npc,  \
                        g.nalm, g.lmax, p->rec, p->cm_mant, p->cm_exp, p->jlive, g.nrings,        \
-                       g.ntorus, ppb, g.mmax)
+                       g.ntorus, ppb, g.mmax, p->dstatus)
     if (fused && in_f32) {
         ADJ(true, float2);
     } else if (fused) {

@@ -255,8 +255,11 @@ size_t fine_elem_bytes(const nusht_plan_s* p)
     return p->g.dtype == NUSHT_MIXED ? sizeof(float) : sizeof(double);
 }
 
-// Scratch for `nmaps` maps.  X and Y each hold the largest per-map intermediate of either
-// mode times the batch; Z holds the spreading subgrids of every group of four maps.
+// Scratch for up to `nmaps` maps.  X and Y each hold the largest per-map intermediate of
+// either mode times the batch; Z holds the spreading subgrids of every group of maps.  The
+// group count point_groups(k) is not monotone in k (4 maps make one group, 3 make three), so Z
+// is sized for the largest count of any batch up to nmaps: every batch the plan accepts
+// without growing fits.
 int ensure_capacity(nusht_plan_s* p, int nmaps)
 {
     if (nmaps <= p->bcap) return NUSHT_OK;
@@ -271,7 +274,8 @@ int ensure_capacity(nusht_plan_s* p, int nmaps)
     const size_t gfused = (size_t)(g.mmax + 1) * g.ntorus * 2 * 8;  // doubled columns, <= c128
     size_t per = fine_real;
     for (size_t v : {fine_spec, gpaper, ring, torus, tspec, gfused}) per = v > per ? v : per;
-    const int groups = point_groups(nmaps);
+    int groups = 0;
+    for (int k = 1; k <= nmaps; ++k) groups = std::max(groups, point_groups(k));
     const int P = kTile + g.width - 1;
     const size_t zbytes = (size_t)groups * p->nslots * P * P * 4 * e;
     NUSHT_HIP(hipDeviceSynchronize());
@@ -319,9 +323,10 @@ int bin_points(nusht_plan_s* p, const double* theta, const double* phi, hipStrea
             (rc = dmalloc(&p->perm, n)) || (rc = dmalloc(&p->iperm, n)) ||
             (rc = dmalloc(&p->sth, n)) ||
             (rc = dmalloc(&p->sph, n)) || (rc = dmalloc(&p->tile_slot, ntiles)) ||
-            (rc = dmalloc(&p->dflag, 1)))
+            (rc = dmalloc(&p->dflag, 1)) || (rc = dmalloc(&p->dstatus, 1)))
             break;
-        if (hipMemsetAsync(p->dflag, 0, sizeof(int), s) != hipSuccess) { rc = NUSHT_EDEVICE; break; }
+        if (hipMemsetAsync(p->dflag, 0, sizeof(int), s) != hipSuccess ||
+            hipMemsetAsync(p->dstatus, 0, sizeof(int), s) != hipSuccess) { rc = NUSHT_EDEVICE; break; }
         hipLaunchKernelGGL(k_bin_keys, dim3(blocks), dim3(256), 0, s, theta, phi, n, g.width,
                            g.n1 / (2.0 * M_PI), g.n2 / (2.0 * M_PI), g.n1, g.n2, p->nt2, phw,
                            keys, idx, p->dflag);
@@ -542,6 +547,29 @@ static int build_tables(nusht_plan_s* p)
 int create_fft_plans(nusht_plan_s* p);
 void destroy_fft_plans(nusht_plan_s* p);
 
+int check_device_status(nusht_plan_s* p)
+{
+    int cur = 0, word = 0;
+    hipGetDevice(&cur);
+    if (cur != p->device) hipSetDevice(p->device);
+    const hipError_t e = hipDeviceSynchronize();
+    const hipError_t e2 = e == hipSuccess
+                              ? hipMemcpy(&word, p->dstatus, sizeof(int), hipMemcpyDeviceToHost)
+                              : e;
+    if (cur != p->device) hipSetDevice(cur);
+    if (e2 != hipSuccess) {
+        set_last_error("nusht_plan_status", hipGetErrorString(e2));
+        return NUSHT_EDEVICE;
+    }
+    if (word & kErrAdjWait) {
+        set_last_error("nusht_plan_status",
+                       "a Legendre-adjoint cross-wave wait reached its bound: adjoint sums may be "
+                       "wrong");
+        return NUSHT_EDEVICE;
+    }
+    return NUSHT_OK;
+}
+
 }  // namespace nusht
 
 using namespace nusht;
@@ -586,7 +614,7 @@ void nusht_destroy(nusht_plan_t p)
     void* bufs[] = {p->rec,  p->cm_mant, p->cm_exp,   p->dec1,      p->dec2,      p->dec1f,
                     p->dec2f, p->sth,    p->sph,      p->perm,      p->iperm,     p->V,
                     p->slot_off,  p->slot_tile,
-                    p->tile_slot, p->dflag, p->X,     p->Y,         p->Z,         p->W,
+                    p->tile_slot, p->dflag, p->dstatus, p->X,     p->Y,         p->Z,         p->W,
                     p->fftwork,   p->rowtw,
                     p->red,      p->jlive,  p->jscale};
     for (void* b : bufs)
@@ -657,6 +685,12 @@ int nusht_plan_info(nusht_plan_t p, nusht_geometry* out)
     if (!p || !out) return NUSHT_EINVAL;
     *out = p->g;
     return NUSHT_OK;
+}
+
+int nusht_plan_status(nusht_plan_t p)
+{
+    if (!p) return NUSHT_EINVAL;
+    return check_device_status(p);
 }
 
 }  // extern "C"

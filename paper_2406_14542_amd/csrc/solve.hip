@@ -8,8 +8,12 @@
 //   until ||u|| / ||d|| <= tol   (u is the unweighted residual d - S x, kept by recurrence)
 //
 // All vectors stay on the device; alpha and beta are formed on the device; every reduction
-// is a fixed-shape two-pass sum, so a solve is bitwise reproducible for a fixed plan.  The
-// host reads one 8-byte residual per iteration for the stopping test.
+// is a fixed-shape two-pass sum that adds in a fixed order (the adjoint transform itself adds
+// with atomics in no fixed order, so two solves can differ by rounding).  The host reads one 8-byte
+// residual per iteration for the stopping test.  When the recurred residual reaches tol, the
+// true residual d - S x is formed again; if it is still above tol (the recurrence drifts, more
+// so in mixed precision or with weights), CGLS restarts from x with that true residual, at
+// most kMaxRestarts times.
 #include <cmath>
 
 #include "internal.h"
@@ -19,6 +23,7 @@ namespace {
 
 constexpr int kRedBlocks = 1024;
 constexpr int kRedThreads = 256;
+constexpr int kMaxRestarts = 4;
 
 enum { SC_GAMMA = 0, SC_DELTA, SC_RR, SC_DN2, SC_GNEW, SC_ALPHA, SC_BETA, SC_COUNT };
 
@@ -226,48 +231,51 @@ int nusht_solve_ex(nusht_plan_t p, const double* map, double* alm, const float* 
         return NUSHT_OK;
     };
 
-    // u = d - S x, s = S^H W u, p = s, gamma = <s, s>_m
-    NUSHT_TRY(nusht_synthesis(p, alm, b.q, 1, stream));
-    hipLaunchKernelGGL(k_residual, dim3(blocks_for(n)), dim3(256), 0, s, map, b.q, weights, b.u,
-                       b.wu, n);
+    // ||d||^2 once
     NUSHT_TRY(dot_map(map, map, nullptr, SC_DN2));
-    NUSHT_TRY(nusht_adjoint(p, b.wu, reinterpret_cast<double*>(b.s), 1, stream));
-    NUSHT_HIP(hipMemcpyAsync(b.p, b.s, (size_t)na * sizeof(double2), hipMemcpyDeviceToDevice, s));
-    NUSHT_TRY(dot_alm(b.s, b.s, SC_GAMMA));
     double dn2 = 0.0, rr = 0.0;
     NUSHT_TRY(read_scalar(SC_DN2, &dn2));
-    NUSHT_TRY(dot_map(b.u, b.u, nullptr, SC_RR));
-    NUSHT_TRY(read_scalar(SC_RR, &rr));
     if (dn2 == 0.0) dn2 = 1.0;  // d = 0: report the absolute residual
-    int it = 0;
-    if (history) history[0] = std::sqrt(rr / dn2);
     const double tol2 = tol * tol;
-    while (rr > tol2 * dn2 && it < maxiter) {
-        NUSHT_TRY(nusht_synthesis(p, reinterpret_cast<const double*>(b.p), b.q, 1, stream));
-        NUSHT_TRY(dot_map(b.q, b.q, weights, SC_DELTA));
-        hipLaunchKernelGGL(k_alpha, dim3(1), dim3(1), 0, s, b.sc);
-        hipLaunchKernelGGL(k_axpy_alm, dim3(blocks_for(na)), dim3(256), 0, s, x, b.p, b.sc, na);
-        hipLaunchKernelGGL(k_update_u, dim3(blocks_for(n)), dim3(256), 0, s, b.u, b.q, weights,
-                           b.wu, b.sc, n);
-        NUSHT_TRY(nusht_adjoint(p, b.wu, reinterpret_cast<double*>(b.s), 1, stream));
-        NUSHT_TRY(dot_alm(b.s, b.s, SC_GNEW));
-        hipLaunchKernelGGL(k_beta, dim3(1), dim3(1), 0, s, b.sc);
-        hipLaunchKernelGGL(k_update_p, dim3(blocks_for(na)), dim3(256), 0, s, b.p, b.s, b.sc, na);
+    int it = 0;
+    for (int restart = 0;; ++restart) {
+        // u = d - S x (the true residual), then s = S^H W u, p = s, gamma = <s, s>_m
+        NUSHT_TRY(nusht_synthesis(p, alm, b.q, 1, stream));
+        hipLaunchKernelGGL(k_residual, dim3(blocks_for(n)), dim3(256), 0, s, map, b.q, weights,
+                           b.u, b.wu, n);
         NUSHT_TRY(dot_map(b.u, b.u, nullptr, SC_RR));
-        NUSHT_HIP(hipGetLastError());
         NUSHT_TRY(read_scalar(SC_RR, &rr));
-        ++it;
-        if (history) history[it] = std::sqrt(rr / dn2);
+        if (history && restart == 0) history[0] = std::sqrt(rr / dn2);
+        if (rr <= tol2 * dn2 || it >= maxiter || restart > kMaxRestarts) break;
+        NUSHT_TRY(nusht_adjoint(p, b.wu, reinterpret_cast<double*>(b.s), 1, stream));
+        NUSHT_HIP(hipMemcpyAsync(b.p, b.s, (size_t)na * sizeof(double2), hipMemcpyDeviceToDevice,
+                                 s));
+        NUSHT_TRY(dot_alm(b.s, b.s, SC_GAMMA));
+        while (rr > tol2 * dn2 && it < maxiter) {
+            NUSHT_TRY(nusht_synthesis(p, reinterpret_cast<const double*>(b.p), b.q, 1, stream));
+            NUSHT_TRY(dot_map(b.q, b.q, weights, SC_DELTA));
+            hipLaunchKernelGGL(k_alpha, dim3(1), dim3(1), 0, s, b.sc);
+            hipLaunchKernelGGL(k_axpy_alm, dim3(blocks_for(na)), dim3(256), 0, s, x, b.p, b.sc,
+                               na);
+            hipLaunchKernelGGL(k_update_u, dim3(blocks_for(n)), dim3(256), 0, s, b.u, b.q,
+                               weights, b.wu, b.sc, n);
+            NUSHT_TRY(nusht_adjoint(p, b.wu, reinterpret_cast<double*>(b.s), 1, stream));
+            NUSHT_TRY(dot_alm(b.s, b.s, SC_GNEW));
+            hipLaunchKernelGGL(k_beta, dim3(1), dim3(1), 0, s, b.sc);
+            hipLaunchKernelGGL(k_update_p, dim3(blocks_for(na)), dim3(256), 0, s, b.p, b.s, b.sc,
+                               na);
+            NUSHT_TRY(dot_map(b.u, b.u, nullptr, SC_RR));
+            NUSHT_HIP(hipGetLastError());
+            NUSHT_TRY(read_scalar(SC_RR, &rr));
+            ++it;
+            if (history) history[it] = std::sqrt(rr / dn2);
+        }
     }
-    // true residual of the final iterate
-    NUSHT_TRY(nusht_synthesis(p, alm, b.q, 1, stream));
-    hipLaunchKernelGGL(k_residual, dim3(blocks_for(n)), dim3(256), 0, s, map, b.q, weights, b.u,
-                       nullptr, n);
-    NUSHT_TRY(dot_map(b.u, b.u, nullptr, SC_RR));
-    NUSHT_TRY(read_scalar(SC_RR, &rr));
+    // rr is the true residual of the final iterate
     if (iters) *iters = it;
     if (relres) *relres = std::sqrt(rr / dn2);
-    return (std::sqrt(rr / dn2) <= tol || it < maxiter) ? NUSHT_OK : NUSHT_ENOCONV;
+    NUSHT_TRY(check_device_status(p));
+    return rr <= tol2 * dn2 ? NUSHT_OK : NUSHT_ENOCONV;
 }
 
 }  // extern "C"

@@ -602,6 +602,7 @@ int nusht_stage_stats(nusht_plan_t p, int kind, double* ms, int* ncalls, const c
                       int maxn)
 {
     if (!p || !ms || maxn < 0) return NUSHT_EINVAL;
+    NUSHT_TRY(check_device_status(p));
     if (!p->timing) return 0;
     const int nslot = (int)(p->ncalls < nusht_plan_s::kTimingSlots ? p->ncalls
                                                                    : nusht_plan_s::kTimingSlots);

@@ -229,3 +229,103 @@ def test_stage_timing_ring(P):
     assert np.array_equal(f.cpu().numpy(), ref.synthesis(a).cpu().numpy())
     last = pl.stage_times()
     assert last["legendre"] > 0 and last["halo"] > 0
+
+
+@pytest.mark.parametrize("dtype,eps,tol", [("f64", 1e-12, 1e-11), ("mixed", 1e-5, 1e-5)])
+def test_c1_four_maps_headline_launch(P, oracle_mod, dtype, eps, tol):
+    """Four coefficient sets / maps in one call on the C1 points: the launch configuration of
+    the benchmark (one group of four in the point kernels and the Legendre kernels), compared
+    with the oracle's direct sums map by map and element by element."""
+    print(f"[c1 four maps {dtype}]", flush=True)
+    cfg = inputs.config_c1()
+    L = cfg["lmax"]
+    rng = np.random.default_rng(1101)
+    a = inputs.red_alm(rng, L, L, 4)
+    d = rng.standard_normal((4, cfg["theta"].size))
+    th, ph = cfg["theta"], cfg["phi"]
+    fref = oracle_mod.synthesis(L, L, th, ph, a)
+    cref = oracle_mod.adjoint(L, L, th, ph, d)
+    pl = P.Plan(L, L, dev(th), dev(ph), eps, dtype=dtype)
+    f = pl.synthesis(dev(a)).cpu().numpy()
+    c = pl.adjoint(dev(d)).cpu().numpy()
+    ef = [rel(f[b], fref[b]) for b in range(4)]
+    ec = [mrel(c[b], cref[b], L, L) for b in range(4)]
+    print(f"  synthesis {', '.join(f'{x:.2e}' for x in ef)}; "
+          f"adjoint {', '.join(f'{x:.2e}' for x in ec)}", flush=True)
+    assert max(ef) <= tol and max(ec) <= tol
+    # run to run: both adjoint hot kernels add with atomics in no fixed order
+    c2 = pl.adjoint(dev(d)).cpu().numpy()
+    rr = max(mrel(c2[b], c[b], L, L) for b in range(4))
+    print(f"  adjoint run-to-run difference {rr:.2e}", flush=True)
+    assert rr <= (1e-15 if dtype == "f64" else 1e-6)
+    pl.status()
+
+
+def test_eps_eff_curve(P, oracle_mod):
+    """Effective accuracy against the requested one (Sec. IV, Eq. 9-10): relative L2 error of
+    the synthesis against the direct sum over the points, and of the adjoint in the <.,.>_m
+    norm, must stay at or below eps over the whole range, in FP64 and in mixed precision."""
+    print("[eps_eff curve]", flush=True)
+    import json
+    L = 255
+    rng = np.random.default_rng(255)
+    a = inputs.red_alm(rng, L, L, 1)
+    th, ph = inputs.uniform_points(rng, 100_000)
+    d = rng.standard_normal((1, th.size))
+    fref = oracle_mod.synthesis(L, L, th, ph, a)
+    cref = oracle_mod.adjoint(L, L, th, ph, d)
+    thd, phd, ad, dd = dev(th), dev(ph), dev(a), dev(d)
+    curve = []
+    for dtype, epss in (("f64", [1e-2, 1e-4, 1e-6, 1e-8, 1e-10, 1e-12]),
+                        ("mixed", [1e-2, 1e-4, 1e-6])):
+        for eps in epss:
+            pl = P.Plan(L, L, thd, phd, eps, dtype=dtype)
+            f = pl.synthesis(ad).cpu().numpy()
+            c = pl.adjoint(dd).cpu().numpy()
+            es = rel(f, fref)
+            ea = mrel(c[0], cref[0], L, L)
+            curve.append({"dtype": dtype, "eps": eps, "width": pl.geometry["width"],
+                          "synthesis": es, "adjoint": ea})
+            pl.close()
+    print("EPS_EFF_CURVE " + json.dumps({"lmax": L, "npts": int(th.size), "curve": curve}),
+          flush=True)
+    for r in curve:
+        assert r["synthesis"] <= r["eps"] and r["adjoint"] <= r["eps"], r
+
+
+@pytest.mark.parametrize("dtype,eps,tol", [("f64", 1e-12, 1e-11), ("mixed", 1e-5, 1e-5)])
+def test_gauss_legendre_round_trip(P, dtype, eps, tol):
+    """At Gauss-Legendre rings (lmax + 1 nodes in cos theta) times 2 lmax + 2 equi-spaced phi,
+    the quadrature-weighted adjoint inverts the synthesis exactly: S^H W S a = a (Eq. 4 with
+    quadrature weights), so the whole GPU pipeline must return a to its accuracy."""
+    print(f"[gl round trip {dtype}]", flush=True)
+    from scipy.special import roots_legendre
+    L = 127
+    x, wq = roots_legendre(L + 1)
+    nph = 2 * L + 2
+    T, Ph = np.meshgrid(np.arccos(x), 2 * np.pi * np.arange(nph) / nph, indexing="ij")
+    W = np.repeat(wq * (2 * np.pi / nph), nph)
+    rng = np.random.default_rng(127)
+    a = inputs.red_alm(rng, L, L, 2)
+    pl = P.Plan(L, L, dev(T.ravel()), dev(Ph.ravel()), eps, dtype=dtype)
+    f = pl.synthesis(dev(a))
+    back = pl.adjoint(f * dev(W)[None, :]).cpu().numpy()
+    e = max(mrel(back[b], a[b], L, L) for b in range(2))
+    print(f"  S^H W S a vs a: {e:.2e}", flush=True)
+    assert e <= tol
+
+
+def test_batch_shrink_after_growth_reuses_scratch(P):
+    """A plan that ran 8 maps then runs 3 (more point groups than 8 maps make) and 2: every
+    batch equals its single-map calls."""
+    print("[batch shrink]", flush=True)
+    L = 30
+    rng = np.random.default_rng(33)
+    th, ph = inputs.uniform_points(rng, 2000)
+    d = rng.standard_normal((8, th.size))
+    pl = P.Plan(L, L, dev(th), dev(ph), 1e-10)
+    single = [pl.adjoint(dev(d[b:b + 1])).cpu().numpy()[0] for b in range(8)]
+    for B in (8, 3, 2, 7):
+        c = pl.adjoint(dev(d[:B])).cpu().numpy()
+        for b in range(B):
+            assert rel(c[b], single[b]) < 1e-13, (B, b)
