@@ -36,18 +36,29 @@ def log(*a):
 
 def legendre_flops(g, nmaps):
     """Algorithmic flops of one Legendre launch: per (l, m, ring pair) one step of the
-    three-term recurrence lam_l = A (x lam_{l-1}) - B lam_{l-2} (two multiplies and an FMA,
-    4 flops) and, per map, one complex-by-real FMA into the parity accumulator (4 flops)."""
+    three-term recurrence lam_l = A x lam_{l-1} - B lam_{l-2} (a multiply and an FMA, 3 flops)
+    and, per map, one complex-by-real FMA into the parity accumulator (4 flops):
+    nalm x ceil(N_r / 2) x (3 + 4 B)."""
     pairs = (g["nrings"] + 1) // 2
-    return float(g["nalm"]) * pairs * (4 + 4 * nmaps)
+    return float(g["nalm"]) * pairs * (3 + 4 * nmaps)
 
 
 def point_bytes(g, nmaps, elem):
-    """Algorithmic HBM bytes of one interpolation / spreading pass: FP64 theta, phi read once,
-    the B point values, and the touched half of the fine grid (rows theta in [0, pi] + w)."""
+    """Algorithmic HBM bytes of one interpolation / spreading pass: FP64 theta, phi read once
+    (16 N), the B point values in the kernel's precision (s B N) and the touched half of the
+    fine grid (rows theta in [0, pi] plus w) once (s B (n1/2 + w) n2), s = 4 or 8."""
     n = g["npts"]
     touched = (g["n1"] // 2 + g["width"]) * g["n2"]
-    return 16.0 * n + 8.0 * nmaps * n + float(elem) * nmaps * touched
+    return 16.0 * n + float(elem) * nmaps * n + float(elem) * nmaps * touched
+
+
+def step_stats(times):
+    """median of all timed steps, and mean +- 1 sigma over the first five (Sec. IV reports
+    the mean of 5 runs with one standard deviation)"""
+    t = np.asarray(times)
+    five = t[:5]
+    return {"median_s": float(np.median(t)), "mean5_s": float(five.mean()),
+            "std5_s": float(five.std(ddof=1)) if five.size > 1 else 0.0}
 
 
 def run_precision(P, torch, cfg, eps, dtype, steps, warmup, alm, d):
@@ -70,11 +81,18 @@ def run_precision(P, torch, cfg, eps, dtype, steps, warmup, alm, d):
         step()
     torch.cuda.synchronize()
     plan.stage_reset()
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+           for _ in range(steps)]
     t0 = time.perf_counter()
-    for _ in range(steps):
+    for e0, e1 in evs:
+        # the library enqueues on torch's current stream, so these events bracket the step
+        e0.record()
         step()
+        e1.record()
     torch.cuda.synchronize()
     sec = (time.perf_counter() - t0) / steps
+    per_step = [e0.elapsed_time(e1) * 1e-3 for e0, e1 in evs]
+    plan.status()
     # per-stage device times over exactly the timed calls, from the HIP events the library
     # records around each stage on the stream the stage's kernels run on
     syn = {k: v[0] for k, v in plan.stage_stats("synthesis").items() if v[0] > 0}
@@ -83,12 +101,28 @@ def run_precision(P, torch, cfg, eps, dtype, steps, warmup, alm, d):
     f = fmap.cpu().numpy()
     plan.adjoint(d, out=calm)
     c = calm.cpu().numpy()
-    return dict(plan=plan, plan_s=plan_s, sec=sec, syn=syn, adj=adj, f=f, c=c)
+    return dict(plan=plan, plan_s=plan_s, sec=sec, syn=syn, adj=adj, f=f, c=c,
+                stats=step_stats(per_step))
 
 
-def cpu_baseline(cfg, alm_np, d_np, nsample, nmaps):
+def host_cpu():
+    """model name and logical core count of the host"""
+    model = None
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return model, os.cpu_count()
+
+
+def cpu_baseline(cfg, alm_np, d_np, nsample, nmaps, nsample1):
     """The oracle (plain C direct sums) on a bounded sample of the same workload, scaled
-    linearly in the number of points to one full step (synthesis + adjoint of all maps)."""
+    linearly in the number of points to one full step (synthesis + adjoint of all maps), on
+    all the threads the host gives this process and on one thread (smaller sample)."""
     import oracle
     oracle.build(force=False)
     threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
@@ -100,8 +134,32 @@ def cpu_baseline(cfg, alm_np, d_np, nsample, nmaps):
     oracle.adjoint(cfg["lmax"], cfg["mmax"], th, ph, d_np[:1, idx], nthreads=threads)
     t2 = time.perf_counter()
     scale = cfg["theta"].size / nsample * nmaps
+    i1 = idx[:nsample1]
+    t3 = time.perf_counter()
+    oracle.synthesis(cfg["lmax"], cfg["mmax"], cfg["theta"][i1], cfg["phi"][i1], alm_np[:1],
+                     nthreads=1)
+    oracle.adjoint(cfg["lmax"], cfg["mmax"], cfg["theta"][i1], cfg["phi"][i1], d_np[:1, i1],
+                   nthreads=1)
+    t4 = time.perf_counter()
     return dict(value=(t2 - t0) * scale, syn=(t1 - t0) * scale, adj=(t2 - t1) * scale,
-                threads=threads, idx=idx, f_sample=fs, sample_s=t2 - t0)
+                threads=threads, idx=idx, f_sample=fs, sample_s=t2 - t0,
+                one_core=(t4 - t3) * cfg["theta"].size / nsample1 * nmaps,
+                one_core_sample_s=t4 - t3)
+
+
+def golden_adjoint_error(c, lmax, path):
+    """relative error of the adjoint of all maps on the stored whole m-columns of the oracle
+    (written by tests/golden/make_large_oracle_values.py), in the <.,.>_m norm"""
+    if not os.path.exists(path):
+        return None
+    z = np.load(path)
+    ms, ref = [int(m) for m in z["ms"]], z["cols"]
+    got = np.zeros_like(ref)
+    for k, m in enumerate(ms):
+        i0 = m * (2 * lmax + 1 - m) // 2
+        got[:, k, m:] = c[:, i0 + m:i0 + lmax + 1]
+    w = np.where(np.asarray(ms) == 0, 1.0, 2.0)[None, :, None]
+    return float(np.sqrt(np.sum(w * np.abs(got - ref) ** 2) / np.sum(w * np.abs(ref) ** 2)))
 
 
 def run_cg(args):
@@ -206,6 +264,7 @@ def main():
     ap.add_argument("--workload", default="c3", choices=["c3", "c1"])
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--cpu-sample", type=int, default=768)
+    ap.add_argument("--cpu-sample1", type=int, default=32)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cg", action="store_true",
                     help="run the learned-preconditioner CGLS leg instead of the transform step")
@@ -268,42 +327,66 @@ def main():
         fp = run_precision(P, torch, cfg, eps_ref, "f64", args.steps, args.warmup, alm, d)
         log(f"fp64: {fp['sec'] * 1e3:.2f} ms/step; stages syn {fp['syn']} adj {fp['adj']}")
 
-    # roofline of the dominant kernel of the headline (mixed) step
-    cands = []
-    for direction, st in (("synthesis", mx["syn"]), ("adjoint", mx["adj"])):
-        if "legendre" in st:
-            fl = legendre_flops(g, B)
-            cands.append(dict(kernel=f"legendre_{direction}", ms=st["legendre"], bound="alu",
-                              work=fl, achieved=fl / (st["legendre"] * 1e-3) / 1e12,
-                              peak=FP64_PEAK_TFLOPS, unit="TFLOP/s"))
-        if "points" in st:
-            by = point_bytes(g, B, 4)
-            name = "interp" if direction == "synthesis" else "spread"
-            cands.append(dict(kernel=name, ms=st["points"], bound="hbm", work=by,
-                              achieved=by / (st["points"] * 1e-3) / 1e9, peak=HBM_PEAK_GBS,
-                              unit="GB/s"))
-    dom = max(cands, key=lambda c: c["ms"])
-    # measured HBM bytes per launch of that kernel (rocprofv3 FETCH_SIZE / WRITE_SIZE runs,
-    # scaled by a copy kernel; see profiles/c3_pmc_counters.md), when they are on record
-    # for the kernel as it stands
-    traffic = None
-    tfile = os.path.join(ROOT, "profiles", "c3_traffic.json")
-    if args.workload == "c3" and os.path.exists(tfile):
-        rec = json.load(open(tfile)).get("kernels", {}).get(dom["kernel"])
-        if rec:
-            traffic = round(rec["hbm_bytes"], -6)
-    roofline = {"bound": dom["bound"], "achieved": round(dom["achieved"], 3),
+    def kernels(run, elem, geo):
+        """per-kernel roofline figures of one precision's step: the Legendre launches against
+        the FP64 peak, the point stages (a7 interpolation, b1 spreading) against HBM"""
+        cands = []
+        for direction, st in (("synthesis", run["syn"]), ("adjoint", run["adj"])):
+            if "legendre" in st:
+                fl = legendre_flops(geo, B)
+                cands.append(dict(kernel=f"legendre_{direction}", ms=st["legendre"],
+                                  bound="alu", work=fl,
+                                  achieved=fl / (st["legendre"] * 1e-3) / 1e12,
+                                  peak=FP64_PEAK_TFLOPS, unit="TFLOP/s"))
+            if "points" in st:
+                by = point_bytes(geo, B, elem)
+                ms = st["points"]
+                name = "interp" if direction == "synthesis" else "spread"
+                cands.append(dict(kernel=name, ms=ms, bound="hbm", work=by,
+                                  achieved=by / (ms * 1e-3) / 1e9, peak=HBM_PEAK_GBS,
+                                  unit="GB/s"))
+        return cands
+
+    def roofline_of(cands, traffic_key):
+        dom = max(cands, key=lambda c: c["ms"])
+        # measured HBM bytes per launch of that kernel (rocprofv3 FETCH_SIZE / WRITE_SIZE
+        # runs scaled by a copy kernel), when they are on record for the kernel as it stands
+        traffic = None
+        tfile = os.path.join(ROOT, "profiles", "c3_traffic.json")
+        if args.workload == "c3" and os.path.exists(tfile):
+            rec = json.load(open(tfile)).get(traffic_key, {}).get(dom["kernel"])
+            if rec:
+                traffic = round(rec["hbm_bytes"], -6)
+        return {"bound": dom["bound"], "achieved": round(dom["achieved"], 3),
                 "peak": dom["peak"], "unit": dom["unit"],
                 "frac": round(dom["achieved"] / dom["peak"], 4), "traffic": traffic,
                 "kernel": dom["kernel"], "ms_per_launch": round(dom["ms"], 4),
                 "algorithmic_work_per_launch": dom["work"]}
+
+    cands = kernels(mx, 4, g)
+    roofline = roofline_of(cands, "kernels")
     others = {c["kernel"]: {"ms": round(c["ms"], 4), "achieved": round(c["achieved"], 3),
                             "unit": c["unit"], "frac": round(c["achieved"] / c["peak"], 4)}
               for c in cands}
+    fp_roofline = fp_others = None
+    if fp is not None:
+        fcands = kernels(fp, 8, fp["plan"].geometry)
+        fp_roofline = roofline_of(fcands, "kernels_fp64")
+        fp_others = {c["kernel"]: {"ms": round(c["ms"], 4), "achieved": round(c["achieved"], 3),
+                                   "unit": c["unit"], "frac": round(c["achieved"] / c["peak"], 4)}
+                     for c in fcands}
 
-    # accuracy: mixed vs FP64 path, and both vs the oracle on a sample of points
+    # accuracy: mixed vs FP64 path, both vs the oracle on a sample of points (synthesis) and on
+    # whole m-columns over all points (adjoint, stored oracle values)
     acc = {}
     cpu = None
+    golden = os.path.join(ROOT, "tests", "golden", "c3_adjoint_columns.npz")
+    if args.workload == "c3":
+        acc["mixed_adjoint_vs_oracle_columns_rel"] = golden_adjoint_error(mx["c"], cfg["lmax"],
+                                                                          golden)
+        if fp is not None:
+            acc["fp64_adjoint_vs_oracle_columns_rel"] = golden_adjoint_error(
+                fp["c"], cfg["lmax"], golden)
     if fp is not None:
         acc["mixed_vs_fp64_synthesis_rel_l2"] = float(
             np.linalg.norm(mx["f"] - fp["f"]) / np.linalg.norm(fp["f"]))
@@ -312,8 +395,8 @@ def main():
         acc["mixed_vs_fp64_adjoint_rel_l2"] = float(np.sqrt(
             np.sum(w * np.abs(mx["c"] - fp["c"]) ** 2) / np.sum(w * np.abs(fp["c"]) ** 2)))
     if not args.no_cpu_baseline:
-        log(f"cpu baseline on {args.cpu_sample} points")
-        cpu = cpu_baseline(cfg, alm_np, d_np, args.cpu_sample, B)
+        log(f"cpu baseline on {args.cpu_sample} points ({args.cpu_sample1} on one core)")
+        cpu = cpu_baseline(cfg, alm_np, d_np, args.cpu_sample, B, args.cpu_sample1)
         idx = cpu["idx"]
         ref = cpu["f_sample"][0]
         acc["mixed_vs_oracle_sample_rel_l2"] = float(
@@ -343,23 +426,31 @@ def main():
                    "nmaps": B, "npts": int(cfg["theta"].size), "lmax": cfg["lmax"],
                    "dfs_mode": "fused", "sigma": g["sigma"], "width": g["width"],
                    "fine_grid": [g["n1"], g["n2"]]},
-        "mixed": {"s_per_step": mx["sec"], "synthesis_stages_ms": mx["syn"],
+        "mixed": {"s_per_step": mx["sec"], **mx["stats"], "synthesis_stages_ms": mx["syn"],
                   "adjoint_stages_ms": mx["adj"], "plan_s": mx["plan_s"]},
         "roofline": roofline,
         "roofline_kernels": others,
         "accuracy": acc,
     }
     if fp is not None:
-        out["fp64"] = {"s_per_step": fp["sec"], "eps": eps_ref, "synthesis_stages_ms": fp["syn"],
-                       "adjoint_stages_ms": fp["adj"], "plan_s": fp["plan_s"],
-                       "width": fp["plan"].geometry["width"]}
+        out["fp64"] = {"s_per_step": fp["sec"], **fp["stats"], "eps": eps_ref,
+                       "synthesis_stages_ms": fp["syn"], "adjoint_stages_ms": fp["adj"],
+                       "plan_s": fp["plan_s"], "width": fp["plan"].geometry["width"],
+                       "roofline": fp_roofline, "roofline_kernels": fp_others}
         out["speedup_mixed_over_fp64"] = round(fp["sec"] / mx["sec"], 3)
     if cpu is not None:
+        model, ncpu = host_cpu()
         out["cpu_baseline"] = {"value": round(cpu["value"], 3), "unit": "s", "cores": cpu["threads"],
                                "kind": "oracle",
                                "sample": f"FP64 direct-sum synthesis+adjoint of 1 map on "
                                          f"{args.cpu_sample} of the {cfg['theta'].size} points, "
-                                         f"scaled by N/{args.cpu_sample} x {B} maps"}
+                                         f"scaled by N/{args.cpu_sample} x {B} maps "
+                                         f"(extrapolated O(N lmax^2) direct sum)",
+                               "host_cpu": model, "host_logical_cpus": ncpu,
+                               "sample_s": round(cpu["sample_s"], 3),
+                               "one_core_value": round(cpu["one_core"], 3),
+                               "one_core_sample": f"{args.cpu_sample1} points, 1 thread, "
+                                                  f"{cpu['one_core_sample_s']:.2f} s"}
     print(json.dumps(out), flush=True)
 
 

@@ -68,8 +68,18 @@ typedef struct {
                             0.97 pi (1 - 1/(2 sigma)) */
     int dfs_mode;        /* NUSHT_DFS_FUSED (default) or NUSHT_DFS_PAPER */
     int timing;          /* nonzero: record one hipEvent pair per stage (nusht_stage_times) */
-    int reserved[6];     /* must be zero */
+    int deterministic;   /* nonzero: the adjoint adds in a fixed order, so repeated calls give
+                            identical bits (the Legendre adjoint then writes per-pair-chunk
+                            partial sums, nmaps * nalm * 16 bytes per 256 ring pairs, and adds
+                            them in order; spreading is fixed-order in every plan) */
+    int kernel_eval;     /* NUSHT_KERNEL_POLY (default): interpolation and spreading form the ES
+                            taps from per-tap polynomials of degree w fitted at plan time (used
+                            when the fit deviates from the kernel by at most eps / 20);
+                            NUSHT_KERNEL_EXACT: from sqrt and exp at every tap */
+    int reserved[4];     /* must be zero */
 } nusht_plan_opts;
+
+enum { NUSHT_KERNEL_POLY = 0, NUSHT_KERNEL_EXACT = 1 };
 
 /* Sizes a plan uses; filled by nusht_geometry_for and nusht_plan_info. */
 typedef struct {
@@ -87,6 +97,8 @@ typedef struct {
     int64_t npts;
     int64_t nalm;
     int64_t ntiles_used; /* tiles holding at least one point (plan only; 0 from nusht_geometry_for) */
+    int kernel_eval;     /* taps the plan's point kernels use: NUSHT_KERNEL_POLY or _EXACT (plan only) */
+    double kernel_poly_dev; /* largest deviation of the tap polynomials from the kernel (plan only) */
 } nusht_geometry;
 
 /* Number of stored coefficients for (lmax, mmax); -1 if the arguments are invalid. */
@@ -134,6 +146,25 @@ int nusht_adjoint(nusht_plan_t plan, const double* map, double* alm, int nmaps, 
    (NUSHT_EPRECISION otherwise).  Used for gradients with respect to lensing deflections. */
 int nusht_synthesis_deriv(nusht_plan_t plan, const double* alm, double* map, double* dtheta,
                           double* dphi, int nmaps, void* stream);
+
+/* Lensing pointing (App. C): the deflected angles of the plan's points under the lensing
+   potential Phi with coefficients dlm (complex128 [nalm], same layout as alm).  The
+   deflection is the gradient of Phi (Eq. C2): alpha_theta = dPhi/dtheta and
+   alpha_phi = (dPhi/dphi) / sin(theta) (0 at an exact pole), from nusht_synthesis_deriv; each
+   point then moves a distance alpha = |alpha| along the great circle in the direction
+   (alpha_theta, alpha_phi) (Eq. C1).  theta_out, phi_out: float64 [npts], caller's point
+   order, theta' in [0, pi], phi' in [0, 2 pi).  FP64 plans only (NUSHT_EPRECISION
+   otherwise); the accuracy of alpha is the plan's eps.  Enqueues only. */
+int nusht_pointing(nusht_plan_t plan, const double* dlm, double* theta_out, double* phi_out,
+                   void* stream);
+
+/* Eq. (C1) alone, for given deflection components: theta_out, phi_out [npts] are the angles
+   of n' = cos(a) n + sin(a)/a (alpha_theta e_theta + alpha_phi e_phi), a = |alpha|, with
+   n, e_theta, e_phi the right-handed basis at (theta, phi).  All arrays float64 device
+   pointers [npts]; the outputs may alias the inputs.  Enqueues only. */
+int nusht_deflect(const double* theta, const double* phi, const double* alpha_theta,
+                  const double* alpha_phi, int64_t npts, double* theta_out, double* phi_out,
+                  void* stream);
 
 /* Gradients of a loss L(map) through the synthesis, given g = dL/dmap [nmaps][npts]:
    nusht_vjp_alm writes dL/dRe a + i dL/dIm a [nmaps][nalm], i.e. the adjoint Y^H g (Eq. 2)

@@ -21,7 +21,8 @@ NUSHT_DFS_FUSED, NUSHT_DFS_PAPER = 0, 1
 class PlanOpts(ctypes.Structure):
     _fields_ = [("sigma", ctypes.c_double), ("width", ctypes.c_int),
                 ("beta_per_w", ctypes.c_double), ("dfs_mode", ctypes.c_int),
-                ("timing", ctypes.c_int), ("reserved", ctypes.c_int * 6)]
+                ("timing", ctypes.c_int), ("deterministic", ctypes.c_int),
+                ("kernel_eval", ctypes.c_int), ("reserved", ctypes.c_int * 4)]
 
 
 class Geometry(ctypes.Structure):
@@ -30,7 +31,8 @@ class Geometry(ctypes.Structure):
                 ("n2", ctypes.c_int), ("width", ctypes.c_int), ("beta", ctypes.c_double),
                 ("sigma", ctypes.c_double), ("tile", ctypes.c_int), ("dtype", ctypes.c_int),
                 ("dfs_mode", ctypes.c_int), ("npts", ctypes.c_int64), ("nalm", ctypes.c_int64),
-                ("ntiles_used", ctypes.c_int64)]
+                ("ntiles_used", ctypes.c_int64), ("kernel_eval", ctypes.c_int),
+                ("kernel_poly_dev", ctypes.c_double)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -81,6 +83,8 @@ def lib():
             "nusht_adjoint": (ctypes.c_int, [_vp, _vp, _vp, ctypes.c_int, _vp]),
             "nusht_synthesis_deriv": (ctypes.c_int, [_vp, _vp, _vp, _vp, _vp, ctypes.c_int,
                                                      _vp]),
+            "nusht_pointing": (ctypes.c_int, [_vp, _vp, _vp, _vp, _vp]),
+            "nusht_deflect": (ctypes.c_int, [_vp, _vp, _vp, _vp, _i64, _vp, _vp, _vp]),
             "nusht_vjp_alm": (ctypes.c_int, [_vp, _vp, _vp, ctypes.c_int, _vp]),
             "nusht_vjp_points": (ctypes.c_int, [_vp, _vp, _vp, _vp, _vp, ctypes.c_int, _i64,
                                                 _vp]),
@@ -134,8 +138,11 @@ def nalm(lmax: int, mmax: int) -> int:
     return int(lib().nusht_nalm(lmax, mmax))
 
 
-def _opts(sigma=0.0, width=0, beta_per_w=0.0, dfs_mode="fused", timing=False):
+def _opts(sigma=0.0, width=0, beta_per_w=0.0, dfs_mode="fused", timing=False,
+          deterministic=False, kernel_eval="poly"):
     o = PlanOpts()
+    o.deterministic = 1 if deterministic else 0
+    o.kernel_eval = {"poly": 0, "exact": 1}[kernel_eval]
     o.sigma = float(sigma)
     o.width = int(width)
     o.beta_per_w = float(beta_per_w)
@@ -166,7 +173,8 @@ class Plan:
     """A nusht plan for fixed points (theta, phi) -- torch float64 tensors on the GPU."""
 
     def __init__(self, lmax, mmax, theta, phi, eps, dtype="f64", sigma=0.0, width=0,
-                 beta_per_w=0.0, dfs_mode="fused", timing=False):
+                 beta_per_w=0.0, dfs_mode="fused", timing=False, deterministic=False,
+                 kernel_eval="poly"):
         import torch
         if theta.dtype != torch.float64 or phi.dtype != torch.float64:
             raise TypeError("theta and phi must be float64")
@@ -178,7 +186,7 @@ class Plan:
         self.dtype = dtype
         self.npts = int(theta.numel())
         self.device = theta.device
-        o = _opts(sigma, width, beta_per_w, dfs_mode, timing)
+        o = _opts(sigma, width, beta_per_w, dfs_mode, timing, deterministic, kernel_eval)
         h = _vp()
         _check(lib().nusht_plan_ex(self.lmax, self.mmax, self.npts, theta.data_ptr(),
                                    phi.data_ptr(), self.eps, _dtype_code(dtype), ctypes.byref(o),
@@ -263,6 +271,19 @@ class Plan:
         _check(lib().nusht_synthesis_deriv(self._h, a.data_ptr(), f.data_ptr(), dt.data_ptr(),
                                            dp.data_ptr(), B, _stream()), "nusht_synthesis_deriv")
         return f, dt, dp
+
+    def pointing(self, dlm):
+        """nusht_pointing: deflected (theta', phi') of the plan's points under the lensing
+        potential with coefficients dlm (complex128 [nalm])."""
+        import torch
+        a = self._alm_in(dlm)
+        if a.shape[0] != 1:
+            raise ValueError("pointing takes one potential")
+        th = torch.empty(self.npts, dtype=torch.float64, device=a.device)
+        ph = torch.empty_like(th)
+        _check(lib().nusht_pointing(self._h, a.data_ptr(), th.data_ptr(), ph.data_ptr(),
+                                    _stream()), "nusht_pointing")
+        return th, ph
 
     def vjp_alm(self, grad_map):
         """dL/dRe a + i dL/dIm a for g = dL/dmap (nusht_vjp_alm)."""
@@ -427,6 +448,21 @@ def _f64_pts(theta, phi):
 
 def mlp_param_count() -> int:
     return int(lib().nusht_mlp_param_count())
+
+
+def deflect(theta, phi, alpha_theta, alpha_phi):
+    """nusht_deflect: Eq. (C1) for given deflection components (float64 device tensors)."""
+    import torch
+    theta, phi = _f64_pts(theta, phi)
+    at, ap = _f64_pts(alpha_theta, alpha_phi)
+    if at.numel() != theta.numel() or at.device != theta.device:
+        raise ValueError("deflection components must match the points")
+    th = torch.empty_like(theta)
+    ph = torch.empty_like(theta)
+    _check(lib().nusht_deflect(theta.data_ptr(), phi.data_ptr(), at.data_ptr(), ap.data_ptr(),
+                               theta.numel(), th.data_ptr(), ph.data_ptr(), _stream()),
+           "nusht_deflect")
+    return th, ph
 
 
 def density_map(theta, phi, ntheta, nphi):

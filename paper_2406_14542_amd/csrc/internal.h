@@ -13,9 +13,9 @@
 
 namespace nusht {
 
-// Side of the square tiles the points are binned into on the fine grid.  Every tile
-// window (tile + w - 1 halo) must fit in LDS; w <= 16 keeps the halo inside one
-// neighbouring tile, which the halo reduction relies on.
+// Side of the square tiles the points are binned into on the fine grid.  Every tile window
+// (tile + w - 1 cells a side) must fit in LDS for the interpolation; w <= 16 keeps a point's
+// taps inside the next tile row, which the spreading sweep's segment overlap relies on.
 constexpr int kTile = 32;
 constexpr int kMaxWidth = 16;
 // zero entries after the recurrence table, so that a chunk of l values can be loaded whole
@@ -75,7 +75,6 @@ enum Stage {
     ST_DECONV,        // a5 / b3
     ST_FINE_FFT,      // a6 / b2
     ST_POINTS,        // a7 / b1 (interpolation or spreading)
-    ST_HALO,          // b1 halo reduction
     ST_COUNT
 };
 
@@ -109,6 +108,15 @@ struct nusht_plan_s {
     int* slot_off = nullptr;     // [nslots+1] first sorted point of each slot
     int* slot_tile = nullptr;    // [nslots] tile id of each slot
     int* tile_slot = nullptr;    // [ntiles] slot of each tile or -1
+    // Inside a tile the points are sorted by column band (band_w fine columns, band_w >= w)
+    // and then by row: band b of slot s holds the sorted points [band_off[s nsub + b],
+    // band_off[s nsub + b + 1]), nsub = kTile / band_w.  The spreading kernel sweeps bands.
+    int* band_off = nullptr;     // [nslots * nsub + 1]
+    int band_w = 0, nsub = 0;
+    // Rows of the spreading sweep on a virtual axis (tile row nt1 - 1 is tile row -1): tile
+    // rows [-1, band_vt_end) can hold points, rows [-kTile, band_vrow_hi) are written, in
+    // segments of band_seg_tiles tile rows.
+    int band_vt_end = 0, band_vrow_hi = 0, band_seg_tiles = 1;
     int nslots = 0;
     int nt1 = 0, nt2 = 0;        // tiles per fine-grid axis
     int* dflag = nullptr;        // device error flag used by plan validation
@@ -125,12 +133,20 @@ struct nusht_plan_s {
     void* W = nullptr;           // one map's fine row spectrum [n1][n2/2+1]
     size_t Wbytes = 0;
     double* V = nullptr;         // point scratch [npts][4]: packed point values of one group
-    void* Z = nullptr;           // spreading subgrids
-    size_t Zbytes = 0;
     void* fftwork = nullptr;
     size_t fftwork_bytes = 0;
     double* red = nullptr;       // small reduction scratch for the CG solve
     size_t redbytes = 0;
+    // ES taps: polynomial coefficients [(w + 1) * w] (s^k of tap a at k * w + a) in FP64 and
+    // FP32, or null when the taps are formed from sqrt and exp (option, or fit not accurate)
+    int es_eval = 0;
+    double es_poly_dev = 0.0;
+    double* es_coef = nullptr;
+    float* es_coeff = nullptr;
+    // deterministic plans: the Legendre adjoint's per-pair-chunk partial sums
+    int deterministic = 0;
+    double* adj_part = nullptr;
+    size_t adj_part_bytes = 0;
 
     // rocFFT plans (all per map; executed once per map of a batch).
     nusht::FftPlan ring_c2r, ring_r2c;      // 1D over phi, batch N_r, FP64
@@ -165,8 +181,12 @@ struct nusht_plan_s {
 
 namespace nusht {
 
+// Width of the column bands of the spreading kernel (one band per lane group of a wave): the
+// taps of a point reach at most w - 1 columns past its first tap, so one band to the left holds
+// every point that reaches a band, and the group's lanes hold the w row taps of a point.
+inline int band_width_for(int w) { return w <= 8 ? 8 : 16; }
+
 // Maps are processed by the point kernels in groups of four, the remainder one by one.
-inline int point_groups(int nmaps) { return nmaps / 4 + nmaps % 4; }
 inline int group_width(int nmaps, int b) { return (nmaps - b) >= 4 ? 4 : 1; }
 
 // ---- geometry (plan.hip) ----
@@ -191,7 +211,7 @@ int launch_legendre_synth(const nusht_plan_s* p, const double* alm, void* out, i
 int synth_pairs_per_lane(int npairs);
 int synth_scaled_pairs_per_lane(int npairs);
 // adjoint into alm [nmaps][nalm] (complex128), which it zeroes and then accumulates into
-int launch_legendre_adjoint(const nusht_plan_s* p, const void* in, double* alm, int nmaps,
+int launch_legendre_adjoint(nusht_plan_s* p, const void* in, double* alm, int nmaps,
                             int fused, int in_f32, hipStream_t s);
 
 // ---- DFS glue (dfs.hip) ----
@@ -224,8 +244,6 @@ int launch_interp(const nusht_plan_s* p, const void* fine, double* out, int nmap
                   hipStream_t s);
 int launch_interp_deriv(const nusht_plan_s* p, const double* fine, double* out, double* dth,
                         double* dph, int nmaps, hipStream_t s);
-int launch_spread(const nusht_plan_s* p, const double* in, void* fine, int nmaps, int f32,
-                  hipStream_t s);
 
 // ---- point binning (plan.hip) ----
 int bin_points(nusht_plan_s* p, const double* theta, const double* phi, hipStream_t s);

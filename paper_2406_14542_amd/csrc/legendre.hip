@@ -410,8 +410,8 @@ __device__ inline double2 load_c(const InT* p)
     return make_double2((double)v.x, (double)v.y);
 }
 
-template <bool FUSED, typename InT>
-__global__ __launch_bounds__(kAdjWaves * 64, 4) void k_legendre_adj(
+template <bool FUSED, typename InT, bool DET>
+__global__ __launch_bounds__(kAdjWaves * 64, DET ? 3 : 4) void k_legendre_adj(
     const InT* __restrict__ in, int64_t in_map_stride, int64_t in_row_stride, int nmaps,
     double* __restrict__ alm, int npc, int64_t nalm, int lmax,
     const double2* __restrict__ rec, const double* __restrict__ cm_mant,
@@ -422,15 +422,18 @@ __global__ __launch_bounds__(kAdjWaves * 64, 4) void k_legendre_adj(
     // (128 D values: 64 lanes x real/imaginary), their arrival counts and hand-on counts
     __shared__ double stage[kAdjWaves][64 * kLS];
     __shared__ float pf_sink[kAdjWaves][64];
-    __shared__ double slot[kAdjSlots][kAdjGroup * 128];
+    // DET: one region per wave, summed in wave order by the flushing wave (fixed order)
+    constexpr int kSlotWaves = DET ? kAdjWaves : 1;
+    __shared__ double slot[kAdjSlots][kSlotWaves][kAdjGroup * 128];
     __shared__ unsigned scnt[kAdjSlots], sgen[kAdjSlots];
-    static_assert((kAdjSlots & (kAdjSlots - 1)) == 0 && kAdjSlots * kAdjGroup * 128 <= 2 * 256,
-                  "slot count a power of two, cleared by the block's threads in two stores");
+    static_assert((kAdjSlots & (kAdjSlots - 1)) == 0, "slot count a power of two");
     // all pair-chunks of one m on one XCD, one after the other: they share the m's
     // coefficient stream in that XCD's L2
     int m, pc;
     xcd_block(blockIdx.x, npc, m, pc);
     if (m > mmax) return;
+    // DET: alm is the partial-sum array [npc][nmaps][nalm] (complex); this block's part
+    if (DET) alm += (int64_t)pc * nmaps * nalm * 2;
     const int grp = blockIdx.y;
     const int nmb = min(4, nmaps - 4 * grp);
     // the wave index read through a scalar register: everything derived from it (dead waves,
@@ -507,8 +510,8 @@ __global__ __launch_bounds__(kAdjWaves * 64, 4) void k_legendre_adj(
 #pragma unroll
         for (int c = 0; c < 16; ++c) st[lane * kLS + c] = hv[c];
     }
-    for (int e = threadIdx.x; e < kAdjSlots * kAdjGroup * 128; e += blockDim.x)
-        (&slot[0][0])[e] = 0.0;
+    for (int e = threadIdx.x; e < kAdjSlots * kSlotWaves * kAdjGroup * 128; e += blockDim.x)
+        (&slot[0][0][0])[e] = 0.0;
     if (threadIdx.x < kAdjSlots) {
         scnt[threadIdx.x] = 0;
         sgen[threadIdx.x] = 0;
@@ -688,10 +691,15 @@ __global__ __launch_bounds__(kAdjWaves * 64, 4) void k_legendre_adj(
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
 #pragma unroll
         for (int g = 0; g < kAdjGroup; ++g) {
-            __hip_atomic_fetch_add(&slot[sl][g * 128 + lane], dv[g][0], __ATOMIC_RELAXED,
-                                   __HIP_MEMORY_SCOPE_WORKGROUP);
-            __hip_atomic_fetch_add(&slot[sl][g * 128 + 64 + lane], dv[g][1], __ATOMIC_RELAXED,
-                                   __HIP_MEMORY_SCOPE_WORKGROUP);
+            if (DET) {
+                slot[sl][DET ? wave : 0][g * 128 + lane] = dv[g][0];
+                slot[sl][DET ? wave : 0][g * 128 + 64 + lane] = dv[g][1];
+            } else {
+                __hip_atomic_fetch_add(&slot[sl][0][g * 128 + lane], dv[g][0], __ATOMIC_RELAXED,
+                                       __HIP_MEMORY_SCOPE_WORKGROUP);
+                __hip_atomic_fetch_add(&slot[sl][0][g * 128 + 64 + lane], dv[g][1],
+                                       __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+            }
         }
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
         unsigned arrived = 0;
@@ -705,10 +713,19 @@ __global__ __launch_bounds__(kAdjWaves * 64, 4) void k_legendre_adj(
             double v[kAdjGroup][2];
 #pragma unroll
             for (int g = 0; g < kAdjGroup; ++g) {
-                v[g][0] = slot[sl][g * 128 + lane];
-                v[g][1] = slot[sl][g * 128 + 64 + lane];
-                slot[sl][g * 128 + lane] = 0.0;
-                slot[sl][g * 128 + 64 + lane] = 0.0;
+                if (DET) {
+                    // waves in order; a dead wave's region stays zero
+                    v[g][0] = v[g][1] = 0.0;
+                    for (int w = 0; w < nwaves; ++w) {
+                        v[g][0] += slot[sl][DET ? w : 0][g * 128 + lane];
+                        v[g][1] += slot[sl][DET ? w : 0][g * 128 + 64 + lane];
+                    }
+                } else {
+                    v[g][0] = slot[sl][0][g * 128 + lane];
+                    v[g][1] = slot[sl][0][g * 128 + 64 + lane];
+                    slot[sl][0][g * 128 + lane] = 0.0;
+                    slot[sl][0][g * 128 + 64 + lane] = 0.0;
+                }
             }
             // the lane index re-read here (opaque to the compiler), so that the lane's output
             // offset is formed in this branch instead of being held in registers throughout
@@ -725,8 +742,15 @@ __global__ __launch_bounds__(kAdjWaves * 64, 4) void k_legendre_adj(
                     // the lane's map offset in 32 bits (b nalm 2 < 2^32), the rest uniform
                     double* o = alm + ((int64_t)(4 * grp) * nalm + moff + m + (c0 + g) * kLC) * 2 +
                                 (unsigned)(b * (unsigned)nalm * 2u + (unsigned)dl * 2u);
-                    if (v[g][0] != 0.0) unsafeAtomicAdd(o, v[g][0]);
-                    if (m > 0 && v[g][1] != 0.0) unsafeAtomicAdd(o + 1, v[g][1]);  // c_l0 is real
+                    if (DET) {
+                        // this pair-chunk's own partial sums (alm points at them), summed
+                        // over the pair-chunks in order afterwards
+                        o[0] = v[g][0];
+                        o[1] = m > 0 ? v[g][1] : 0.0;
+                    } else {
+                        if (v[g][0] != 0.0) unsafeAtomicAdd(o, v[g][0]);
+                        if (m > 0 && v[g][1] != 0.0) unsafeAtomicAdd(o + 1, v[g][1]);  // c_l0 real
+                    }
                 }
             }
             __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
@@ -747,6 +771,36 @@ __global__ void k_fill_zero(double* __restrict__ a, int64_t n)
 {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i < n) a[i] = 0.0;
+}
+
+// Deterministic adjoint: alm[b][i] = sum over the pair-chunks pc of part[pc][b][i], in pc order.
+// Pair-chunks that wrote nothing for the element's m (all their ring pairs below the live-ring
+// bound jlive[m], or past the last pair) are skipped.
+__global__ void k_adj_reduce(const double2* __restrict__ part, int npc, int nmaps, int64_t nalm,
+                             int lmax, int mmax, const int* __restrict__ jlive, int ppb,
+                             int npairs, double2* __restrict__ alm)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= nalm) return;
+    // m of index i: the largest m <= mmax whose first index first(m) = idx(m, m) =
+    // m (2 lmax + 3 - m) / 2 is <= i.  first() grows with m up to lmax, and the discriminant
+    // (2 lmax + 3)^2 - 8 i stays positive over the triangle; the estimate is corrected by
+    // steps that cannot leave [0, mmax].
+    const double bq = 2.0 * lmax + 3.0;
+    const double disc = fmax(bq * bq - 8.0 * (double)i, 0.0);
+    int m = (int)fmin(fmax(floor(0.5 * (bq - sqrt(disc))), 0.0), (double)mmax);
+    while (m > 0 && (int64_t)m * (2 * lmax + 3 - m) / 2 > i) --m;
+    while (m < mmax && (int64_t)(m + 1) * (2 * lmax + 2 - m) / 2 <= i) ++m;
+    const int pc0 = jlive[m] / ppb;
+    for (int b = 0; b < nmaps; ++b) {
+        double2 acc = make_double2(0.0, 0.0);
+        for (int pc = pc0; pc < npc && pc * ppb < npairs; ++pc) {
+            const double2 v = part[((int64_t)pc * nmaps + b) * nalm + i];
+            acc.x += v.x;
+            acc.y += v.y;
+        }
+        alm[(int64_t)b * nalm + i] = acc;
+    }
 }
 
 }  // namespace
@@ -828,7 +882,7 @@ int launch_legendre_synth(const nusht_plan_s* p, const double* alm, void* out, i
     return NUSHT_OK;
 }
 
-int launch_legendre_adjoint(const nusht_plan_s* p, const void* in, double* alm, int nmaps,
+int launch_legendre_adjoint(nusht_plan_s* p, const void* in, double* alm, int nmaps,
                             int fused, int in_f32, hipStream_t s)
 {
     const nusht_geometry& g = p->g;
@@ -846,23 +900,49 @@ int launch_legendre_adjoint(const nusht_plan_s* p, const void* in, double* alm, 
         row_stride = g.nphi / 2 + 1;
         map_stride = (int64_t)g.nrings * row_stride;
     }
-    // the pair-chunk workgroups of one m add their sums into the zeroed output with FP64
-    // atomics, which resolve in the L2 of the XCD those workgroups share
-    const int64_t nz = (int64_t)nmaps * g.nalm * 2;
-    hipLaunchKernelGGL(k_fill_zero, dim3((unsigned)((nz + 255) / 256)), dim3(256), 0, s, alm, nz);
     const int mpad = (g.mmax + 1 + 7) / 8 * 8;
     dim3 grid(npc * mpad, groups);
-#define ADJ(F, IT)                                                                              \
-    hipLaunchKernelGGL((k_legendre_adj<F, IT>), grid, dim3(threads), 0, s,                       \
-                       reinterpret_cast<const IT*>(in), map_stride, row_stride, nmaps, alm, npc,  \
+#define ADJ(F, IT, D, OUT)                                                                      \
+    hipLaunchKernelGGL((k_legendre_adj<F, IT, D>), grid, dim3(threads), 0, s,                    \
+                       reinterpret_cast<const IT*>(in), map_stride, row_stride, nmaps, OUT, npc,  \
                        g.nalm, g.lmax, p->rec, p->cm_mant, p->cm_exp, p->jlive, g.nrings,        \
                        g.ntorus, ppb, g.mmax, p->dstatus)
-    if (fused && in_f32) {
-        ADJ(true, float2);
-    } else if (fused) {
-        ADJ(true, double2);
+    if (p->deterministic) {
+        // every pair-chunk writes its own partial sums; one pass adds them in pair-chunk order
+        const size_t need = (size_t)npc * nmaps * g.nalm * 2 * sizeof(double);
+        if (need > p->adj_part_bytes) {
+            NUSHT_HIP(hipStreamSynchronize(s));
+            if (p->adj_part) hipFree(p->adj_part);
+            p->adj_part = nullptr;
+            p->adj_part_bytes = 0;
+            NUSHT_HIP(hipMalloc((void**)&p->adj_part, need));
+            p->adj_part_bytes = need;
+        }
+        double* part = p->adj_part;
+        if (fused && in_f32) {
+            ADJ(true, float2, true, part);
+        } else if (fused) {
+            ADJ(true, double2, true, part);
+        } else {
+            ADJ(false, double2, true, part);
+        }
+        NUSHT_HIP(hipGetLastError());
+        hipLaunchKernelGGL(k_adj_reduce, dim3((unsigned)((g.nalm + 255) / 256)), dim3(256), 0, s,
+                           reinterpret_cast<const double2*>(part), npc, nmaps, g.nalm, g.lmax,
+                           g.mmax, p->jlive, ppb, npairs, reinterpret_cast<double2*>(alm));
     } else {
-        ADJ(false, double2);
+        // the pair-chunk workgroups of one m add their sums into the zeroed output with FP64
+        // atomics, which resolve in the L2 of the XCD those workgroups share
+        const int64_t nz = (int64_t)nmaps * g.nalm * 2;
+        hipLaunchKernelGGL(k_fill_zero, dim3((unsigned)((nz + 255) / 256)), dim3(256), 0, s, alm,
+                           nz);
+        if (fused && in_f32) {
+            ADJ(true, float2, false, alm);
+        } else if (fused) {
+            ADJ(true, double2, false, alm);
+        } else {
+            ADJ(false, double2, false, alm);
+        }
     }
 #undef ADJ
     NUSHT_HIP(hipGetLastError());

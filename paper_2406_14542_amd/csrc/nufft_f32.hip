@@ -9,16 +9,10 @@ int interp_f32(const nusht_plan_s* p, const float* fine, double* out, int nmaps,
     return dispatch_interp_impl<float>(p, fine, out, nmaps, (float)p->g.beta, s);
 }
 
-int spread_group_f32(const nusht_plan_s* p, const double* vals, float* sub, int mb,
+int spread_group_f32(const nusht_plan_s* p, const double* vals, float* fine, int mb,
                      hipStream_t s)
 {
-    return spread_group_impl<float>(p, vals, sub, mb, (float)p->g.beta, s);
-}
-
-int halo_group_f32(const nusht_plan_s* p, const float* sub, float* fine, int b, int mb,
-                   hipStream_t s)
-{
-    return halo_group_impl<float>(p, sub, fine, b, mb, s);
+    return spread_group_impl<float>(p, vals, fine, mb, (float)p->g.beta, s);
 }
 
 }  // namespace nusht

@@ -1,4 +1,4 @@
-// FP64 instantiations of the nuFFT point kernels (interpolation, spreading, halo reduction,
+// FP64 instantiations of the nuFFT point kernels (interpolation, spreading,
 // and the derivative interpolation used for gradients with respect to point positions).
 #include "nufft_impl.h"
 
@@ -9,16 +9,10 @@ int interp_f64(const nusht_plan_s* p, const double* fine, double* out, int nmaps
     return dispatch_interp_impl<double>(p, fine, out, nmaps, p->g.beta, s);
 }
 
-int spread_group_f64(const nusht_plan_s* p, const double* vals, double* sub, int mb,
+int spread_group_f64(const nusht_plan_s* p, const double* vals, double* fine, int mb,
                      hipStream_t s)
 {
-    return spread_group_impl<double>(p, vals, sub, mb, p->g.beta, s);
-}
-
-int halo_group_f64(const nusht_plan_s* p, const double* sub, double* fine, int b, int mb,
-                   hipStream_t s)
-{
-    return halo_group_impl<double>(p, sub, fine, b, mb, s);
+    return spread_group_impl<double>(p, vals, fine, mb, p->g.beta, s);
 }
 
 int launch_interp_deriv(const nusht_plan_s* p, const double* fine, double* out, double* dth,

@@ -1,18 +1,17 @@
 // Type-2 interpolation and type-1 spreading of the ES-kernel nuFFT on the fine torus grid
-// (arXiv:2406.14542 Sec. III: N and N^H, "shared memory" spreading).
+// (arXiv:2406.14542 Sec. III: N and N^H of Eq. 5 / Eq. 6).
 //
 // Kernel: psi(z) = exp(beta (sqrt(1 - z^2) - 1)) for |z| < 1, z = 2 (x - x_l) / (w h).
 // For a coordinate x with t = x / h (grid units) the w taps start at cell
 //   ls = ceil(t - w/2),  and tap a has z_a = 2 (t - ls - a) / w  in (-1, 1].
-// Points were binned by the plan into kTile x kTile tiles by (ls1 mod n1, ls2 mod n2); a
-// workgroup owns one non-empty tile ("slot") and the tile's window of
-// (kTile + w - 1)^2 cells, which it stages in LDS.
-//  * interpolation: window loaded once from HBM, every point of the tile reads its w x w taps
-//    from LDS, results written packed per point in the caller's point order;
-//  * spreading: the tile's points (values packed per point, fetched through the permutation)
-//    are added into an FP64 LDS copy of the window with LDS atomics; the window is written
-//    once to a per-slot subgrid, and a second pass sums, for every fine cell, the subgrids of
-//    the (at most four) windows that cover it (no global atomics).
+// Points were binned by the plan into kTile x kTile tiles by (ls1 mod n1, ls2 mod n2), inside
+// a tile by column band and then by row.
+//  * interpolation: a workgroup owns one non-empty tile ("slot") and stages the tile's window
+//    of (kTile + w - 1)^2 cells in LDS once; every point of the tile reads its w x w taps from
+//    LDS; results are written packed per point;
+//  * spreading: waves sweep column bands row by row and keep the rows a point can reach in
+//    registers (k_spread_band): every fine cell is written once, with its points summed in a
+//    fixed order, and no atomics or partial grids are involved.
 // Offsets are formed in FP64 from FP64 coordinates before any cast to the kernel's type T.
 #pragma once
 
@@ -77,6 +76,31 @@ __device__ inline void es_taps(double d, T beta, T (&psi)[W])
     const T c = T(2) / T(W);
 #pragma unroll
     for (int a = 0; a < W; ++a) psi[a] = es_value<T>((dd - T(a)) * c, beta);
+}
+
+// The same taps from the plan's polynomials (degree W in s = 2 d - W + 1, coefficient of s^k
+// for tap a at coef[k W + a]): W Horner chains advanced together, one wave-uniform coefficient
+// row per step.
+template <typename T, int W>
+__device__ inline void es_taps_poly(double d, const T* __restrict__ coef, T (&psi)[W])
+{
+    const T sv = (T)(2.0 * d - (double)(W - 1));
+#pragma unroll
+    for (int a = 0; a < W; ++a) psi[a] = coef[W * W + a];
+#pragma unroll
+    for (int k = W - 1; k >= 0; --k)
+#pragma unroll
+        for (int a = 0; a < W; ++a) psi[a] = psi[a] * sv + coef[k * W + a];
+}
+
+// one tap a of one point from the polynomial coefficients creg[k] = coef[k W + a]
+template <typename T, int W>
+__device__ inline T es_tap_poly(T sv, const T (&creg)[W + 1])
+{
+    T v = creg[W];
+#pragma unroll
+    for (int k = W - 1; k >= 0; --k) v = v * sv + creg[k];
+    return v;
 }
 
 // taps and their derivatives with respect to t (grid units):
@@ -148,8 +172,9 @@ __device__ inline void stage_window(const T* __restrict__ fine, int64_t map_stri
 // out[b][dst] (MB scattered 8-byte stores).
 template <typename T, int W, int MB, bool PACKED>
 __global__ __launch_bounds__(256) void k_interp(const T* __restrict__ fine, int64_t map_stride,
-                                                PointBins pb, T beta, double* __restrict__ out,
-                                                int64_t npts)
+                                                PointBins pb, T beta,
+                                                const T* __restrict__ coef,
+                                                double* __restrict__ out, int64_t npts)
 {
     constexpr int P = kTile + W - 1;
     constexpr bool kUserRows = !PACKED || sizeof(T) == 8;  // results addressed by caller index
@@ -187,8 +212,13 @@ __global__ __launch_bounds__(256) void k_interp(const T* __restrict__ fine, int6
         r = min(max(r, 0), kTile - 1);
         c = min(max(c, 0), kTile - 1);
         T p1v[W], p2v[W];
-        es_taps<T, W>(d1, beta, p1v);
-        es_taps<T, W>(d2, beta, p2v);
+        if (coef) {
+            es_taps_poly<T, W>(d1, coef, p1v);
+            es_taps_poly<T, W>(d2, coef, p2v);
+        } else {
+            es_taps<T, W>(d1, beta, p1v);
+            es_taps<T, W>(d2, beta, p2v);
+        }
         T acc[MB];
 #pragma unroll
         for (int b = 0; b < MB; ++b) acc[b] = T(0);
@@ -336,143 +366,251 @@ __global__ __launch_bounds__(256) void k_interp_deriv(const double* __restrict__
     }
 }
 
-// Spreading with LDS atomics, batched.  The block stages up to NB of the slot's points (tap
-// offsets, first cells relative to the tile, values) in LDS, then every wave takes
-// PPW = 64 / LPP points at a time with LPP lanes per point, lane = column tap: each lane forms
-// its column tap psi2[col] and the row tap psi1[col], the row taps of the point are exchanged
-// through a per-wave LDS row, and lane (point, col) adds f psi1[a] psi2[col] into window
-// rows r + a, a < W, of its column.  The window is planar (map-major), so the lanes of one
-// point add into consecutive words of one row.  Values come in packed, [point][MB], in the
-// caller's order, and are fetched through the permutation.  The window sums in FP64; the order of the additions into a cell is not fixed, so results can
-// differ between runs by FP64 rounding (~1e-16 relative) before the cast to T.
-template <typename T, int MB>
-struct SpreadPoint {
-    T d1, d2;  // offsets of the first taps, grid units
-    int r, c;  // first tap cell relative to the tile
-    T f[MB];
+// Spreading (type 1, N^H of Eq. 6): u(l1, l2) = sum_i f_i psi(row taps) psi(column taps), the
+// exact adjoint of the interpolation above (same taps).
+//
+// Band sweep, no atomics.  The fine columns are cut into bands of SW = band_w columns; each
+// group of SW lanes of a wave owns one band (lane q = column c0 + q), so a wave sweeps
+// K = 64 / SW bands side by side.  A band's points -- its own band's points and those of the
+// band to its left whose taps reach it (SW >= w) -- are taken in order of their first-tap
+// row, tile row after tile row.  Every lane keeps the w rows [R, R + w) of its column in
+// registers: a point whose first tap is row r (>= R, rows only grow) first pushes rows R .. r-1
+// out to the fine grid, then adds f psi1[a] psi2[q - c] to rows r + a.  Each cell is written
+// once, by the lane that owns its column, as the sum of its points in a fixed order: the
+// result does not depend on scheduling, and nothing is written twice.
+//
+// Rows are handled on a virtual axis: physical tile row nt1 - 1 (points near theta = 0 whose
+// first tap wraps below row 0) is virtual tile row -1, so a band's rows run on without a wrap
+// from -kTile up.  The rows are cut into segments of seg_tiles tile rows (grid.y); a segment
+// owns the rows of its tile rows and also sweeps the points of the tile row above it whose
+// taps reach its first row (and drops their rows above it), so segments never write the same
+// cell either.  The owned rows of all segments are exactly the rows any point window reaches
+// ([n1 - kTile, n1) and [0, ra)); when every row is reached, the first segment's overlap row
+// is the last tile row shifted by -n1, which carries the wrap.
+struct BandBins {
+    const double* sth;
+    const double* sph;
+    const int* perm;
+    const int* band_off;   // [nslots * nsub + 1]
+    const int* tile_slot;  // [nt1 * nt2]
+    int nt1, nt2, n1, n2, nsub, nbands;
+    double s1, s2;
+    int vt_end;     // virtual tile rows [-1, vt_end) can hold points
+    int vrow_hi;    // owned virtual rows are [-kTile, vrow_hi)
+    int seg_tiles;  // tile rows per segment
 };
 
-template <typename T, int W, int MB>
-__global__ __launch_bounds__(256) void k_spread_lds(const T* __restrict__ vals, PointBins pb,
-                                                    T beta, T* __restrict__ sub)
+constexpr int kNoRow = 0x7fffffff;
+
+template <typename T, int MB>
+struct BandHead {
+    int r, c;  // first tap: virtual row, column relative to the band start
+    T s1, s2;  // offsets of the first taps as s = 2 d - w + 1 in (-1, 1], formed in FP64
+    T f[MB];   // the point's values
+};
+
+// first sorted point of band group g of tile (ptr, tcol), or an empty range
+__device__ inline void band_range(const BandBins& bb, int ptr, int tcol, int sub, int& p, int& e)
 {
-    constexpr int P = kTile + W - 1;
-    constexpr int LPP = W <= 8 ? 8 : 16;
-    constexpr int PPW = 64 / LPP;
-    constexpr int NB = 128;  // points staged per batch (64 for FP64 measured 0.6 ms slower)
-    static_assert(W <= 16, "one lane per column tap");
-    // the window accumulates in FP64 for either T: LDS atomic adds of FP64 measured fast on
-    // gfx950, those of FP32 an order of magnitude slower than the whole kernel
-    __shared__ double win[MB * P * P];
-    __shared__ SpreadPoint<T, MB> s_pt[NB];
-    __shared__ T s_p1[4][PPW][LPP];
-    const int slot = blockIdx.x;
-    const int tile = pb.slot_tile[slot];
-    const int r0 = (tile / pb.nt2) * kTile;
-    const int c0 = (tile % pb.nt2) * kTile;
-    const int t = threadIdx.x;
-    for (int e = t; e < MB * P * P; e += blockDim.x) win[e] = 0.0;
-    const int wave = t >> 6, lane = t & 63;
-    const int grp = lane / LPP, col = lane - grp * LPP;
-    const int p0 = pb.slot_off[slot], p1 = pb.slot_off[slot + 1];
-    const T cw = T(2) / T(W);
-    T* p1row = s_p1[wave][grp];
-    for (int base = p0; base < p1; base += NB) {
-        const int nb = min(NB, p1 - base);
-        __syncthreads();  // window cleared, or the previous batch consumed
-        if (t < nb) {
-            const int p = base + t;
-            double d1, d2;
-            const int l1 = first_tap(pb.sth[p], pb.s1, W, d1);
-            const int l2 = first_tap(pb.sph[p], pb.s2, W, d2);
-            int r = wrap_index(l1, pb.n1) - r0;
-            int c = wrap_index(l2, pb.n2) - c0;
-            const int64_t src = pb.perm[p];
-            SpreadPoint<T, MB> sp;
-            sp.d1 = (T)d1;
-            sp.d2 = (T)d2;
-            sp.r = min(max(r, 0), kTile - 1);
-            sp.c = min(max(c, 0), kTile - 1);
-#pragma unroll
-            for (int b = 0; b < MB; ++b) sp.f[b] = vals[src * MB + b];
-            s_pt[t] = sp;
-        }
-        __syncthreads();
-        // lane group g takes the points g S + i of the row-sorted batch: the PPW points of one
-        // step lie S apart, in different rows, so no two lanes of an atomic add address the
-        // same cell (a point adds into rows r + a for the step's common a)
-        const int S = (nb + PPW - 1) / PPW;
-        for (int i = wave; i < S; i += 4) {
-            const int q = grp * S + i;
-            const bool live = q < nb;
-            const SpreadPoint<T, MB> sp = s_pt[live ? q : 0];
-            const bool act = live && col < W;
-            const T p2 = act ? es_value<T>((sp.d2 - T(col)) * cw, beta) : T(0);
-            p1row[col] = col < W ? es_value<T>((sp.d1 - T(col)) * cw, beta) : T(0);
-            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-            __builtin_amdgcn_wave_barrier();
-            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-            T pr[W];
-#pragma unroll
-            for (int a = 0; a < W; ++a) pr[a] = p1row[a];
-            // the next step rewrites the row: every lane's reads come first
-            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-            __builtin_amdgcn_wave_barrier();
-            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-            if (act) {
-                T fb[MB];
-#pragma unroll
-                for (int b = 0; b < MB; ++b) fb[b] = sp.f[b] * p2;
-                double* w0 = win + sp.r * P + sp.c + col;
-#pragma unroll
-                for (int a = 0; a < W; ++a)
-#pragma unroll
-                    for (int b = 0; b < MB; ++b)
-                        atomicAdd(w0 + (b * P + a) * P, (double)(fb[b] * pr[a]));
-            }
-        }
+    const int sl = bb.tile_slot[ptr * bb.nt2 + tcol];
+    if (sl < 0) {
+        p = e = 0;
+        return;
     }
-    __syncthreads();
-    T* dst = sub + (int64_t)slot * (P * P * MB);
-    for (int e = t; e < P * P; e += blockDim.x) {
-#pragma unroll
-        for (int b = 0; b < MB; ++b) dst[e * MB + b] = (T)win[b * P * P + e];
-    }
+    const int g = sl * bb.nsub + sub;
+    p = bb.band_off[g];
+    e = bb.band_off[g + 1];
 }
 
-// fine[b][i][j] = sum of the subgrids of the windows covering cell (i, j); zero elsewhere
 template <typename T, int W, int MB>
-__global__ __launch_bounds__(256) void k_halo(const T* __restrict__ sub,
-                                              const int* __restrict__ tile_slot, int nt1, int nt2,
-                                              int n1, int n2, int ra, int rb,
-                                              T* __restrict__ fine, int64_t map_stride)
+__device__ inline int band_row(const BandBins& bb, int p, int voff)
 {
-    constexpr int P = kTile + W - 1;
-    const int j = blockIdx.x * blockDim.x + threadIdx.x;
-    // rows [0, ra) and [n1 - rb, n1): the only rows any window reaches
-    const int i = (int)blockIdx.y < ra ? (int)blockIdx.y : n1 - rb + ((int)blockIdx.y - ra);
-    if (j >= n2) return;
-    const int tr = i / kTile, rr = i - tr * kTile;
-    const int tc = j / kTile, cc = j - tc * kTile;
-    const int trp = tr == 0 ? nt1 - 1 : tr - 1;
-    const int tcp = tc == 0 ? nt2 - 1 : tc - 1;
-    T acc[MB];
+    double d;
+    return wrap_index(first_tap(bb.sth[p], bb.s1, W, d), bb.n1) + voff;
+}
+
+template <typename T, int W, int MB>
+__device__ inline void band_decode(const BandBins& bb, const T* __restrict__ vals, int p,
+                                   int voff, int cbase, BandHead<T, MB>& h)
+{
+    double d1, d2;
+    const int l1 = first_tap(bb.sth[p], bb.s1, W, d1);
+    const int l2 = first_tap(bb.sph[p], bb.s2, W, d2);
+    h.r = wrap_index(l1, bb.n1) + voff;
+    h.c = wrap_index(l2, bb.n2) - cbase;
+    h.s1 = (T)(2.0 * d1 - (double)(W - 1));
+    h.s2 = (T)(2.0 * d2 - (double)(W - 1));
+    const int64_t src = bb.perm[p];
 #pragma unroll
-    for (int b = 0; b < MB; ++b) acc[b] = T(0);
-    auto add = [&](int t_r, int t_c, int r, int c) {
-        const int sl = tile_slot[t_r * nt2 + t_c];
-        if (sl < 0) return;
-        const T* s = sub + (int64_t)sl * (P * P * MB) + (r * P + c) * MB;
+    for (int m = 0; m < MB; ++m) h.f[m] = vals[src * MB + m];
+}
+
+template <typename T, int W, int MB, int SW>
+__global__ __launch_bounds__(256) void k_spread_band(const T* __restrict__ vals, BandBins bb,
+                                                     T beta, const T* __restrict__ coef,
+                                                     T* __restrict__ fine, int64_t map_stride)
+{
+    constexpr int K = 64 / SW;
+    static_assert(SW >= W && kTile % SW == 0,
+                  "one band to the left reaches a band; a group's lanes hold the row taps");
+    const int lane = threadIdx.x & 63;
+    const int grp = lane / SW, q = lane - grp * SW;
+    const int band = (int)(blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6)) * K + grp;
+    const bool bvalid = band < bb.nbands;
+    const int c0 = bvalid ? band * SW : 0;
+    const int tcol = c0 / kTile, sub = (c0 % kTile) / SW;
+    const int lband = !bvalid ? 0 : band == 0 ? bb.nbands - 1 : band - 1;
+    const int lc0 = lband * SW;
+    const int ltcol = lc0 / kTile, lsub = (lc0 % kTile) / SW;
+    // the left band's columns in this band's frame (band 0: the last band, one period back)
+    const int lbase = band == 0 ? c0 + bb.n2 : c0;
+    const int vt0 = -1 + (int)blockIdx.y * bb.seg_tiles;
+    const int vt1 = min(vt0 + bb.seg_tiles, bb.vt_end);
+    const int own_lo = vt0 * kTile;
+    const int own_hi = vt1 == bb.vt_end ? bb.vrow_hi : vt1 * kTile;
+    const int first_row = own_lo - (W - 1);  // the overlap tile row's points from this row on
+    const T cw = T(2) / T(W);
+    // lane q forms tap q of a point (row tap q, and column tap q for the group): with tap
+    // polynomials, its coefficient column in registers for the whole sweep
+    const bool poly = coef != nullptr;
+    T creg[W + 1];
 #pragma unroll
-        for (int b = 0; b < MB; ++b) acc[b] += s[b];
+    for (int k = 0; k <= W; ++k) creg[k] = (poly && q < W) ? coef[k * W + q] : T(0);
+
+    T acc[W][MB];
+#pragma unroll
+    for (int a = 0; a < W; ++a)
+#pragma unroll
+        for (int m = 0; m < MB; ++m) acc[a][m] = T(0);
+    int R = first_row;
+
+    // push row R out (if this segment owns it) and move the register rows up by one
+    auto push_row = [&]() {
+        if (bvalid && R >= own_lo && R < own_hi) {
+            const int pr = R < 0 ? R + bb.n1 : R;
+            T* o = fine + (int64_t)pr * bb.n2 + c0 + q;
+#pragma unroll
+            for (int m = 0; m < MB; ++m) o[m * map_stride] = acc[0][m];
+        }
+#pragma unroll
+        for (int a = 0; a < W - 1; ++a)
+#pragma unroll
+            for (int m = 0; m < MB; ++m) acc[a][m] = acc[a + 1][m];
+#pragma unroll
+        for (int m = 0; m < MB; ++m) acc[W - 1][m] = T(0);
+        ++R;
     };
-    add(tr, tc, rr, cc);
-    if (rr < W - 1) add(trp, tc, rr + kTile, cc);
-    if (cc < W - 1) add(tr, tcp, rr, cc + kTile);
-    if (rr < W - 1 && cc < W - 1) add(trp, tcp, rr + kTile, cc + kTile);
-    const int64_t off = (int64_t)i * n2 + j;
+
+    // the lists of the current tile row: own band [po, eo), left band [pl, el); the first
+    // row opened is the overlap row vt0 - 1
+    int vt = vt0 - 2;
+    int po = 0, eo = 0, pl = 0, el = 0, voff = 0;
+    BandHead<T, MB> ho, hl;
+    ho.r = hl.r = kNoRow;
+    ho.c = hl.c = 0;
+    ho.s1 = ho.s2 = hl.s1 = hl.s2 = T(0);
 #pragma unroll
-    for (int b = 0; b < MB; ++b) fine[b * map_stride + off] = acc[b];
+    for (int m = 0; m < MB; ++m) ho.f[m] = hl.f[m] = T(0);
+    bool live = bvalid;
+    // open tile row vt: list ranges, and in the overlap row the first point that can reach
+    // the segment's rows (rows are sorted along a list: lower bound by bisection)
+    auto open_row = [&]() {
+        const int ptr = ((vt % bb.nt1) + bb.nt1) % bb.nt1;
+        voff = (vt - ptr) * kTile;
+        band_range(bb, ptr, tcol, sub, po, eo);
+        band_range(bb, ptr, ltcol, lsub, pl, el);
+        if (vt < vt0) {
+            int lo = po, hi = eo;
+            while (lo < hi) {
+                const int mid = (lo + hi) >> 1;
+                if (band_row<T, W, MB>(bb, mid, voff) < first_row) lo = mid + 1; else hi = mid;
+            }
+            po = lo;
+            lo = pl;
+            hi = el;
+            while (lo < hi) {
+                const int mid = (lo + hi) >> 1;
+                if (band_row<T, W, MB>(bb, mid, voff) < first_row) lo = mid + 1; else hi = mid;
+            }
+            pl = lo;
+        }
+    };
+    // next head of the own list / of the left list (skipping points whose taps miss the band)
+    auto next_own = [&]() {
+        if (po < eo) {
+            band_decode<T, W, MB>(bb, vals, po, voff, c0, ho);
+            ++po;
+        } else {
+            ho.r = kNoRow;
+        }
+    };
+    auto next_left = [&]() {
+        hl.r = kNoRow;
+        while (pl < el) {
+            band_decode<T, W, MB>(bb, vals, pl, voff, lbase, hl);
+            ++pl;
+            if (hl.c > -W) return;
+            hl.r = kNoRow;
+        }
+    };
+
+    while (__any(live)) {
+        // the next point of this band, moving on to later tile rows as lists run out
+        while (live && ho.r == kNoRow && hl.r == kNoRow) {
+            ++vt;
+            if (vt >= vt1) {
+                live = false;
+                break;
+            }
+            open_row();
+            next_own();
+            next_left();
+        }
+        const bool take_own = live && ho.r <= hl.r;
+        BandHead<T, MB> h = take_own ? ho : hl;
+        const bool has = live && h.r != kNoRow;
+        // push the rows above the point's first row
+        const int target = has ? h.r : R;
+        while (__any(R < target)) {
+            if (R < target) push_row();
+        }
+        // add the point: column tap of this lane, row taps from lanes 0 .. W-1 of the group
+        // (a group without a point adds exact zeros: its head's values are not used)
+        const int b = q - h.c;
+        const bool act = has && b >= 0 && b < W;
+        T p1, p2;
+        if (poly) {
+            // taps q of the point's row and column offsets, then this lane's column tap b
+            // from lane b of the group
+            const T t1 = (has && q < W) ? es_tap_poly<T, W>(h.s1, creg) : T(0);
+            const T t2 = (has && q < W) ? es_tap_poly<T, W>(h.s2, creg) : T(0);
+            const T t2b = __shfl(t2, grp * SW + (act ? b : 0), 64);
+            p1 = t1;
+            p2 = act ? t2b : T(0);
+        } else {
+            // z of tap a = 2 (d - a) / w = (s + w - 1 - 2 a) / w
+            p2 = act ? es_value<T>((h.s2 + T(W - 1 - 2 * b)) * cw * T(0.5), beta) : T(0);
+            p1 = (has && q < W) ? es_value<T>((h.s1 + T(W - 1 - 2 * q)) * cw * T(0.5), beta)
+                                : T(0);
+        }
+        T g[MB];
+#pragma unroll
+        for (int m = 0; m < MB; ++m) g[m] = act ? h.f[m] * p2 : T(0);
+#pragma unroll
+        for (int a = 0; a < W; ++a) {
+            const T pa = __shfl(p1, grp * SW + a, 64);
+#pragma unroll
+            for (int m = 0; m < MB; ++m) acc[a][m] += g[m] * pa;
+        }
+        if (has) {
+            if (take_own) next_own();
+            else next_left();
+        }
+    }
+    // the rows after the last point, up to the end of the segment
+    while (__any(R < own_hi)) {
+        if (R < own_hi) push_row();
+    }
 }
 
 // ---- dispatch over the kernel width ---------------------------------------------------
@@ -517,10 +655,19 @@ inline PointBins make_bins(const nusht_plan_s* p)
 // point scratch (one 32-byte store per point instead of four scattered 8-byte ones), unpacked
 // into out afterwards; a single map writes straight to out.
 
+// the plan's tap polynomials in the kernels' precision, or null (taps from sqrt and exp)
+template <typename T>
+inline const T* es_coef_of(const nusht_plan_s* p);
+template <>
+inline const double* es_coef_of<double>(const nusht_plan_s* p) { return p->es_coef; }
+template <>
+inline const float* es_coef_of<float>(const nusht_plan_s* p) { return p->es_coeff; }
+
 template <typename T>
 int dispatch_interp_impl(const nusht_plan_s* p, const T* fine, double* out, int nmaps, T beta,
                          hipStream_t s)
 {
+    const T* coef = es_coef_of<T>(p);
     if (p->nslots == 0) return NUSHT_OK;
     const PointBins pb = make_bins(p);
     const int64_t ms = (int64_t)p->g.n1 * p->g.n2;
@@ -532,12 +679,12 @@ int dispatch_interp_impl(const nusht_plan_s* p, const T* fine, double* out, int 
         NUSHT_WIDTH_SWITCH(p->g.width, {
             if (mb == 4) {
                 hipLaunchKernelGGL((k_interp<T, WV, 4, true>), dim3(p->nslots), dim3(256), 0, s,
-                                   fine + b * ms, ms, pb, beta, p->V, npts);
+                                   fine + b * ms, ms, pb, beta, coef, p->V, npts);
                 hipLaunchKernelGGL((k_unpack_points<4, sizeof(T) == 4>), dim3(pblocks), dim3(256),
                                    0, s, p->V, p->iperm, npts, out + b * npts);
             } else {
                 hipLaunchKernelGGL((k_interp<T, WV, 1, false>), dim3(p->nslots), dim3(256), 0,
-                                   s, fine + b * ms, ms, pb, beta, out + b * npts, npts);
+                                   s, fine + b * ms, ms, pb, beta, coef, out + b * npts, npts);
             }
         });
         NUSHT_HIP(hipGetLastError());
@@ -546,16 +693,36 @@ int dispatch_interp_impl(const nusht_plan_s* p, const T* fine, double* out, int 
     return NUSHT_OK;
 }
 
-// Spreading of the caller's maps [b, b + mb) (`vals` = its map block [mb][npts]) into the
-// slot subgrids: the values are first packed [point][mb] in the caller's order into the
-// plan's point scratch, and the spreading kernel fetches a point's mb values with one load
-// through the permutation.
+inline BandBins make_band_bins(const nusht_plan_s* p)
+{
+    BandBins bb;
+    bb.sth = p->sth;
+    bb.sph = p->sph;
+    bb.perm = p->perm;
+    bb.band_off = p->band_off;
+    bb.tile_slot = p->tile_slot;
+    bb.nt1 = p->nt1;
+    bb.nt2 = p->nt2;
+    bb.n1 = p->g.n1;
+    bb.n2 = p->g.n2;
+    bb.nsub = p->nsub;
+    bb.nbands = p->g.n2 / p->band_w;
+    bb.s1 = p->g.n1 / (2.0 * M_PI);
+    bb.s2 = p->g.n2 / (2.0 * M_PI);
+    bb.vt_end = p->band_vt_end;
+    bb.vrow_hi = p->band_vrow_hi;
+    bb.seg_tiles = p->band_seg_tiles;
+    return bb;
+}
+
+// Spreading of the caller's maps [b, b + mb) (`vals` = its map block [mb][npts]) straight onto
+// the fine grids of those maps: the values are first packed [point][mb] in the caller's order
+// into the plan's point scratch, so that the band kernel fetches a point's mb values with one
+// load through the permutation.
 template <typename T>
-int spread_group_impl(const nusht_plan_s* p, const double* vals, T* sub, int mb, T beta,
+int spread_group_impl(const nusht_plan_s* p, const double* vals, T* fine, int mb, T beta,
                       hipStream_t s)
 {
-    if (p->nslots == 0) return NUSHT_OK;
-    const PointBins pb = make_bins(p);
     const int64_t npts = p->g.npts;
     const unsigned pblocks = (unsigned)((npts + 255) / 256);
     T* packed = reinterpret_cast<T*>(p->V);
@@ -566,33 +733,20 @@ int spread_group_impl(const nusht_plan_s* p, const double* vals, T* sub, int mb,
         hipLaunchKernelGGL((k_pack_values<T, 1>), dim3(pblocks), dim3(256), 0, s, vals, npts,
                            packed);
     NUSHT_HIP(hipGetLastError());
-    NUSHT_WIDTH_SWITCH(p->g.width, {
-        if (mb == 4)
-            hipLaunchKernelGGL((k_spread_lds<T, WV, 4>), dim3(p->nslots), dim3(256), 0, s,
-                               packed, pb, beta, sub);
-        else
-            hipLaunchKernelGGL((k_spread_lds<T, WV, 1>), dim3(p->nslots), dim3(256), 0, s,
-                               packed, pb, beta, sub);
-    });
-    NUSHT_HIP(hipGetLastError());
-    return NUSHT_OK;
-}
-
-// halo reduction of the slot subgrids into fine maps [b, b + mb)
-template <typename T>
-int halo_group_impl(const nusht_plan_s* p, const T* sub, T* fine, int b, int mb, hipStream_t s)
-{
+    const BandBins bb = make_band_bins(p);
+    const T* coef = es_coef_of<T>(p);
     const int64_t ms = (int64_t)p->g.n1 * p->g.n2;
-    dim3 hgrid((p->g.n2 + 255) / 256, p->fine_ra + p->fine_rb);
+    const int K = 64 / p->band_w;
+    const dim3 grid((unsigned)((bb.nbands + 4 * K - 1) / (4 * K)),
+                    (unsigned)((bb.vt_end + 1 + bb.seg_tiles - 1) / bb.seg_tiles));
     NUSHT_WIDTH_SWITCH(p->g.width, {
+        constexpr int SWV = WV <= 8 ? 8 : 16;
         if (mb == 4)
-            hipLaunchKernelGGL((k_halo<T, WV, 4>), hgrid, dim3(256), 0, s, sub, p->tile_slot,
-                               p->nt1, p->nt2, p->g.n1, p->g.n2, p->fine_ra, p->fine_rb,
-                               fine + b * ms, ms);
+            hipLaunchKernelGGL((k_spread_band<T, WV, 4, SWV>), grid, dim3(256), 0, s, packed, bb,
+                               beta, coef, fine, ms);
         else
-            hipLaunchKernelGGL((k_halo<T, WV, 1>), hgrid, dim3(256), 0, s, sub, p->tile_slot,
-                               p->nt1, p->nt2, p->g.n1, p->g.n2, p->fine_ra, p->fine_rb,
-                               fine + b * ms, ms);
+            hipLaunchKernelGGL((k_spread_band<T, WV, 1, SWV>), grid, dim3(256), 0, s, packed, bb,
+                               beta, coef, fine, ms);
     });
     NUSHT_HIP(hipGetLastError());
     return NUSHT_OK;

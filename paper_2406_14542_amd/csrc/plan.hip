@@ -78,6 +78,72 @@ void es_fourier(double beta, double alpha, int kmax, std::vector<double>& out)
     }
 }
 
+// ES kernel taps as polynomials.  With t the coordinate in grid units and ls = ceil(t - w/2)
+// the first tap, the offset d = t - ls lies in (w/2 - 1, w/2]; tap a has the value
+// psi(2 (d - a) / w).  For every tap the value is fitted by a polynomial of degree w in
+// s = 2 d - w + 1 in [-1, 1] (interpolation at w + 1 Chebyshev points, long double), so the
+// kernels form all taps of a point with w Horner steps instead of a square root and an
+// exponential per tap.  coef[k * w + a] holds the coefficient of s^k for tap a.  Returns the
+// largest deviation from psi on a fine grid of s.
+long double es_psi(long double z, long double beta)
+{
+    const long double q = (1.0L - z) * (1.0L + z);
+    return q > 0.0L ? expl(beta * (sqrtl(q) - 1.0L)) : 0.0L;
+}
+
+double es_poly_fit(int w, double beta, std::vector<double>& coef)
+{
+    const int D = w, n = D + 1;
+    coef.assign((size_t)n * w, 0.0);
+    std::vector<long double> s(n), A((size_t)n * n), y(n);
+    for (int k = 0; k < n; ++k)
+        s[k] = cosl(3.14159265358979323846264338327950288L * (k + 0.5L) / n);
+    long double worst = 0.0L;
+    for (int a = 0; a < w; ++a) {
+        // Vandermonde system V c = psi at the nodes, Gaussian elimination with pivoting
+        for (int i = 0; i < n; ++i) {
+            long double pw = 1.0L;
+            for (int k = 0; k < n; ++k) {
+                A[(size_t)i * n + k] = pw;
+                pw *= s[i];
+            }
+            const long double d = 0.5L * (s[i] + (long double)w - 1.0L);
+            y[i] = es_psi(2.0L * (d - a) / w, beta);
+        }
+        for (int c = 0; c < n; ++c) {
+            int piv = c;
+            for (int i = c + 1; i < n; ++i)
+                if (fabsl(A[(size_t)i * n + c]) > fabsl(A[(size_t)piv * n + c])) piv = i;
+            if (piv != c) {
+                for (int k = 0; k < n; ++k) std::swap(A[(size_t)c * n + k], A[(size_t)piv * n + k]);
+                std::swap(y[c], y[piv]);
+            }
+            for (int i = c + 1; i < n; ++i) {
+                const long double f = A[(size_t)i * n + c] / A[(size_t)c * n + c];
+                for (int k = c; k < n; ++k) A[(size_t)i * n + k] -= f * A[(size_t)c * n + k];
+                y[i] -= f * y[c];
+            }
+        }
+        std::vector<long double> cc(n);
+        for (int i = n - 1; i >= 0; --i) {
+            long double v = y[i];
+            for (int k = i + 1; k < n; ++k) v -= A[(size_t)i * n + k] * cc[k];
+            cc[i] = v / A[(size_t)i * n + i];
+        }
+        for (int k = 0; k < n; ++k) coef[(size_t)k * w + a] = (double)cc[k];
+        // deviation of the rounded coefficients on a fine grid
+        for (int j = 0; j <= 2000; ++j) {
+            const long double sj = -1.0L + j / 1000.0L;
+            long double pv = 0.0L;
+            for (int k = n - 1; k >= 0; --k) pv = pv * sj + (long double)coef[(size_t)k * w + a];
+            const long double d = 0.5L * (sj + (long double)w - 1.0L);
+            const long double e = fabsl(pv - es_psi(2.0L * (d - a) / w, beta));
+            if (e > worst) worst = e;
+        }
+    }
+    return (double)worst;
+}
+
 template <typename T>
 int dmalloc(T** p, size_t n)
 {
@@ -96,7 +162,7 @@ int dmalloc(T** p, size_t n)
 
 __global__ void k_bin_keys(const double* __restrict__ theta, const double* __restrict__ phi,
                            int64_t n, int w, double s1, double s2, int n1, int n2, int nt2,
-                           double* __restrict__ phw, int* __restrict__ keys,
+                           int bw, double* __restrict__ phw, int* __restrict__ keys,
                            int* __restrict__ idx, int* __restrict__ flag)
 {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -116,8 +182,11 @@ __global__ void k_bin_keys(const double* __restrict__ theta, const double* __res
     double d;
     const int l1 = wrap_index(first_tap(thc, s1, w, d), n1);
     const int l2 = wrap_index(first_tap(ph, s2, w, d), n2);
-    // tile id, then the row inside the tile: the spreading kernel walks a tile's points by row
-    keys[i] = ((l1 / kTile) * nt2 + (l2 / kTile)) * kTile + (l1 % kTile);
+    // tile id, then the column band inside the tile, then the row inside the tile: the
+    // spreading kernel walks a band's points by row
+    const int nsub = kTile / bw;
+    keys[i] = (((l1 / kTile) * nt2 + (l2 / kTile)) * nsub + (l2 % kTile) / bw) * kTile +
+              (l1 % kTile);
     idx[i] = (int)i;
     phw[i] = ph;
 }
@@ -134,26 +203,50 @@ __global__ void k_gather_sorted(const double* __restrict__ theta, const double* 
     iperm[i] = (int)k;
 }
 
-__global__ void k_mark(const int* __restrict__ keys, int64_t n, int* __restrict__ first)
+// tile of a sorted key (keys hold tile, band, row)
+__device__ inline int key_tile(int key, int nsub) { return key / (kTile * nsub); }
+
+__global__ void k_mark(const int* __restrict__ keys, int64_t n, int nsub, int* __restrict__ first)
 {
     const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (k >= n) return;
-    first[k] = (k == 0 || (keys[k] / kTile) != (keys[k - 1] / kTile)) ? 1 : 0;
+    first[k] = (k == 0 || key_tile(keys[k], nsub) != key_tile(keys[k - 1], nsub)) ? 1 : 0;
 }
 
 __global__ void k_slots(const int* __restrict__ keys, const int* __restrict__ first,
-                        const int* __restrict__ slotidx, int64_t n, int* __restrict__ slot_off,
-                        int* __restrict__ slot_tile, int* __restrict__ tile_slot)
+                        const int* __restrict__ slotidx, int64_t n, int nsub,
+                        int* __restrict__ slot_off, int* __restrict__ slot_tile,
+                        int* __restrict__ tile_slot)
 {
     const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (k >= n) return;
     if (first[k]) {
         const int s = slotidx[k];
-        const int t = keys[k] / kTile;
+        const int t = key_tile(keys[k], nsub);
         slot_off[s] = (int)k;
         slot_tile[s] = t;
         tile_slot[t] = s;
     }
+}
+
+// band_off[g] = first sorted point of band group g = slot * nsub + band.  A point that starts
+// a group (or follows a run of empty groups) writes the start of every group from the one
+// after its predecessor's up to its own; the last point closes the remaining groups.
+__global__ void k_band_off(const int* __restrict__ keys, const int* __restrict__ first,
+                           const int* __restrict__ slotidx, int64_t n, int nsub, int ngroups,
+                           int* __restrict__ band_off)
+{
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= n) return;
+    auto group = [&](int64_t i) {
+        const int slot = slotidx[i] + first[i] - 1;
+        return slot * nsub + (keys[i] / kTile) % nsub;
+    };
+    const int g = group(k);
+    const int gp = k == 0 ? -1 : group(k - 1);
+    for (int h = gp + 1; h <= g; ++h) band_off[h] = (int)k;
+    if (k == n - 1)
+        for (int h = g + 1; h <= ngroups; ++h) band_off[h] = (int)n;
 }
 
 __global__ void k_fill_int(int* p, int64_t n, int v)
@@ -206,6 +299,10 @@ int compute_geometry(int lmax, int mmax, double eps, int dtype, const nusht_plan
         set_last_error("geometry", "unknown dfs_mode");
         return NUSHT_EINVAL;
     }
+    if (opts && opts->kernel_eval != NUSHT_KERNEL_POLY && opts->kernel_eval != NUSHT_KERNEL_EXACT) {
+        set_last_error("geometry", "unknown kernel_eval");
+        return NUSHT_EINVAL;
+    }
     if (width == 0) {
         // ES kernel: error ~ exp(-pi w sqrt(1 - 1/sigma)); one extra cell of margin
         width = (int)std::ceil(std::log(1.0 / eps) / (M_PI * std::sqrt(1.0 - 1.0 / sigma))) + 1;
@@ -255,11 +352,8 @@ size_t fine_elem_bytes(const nusht_plan_s* p)
     return p->g.dtype == NUSHT_MIXED ? sizeof(float) : sizeof(double);
 }
 
-// Scratch for up to `nmaps` maps.  X and Y each hold the largest per-map intermediate of
-// either mode times the batch; Z holds the spreading subgrids of every group of maps.  The
-// group count point_groups(k) is not monotone in k (4 maps make one group, 3 make three), so Z
-// is sized for the largest count of any batch up to nmaps: every batch the plan accepts
-// without growing fits.
+// Scratch for up to `nmaps` maps: X and Y each hold the largest per-map intermediate of
+// either mode times the batch.
 int ensure_capacity(nusht_plan_s* p, int nmaps)
 {
     if (nmaps <= p->bcap) return NUSHT_OK;
@@ -274,21 +368,14 @@ int ensure_capacity(nusht_plan_s* p, int nmaps)
     const size_t gfused = (size_t)(g.mmax + 1) * g.ntorus * 2 * 8;  // doubled columns, <= c128
     size_t per = fine_real;
     for (size_t v : {fine_spec, gpaper, ring, torus, tspec, gfused}) per = v > per ? v : per;
-    int groups = 0;
-    for (int k = 1; k <= nmaps; ++k) groups = std::max(groups, point_groups(k));
-    const int P = kTile + g.width - 1;
-    const size_t zbytes = (size_t)groups * p->nslots * P * P * 4 * e;
     NUSHT_HIP(hipDeviceSynchronize());
     if (p->X) hipFree(p->X);
     if (p->Y) hipFree(p->Y);
-    if (p->Z) hipFree(p->Z);
-    p->X = p->Y = p->Z = nullptr;
+    p->X = p->Y = nullptr;
     p->bcap = 0;
     NUSHT_TRY(dmalloc((char**)&p->X, per * nmaps));
     NUSHT_TRY(dmalloc((char**)&p->Y, per * nmaps));
-    NUSHT_TRY(dmalloc((char**)&p->Z, zbytes > 0 ? zbytes : 256));
     p->Xbytes = p->Ybytes = per * nmaps;
-    p->Zbytes = zbytes;
     if (!p->W) {
         NUSHT_TRY(dmalloc((char**)&p->W, fine_spec));
         p->Wbytes = fine_spec;
@@ -311,9 +398,12 @@ int bin_points(nusht_plan_s* p, const double* theta, const double* phi, hipStrea
     int rc = NUSHT_OK;
     size_t tbytes = 0, t2 = 0;
     const int blocks = (int)((n + 255) / 256);
+    p->band_w = band_width_for(g.width);
+    p->nsub = kTile / p->band_w;
+    const int nsub = p->nsub;
     int bits = 1;
-    while ((1LL << bits) < ntiles * kTile) ++bits;
-    if (ntiles * kTile >= (1LL << 31)) {
+    while ((1LL << bits) < ntiles * kTile * nsub) ++bits;
+    if (ntiles * kTile * nsub >= (1LL << 31)) {
         set_last_error("nusht_plan", "fine grid too large for 32-bit bin keys");
         return NUSHT_EINVAL;
     }
@@ -328,8 +418,8 @@ int bin_points(nusht_plan_s* p, const double* theta, const double* phi, hipStrea
         if (hipMemsetAsync(p->dflag, 0, sizeof(int), s) != hipSuccess ||
             hipMemsetAsync(p->dstatus, 0, sizeof(int), s) != hipSuccess) { rc = NUSHT_EDEVICE; break; }
         hipLaunchKernelGGL(k_bin_keys, dim3(blocks), dim3(256), 0, s, theta, phi, n, g.width,
-                           g.n1 / (2.0 * M_PI), g.n2 / (2.0 * M_PI), g.n1, g.n2, p->nt2, phw,
-                           keys, idx, p->dflag);
+                           g.n1 / (2.0 * M_PI), g.n2 / (2.0 * M_PI), g.n1, g.n2, p->nt2,
+                           p->band_w, phw, keys, idx, p->dflag);
         if (hipcub::DeviceRadixSort::SortPairs(nullptr, tbytes, keys, keys_s, idx, p->perm,
                                                (int)n, 0, bits, s) != hipSuccess) { rc = NUSHT_EDEVICE; break; }
         if (hipcub::DeviceScan::ExclusiveSum(nullptr, t2, first, sidx, (int)n, s) != hipSuccess) { rc = NUSHT_EDEVICE; break; }
@@ -339,7 +429,7 @@ int bin_points(nusht_plan_s* p, const double* theta, const double* phi, hipStrea
                                                bits, s) != hipSuccess) { rc = NUSHT_EDEVICE; break; }
         hipLaunchKernelGGL(k_gather_sorted, dim3(blocks), dim3(256), 0, s, theta, phw, p->perm, n,
                            p->sth, p->sph, p->iperm);
-        hipLaunchKernelGGL(k_mark, dim3(blocks), dim3(256), 0, s, keys_s, n, first);
+        hipLaunchKernelGGL(k_mark, dim3(blocks), dim3(256), 0, s, keys_s, n, nsub, first);
         if (hipcub::DeviceScan::ExclusiveSum(tmp, tbytes, first, sidx, (int)n, s) != hipSuccess) { rc = NUSHT_EDEVICE; break; }
         int last_first = 0, last_idx = 0, flag = 0;
         if (hipMemcpyAsync(&last_first, first + n - 1, sizeof(int), hipMemcpyDeviceToHost, s) != hipSuccess ||
@@ -352,11 +442,16 @@ int bin_points(nusht_plan_s* p, const double* theta, const double* phi, hipStrea
             break;
         }
         p->nslots = last_idx + last_first;
-        if ((rc = dmalloc(&p->slot_off, p->nslots + 1)) || (rc = dmalloc(&p->slot_tile, p->nslots))) break;
+        const int ngroups = p->nslots * nsub;
+        if ((rc = dmalloc(&p->slot_off, p->nslots + 1)) || (rc = dmalloc(&p->slot_tile, p->nslots)) ||
+            (rc = dmalloc(&p->band_off, ngroups + 1)))
+            break;
         hipLaunchKernelGGL(k_fill_int, dim3((int)((ntiles + 255) / 256)), dim3(256), 0, s,
                            p->tile_slot, ntiles, -1);
-        hipLaunchKernelGGL(k_slots, dim3(blocks), dim3(256), 0, s, keys_s, first, sidx, n,
+        hipLaunchKernelGGL(k_slots, dim3(blocks), dim3(256), 0, s, keys_s, first, sidx, n, nsub,
                            p->slot_off, p->slot_tile, p->tile_slot);
+        hipLaunchKernelGGL(k_band_off, dim3(blocks), dim3(256), 0, s, keys_s, first, sidx, n,
+                           nsub, ngroups, p->band_off);
         const int nn = (int)n;
         if (hipMemcpyAsync(p->slot_off + p->nslots, &nn, sizeof(int), hipMemcpyHostToDevice, s) != hipSuccess ||
             hipStreamSynchronize(s) != hipSuccess) { rc = NUSHT_EDEVICE; break; }
@@ -522,6 +617,24 @@ static int build_tables(nusht_plan_s* p)
         d2[k] = 2.0 / (g.width * i2[k]);
         d2f[k] = (float)d2[k];
     }
+    // tap polynomials, used when their deviation stays well below eps (and, for FP32 taps,
+    // above the FP32 rounding of their coefficients); otherwise the kernels form each tap
+    // from its square root and exponential
+    {
+        std::vector<double> coef;
+        const double dev = es_poly_fit(g.width, g.beta, coef);
+        const double tol = g.dtype == NUSHT_MIXED ? std::max(0.05 * p->eps, 1e-7) : 0.05 * p->eps;
+        p->es_poly_dev = dev;
+        if (p->es_eval == 0 && dev <= tol) {
+            std::vector<float> coeff(coef.begin(), coef.end());
+            NUSHT_TRY(dmalloc(&p->es_coef, coef.size()));
+            NUSHT_TRY(dmalloc(&p->es_coeff, coeff.size()));
+            NUSHT_HIP(hipMemcpy(p->es_coef, coef.data(), coef.size() * sizeof(double),
+                                hipMemcpyHostToDevice));
+            NUSHT_HIP(hipMemcpy(p->es_coeff, coeff.data(), coeff.size() * sizeof(float),
+                                hipMemcpyHostToDevice));
+        }
+    }
     NUSHT_TRY(dmalloc(&p->rec, (size_t)g.nalm + kRecPad));
     NUSHT_TRY(dmalloc(&p->cm_mant, M + 1));
     NUSHT_TRY(dmalloc(&p->cm_exp, M + 1));
@@ -614,9 +727,9 @@ void nusht_destroy(nusht_plan_t p)
     void* bufs[] = {p->rec,  p->cm_mant, p->cm_exp,   p->dec1,      p->dec2,      p->dec1f,
                     p->dec2f, p->sth,    p->sph,      p->perm,      p->iperm,     p->V,
                     p->slot_off,  p->slot_tile,
-                    p->tile_slot, p->dflag, p->dstatus, p->X,     p->Y,         p->Z,         p->W,
+                    p->tile_slot, p->band_off, p->dflag, p->dstatus, p->X,     p->Y,         p->W,
                     p->fftwork,   p->rowtw,
-                    p->red,      p->jlive,  p->jscale};
+                    p->red,      p->jlive,  p->jscale, p->adj_part, p->es_coef, p->es_coeff};
     for (void* b : bufs)
         if (b) hipFree(b);
     for (int c = 0; c < nusht_plan_s::kTimingSlots; ++c)
@@ -650,6 +763,8 @@ int nusht_plan_ex(int lmax, int mmax, int64_t npts, const double* theta, const d
     do {
         if (hipGetDevice(&p->device) != hipSuccess) { rc = NUSHT_EDEVICE; break; }
         p->timing = opts ? opts->timing : 0;
+        p->deterministic = opts ? (opts->deterministic != 0) : 0;
+        p->es_eval = opts ? opts->kernel_eval : 0;
         if ((rc = build_tables(p))) break;
         if ((rc = bin_points(p, theta, phi, s))) break;
         p->g.ntiles_used = p->nslots;
@@ -684,6 +799,8 @@ int nusht_plan_info(nusht_plan_t p, nusht_geometry* out)
 {
     if (!p || !out) return NUSHT_EINVAL;
     *out = p->g;
+    out->kernel_eval = p->es_coef ? NUSHT_KERNEL_POLY : NUSHT_KERNEL_EXACT;
+    out->kernel_poly_dev = p->es_poly_dev;
     return NUSHT_OK;
 }
 

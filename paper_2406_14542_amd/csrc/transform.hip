@@ -2,6 +2,7 @@
 // (Eq. 6) of arXiv:2406.14542 on one HIP stream, with rocFFT for the uniform FFTs.
 // Everything is enqueued asynchronously; intermediates live in two ping-pong scratch
 // regions X and Y (and Z for the spreading subgrids) that the plan owns.
+#include <algorithm>
 #include <cmath>
 #include <cstring>
 #include <mutex>
@@ -13,14 +14,10 @@ namespace nusht {
 
 int interp_f64(const nusht_plan_s* p, const double* fine, double* out, int nmaps, hipStream_t s);
 int interp_f32(const nusht_plan_s* p, const float* fine, double* out, int nmaps, hipStream_t s);
-int spread_group_f64(const nusht_plan_s* p, const double* vals, double* sub, int mb,
+int spread_group_f64(const nusht_plan_s* p, const double* vals, double* fine, int mb,
                      hipStream_t s);
-int spread_group_f32(const nusht_plan_s* p, const double* vals, float* sub, int mb,
+int spread_group_f32(const nusht_plan_s* p, const double* vals, float* fine, int mb,
                      hipStream_t s);
-int halo_group_f64(const nusht_plan_s* p, const double* sub, double* fine, int b, int mb,
-                   hipStream_t s);
-int halo_group_f32(const nusht_plan_s* p, const float* sub, float* fine, int b, int mb,
-                   hipStream_t s);
 
 namespace {
 
@@ -116,6 +113,21 @@ int create_fft_plans(nusht_plan_s* p)
         }
         p->fine_ra = ra;
         p->fine_rb = rb;
+        // the spreading sweep: virtual tile rows [-1, vt_end) hold points, virtual rows
+        // [-kTile, vrow_hi) are written (rb > 0: tile rows 0 .. ra/kTile - 1 and the w - 1 rows
+        // after them; every row otherwise); segments sized for about 8192 waves
+        const int nt1 = g.n1 / kTile;
+        if (rb > 0) {
+            p->band_vt_end = last_tap / kTile + 1;
+            p->band_vrow_hi = ra;
+        } else {
+            p->band_vt_end = nt1 - 1;
+            p->band_vrow_hi = g.n1 - kTile;
+        }
+        const long waves_per_row = (long)(g.n2 / p->band_w) / (64 / p->band_w);
+        const long rows = p->band_vt_end + 1;
+        long seg = waves_per_row * rows / 8192;
+        p->band_seg_tiles = (int)std::max(1L, std::min(16L, seg));
     }
     const size_t fw = (size_t)g.n2 / 2 + 1;
     const size_t ncol = (size_t)g.mmax + 1;
@@ -464,37 +476,18 @@ int nusht_adjoint(nusht_plan_t p, const double* map, double* alm, int nmaps, voi
     const nusht_geometry& g = p->g;
     const int f32 = g.dtype == NUSHT_MIXED;
     const size_t e = fine_elem_bytes(p);
-    const int P = kTile + g.width - 1;
-    const size_t zgroup = (size_t)p->nslots * P * P * 4 * e;
-    // N^H (i): spreading into per-slot subgrids, then the halo reduction onto the fine grid
-    if ((size_t)point_groups(nmaps) * zgroup > p->Zbytes) {
-        set_last_error("nusht_adjoint", "spreading scratch too small for this batch");
-        return NUSHT_EINVAL;
-    }
+    // N^H (i): spreading of each group of maps straight onto their fine grids (window rows)
     stage_begin(p, ST_POINTS, s);
-    for (int b = 0, grp = 0; b < nmaps; ++grp) {
+    for (int b = 0; b < nmaps;) {
         const int mb = group_width(nmaps, b);
-        void* sub = bytes(p->Z) + grp * zgroup;
+        char* fine = bytes(p->X) + b * fine_real_bytes(p);
         if (f32)
-            NUSHT_TRY(spread_group_f32(p, map + b * g.npts, reinterpret_cast<float*>(sub), mb, s));
+            NUSHT_TRY(spread_group_f32(p, map + b * g.npts, reinterpret_cast<float*>(fine), mb, s));
         else
-            NUSHT_TRY(spread_group_f64(p, map + b * g.npts, reinterpret_cast<double*>(sub), mb, s));
+            NUSHT_TRY(spread_group_f64(p, map + b * g.npts, reinterpret_cast<double*>(fine), mb, s));
         b += mb;
     }
     stage_end(p, ST_POINTS, s);
-    stage_begin(p, ST_HALO, s);
-    for (int b = 0, grp = 0; b < nmaps; ++grp) {
-        const int mb = group_width(nmaps, b);
-        const void* sub = bytes(p->Z) + grp * zgroup;
-        if (f32)
-            NUSHT_TRY(halo_group_f32(p, reinterpret_cast<const float*>(sub),
-                                     reinterpret_cast<float*>(p->X), b, mb, s));
-        else
-            NUSHT_TRY(halo_group_f64(p, reinterpret_cast<const double*>(sub),
-                                     reinterpret_cast<double*>(p->X), b, mb, s));
-        b += mb;
-    }
-    stage_end(p, ST_HALO, s);
     // N^H (ii): fine-grid R2C
     stage_begin(p, ST_FINE_FFT, s);
     for (int b = 0; b < nmaps; ++b)
@@ -576,7 +569,7 @@ int nusht_ring_adjoint(nusht_plan_t p, const double* ring, double* alm, int nmap
 }
 
 static const char* kStageNames[ST_COUNT] = {"legendre", "ring_fft", "double_fold", "torus_fft",
-                                            "deconv", "fine_fft", "points", "halo"};
+                                            "deconv", "fine_fft", "points"};
 
 int nusht_stage_times(nusht_plan_t p, double* ms, const char** names, int maxn)
 {

@@ -49,6 +49,25 @@ def red_alm(rng: np.random.Generator, lmax: int, mmax: int, nmaps: int = 1) -> n
     return out
 
 
+def potential_alm(rng: np.random.Generator, lmax: int, mmax: int, rms_arcmin: float) -> np.ndarray:
+    """A lensing-potential-like field Phi_lm [1, nalm]: C_l proportional to l^-4 for l >= 2
+    (0 below), scaled so that the rms of the gradient (the deflection) over the sphere is
+    rms_arcmin: sum_l (2l+1)/(4 pi) l (l+1) C_l = rms^2.  Real-field convention as red_alm."""
+    ls, ms = ell_of_index(lmax, mmax)
+    ell = np.arange(lmax + 1, dtype=np.float64)
+    cl = np.zeros(lmax + 1)
+    cl[2:] = ell[2:] ** -4.0
+    # mean over the sphere of |grad Phi|^2 for a statistically isotropic field
+    power = np.sum((2 * ell + 1) / (4 * np.pi) * ell * (ell + 1) * cl)
+    cl *= (rms_arcmin * ARCMIN) ** 2 / power
+    out = np.empty((1, ls.size), dtype=np.complex128)
+    c = cl[ls]
+    re = rng.standard_normal(ls.size)
+    im = rng.standard_normal(ls.size)
+    out[0] = np.where(ms == 0, np.sqrt(c) * re, np.sqrt(c / 2) * (re + 1j * im))
+    return out
+
+
 def uniform_points(rng: np.random.Generator, n: int) -> tuple[np.ndarray, np.ndarray]:
     z = rng.uniform(-1.0, 1.0, n)
     phi = rng.uniform(0.0, 2.0 * np.pi, n)

@@ -89,6 +89,16 @@ def test_c2_full_size(P, oracle_mod):
     print(f"  adjoint on m = {ms}: {e:.2e} (per column {', '.join(f'{x:.1e}' for x in per)})",
           flush=True)
     assert e <= eps and max(per) <= 10 * eps
+    # a deterministic plan: identical bits on a second call, the same columns
+    pld = P.Plan(L, L, dev(th), dev(ph), eps, deterministic=True)
+    cd = pld.adjoint(dev(cfg["d"])).cpu().numpy()
+    cd2 = pld.adjoint(dev(cfg["d"])).cpu().numpy()
+    assert np.array_equal(cd.view(np.float64), cd2.view(np.float64))
+    ed = col_err(columns(cd, L, ms)[0], g["cols"][0], ms)
+    print(f"  deterministic adjoint on the same columns: {ed:.2e}", flush=True)
+    assert ed <= eps
+    pld.close()
+    del cd, cd2
     # <S a, S a> = <S^H S a, a>_m
     shf = pl.adjoint(dev(f)).cpu().numpy()
     lhs = float(np.dot(f[0], f[0]))
@@ -144,3 +154,13 @@ def test_c3_full_size(P):
     e = rel(res["mixed"], res["f64"])
     print(f"  mixed vs FP64 synthesis over all points: {e:.2e}", flush=True)
     assert e <= 1e-5
+    # the benchmark's mixed plan built deterministic: identical bits on a second call
+    pld = P.Plan(L, L, thd, phd, cfg["eps"], dtype="mixed", deterministic=True)
+    cd = pld.adjoint(d).cpu().numpy()
+    cd2 = pld.adjoint(d).cpu().numpy()
+    assert np.array_equal(cd.view(np.float64), cd2.view(np.float64))
+    got = columns(cd, L, ms)
+    ed = max(col_err(got[b], ga["cols"][b], ms) for b in range(4))
+    print(f"  mixed deterministic adjoint vs oracle columns: {ed:.2e}", flush=True)
+    assert ed <= 1e-5
+    pld.status()
