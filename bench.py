@@ -61,11 +61,11 @@ def step_stats(times):
             "std5_s": float(five.std(ddof=1)) if five.size > 1 else 0.0}
 
 
-def run_precision(P, torch, cfg, eps, dtype, steps, warmup, alm, d):
+def run_precision(P, torch, cfg, eps, dtype, steps, warmup, alm, d, sigma=0.0):
     th = torch.from_numpy(cfg["theta"]).cuda()
     ph = torch.from_numpy(cfg["phi"]).cuda()
     t0 = time.perf_counter()
-    plan = P.Plan(cfg["lmax"], cfg["mmax"], th, ph, eps, dtype=dtype, timing=True)
+    plan = P.Plan(cfg["lmax"], cfg["mmax"], th, ph, eps, dtype=dtype, timing=True, sigma=sigma)
     torch.cuda.synchronize()
     plan_s = time.perf_counter() - t0
     del th, ph
@@ -165,11 +165,18 @@ def golden_adjoint_error(c, lmax, path):
 def run_cg(args):
     """Learned-preconditioner leg (`--cg`): CGLS iterations to ||S a - d|| / ||d|| <= tol on
     holey point sets (lmax = mmax, N = 1.5 (lmax+1)^2 points with density
-    (1 + 0.8 cos^2 theta) and 20 Gaussian holes of 5 degrees, d = S a_true), plain CGLS from
-    zero vs CGLS on W^(1/2) S from S^H W d with the network's weights.  The network is
-    trained on the GPU by the library's kernels on `--cg-train` seeded sets whose targets a*
-    are the method's own plain solves (after at most `--cg-maxiter` iterations), then
-    evaluated on `--cg-test` held-out sets.  Prints ONE JSON line."""
+    (1 + 0.8 cos^2 theta) and 20 Gaussian holes of 5 degrees, d = S a_true).
+
+    `--cg-phase train`: the network is trained on the GPU by the library's kernels on the
+    seeded sets 1000 .. 1000 + cg-train - 1, streamed: every new set is planned, its target a*
+    is the method's own plain CGLS solve (at most `--cg-target-iters` iterations), and it joins
+    a replay buffer of the last `--cg-buffer` sets; after each new set `--cg-steps-per-set`
+    Adam steps run on `--cg-batch` sets drawn from the buffer.  The parameters and Adam state
+    are saved to `--cg-save`.
+    `--cg-phase eval`: the network loaded from `--cg-load` is evaluated on the held-out sets
+    1160 .. 1160 + cg-test - 1: plain CGLS from zero, CGLS on W^(1/2) S from S^H W d with the
+    network's weights, and the same with the analytic weights (4 pi / N) / rho^ (the coarse
+    density map at the point), each to `--cg-maxiter` iterations.  Prints ONE JSON line."""
     import torch
     import paper_2406_14542_amd as P
     from paper_2406_14542_amd import inputs
@@ -177,7 +184,7 @@ def run_cg(args):
 
     P.lib()
     L = args.cg_lmax
-    tol, maxit = args.cg_tol, args.cg_maxiter
+    tol = args.cg_tol
     marks = [1e-2, 1e-3, 1e-4, 1e-5, 1e-6, 1e-8]
 
     def first_below(hist, t):
@@ -188,70 +195,102 @@ def run_cg(args):
         cfg = inputs.config_c5(seed, lmax=L)
         th = torch.from_numpy(cfg["theta"]).cuda()
         ph = torch.from_numpy(cfg["phi"]).cuda()
-        pl = P.Plan(L, L, th, ph, 1e-12)
+        pl = P.Plan(L, L, th, ph, args.cg_eps)
         d = pl.synthesis(torch.from_numpy(cfg["alm"]).cuda())
-        return dict(plan=pl, theta=th, phi=ph, d=d)
+        return dict(plan=pl, theta=th, phi=ph, d=d, seed=seed)
 
-    lw = LearnedWeights(64, 128, seed=args.cg_seed)
-    t0 = time.perf_counter()
-    train = []
-    for s in range(args.cg_train):
-        ex = make(1000 + s)
-        ex["features"] = lw.features(ex["theta"], ex["phi"])
-        a, it, rr, st = ex["plan"].solve(ex["d"], tol=tol, maxiter=maxit, check=False)
-        ex["astar"] = a
-        log(f"train set {1000 + s}: plain CGLS {it} iterations, residual {rr:.3e}")
-        train.append(ex)
-    t_targets = time.perf_counter() - t0
-    t0 = time.perf_counter()
-    def train_log(step, total):
-        if step == 1 or step % 10 == 0:
-            log(f"training step {step}: loss {total / len(train):.4f} "
-                f"({time.perf_counter() - t0:.1f} s)")
+    workload = (f"holey point sets: lmax=mmax={L}, N={int(1.5 * (L + 1) ** 2)}, 20 holes of "
+                f"5 deg, density 1 + 0.8 cos^2 theta")
+    if args.cg_phase == "train":
+        lw = LearnedWeights(64, 128, seed=args.cg_seed)
+        rng = np.random.default_rng(args.cg_seed)
+        buf = []
+        losses = []
+        t0 = time.perf_counter()
+        for s in range(args.cg_train):
+            ex = make(1000 + s)
+            ex["features"] = lw.features(ex["theta"], ex["phi"])
+            a, it, rr, st = ex["plan"].solve(ex["d"], tol=tol, maxiter=args.cg_target_iters,
+                                             check=False)
+            ex["astar"] = a
+            buf.append(ex)
+            if len(buf) > args.cg_buffer:
+                old = buf.pop(0)
+                old["plan"].close()
+            for _ in range(args.cg_steps_per_set):
+                pick = rng.choice(len(buf), size=min(args.cg_batch, len(buf)), replace=False)
+                h = lw.train([buf[k] for k in pick], steps=1, lr=args.cg_lr)
+                losses.append(h[-1] / len(pick))
+            torch.cuda.synchronize()
+            log(f"train set {1000 + s}: target after {it} iterations (residual {rr:.2e}); "
+                f"loss {losses[-1]:.4f} ({time.perf_counter() - t0:.0f} s)")
+        lw.save(args.cg_save)
+        out = {"metric": "learned-weight training (CGLS preconditioner)", "phase": "train",
+               "value": float(np.mean(losses[-20:])), "unit": "loss", "n_gpus": 1,
+               "higher_is_better": False, "data": "synthetic",
+               "config": {"workload": workload, "train_seeds": [1000, 1000 + args.cg_train - 1],
+                          "target_iters": args.cg_target_iters, "buffer": args.cg_buffer,
+                          "batch": args.cg_batch, "steps_per_set": args.cg_steps_per_set,
+                          "lr": args.cg_lr, "eps": args.cg_eps, "density_map": [64, 128]},
+               "loss_first": losses[:10], "loss_last": losses[-10:],
+               "adam_steps": len(losses), "train_s": round(time.perf_counter() - t0, 1)}
+        print(json.dumps(out), flush=True)
+        return
 
-    hist = lw.train(train, steps=args.cg_steps, lr=args.cg_lr, log=train_log)
-    torch.cuda.synchronize()
-    t_train = time.perf_counter() - t0
-    log(f"training loss {hist[0] / len(train):.4f} -> {hist[-1] / len(train):.4f} "
-        f"({t_train:.1f} s)")
-    for ex in train:
-        ex["plan"].close()
+    lw = LearnedWeights.load(args.cg_load)
     rows = []
     for s in range(args.cg_test):
         ex = make(1160 + s)
-        torch.cuda.synchronize()
-        t1 = time.perf_counter()
-        _, it0, rr0, st0, h0 = ex["plan"].solve(ex["d"], tol=tol, maxiter=maxit, check=False,
-                                                history=True)
-        torch.cuda.synchronize()
-        t2 = time.perf_counter()
-        w = lw.weights(ex["theta"], ex["phi"])
-        x0 = ex["plan"].weighted_adjoint(ex["d"], w)
-        _, it1, rr1, st1, h1 = ex["plan"].solve(ex["d"], x0=x0, weights=w, tol=tol,
-                                                maxiter=maxit, check=False, history=True)
-        torch.cuda.synchronize()
-        t3 = time.perf_counter()
-        rows.append({"seed": 1160 + s,
-                     "plain": {"iters": it0, "relres": rr0, "s": round(t2 - t1, 3),
-                               "iters_to": {f"{m:g}": first_below(h0, m) for m in marks}},
-                     "learned": {"iters": it1, "relres": rr1, "s": round(t3 - t2, 3),
-                                 "iters_to": {f"{m:g}": first_below(h1, m) for m in marks}}})
-        log(f"held-out {1160 + s}: plain {it0} ({rr0:.2e}), learned {it1} ({rr1:.2e})")
-        ex["plan"].close()
-    out = {"metric": f"CGLS iterations to relative residual {tol:g} at lmax={L} "
-                     "(learned weights vs plain)",
-           "value": float(np.mean([r["learned"]["iters"] for r in rows])),
-           "unit": "iterations", "n_gpus": 1, "higher_is_better": False,
-           "vs_baseline": None, "dtype": "f64 transforms, f32 network", "data": "synthetic",
-           "config": {"workload": f"holey point sets: lmax=mmax={L}, "
-                                  f"N={int(1.5 * (L + 1) ** 2)}, 20 holes of 5 deg, "
-                                  "density 1 + 0.8 cos^2 theta",
-                      "tol": tol, "maxiter": maxit, "train_sets": args.cg_train,
-                      "test_sets": args.cg_test, "adam_steps": args.cg_steps, "lr": args.cg_lr,
-                      "density_map": [64, 128]},
-           "plain_mean_iters": float(np.mean([r["plain"]["iters"] for r in rows])),
-           "targets_s": round(t_targets, 2), "train_s": round(t_train, 2),
-           "train_loss": [hist[0] / len(train), hist[-1] / len(train)],
+        pl, d = ex["plan"], ex["d"]
+        res = {"seed": 1160 + s}
+        feats = lw.features(ex["theta"], ex["phi"])
+        scale = LearnedWeights.scale(pl.npts)
+        for kind in ("plain", "learned", "analytic"):
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            if kind == "plain":
+                _, it, rr, st, h = pl.solve(d, tol=tol, maxiter=args.cg_maxiter, check=False,
+                                            history=True)
+            else:
+                if kind == "learned":
+                    w = lw.weights(features=feats)
+                else:
+                    # 1 / rho^ at the point (feature 0 is log rho^, bilinear in the map)
+                    w = (torch.exp(-feats[:, 0]) * scale).contiguous()
+                x0 = pl.weighted_adjoint(d, w)
+                _, it, rr, st, h = pl.solve(d, x0=x0, weights=w, tol=tol,
+                                            maxiter=args.cg_maxiter, check=False, history=True)
+            torch.cuda.synchronize()
+            res[kind] = {"iters": it, "relres": rr, "s": round(time.perf_counter() - t1, 3),
+                         "iters_to": {f"{m:g}": first_below(h, m) for m in marks}}
+        rows.append(res)
+        log(f"held-out {1160 + s}: " + ", ".join(
+            f"{k} {res[k]['iters']} it ({res[k]['relres']:.2e}), to 1e-4 in "
+            f"{res[k]['iters_to']['0.0001']}" for k in ("plain", "learned", "analytic")))
+        pl.close()
+
+    def stat(kind, m):
+        v = [r[kind]["iters_to"][f"{m:g}"] for r in rows]
+        got = [x for x in v if x is not None]
+        return {"reached": len(got), "of": len(v),
+                "mean": float(np.mean(got)) if got else None,
+                "median": float(np.median(got)) if got else None}
+
+    table = {kind: {f"{m:g}": stat(kind, m) for m in marks}
+             for kind in ("plain", "learned", "analytic")}
+    out = {"metric": f"CGLS iterations to relative residual thresholds at lmax={L} "
+                     "(learned weights vs plain vs analytic 1/rho)",
+           "phase": "eval",
+           "value": table["learned"]["0.0001"]["mean"], "unit": "iterations to 1e-4 (mean)",
+           "n_gpus": 1, "higher_is_better": False, "vs_baseline": None,
+           "dtype": "f64 transforms, f32 network", "data": "synthetic",
+           "config": {"workload": workload, "tol": tol, "maxiter": args.cg_maxiter,
+                      "test_seeds": [1160, 1160 + args.cg_test - 1], "eps": args.cg_eps},
+           "thresholds": table,
+           "residual_after_maxiter_mean": {k: float(np.mean([r[k]["relres"] for r in rows]))
+                                           for k in ("plain", "learned", "analytic")},
+           "wall_s_mean": {k: float(np.mean([r[k]["s"] for r in rows]))
+                           for k in ("plain", "learned", "analytic")},
            "held_out": rows}
     print(json.dumps(out), flush=True)
 
@@ -265,17 +304,26 @@ def main():
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--cpu-sample", type=int, default=768)
     ap.add_argument("--cpu-sample1", type=int, default=32)
+    ap.add_argument("--sigma125-steps", type=int, default=5,
+                    help="timed steps of the mixed plan at sigma = 1.25 (0: skip)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cg", action="store_true",
                     help="run the learned-preconditioner CGLS leg instead of the transform step")
     ap.add_argument("--cg-lmax", type=int, default=2047)
+    ap.add_argument("--cg-phase", choices=["train", "eval"], default="eval")
     ap.add_argument("--cg-tol", type=float, default=1e-8)
-    ap.add_argument("--cg-maxiter", type=int, default=3000)
-    ap.add_argument("--cg-train", type=int, default=8)
-    ap.add_argument("--cg-test", type=int, default=2)
-    ap.add_argument("--cg-steps", type=int, default=200)
+    ap.add_argument("--cg-eps", type=float, default=1e-12)
+    ap.add_argument("--cg-maxiter", type=int, default=1500)
+    ap.add_argument("--cg-target-iters", type=int, default=600)
+    ap.add_argument("--cg-train", type=int, default=160)
+    ap.add_argument("--cg-test", type=int, default=40)
+    ap.add_argument("--cg-buffer", type=int, default=16)
+    ap.add_argument("--cg-batch", type=int, default=4)
+    ap.add_argument("--cg-steps-per-set", type=int, default=1)
     ap.add_argument("--cg-lr", type=float, default=1e-3)
     ap.add_argument("--cg-seed", type=int, default=7)
+    ap.add_argument("--cg-save", default="gpurun_out/c5_network.npz")
+    ap.add_argument("--cg-load", default="gpurun_out/c5_network.npz")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
                     help="only run one elementwise device copy of BYTES bytes (the reference "
                          "kernel that scales HBM byte counters)")
@@ -326,6 +374,19 @@ def main():
         log("fp64")
         fp = run_precision(P, torch, cfg, eps_ref, "f64", args.steps, args.warmup, alm, d)
         log(f"fp64: {fp['sec'] * 1e3:.2f} ms/step; stages syn {fp['syn']} adj {fp['adj']}")
+
+    # the paper's upsampling sigma = 1.25 beside sigma = 2 (mixed, same eps; fewer steps)
+    s125 = None
+    if args.sigma125_steps > 0:
+        if fp is not None:
+            fp["plan"].close()
+        else:
+            mx["plan"].close()
+        log("mixed, sigma = 1.25")
+        s125 = run_precision(P, torch, cfg, eps_mixed, "mixed", args.sigma125_steps, 2, alm, d,
+                             sigma=1.25)
+        log(f"sigma 1.25: {s125['sec'] * 1e3:.2f} ms/step; stages syn {s125['syn']} "
+            f"adj {s125['adj']}")
 
     def kernels(run, elem, geo):
         """per-kernel roofline figures of one precision's step: the Legendre launches against
@@ -438,6 +499,21 @@ def main():
                        "plan_s": fp["plan_s"], "width": fp["plan"].geometry["width"],
                        "roofline": fp_roofline, "roofline_kernels": fp_others}
         out["speedup_mixed_over_fp64"] = round(fp["sec"] / mx["sec"], 3)
+    if s125 is not None:
+        g125 = s125["plan"].geometry
+        e125 = {}
+        if fp is not None:
+            e125["synthesis_vs_fp64_rel_l2"] = float(
+                np.linalg.norm(s125["f"] - fp["f"]) / np.linalg.norm(fp["f"]))
+        if args.workload == "c3":
+            e125["adjoint_vs_oracle_columns_rel"] = golden_adjoint_error(
+                s125["c"], cfg["lmax"], os.path.join(ROOT, "tests", "golden",
+                                                     "c3_adjoint_columns.npz"))
+        out["mixed_sigma_1_25"] = {"s_per_step": s125["sec"], **s125["stats"],
+                                   "steps": args.sigma125_steps, "width": g125["width"],
+                                   "fine_grid": [g125["n1"], g125["n2"]],
+                                   "synthesis_stages_ms": s125["syn"],
+                                   "adjoint_stages_ms": s125["adj"], "accuracy": e125}
     if cpu is not None:
         model, ncpu = host_cpu()
         out["cpu_baseline"] = {"value": round(cpu["value"], 3), "unit": "s", "cores": cpu["threads"],

@@ -24,10 +24,10 @@
  *   work and return; the caller keeps the buffers alive until the stream has finished.
  *   nusht_plan* and nusht_solve synchronise.  A plan runs on one stream at a time.
  * - Precision.  `dtype` selects the internal precision only; user arrays are always FP64.
- *   NUSHT_F64: everything in FP64.  NUSHT_MIXED (eps >= 1e-6): Legendre step, ring FFTs and
- *   point coordinates in FP64; torus, 2D FFTs, deconvolution, spreading and interpolation
- *   in FP32, with each point's grid offset formed in FP64 before the cast (Sec. IV: an FP32
- *   nuFFT with FP32 coordinates cannot get below about 1e-4).
+ *   NUSHT_F64: everything in FP64.  NUSHT_MIXED (eps >= 1e-6; 1e-5 below sigma = 2):
+ *   Legendre step, ring FFTs and point coordinates in FP64; torus, 2D FFTs, deconvolution,
+ *   spreading and interpolation in FP32, with each point's grid offset formed in FP64 before
+ *   the cast (Sec. IV: an FP32 nuFFT with FP32 coordinates cannot get below about 1e-4).
  * - Errors.  Every call returns a status code; nothing is thrown across the ABI.  On error
  *   no output is written by a call that fails validation on the host.
  */
@@ -50,7 +50,8 @@ enum {
     NUSHT_ENOMEM = -2,     /* device allocation failed */
     NUSHT_EDEVICE = -3,    /* HIP or rocFFT call failed */
     NUSHT_ENOCONV = -4,    /* nusht_solve: true residual above tol; iterate, residual written */
-    NUSHT_EPRECISION = -5  /* NUSHT_MIXED requested with eps < 1e-6 */
+    NUSHT_EPRECISION = -5  /* NUSHT_MIXED requested below its floor: eps < 1e-6 at sigma >= 2,
+                              eps < 1e-5 at sigma < 2 */
 };
 
 /* How the torus spectrum is produced from the Legendre output.

@@ -108,11 +108,16 @@ struct nusht_plan_s {
     int* slot_off = nullptr;     // [nslots+1] first sorted point of each slot
     int* slot_tile = nullptr;    // [nslots] tile id of each slot
     int* tile_slot = nullptr;    // [ntiles] slot of each tile or -1
-    // Inside a tile the points are sorted by column band (band_w fine columns, band_w >= w)
-    // and then by row: band b of slot s holds the sorted points [band_off[s nsub + b],
-    // band_off[s nsub + b + 1]), nsub = kTile / band_w.  The spreading kernel sweeps bands.
-    int* band_off = nullptr;     // [nslots * nsub + 1]
-    int band_w = 0, nsub = 0;
+    // Records of the spreading sweep: the fine columns are cut into bands of band_w columns
+    // (band_w >= w); every point has a record in its own band and one in the next band when
+    // its taps reach it, sorted by (band, tile row, row); boff[band * nt1 + tile row] is the
+    // first record of that band and tile row.  Records hold the first-tap row and the column
+    // relative to the band, the caller's point index and the two tap offsets in the plan's
+    // precision (BandRec<float> or BandRec<double>).
+    void* brec = nullptr;
+    int64_t nrec = 0;
+    int* boff = nullptr;         // [n2 / band_w * nt1 + 1]
+    int band_w = 0;
     // Rows of the spreading sweep on a virtual axis (tile row nt1 - 1 is tile row -1): tile
     // rows [-1, band_vt_end) can hold points, rows [-kTile, band_vrow_hi) are written, in
     // segments of band_seg_tiles tile rows.
@@ -133,6 +138,8 @@ struct nusht_plan_s {
     void* W = nullptr;           // one map's fine row spectrum [n1][n2/2+1]
     size_t Wbytes = 0;
     double* V = nullptr;         // point scratch [npts][4]: packed point values of one group
+    void* Z = nullptr;           // tile subgrids of the wide-kernel spreading [nslots][P][P][4]
+    size_t Zbytes = 0;
     void* fftwork = nullptr;
     size_t fftwork_bytes = 0;
     double* red = nullptr;       // small reduction scratch for the CG solve
@@ -186,8 +193,21 @@ namespace nusht {
 // every point that reaches a band, and the group's lanes hold the w row taps of a point.
 inline int band_width_for(int w) { return w <= 8 ? 8 : 16; }
 
+// A record of the spreading sweep: rc = first-tap row | (column relative to the band + 32) << 16,
+// src = the caller's point index, s1 / s2 = tap offsets as s = 2 d - w + 1 in (-1, 1]
+template <typename T>
+struct BandRec {
+    int rc;
+    int src;
+    T s1, s2;
+};
+
 // Maps are processed by the point kernels in groups of four, the remainder one by one.
 inline int group_width(int nmaps, int b) { return (nmaps - b) >= 4 ? 4 : 1; }
+
+// Spreading strategy: the band sweep for kernels of width <= 8 and for deterministic plans;
+// tile subgrids with LDS atomics and a halo pass for wider kernels.
+inline bool spread_uses_tiles(const nusht_plan_s* p) { return p->g.width > 8 && !p->deterministic; }
 
 // ---- geometry (plan.hip) ----
 int compute_geometry(int lmax, int mmax, double eps, int dtype, const nusht_plan_opts* opts,

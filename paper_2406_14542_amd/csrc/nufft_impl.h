@@ -9,9 +9,11 @@
 //  * interpolation: a workgroup owns one non-empty tile ("slot") and stages the tile's window
 //    of (kTile + w - 1)^2 cells in LDS once; every point of the tile reads its w x w taps from
 //    LDS; results are written packed per point;
-//  * spreading: waves sweep column bands row by row and keep the rows a point can reach in
-//    registers (k_spread_band): every fine cell is written once, with its points summed in a
-//    fixed order, and no atomics or partial grids are involved.
+//  * spreading, w <= 8 or deterministic plans: waves sweep column bands row by row and keep
+//    the rows a point can reach in registers (k_spread_band): every fine cell is written once,
+//    with its points summed in a fixed order, and no atomics or partial grids are involved;
+//  * spreading, w > 8: tile subgrids accumulated with LDS atomics (k_spread_lds) and a halo
+//    pass that sums, for every fine cell, the subgrids of the windows covering it (k_halo).
 // Offsets are formed in FP64 from FP64 coordinates before any cast to the kernel's type T.
 #pragma once
 
@@ -366,104 +368,241 @@ __global__ __launch_bounds__(256) void k_interp_deriv(const double* __restrict__
     }
 }
 
+// Spreading of wide kernels (w > 8), not deterministic: tile subgrids with LDS atomics and a
+// halo pass.  (The band sweep below does only 64 / 16 = 4 points per wave step once w > 8, and
+// its per-point tap and broadcast work then outweighs the atomics this kernel pays.)
+// Batched: the block stages up to NB of the slot's points (tap
+// offsets, first cells relative to the tile, values) in LDS, then every wave takes
+// PPW = 64 / LPP points at a time with LPP lanes per point, lane = column tap: each lane forms
+// its column tap psi2[col] and the row tap psi1[col], the row taps of the point are exchanged
+// through a per-wave LDS row, and lane (point, col) adds f psi1[a] psi2[col] into window
+// rows r + a, a < W, of its column.  The window is planar (map-major), so the lanes of one
+// point add into consecutive words of one row.  Values come in packed, [point][MB], in the
+// caller's order, and are fetched through the permutation.  The window sums in FP64; the order of the additions into a cell is not fixed, so results can
+// differ between runs by FP64 rounding (~1e-16 relative) before the cast to T.
+template <typename T, int MB>
+struct SpreadPoint {
+    T d1, d2;  // offsets of the first taps, grid units
+    int r, c;  // first tap cell relative to the tile
+    T f[MB];
+};
+
+template <typename T, int W, int MB>
+__global__ __launch_bounds__(256) void k_spread_lds(const T* __restrict__ vals, PointBins pb,
+                                                    T beta, T* __restrict__ sub)
+{
+    constexpr int P = kTile + W - 1;
+    constexpr int LPP = W <= 8 ? 8 : 16;
+    constexpr int PPW = 64 / LPP;
+    constexpr int NB = 128;  // points staged per batch (64 for FP64 measured 0.6 ms slower)
+    static_assert(W <= 16, "one lane per column tap");
+    // the window accumulates in FP64 for either T: LDS atomic adds of FP64 measured fast on
+    // gfx950, those of FP32 an order of magnitude slower than the whole kernel
+    __shared__ double win[MB * P * P];
+    __shared__ SpreadPoint<T, MB> s_pt[NB];
+    __shared__ T s_p1[4][PPW][LPP];
+    const int slot = blockIdx.x;
+    const int tile = pb.slot_tile[slot];
+    const int r0 = (tile / pb.nt2) * kTile;
+    const int c0 = (tile % pb.nt2) * kTile;
+    const int t = threadIdx.x;
+    for (int e = t; e < MB * P * P; e += blockDim.x) win[e] = 0.0;
+    const int wave = t >> 6, lane = t & 63;
+    const int grp = lane / LPP, col = lane - grp * LPP;
+    const int p0 = pb.slot_off[slot], p1 = pb.slot_off[slot + 1];
+    const T cw = T(2) / T(W);
+    T* p1row = s_p1[wave][grp];
+    for (int base = p0; base < p1; base += NB) {
+        const int nb = min(NB, p1 - base);
+        __syncthreads();  // window cleared, or the previous batch consumed
+        if (t < nb) {
+            const int p = base + t;
+            double d1, d2;
+            const int l1 = first_tap(pb.sth[p], pb.s1, W, d1);
+            const int l2 = first_tap(pb.sph[p], pb.s2, W, d2);
+            int r = wrap_index(l1, pb.n1) - r0;
+            int c = wrap_index(l2, pb.n2) - c0;
+            const int64_t src = pb.perm[p];
+            SpreadPoint<T, MB> sp;
+            sp.d1 = (T)d1;
+            sp.d2 = (T)d2;
+            sp.r = min(max(r, 0), kTile - 1);
+            sp.c = min(max(c, 0), kTile - 1);
+#pragma unroll
+            for (int b = 0; b < MB; ++b) sp.f[b] = vals[src * MB + b];
+            s_pt[t] = sp;
+        }
+        __syncthreads();
+        // lane group g takes the points g S + i of the row-sorted batch: the PPW points of one
+        // step lie S apart, in different rows, so no two lanes of an atomic add address the
+        // same cell (a point adds into rows r + a for the step's common a)
+        const int S = (nb + PPW - 1) / PPW;
+        for (int i = wave; i < S; i += 4) {
+            const int q = grp * S + i;
+            const bool live = q < nb;
+            const SpreadPoint<T, MB> sp = s_pt[live ? q : 0];
+            const bool act = live && col < W;
+            const T p2 = act ? es_value<T>((sp.d2 - T(col)) * cw, beta) : T(0);
+            p1row[col] = col < W ? es_value<T>((sp.d1 - T(col)) * cw, beta) : T(0);
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+            T pr[W];
+#pragma unroll
+            for (int a = 0; a < W; ++a) pr[a] = p1row[a];
+            // the next step rewrites the row: every lane's reads come first
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+            if (act) {
+                T fb[MB];
+#pragma unroll
+                for (int b = 0; b < MB; ++b) fb[b] = sp.f[b] * p2;
+                double* w0 = win + sp.r * P + sp.c + col;
+#pragma unroll
+                for (int a = 0; a < W; ++a)
+#pragma unroll
+                    for (int b = 0; b < MB; ++b)
+                        atomicAdd(w0 + (b * P + a) * P, (double)(fb[b] * pr[a]));
+            }
+        }
+    }
+    __syncthreads();
+    T* dst = sub + (int64_t)slot * (P * P * MB);
+    for (int e = t; e < P * P; e += blockDim.x) {
+#pragma unroll
+        for (int b = 0; b < MB; ++b) dst[e * MB + b] = (T)win[b * P * P + e];
+    }
+}
+
+// fine[b][i][j] = sum of the subgrids of the windows covering cell (i, j); zero elsewhere
+template <typename T, int W, int MB>
+__global__ __launch_bounds__(256) void k_halo(const T* __restrict__ sub,
+                                              const int* __restrict__ tile_slot, int nt1, int nt2,
+                                              int n1, int n2, int ra, int rb,
+                                              T* __restrict__ fine, int64_t map_stride)
+{
+    constexpr int P = kTile + W - 1;
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    // rows [0, ra) and [n1 - rb, n1): the only rows any window reaches
+    const int i = (int)blockIdx.y < ra ? (int)blockIdx.y : n1 - rb + ((int)blockIdx.y - ra);
+    if (j >= n2) return;
+    const int tr = i / kTile, rr = i - tr * kTile;
+    const int tc = j / kTile, cc = j - tc * kTile;
+    const int trp = tr == 0 ? nt1 - 1 : tr - 1;
+    const int tcp = tc == 0 ? nt2 - 1 : tc - 1;
+    T acc[MB];
+#pragma unroll
+    for (int b = 0; b < MB; ++b) acc[b] = T(0);
+    auto add = [&](int t_r, int t_c, int r, int c) {
+        const int sl = tile_slot[t_r * nt2 + t_c];
+        if (sl < 0) return;
+        const T* s = sub + (int64_t)sl * (P * P * MB) + (r * P + c) * MB;
+#pragma unroll
+        for (int b = 0; b < MB; ++b) acc[b] += s[b];
+    };
+    add(tr, tc, rr, cc);
+    if (rr < W - 1) add(trp, tc, rr + kTile, cc);
+    if (cc < W - 1) add(tr, tcp, rr, cc + kTile);
+    if (rr < W - 1 && cc < W - 1) add(trp, tcp, rr + kTile, cc + kTile);
+    const int64_t off = (int64_t)i * n2 + j;
+#pragma unroll
+    for (int b = 0; b < MB; ++b) fine[b * map_stride + off] = acc[b];
+}
+
 // Spreading (type 1, N^H of Eq. 6): u(l1, l2) = sum_i f_i psi(row taps) psi(column taps), the
 // exact adjoint of the interpolation above (same taps).
 //
 // Band sweep, no atomics.  The fine columns are cut into bands of SW = band_w columns; each
 // group of SW lanes of a wave owns one band (lane q = column c0 + q), so a wave sweeps
-// K = 64 / SW bands side by side.  A band's points -- its own band's points and those of the
-// band to its left whose taps reach it (SW >= w) -- are taken in order of their first-tap
-// row, tile row after tile row.  Every lane keeps the w rows [R, R + w) of its column in
-// registers: a point whose first tap is row r (>= R, rows only grow) first pushes rows R .. r-1
-// out to the fine grid, then adds f psi1[a] psi2[q - c] to rows r + a.  Each cell is written
-// once, by the lane that owns its column, as the sum of its points in a fixed order: the
-// result does not depend on scheduling, and nothing is written twice.
+// K = 64 / SW bands side by side.  The plan keeps, per band, a record of every point whose
+// taps reach the band (its own band's points and those of the band to its left), sorted by
+// first-tap row.  Every lane keeps the w rows [R, R + w) of its column in registers: a point
+// whose first tap is row r (>= R, rows only grow) first pushes rows R .. r-1 out to the fine
+// grid, then adds f psi1[a] psi2[q - c] to rows r + a.  Each cell is written once, by the lane
+// that owns its column, as the sum of its points in a fixed order: the result does not depend
+// on scheduling, and nothing is written twice.
+//
+// The records stream through LDS in batches of SW (lane j of a group stages record j), with
+// the loads two stages ahead: a batch's records are fetched two batches before their turn and
+// their point values (gathered through the caller's index) one batch before, so the
+// sequential row sweep never waits on a load of its own.
 //
 // Rows are handled on a virtual axis: physical tile row nt1 - 1 (points near theta = 0 whose
 // first tap wraps below row 0) is virtual tile row -1, so a band's rows run on without a wrap
 // from -kTile up.  The rows are cut into segments of seg_tiles tile rows (grid.y); a segment
-// owns the rows of its tile rows and also sweeps the points of the tile row above it whose
+// owns the rows of its tile rows and also sweeps the records of the tile row above it whose
 // taps reach its first row (and drops their rows above it), so segments never write the same
 // cell either.  The owned rows of all segments are exactly the rows any point window reaches
 // ([n1 - kTile, n1) and [0, ra)); when every row is reached, the first segment's overlap row
 // is the last tile row shifted by -n1, which carries the wrap.
 struct BandBins {
-    const double* sth;
-    const double* sph;
-    const int* perm;
-    const int* band_off;   // [nslots * nsub + 1]
-    const int* tile_slot;  // [nt1 * nt2]
-    int nt1, nt2, n1, n2, nsub, nbands;
-    double s1, s2;
+    const int* boff;  // [nbands * nt1 + 1]
+    int nt1, n1, n2, nbands;
+    int64_t nrec;
     int vt_end;     // virtual tile rows [-1, vt_end) can hold points
     int vrow_hi;    // owned virtual rows are [-kTile, vrow_hi)
     int seg_tiles;  // tile rows per segment
 };
 
-constexpr int kNoRow = 0x7fffffff;
-
-template <typename T, int MB>
-struct BandHead {
-    int r, c;  // first tap: virtual row, column relative to the band start
-    T s1, s2;  // offsets of the first taps as s = 2 d - w + 1 in (-1, 1], formed in FP64
-    T f[MB];   // the point's values
-};
-
-// first sorted point of band group g of tile (ptr, tcol), or an empty range
-__device__ inline void band_range(const BandBins& bb, int ptr, int tcol, int sub, int& p, int& e)
+// first record of [a, e) whose virtual row (first-tap row + voff) is >= row
+template <typename T>
+__device__ inline int band_lower_bound(const BandRec<T>* __restrict__ recs, int a, int e,
+                                       int voff, int row)
 {
-    const int sl = bb.tile_slot[ptr * bb.nt2 + tcol];
-    if (sl < 0) {
-        p = e = 0;
-        return;
+    while (a < e) {
+        const int mid = (a + e) >> 1;
+        if ((recs[mid].rc & 0xffff) + voff < row) a = mid + 1; else e = mid;
     }
-    const int g = sl * bb.nsub + sub;
-    p = bb.band_off[g];
-    e = bb.band_off[g + 1];
+    return a;
 }
 
-template <typename T, int W, int MB>
-__device__ inline int band_row(const BandBins& bb, int p, int voff)
+// r = lane's bit of mask ? b : a, per lane, on registers (v_cndmask with the lane mask in an
+// SGPR pair).  Written out so that the compiler keeps the register rows of the spreading sweep
+// in place: a select it is free to rewrite became a select between two addresses, which put
+// the rows in scratch memory.
+__device__ inline float lane_select(float a, float b, uint64_t mask)
 {
-    double d;
-    return wrap_index(first_tap(bb.sth[p], bb.s1, W, d), bb.n1) + voff;
+    float r;
+    asm("v_cndmask_b32_e64 %0, %1, %2, %3" : "=v"(r) : "v"(a), "v"(b), "s"(mask));
+    return r;
 }
 
-template <typename T, int W, int MB>
-__device__ inline void band_decode(const BandBins& bb, const T* __restrict__ vals, int p,
-                                   int voff, int cbase, BandHead<T, MB>& h)
+__device__ inline double lane_select(double a, double b, uint64_t mask)
 {
-    double d1, d2;
-    const int l1 = first_tap(bb.sth[p], bb.s1, W, d1);
-    const int l2 = first_tap(bb.sph[p], bb.s2, W, d2);
-    h.r = wrap_index(l1, bb.n1) + voff;
-    h.c = wrap_index(l2, bb.n2) - cbase;
-    h.s1 = (T)(2.0 * d1 - (double)(W - 1));
-    h.s2 = (T)(2.0 * d2 - (double)(W - 1));
-    const int64_t src = bb.perm[p];
-#pragma unroll
-    for (int m = 0; m < MB; ++m) h.f[m] = vals[src * MB + m];
+    const uint64_t ua = __builtin_bit_cast(uint64_t, a), ub = __builtin_bit_cast(uint64_t, b);
+    unsigned lo, hi;
+    asm("v_cndmask_b32_e64 %0, %1, %2, %3"
+        : "=v"(lo)
+        : "v"((unsigned)ua), "v"((unsigned)ub), "s"(mask));
+    asm("v_cndmask_b32_e64 %0, %1, %2, %3"
+        : "=v"(hi)
+        : "v"((unsigned)(ua >> 32)), "v"((unsigned)(ub >> 32)), "s"(mask));
+    return __builtin_bit_cast(double, ((uint64_t)hi << 32) | lo);
 }
 
 template <typename T, int W, int MB, int SW>
-__global__ __launch_bounds__(256) void k_spread_band(const T* __restrict__ vals, BandBins bb,
-                                                     T beta, const T* __restrict__ coef,
+__global__ __launch_bounds__(256) void k_spread_band(const BandRec<T>* __restrict__ recs,
+                                                     const T* __restrict__ vals, int vstride,
+                                                     BandBins bb, T beta,
+                                                     const T* __restrict__ coef,
                                                      T* __restrict__ fine, int64_t map_stride)
 {
     constexpr int K = 64 / SW;
     static_assert(SW >= W && kTile % SW == 0,
                   "one band to the left reaches a band; a group's lanes hold the row taps");
-    const int lane = threadIdx.x & 63;
+    // staged records (virtual row, column relative to the band, tap offsets) and values
+    struct Staged {
+        int r, c;
+        T s1, s2;
+    };
+    __shared__ Staged s_rec[4][64];
+    __shared__ T s_val[4][64 * MB];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int grp = lane / SW, q = lane - grp * SW;
-    const int band = (int)(blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6)) * K + grp;
+    const int band = (int)(blockIdx.x * 4 + wave) * K + grp;
     const bool bvalid = band < bb.nbands;
     const int c0 = bvalid ? band * SW : 0;
-    const int tcol = c0 / kTile, sub = (c0 % kTile) / SW;
-    const int lband = !bvalid ? 0 : band == 0 ? bb.nbands - 1 : band - 1;
-    const int lc0 = lband * SW;
-    const int ltcol = lc0 / kTile, lsub = (lc0 % kTile) / SW;
-    // the left band's columns in this band's frame (band 0: the last band, one period back)
-    const int lbase = band == 0 ? c0 + bb.n2 : c0;
     const int vt0 = -1 + (int)blockIdx.y * bb.seg_tiles;
     const int vt1 = min(vt0 + bb.seg_tiles, bb.vt_end);
     const int own_lo = vt0 * kTile;
@@ -477,140 +616,152 @@ __global__ __launch_bounds__(256) void k_spread_band(const T* __restrict__ vals,
 #pragma unroll
     for (int k = 0; k <= W; ++k) creg[k] = (poly && q < W) ? coef[k * W + q] : T(0);
 
+    // this band's records for the segment: at most two runs [a0, e0) (row offset vo0) and
+    // [a1, e1) (vo1) -- the overlap tile row vt0 - 1 (from its first record that reaches
+    // first_row on) and the segment's own tile rows, split where virtual tile row -1
+    // (physical nt1 - 1) is followed by physical tile row 0
+    int a0 = 0, e0 = 0, vo0 = 0, a1 = 0, e1 = 0, vo1 = 0;
+    if (bvalid) {
+        const int gb = band * bb.nt1;
+        const int nt1 = bb.nt1;
+        if (vt0 <= 0) {
+            // overlap row nt1 - 2 (vt0 = -1) or nt1 - 1 (vt0 = 0), shifted by -n1; for vt0 = -1
+            // the virtual tile row -1 (physical nt1 - 1) follows it in the same run
+            const int po = vt0 < 0 ? nt1 - 2 : nt1 - 1;
+            vo0 = -bb.n1;
+            a0 = band_lower_bound(recs, bb.boff[gb + po], bb.boff[gb + po + 1], vo0, first_row);
+            e0 = bb.boff[gb + nt1];
+            a1 = bb.boff[gb];
+            e1 = bb.boff[gb + vt1];
+        } else {
+            a0 = band_lower_bound(recs, bb.boff[gb + vt0 - 1], bb.boff[gb + vt0], 0, first_row);
+            e0 = bb.boff[gb + vt1];
+        }
+    }
+    const int n0 = e0 - a0;
+    const int total = n0 + (e1 - a1);
+    const int nbatch = (total + SW - 1) / SW;
+    // record t of the band's stream, clamped into the array (unused when t >= total)
+    auto rec_index = [&](int t, int& voff) {
+        voff = t < n0 ? vo0 : vo1;
+        int idx = t < n0 ? a0 + t : a1 + (t - n0);
+        return (t < total) ? idx : 0;
+    };
+
     T acc[W][MB];
 #pragma unroll
     for (int a = 0; a < W; ++a)
 #pragma unroll
         for (int m = 0; m < MB; ++m) acc[a][m] = T(0);
     int R = first_row;
-
-    // push row R out (if this segment owns it) and move the register rows up by one
-    auto push_row = [&]() {
-        if (bvalid && R >= own_lo && R < own_hi) {
+    // lanes with adv: push row R out (if this segment owns it) and move the register rows up
+    // by one.  Straight-line code with selects, so that the rows stay in place in registers
+    // (a branch around the move made the compiler keep copies of all of them).
+    auto advance = [&](bool adv) {
+        if (adv && bvalid && R >= own_lo && R < own_hi) {
             const int pr = R < 0 ? R + bb.n1 : R;
             T* o = fine + (int64_t)pr * bb.n2 + c0 + q;
 #pragma unroll
             for (int m = 0; m < MB; ++m) o[m * map_stride] = acc[0][m];
         }
+        const uint64_t mask = __builtin_amdgcn_ballot_w64(adv);
 #pragma unroll
         for (int a = 0; a < W - 1; ++a)
 #pragma unroll
-            for (int m = 0; m < MB; ++m) acc[a][m] = acc[a + 1][m];
+            for (int m = 0; m < MB; ++m) acc[a][m] = lane_select(acc[a][m], acc[a + 1][m], mask);
 #pragma unroll
-        for (int m = 0; m < MB; ++m) acc[W - 1][m] = T(0);
-        ++R;
+        for (int m = 0; m < MB; ++m) acc[W - 1][m] = lane_select(acc[W - 1][m], T(0), mask);
+        R += adv ? 1 : 0;
     };
 
-    // the lists of the current tile row: own band [po, eo), left band [pl, el); the first
-    // row opened is the overlap row vt0 - 1
-    int vt = vt0 - 2;
-    int po = 0, eo = 0, pl = 0, el = 0, voff = 0;
-    BandHead<T, MB> ho, hl;
-    ho.r = hl.r = kNoRow;
-    ho.c = hl.c = 0;
-    ho.s1 = ho.s2 = hl.s1 = hl.s2 = T(0);
+    // pipeline: recA / valA = batch b (staged at the top of iteration b), recB = batch b + 1
+    int voA, voB;
+    BandRec<T> recA = recs[rec_index(q, voA)];
+    T valA[MB];
+    {
+        const int64_t src = recA.src;
 #pragma unroll
-    for (int m = 0; m < MB; ++m) ho.f[m] = hl.f[m] = T(0);
-    bool live = bvalid;
-    // open tile row vt: list ranges, and in the overlap row the first point that can reach
-    // the segment's rows (rows are sorted along a list: lower bound by bisection)
-    auto open_row = [&]() {
-        const int ptr = ((vt % bb.nt1) + bb.nt1) % bb.nt1;
-        voff = (vt - ptr) * kTile;
-        band_range(bb, ptr, tcol, sub, po, eo);
-        band_range(bb, ptr, ltcol, lsub, pl, el);
-        if (vt < vt0) {
-            int lo = po, hi = eo;
-            while (lo < hi) {
-                const int mid = (lo + hi) >> 1;
-                if (band_row<T, W, MB>(bb, mid, voff) < first_row) lo = mid + 1; else hi = mid;
-            }
-            po = lo;
-            lo = pl;
-            hi = el;
-            while (lo < hi) {
-                const int mid = (lo + hi) >> 1;
-                if (band_row<T, W, MB>(bb, mid, voff) < first_row) lo = mid + 1; else hi = mid;
-            }
-            pl = lo;
-        }
-    };
-    // next head of the own list / of the left list (skipping points whose taps miss the band)
-    auto next_own = [&]() {
-        if (po < eo) {
-            band_decode<T, W, MB>(bb, vals, po, voff, c0, ho);
-            ++po;
-        } else {
-            ho.r = kNoRow;
-        }
-    };
-    auto next_left = [&]() {
-        hl.r = kNoRow;
-        while (pl < el) {
-            band_decode<T, W, MB>(bb, vals, pl, voff, lbase, hl);
-            ++pl;
-            if (hl.c > -W) return;
-            hl.r = kNoRow;
-        }
-    };
+        for (int m = 0; m < MB; ++m) valA[m] = vals[src * vstride + m];
+    }
+    BandRec<T> recB = recs[rec_index(SW + q, voB)];
+    bool okA = q < total;
 
-    while (__any(live)) {
-        // the next point of this band, moving on to later tile rows as lists run out
-        while (live && ho.r == kNoRow && hl.r == kNoRow) {
-            ++vt;
-            if (vt >= vt1) {
-                live = false;
-                break;
+    for (int b = 0; __any(b < nbatch); ++b) {
+        // stage batch b
+        {
+            Staged st;
+            st.r = (recA.rc & 0xffff) + voA;
+            st.c = (recA.rc >> 16) - 32;
+            st.s1 = recA.s1;
+            st.s2 = recA.s2;
+            s_rec[wave][lane] = st;
+#pragma unroll
+            for (int m = 0; m < MB; ++m) s_val[wave][lane * MB + m] = okA ? valA[m] : T(0);
+        }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        // the next stages: values of batch b + 1, records of batch b + 2
+        T valB[MB];
+        {
+            const int64_t src = recB.src;
+#pragma unroll
+            for (int m = 0; m < MB; ++m) valB[m] = vals[src * vstride + m];
+        }
+        int voC;
+        const BandRec<T> recC = recs[rec_index((b + 2) * SW + q, voC)];
+        // the batch's points, one per group and step (not unrolled: the register rows, the tap
+        // coefficients and the pipelined loads already fill the register file)
+#pragma unroll 1
+        for (int jj = 0; jj < SW; ++jj) {
+            const int t = b * SW + jj;
+            const bool has = bvalid && t < total;
+            const Staged h = s_rec[wave][grp * SW + jj];
+            // push the rows above the point's first row
+            const int target = has ? h.r : R;
+            while (__any(R < target)) advance(R < target);
+            // column tap of this lane, row taps from lanes 0 .. W-1 of the group (a group
+            // without a point adds exact zeros)
+            const int cb = q - h.c;
+            const bool act = has && cb >= 0 && cb < W;
+            T p1, p2;
+            if (poly) {
+                const T t1 = (has && q < W) ? es_tap_poly<T, W>(h.s1, creg) : T(0);
+                const T t2 = (has && q < W) ? es_tap_poly<T, W>(h.s2, creg) : T(0);
+                const T t2b = __shfl(t2, grp * SW + (act ? cb : 0), 64);
+                p1 = t1;
+                p2 = act ? t2b : T(0);
+            } else {
+                // z of tap a = 2 (d - a) / w = (s + w - 1 - 2 a) / w
+                p2 = act ? es_value<T>((h.s2 + T(W - 1 - 2 * cb)) * cw * T(0.5), beta) : T(0);
+                p1 = (has && q < W) ? es_value<T>((h.s1 + T(W - 1 - 2 * q)) * cw * T(0.5), beta)
+                                    : T(0);
             }
-            open_row();
-            next_own();
-            next_left();
-        }
-        const bool take_own = live && ho.r <= hl.r;
-        BandHead<T, MB> h = take_own ? ho : hl;
-        const bool has = live && h.r != kNoRow;
-        // push the rows above the point's first row
-        const int target = has ? h.r : R;
-        while (__any(R < target)) {
-            if (R < target) push_row();
-        }
-        // add the point: column tap of this lane, row taps from lanes 0 .. W-1 of the group
-        // (a group without a point adds exact zeros: its head's values are not used)
-        const int b = q - h.c;
-        const bool act = has && b >= 0 && b < W;
-        T p1, p2;
-        if (poly) {
-            // taps q of the point's row and column offsets, then this lane's column tap b
-            // from lane b of the group
-            const T t1 = (has && q < W) ? es_tap_poly<T, W>(h.s1, creg) : T(0);
-            const T t2 = (has && q < W) ? es_tap_poly<T, W>(h.s2, creg) : T(0);
-            const T t2b = __shfl(t2, grp * SW + (act ? b : 0), 64);
-            p1 = t1;
-            p2 = act ? t2b : T(0);
-        } else {
-            // z of tap a = 2 (d - a) / w = (s + w - 1 - 2 a) / w
-            p2 = act ? es_value<T>((h.s2 + T(W - 1 - 2 * b)) * cw * T(0.5), beta) : T(0);
-            p1 = (has && q < W) ? es_value<T>((h.s1 + T(W - 1 - 2 * q)) * cw * T(0.5), beta)
-                                : T(0);
-        }
-        T g[MB];
+            T g[MB];
 #pragma unroll
-        for (int m = 0; m < MB; ++m) g[m] = act ? h.f[m] * p2 : T(0);
+            for (int m = 0; m < MB; ++m) g[m] = act ? s_val[wave][(grp * SW + jj) * MB + m] * p2
+                                                    : T(0);
 #pragma unroll
-        for (int a = 0; a < W; ++a) {
-            const T pa = __shfl(p1, grp * SW + a, 64);
+            for (int a = 0; a < W; ++a) {
+                const T pa = __shfl(p1, grp * SW + a, 64);
 #pragma unroll
-            for (int m = 0; m < MB; ++m) acc[a][m] += g[m] * pa;
+                for (int m = 0; m < MB; ++m) acc[a][m] += g[m] * pa;
+            }
         }
-        if (has) {
-            if (take_own) next_own();
-            else next_left();
-        }
+        // every lane's reads of the staged batch come before the next batch is staged
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        recA = recB;
+        voA = voB;
+#pragma unroll
+        for (int m = 0; m < MB; ++m) valA[m] = valB[m];
+        okA = (b + 1) * SW + q < total;
+        recB = recC;
+        voB = voC;
     }
     // the rows after the last point, up to the end of the segment
-    while (__any(R < own_hi)) {
-        if (R < own_hi) push_row();
-    }
+    while (__any(R < own_hi)) advance(R < own_hi);
 }
 
 // ---- dispatch over the kernel width ---------------------------------------------------
@@ -696,29 +847,23 @@ int dispatch_interp_impl(const nusht_plan_s* p, const T* fine, double* out, int 
 inline BandBins make_band_bins(const nusht_plan_s* p)
 {
     BandBins bb;
-    bb.sth = p->sth;
-    bb.sph = p->sph;
-    bb.perm = p->perm;
-    bb.band_off = p->band_off;
-    bb.tile_slot = p->tile_slot;
-    bb.nt1 = p->nt1;
-    bb.nt2 = p->nt2;
+    bb.boff = p->boff;
+    bb.nt1 = p->g.n1 / kTile;
     bb.n1 = p->g.n1;
     bb.n2 = p->g.n2;
-    bb.nsub = p->nsub;
     bb.nbands = p->g.n2 / p->band_w;
-    bb.s1 = p->g.n1 / (2.0 * M_PI);
-    bb.s2 = p->g.n2 / (2.0 * M_PI);
+    bb.nrec = p->nrec;
     bb.vt_end = p->band_vt_end;
     bb.vrow_hi = p->band_vrow_hi;
     bb.seg_tiles = p->band_seg_tiles;
     return bb;
 }
 
-// Spreading of the caller's maps [b, b + mb) (`vals` = its map block [mb][npts]) straight onto
-// the fine grids of those maps: the values are first packed [point][mb] in the caller's order
-// into the plan's point scratch, so that the band kernel fetches a point's mb values with one
-// load through the permutation.
+// Spreading of the caller's maps [b, b + mb) (`vals` = its map block [mb][npts]) onto the
+// fine grids of those maps: the values are first packed [point][mb] in the caller's order into
+// the plan's point scratch, so that the kernels fetch a point's mb values with one load through
+// the caller's index.  Kernels of width <= 8 (and every kernel of a deterministic plan) use the
+// band sweep; wider ones the tile subgrids (into the plan's scratch Z) and the halo pass.
 template <typename T>
 int spread_group_impl(const nusht_plan_s* p, const double* vals, T* fine, int mb, T beta,
                       hipStream_t s)
@@ -733,20 +878,53 @@ int spread_group_impl(const nusht_plan_s* p, const double* vals, T* fine, int mb
         hipLaunchKernelGGL((k_pack_values<T, 1>), dim3(pblocks), dim3(256), 0, s, vals, npts,
                            packed);
     NUSHT_HIP(hipGetLastError());
+    const int64_t ms = (int64_t)p->g.n1 * p->g.n2;
+    if (spread_uses_tiles(p)) {
+        if (p->nslots == 0) return NUSHT_OK;
+        const PointBins pb = make_bins(p);
+        T* sub = reinterpret_cast<T*>(p->Z);
+        dim3 hgrid((p->g.n2 + 255) / 256, p->fine_ra + p->fine_rb);
+        NUSHT_WIDTH_SWITCH(p->g.width, {
+            if (mb == 4) {
+                hipLaunchKernelGGL((k_spread_lds<T, WV, 4>), dim3(p->nslots), dim3(256), 0, s,
+                                   packed, pb, beta, sub);
+                hipLaunchKernelGGL((k_halo<T, WV, 4>), hgrid, dim3(256), 0, s, sub, p->tile_slot,
+                                   p->nt1, p->nt2, p->g.n1, p->g.n2, p->fine_ra, p->fine_rb,
+                                   fine, ms);
+            } else {
+                hipLaunchKernelGGL((k_spread_lds<T, WV, 1>), dim3(p->nslots), dim3(256), 0, s,
+                                   packed, pb, beta, sub);
+                hipLaunchKernelGGL((k_halo<T, WV, 1>), hgrid, dim3(256), 0, s, sub, p->tile_slot,
+                                   p->nt1, p->nt2, p->g.n1, p->g.n2, p->fine_ra, p->fine_rb,
+                                   fine, ms);
+            }
+        });
+        NUSHT_HIP(hipGetLastError());
+        return NUSHT_OK;
+    }
     const BandBins bb = make_band_bins(p);
     const T* coef = es_coef_of<T>(p);
-    const int64_t ms = (int64_t)p->g.n1 * p->g.n2;
+    const BandRec<T>* recs = reinterpret_cast<const BandRec<T>*>(p->brec);
     const int K = 64 / p->band_w;
     const dim3 grid((unsigned)((bb.nbands + 4 * K - 1) / (4 * K)),
                     (unsigned)((bb.vt_end + 1 + bb.seg_tiles - 1) / bb.seg_tiles));
+    // FP32 sweeps the group's maps together; FP64 one map per pass (four maps' FP64 register
+    // rows left one wave per SIMD), reading its values from the packed rows
     NUSHT_WIDTH_SWITCH(p->g.width, {
         constexpr int SWV = WV <= 8 ? 8 : 16;
-        if (mb == 4)
-            hipLaunchKernelGGL((k_spread_band<T, WV, 4, SWV>), grid, dim3(256), 0, s, packed, bb,
-                               beta, coef, fine, ms);
-        else
-            hipLaunchKernelGGL((k_spread_band<T, WV, 1, SWV>), grid, dim3(256), 0, s, packed, bb,
-                               beta, coef, fine, ms);
+        bool done = false;
+        if constexpr (sizeof(T) == 4) {
+            if (mb == 4) {
+                hipLaunchKernelGGL((k_spread_band<T, WV, 4, SWV>), grid, dim3(256), 0, s, recs,
+                                   packed, 4, bb, beta, coef, fine, ms);
+                done = true;
+            }
+        }
+        if (!done) {
+            for (int m = 0; m < mb; ++m)
+                hipLaunchKernelGGL((k_spread_band<T, WV, 1, SWV>), grid, dim3(256), 0, s, recs,
+                                   packed + m, mb, bb, beta, coef, fine + m * ms, ms);
+        }
     });
     NUSHT_HIP(hipGetLastError());
     return NUSHT_OK;

@@ -162,7 +162,7 @@ int dmalloc(T** p, size_t n)
 
 __global__ void k_bin_keys(const double* __restrict__ theta, const double* __restrict__ phi,
                            int64_t n, int w, double s1, double s2, int n1, int n2, int nt2,
-                           int bw, double* __restrict__ phw, int* __restrict__ keys,
+                           double* __restrict__ phw, int* __restrict__ keys,
                            int* __restrict__ idx, int* __restrict__ flag)
 {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -182,11 +182,8 @@ __global__ void k_bin_keys(const double* __restrict__ theta, const double* __res
     double d;
     const int l1 = wrap_index(first_tap(thc, s1, w, d), n1);
     const int l2 = wrap_index(first_tap(ph, s2, w, d), n2);
-    // tile id, then the column band inside the tile, then the row inside the tile: the
-    // spreading kernel walks a band's points by row
-    const int nsub = kTile / bw;
-    keys[i] = (((l1 / kTile) * nt2 + (l2 / kTile)) * nsub + (l2 % kTile) / bw) * kTile +
-              (l1 % kTile);
+    // tile id, then the row inside the tile
+    keys[i] = ((l1 / kTile) * nt2 + (l2 / kTile)) * kTile + (l1 % kTile);
     idx[i] = (int)i;
     phw[i] = ph;
 }
@@ -203,50 +200,117 @@ __global__ void k_gather_sorted(const double* __restrict__ theta, const double* 
     iperm[i] = (int)k;
 }
 
-// tile of a sorted key (keys hold tile, band, row)
-__device__ inline int key_tile(int key, int nsub) { return key / (kTile * nsub); }
-
-__global__ void k_mark(const int* __restrict__ keys, int64_t n, int nsub, int* __restrict__ first)
+__global__ void k_mark(const int* __restrict__ keys, int64_t n, int* __restrict__ first)
 {
     const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (k >= n) return;
-    first[k] = (k == 0 || key_tile(keys[k], nsub) != key_tile(keys[k - 1], nsub)) ? 1 : 0;
+    first[k] = (k == 0 || (keys[k] / kTile) != (keys[k - 1] / kTile)) ? 1 : 0;
 }
 
 __global__ void k_slots(const int* __restrict__ keys, const int* __restrict__ first,
-                        const int* __restrict__ slotidx, int64_t n, int nsub,
-                        int* __restrict__ slot_off, int* __restrict__ slot_tile,
-                        int* __restrict__ tile_slot)
+                        const int* __restrict__ slotidx, int64_t n, int* __restrict__ slot_off,
+                        int* __restrict__ slot_tile, int* __restrict__ tile_slot)
 {
     const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (k >= n) return;
     if (first[k]) {
         const int s = slotidx[k];
-        const int t = key_tile(keys[k], nsub);
+        const int t = keys[k] / kTile;
         slot_off[s] = (int)k;
         slot_tile[s] = t;
         tile_slot[t] = s;
     }
 }
 
-// band_off[g] = first sorted point of band group g = slot * nsub + band.  A point that starts
-// a group (or follows a run of empty groups) writes the start of every group from the one
-// after its predecessor's up to its own; the last point closes the remaining groups.
-__global__ void k_band_off(const int* __restrict__ keys, const int* __restrict__ first,
-                           const int* __restrict__ slotidx, int64_t n, int nsub, int ngroups,
-                           int* __restrict__ band_off)
+// ---- band records of the spreading sweep ----
+// Every sorted point e gets a record in its own column band (band_w columns) and a second one
+// in the next band when its taps reach it.  Records are sorted by (band, tile row, row), and
+// boff[band * nt1 + tile row] is the first record of that (band, tile row).
+
+// first taps of sorted point e: wrapped cells and offsets
+__device__ inline void rec_taps(const double* __restrict__ sth, const double* __restrict__ sph,
+                                int64_t e, int w, double s1, double s2, int n1, int n2, int& l1,
+                                int& l2, double& d1, double& d2)
+{
+    l1 = wrap_index(first_tap(sth[e], s1, w, d1), n1);
+    l2 = wrap_index(first_tap(sph[e], s2, w, d2), n2);
+}
+
+__global__ void k_rec_count(const double* __restrict__ sth, const double* __restrict__ sph,
+                            int64_t n, int w, double s1, double s2, int n1, int n2, int bw,
+                            int* __restrict__ cnt)
+{
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= n) return;
+    int l1, l2;
+    double d1, d2;
+    rec_taps(sth, sph, e, w, s1, s2, n1, n2, l1, l2, d1, d2);
+    cnt[e] = (l2 % bw) + w - 1 >= bw ? 2 : 1;
+}
+
+__global__ void k_rec_keys(const double* __restrict__ sth, const double* __restrict__ sph,
+                           const int* __restrict__ pos, int64_t n, int w, double s1, double s2,
+                           int n1, int n2, int bw, int nt1, int* __restrict__ keys,
+                           int* __restrict__ ids, int* __restrict__ ent_e,
+                           signed char* __restrict__ ent_c)
+{
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= n) return;
+    int l1, l2;
+    double d1, d2;
+    rec_taps(sth, sph, e, w, s1, s2, n1, n2, l1, l2, d1, d2);
+    const int nbands = n2 / bw;
+    const int band = l2 / bw, cin = l2 % bw;
+    const int tr = l1 / kTile, row = l1 % kTile;
+    const int j = pos[e];
+    keys[j] = (band * nt1 + tr) * kTile + row;
+    ids[j] = j;
+    ent_e[j] = (int)e;
+    ent_c[j] = (signed char)cin;
+    if (cin + w - 1 >= bw) {
+        const int b2 = band + 1 == nbands ? 0 : band + 1;
+        keys[j + 1] = (b2 * nt1 + tr) * kTile + row;
+        ids[j + 1] = j + 1;
+        ent_e[j + 1] = (int)e;
+        ent_c[j + 1] = (signed char)(cin - bw);
+    }
+}
+
+template <typename T>
+__global__ void k_rec_build(const int* __restrict__ ids_s, const int* __restrict__ ent_e,
+                            const signed char* __restrict__ ent_c,
+                            const double* __restrict__ sth, const double* __restrict__ sph,
+                            const int* __restrict__ perm, int64_t nrec, int w, double s1,
+                            double s2, int n1, int n2, BandRec<T>* __restrict__ rec)
 {
     const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (k >= n) return;
-    auto group = [&](int64_t i) {
-        const int slot = slotidx[i] + first[i] - 1;
-        return slot * nsub + (keys[i] / kTile) % nsub;
-    };
-    const int g = group(k);
-    const int gp = k == 0 ? -1 : group(k - 1);
-    for (int h = gp + 1; h <= g; ++h) band_off[h] = (int)k;
-    if (k == n - 1)
-        for (int h = g + 1; h <= ngroups; ++h) band_off[h] = (int)n;
+    if (k >= nrec) return;
+    const int j = ids_s[k];
+    const int e = ent_e[j];
+    int l1, l2;
+    double d1, d2;
+    rec_taps(sth, sph, e, w, s1, s2, n1, n2, l1, l2, d1, d2);
+    BandRec<T> r;
+    r.rc = l1 | (((int)ent_c[j] + 32) << 16);
+    r.src = perm[e];
+    r.s1 = (T)(2.0 * d1 - (double)(w - 1));
+    r.s2 = (T)(2.0 * d2 - (double)(w - 1));
+    rec[k] = r;
+}
+
+// boff[g] = first record of group g = band * nt1 + tile row (records sorted by group): a
+// record that starts a group writes the start of every group after its predecessor's up to
+// its own; the last record closes the remaining groups
+__global__ void k_rec_off(const int* __restrict__ keys_s, int64_t nrec, int ngroups,
+                          int* __restrict__ boff)
+{
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= nrec) return;
+    const int g = keys_s[k] / kTile;
+    const int gp = k == 0 ? -1 : keys_s[k - 1] / kTile;
+    for (int h = gp + 1; h <= g; ++h) boff[h] = (int)k;
+    if (k == nrec - 1)
+        for (int h = g + 1; h <= ngroups; ++h) boff[h] = (int)nrec;
 }
 
 __global__ void k_fill_int(int* p, int64_t n, int v)
@@ -274,10 +338,6 @@ int compute_geometry(int lmax, int mmax, double eps, int dtype, const nusht_plan
         set_last_error("geometry", "dtype must be NUSHT_F64 or NUSHT_MIXED");
         return NUSHT_EINVAL;
     }
-    if (dtype == NUSHT_MIXED && eps < 1e-6) {
-        set_last_error("geometry", "NUSHT_MIXED needs eps >= 1e-6");
-        return NUSHT_EPRECISION;
-    }
     double sigma = 2.0, bpw = 0.0;
     int width = 0, mode = NUSHT_DFS_FUSED;
     if (opts) {
@@ -298,6 +358,12 @@ int compute_geometry(int lmax, int mmax, double eps, int dtype, const nusht_plan
     if (mode != NUSHT_DFS_FUSED && mode != NUSHT_DFS_PAPER) {
         set_last_error("geometry", "unknown dfs_mode");
         return NUSHT_EINVAL;
+    }
+    // FP32 grid, FFTs and taps reach about 2e-7 at sigma = 2 and about 2e-6 at sigma = 1.25
+    // (wider kernel, larger deconvolution factors at the band edge)
+    if (dtype == NUSHT_MIXED && eps < (sigma >= 2.0 ? 1e-6 : 1e-5)) {
+        set_last_error("geometry", "NUSHT_MIXED needs eps >= 1e-6 (sigma >= 2) or 1e-5 (sigma < 2)");
+        return NUSHT_EPRECISION;
     }
     if (opts && opts->kernel_eval != NUSHT_KERNEL_POLY && opts->kernel_eval != NUSHT_KERNEL_EXACT) {
         set_last_error("geometry", "unknown kernel_eval");
@@ -381,8 +447,96 @@ int ensure_capacity(nusht_plan_s* p, int nmaps)
         p->Wbytes = fine_spec;
     }
     if (!p->V) NUSHT_TRY(dmalloc(&p->V, (size_t)g.npts * 4));
+    // tile subgrids of the wide-kernel spreading: one group of up to four maps at a time
+    if (spread_uses_tiles(p) && !p->Z) {
+        const int P = kTile + g.width - 1;
+        const size_t zb = (size_t)std::max(p->nslots, 1) * P * P * 4 * e;
+        NUSHT_TRY(dmalloc((char**)&p->Z, zb));
+        p->Zbytes = zb;
+    }
     p->bcap = nmaps;
     return NUSHT_OK;
+}
+
+// Records of the spreading sweep (after bin_points: needs the sorted points).  Synchronises.
+int build_band_records(nusht_plan_s* p, hipStream_t s)
+{
+    const nusht_geometry& g = p->g;
+    const int64_t n = g.npts;
+    const int w = g.width, bw = band_width_for(w);
+    const int nt1 = g.n1 / kTile, nbands = g.n2 / bw;
+    const double s1 = g.n1 / (2.0 * M_PI), s2 = g.n2 / (2.0 * M_PI);
+    p->band_w = bw;
+    const int64_t ngroups = (int64_t)nbands * nt1;
+    if (ngroups * kTile >= (1LL << 31) || 2 * n >= (1LL << 31) || g.n1 > 65536) {
+        set_last_error("nusht_plan", "fine grid or point count too large for the band records");
+        return NUSHT_EINVAL;
+    }
+    int *cnt = nullptr, *pos = nullptr, *keys = nullptr, *keys_s = nullptr, *ids = nullptr,
+        *ids_s = nullptr, *ent_e = nullptr;
+    signed char* ent_c = nullptr;
+    void* tmp = nullptr;
+    int rc = NUSHT_OK;
+    const int blocks = (int)((n + 255) / 256);
+    do {
+        if ((rc = dmalloc(&cnt, n)) || (rc = dmalloc(&pos, n))) break;
+        hipLaunchKernelGGL(k_rec_count, dim3(blocks), dim3(256), 0, s, p->sth, p->sph, n, w, s1,
+                           s2, g.n1, g.n2, bw, cnt);
+        size_t tb = 0, tb2 = 0;
+        if (hipcub::DeviceScan::ExclusiveSum(nullptr, tb, cnt, pos, (int)n, s) != hipSuccess) { rc = NUSHT_EDEVICE; break; }
+        if ((rc = dmalloc((char**)&tmp, tb + 16))) break;
+        if (hipcub::DeviceScan::ExclusiveSum(tmp, tb, cnt, pos, (int)n, s) != hipSuccess) { rc = NUSHT_EDEVICE; break; }
+        int last_pos = 0, last_cnt = 0;
+        if (hipMemcpyAsync(&last_pos, pos + n - 1, sizeof(int), hipMemcpyDeviceToHost, s) != hipSuccess ||
+            hipMemcpyAsync(&last_cnt, cnt + n - 1, sizeof(int), hipMemcpyDeviceToHost, s) != hipSuccess ||
+            hipStreamSynchronize(s) != hipSuccess) { rc = NUSHT_EDEVICE; break; }
+        const int64_t nrec = (int64_t)last_pos + last_cnt;
+        p->nrec = nrec;
+        if ((rc = dmalloc(&keys, nrec)) || (rc = dmalloc(&keys_s, nrec)) || (rc = dmalloc(&ids, nrec)) ||
+            (rc = dmalloc(&ids_s, nrec)) || (rc = dmalloc(&ent_e, nrec)) || (rc = dmalloc(&ent_c, nrec)) ||
+            (rc = dmalloc(&p->boff, ngroups + 1)))
+            break;
+        hipLaunchKernelGGL(k_rec_keys, dim3(blocks), dim3(256), 0, s, p->sth, p->sph, pos, n, w, s1,
+                           s2, g.n1, g.n2, bw, nt1, keys, ids, ent_e, ent_c);
+        int bits = 1;
+        while ((1LL << bits) < ngroups * kTile) ++bits;
+        if (hipcub::DeviceRadixSort::SortPairs(nullptr, tb2, keys, keys_s, ids, ids_s, (int)nrec, 0,
+                                               bits, s) != hipSuccess) { rc = NUSHT_EDEVICE; break; }
+        if (tb2 > tb) {
+            if (hipStreamSynchronize(s) != hipSuccess) { rc = NUSHT_EDEVICE; break; }
+            hipFree(tmp);
+            tmp = nullptr;
+            if ((rc = dmalloc((char**)&tmp, tb2 + 16))) break;
+            tb = tb2;
+        }
+        if (hipcub::DeviceRadixSort::SortPairs(tmp, tb, keys, keys_s, ids, ids_s, (int)nrec, 0, bits,
+                                               s) != hipSuccess) { rc = NUSHT_EDEVICE; break; }
+        const int rblocks = (int)((nrec + 255) / 256);
+        if (g.dtype == NUSHT_MIXED) {
+            if ((rc = dmalloc((BandRec<float>**)&p->brec, nrec))) break;
+            hipLaunchKernelGGL(k_rec_build<float>, dim3(rblocks), dim3(256), 0, s, ids_s, ent_e,
+                               ent_c, p->sth, p->sph, p->perm, nrec, w, s1, s2, g.n1, g.n2,
+                               reinterpret_cast<BandRec<float>*>(p->brec));
+        } else {
+            if ((rc = dmalloc((BandRec<double>**)&p->brec, nrec))) break;
+            hipLaunchKernelGGL(k_rec_build<double>, dim3(rblocks), dim3(256), 0, s, ids_s, ent_e,
+                               ent_c, p->sth, p->sph, p->perm, nrec, w, s1, s2, g.n1, g.n2,
+                               reinterpret_cast<BandRec<double>*>(p->brec));
+        }
+        hipLaunchKernelGGL(k_rec_off, dim3(rblocks), dim3(256), 0, s, keys_s, nrec, (int)ngroups,
+                           p->boff);
+        if (hipGetLastError() != hipSuccess || hipStreamSynchronize(s) != hipSuccess) { rc = NUSHT_EDEVICE; break; }
+    } while (0);
+    hipFree(cnt);
+    hipFree(pos);
+    hipFree(keys);
+    hipFree(keys_s);
+    hipFree(ids);
+    hipFree(ids_s);
+    hipFree(ent_e);
+    hipFree(ent_c);
+    hipFree(tmp);
+    return rc;
 }
 
 int bin_points(nusht_plan_s* p, const double* theta, const double* phi, hipStream_t s)
@@ -398,12 +552,9 @@ int bin_points(nusht_plan_s* p, const double* theta, const double* phi, hipStrea
     int rc = NUSHT_OK;
     size_t tbytes = 0, t2 = 0;
     const int blocks = (int)((n + 255) / 256);
-    p->band_w = band_width_for(g.width);
-    p->nsub = kTile / p->band_w;
-    const int nsub = p->nsub;
     int bits = 1;
-    while ((1LL << bits) < ntiles * kTile * nsub) ++bits;
-    if (ntiles * kTile * nsub >= (1LL << 31)) {
+    while ((1LL << bits) < ntiles * kTile) ++bits;
+    if (ntiles * kTile >= (1LL << 31)) {
         set_last_error("nusht_plan", "fine grid too large for 32-bit bin keys");
         return NUSHT_EINVAL;
     }
@@ -418,8 +569,8 @@ int bin_points(nusht_plan_s* p, const double* theta, const double* phi, hipStrea
         if (hipMemsetAsync(p->dflag, 0, sizeof(int), s) != hipSuccess ||
             hipMemsetAsync(p->dstatus, 0, sizeof(int), s) != hipSuccess) { rc = NUSHT_EDEVICE; break; }
         hipLaunchKernelGGL(k_bin_keys, dim3(blocks), dim3(256), 0, s, theta, phi, n, g.width,
-                           g.n1 / (2.0 * M_PI), g.n2 / (2.0 * M_PI), g.n1, g.n2, p->nt2,
-                           p->band_w, phw, keys, idx, p->dflag);
+                           g.n1 / (2.0 * M_PI), g.n2 / (2.0 * M_PI), g.n1, g.n2, p->nt2, phw,
+                           keys, idx, p->dflag);
         if (hipcub::DeviceRadixSort::SortPairs(nullptr, tbytes, keys, keys_s, idx, p->perm,
                                                (int)n, 0, bits, s) != hipSuccess) { rc = NUSHT_EDEVICE; break; }
         if (hipcub::DeviceScan::ExclusiveSum(nullptr, t2, first, sidx, (int)n, s) != hipSuccess) { rc = NUSHT_EDEVICE; break; }
@@ -429,7 +580,7 @@ int bin_points(nusht_plan_s* p, const double* theta, const double* phi, hipStrea
                                                bits, s) != hipSuccess) { rc = NUSHT_EDEVICE; break; }
         hipLaunchKernelGGL(k_gather_sorted, dim3(blocks), dim3(256), 0, s, theta, phw, p->perm, n,
                            p->sth, p->sph, p->iperm);
-        hipLaunchKernelGGL(k_mark, dim3(blocks), dim3(256), 0, s, keys_s, n, nsub, first);
+        hipLaunchKernelGGL(k_mark, dim3(blocks), dim3(256), 0, s, keys_s, n, first);
         if (hipcub::DeviceScan::ExclusiveSum(tmp, tbytes, first, sidx, (int)n, s) != hipSuccess) { rc = NUSHT_EDEVICE; break; }
         int last_first = 0, last_idx = 0, flag = 0;
         if (hipMemcpyAsync(&last_first, first + n - 1, sizeof(int), hipMemcpyDeviceToHost, s) != hipSuccess ||
@@ -442,16 +593,12 @@ int bin_points(nusht_plan_s* p, const double* theta, const double* phi, hipStrea
             break;
         }
         p->nslots = last_idx + last_first;
-        const int ngroups = p->nslots * nsub;
-        if ((rc = dmalloc(&p->slot_off, p->nslots + 1)) || (rc = dmalloc(&p->slot_tile, p->nslots)) ||
-            (rc = dmalloc(&p->band_off, ngroups + 1)))
+        if ((rc = dmalloc(&p->slot_off, p->nslots + 1)) || (rc = dmalloc(&p->slot_tile, p->nslots)))
             break;
         hipLaunchKernelGGL(k_fill_int, dim3((int)((ntiles + 255) / 256)), dim3(256), 0, s,
                            p->tile_slot, ntiles, -1);
-        hipLaunchKernelGGL(k_slots, dim3(blocks), dim3(256), 0, s, keys_s, first, sidx, n, nsub,
+        hipLaunchKernelGGL(k_slots, dim3(blocks), dim3(256), 0, s, keys_s, first, sidx, n,
                            p->slot_off, p->slot_tile, p->tile_slot);
-        hipLaunchKernelGGL(k_band_off, dim3(blocks), dim3(256), 0, s, keys_s, first, sidx, n,
-                           nsub, ngroups, p->band_off);
         const int nn = (int)n;
         if (hipMemcpyAsync(p->slot_off + p->nslots, &nn, sizeof(int), hipMemcpyHostToDevice, s) != hipSuccess ||
             hipStreamSynchronize(s) != hipSuccess) { rc = NUSHT_EDEVICE; break; }
@@ -727,7 +874,7 @@ void nusht_destroy(nusht_plan_t p)
     void* bufs[] = {p->rec,  p->cm_mant, p->cm_exp,   p->dec1,      p->dec2,      p->dec1f,
                     p->dec2f, p->sth,    p->sph,      p->perm,      p->iperm,     p->V,
                     p->slot_off,  p->slot_tile,
-                    p->tile_slot, p->band_off, p->dflag, p->dstatus, p->X,     p->Y,         p->W,
+                    p->tile_slot, p->boff, p->brec, p->dflag, p->dstatus, p->X,     p->Y,         p->W,   p->Z,
                     p->fftwork,   p->rowtw,
                     p->red,      p->jlive,  p->jscale, p->adj_part, p->es_coef, p->es_coeff};
     for (void* b : bufs)
@@ -767,6 +914,7 @@ int nusht_plan_ex(int lmax, int mmax, int64_t npts, const double* theta, const d
         p->es_eval = opts ? opts->kernel_eval : 0;
         if ((rc = build_tables(p))) break;
         if ((rc = bin_points(p, theta, phi, s))) break;
+        if ((rc = build_band_records(p, s))) break;
         p->g.ntiles_used = p->nslots;
         if ((rc = create_fft_plans(p))) break;
         if (p->timing) {

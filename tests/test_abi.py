@@ -73,8 +73,19 @@ def test_geometry_validation():
     o = P._binding._opts(sigma=1.25)
     assert lib.nusht_geometry_for(5, 5, 1e-12, 0, ctypes.byref(o), ctypes.byref(g)) == \
         P.NUSHT_EINVAL  # would need w > 16
+    # the mixed-precision floor is 1e-6 at sigma = 2 and 1e-5 below
+    assert lib.nusht_geometry_for(5, 5, 1e-6, P.NUSHT_MIXED, None, ctypes.byref(g)) == P.NUSHT_OK
+    o = P._binding._opts(sigma=1.25)
+    assert lib.nusht_geometry_for(5, 5, 1e-6, P.NUSHT_MIXED, ctypes.byref(o), ctypes.byref(g)) \
+        == P.NUSHT_EPRECISION
+    assert lib.nusht_geometry_for(5, 5, 1e-5, P.NUSHT_MIXED, ctypes.byref(o), ctypes.byref(g)) \
+        == P.NUSHT_OK
     o = P._binding._opts()
     o.reserved[2] = 1
+    assert lib.nusht_geometry_for(5, 5, 1e-6, 0, ctypes.byref(o), ctypes.byref(g)) == \
+        P.NUSHT_EINVAL
+    o = P._binding._opts()
+    o.kernel_eval = 5
     assert lib.nusht_geometry_for(5, 5, 1e-6, 0, ctypes.byref(o), ctypes.byref(g)) == \
         P.NUSHT_EINVAL
     # null plan handles are rejected before any device work

@@ -281,7 +281,7 @@ def test_eps_eff_curve(P, oracle_mod):
     runs = [(2.0, "f64", [1e-2, 1e-4, 1e-6, 1e-8, 1e-10, 1e-12]),
             (2.0, "mixed", [1e-2, 1e-4, 1e-6]),
             (1.25, "f64", [1e-2, 1e-4, 1e-6, 1e-8, 1e-9]),
-            (1.25, "mixed", [1e-2, 1e-4, 1e-6])]
+            (1.25, "mixed", [1e-2, 1e-4, 1e-5])]
     for sigma, dtype, epss in runs:
         for eps in epss:
             for kev in ("poly", "exact"):

@@ -71,11 +71,12 @@ def test_pointing_matches_oracle(P, oracle_mod, lmax, rings):
     moved = arc(T, Ph, t_ref, p_ref)
     print(f"  max distance to the oracle {d.max():.2e} rad (deflections up to "
           f"{moved.max():.2e} rad)", flush=True)
-    # alpha carries the plan's relative error (1e-12) times the gradient scale, and
-    # alpha_phi = dPhi/dphi / sin(theta) amplifies it by up to 1 / sin(pi / (2 rings)) on the
-    # rings next to the poles
+    # alpha carries the derivative synthesis' relative error (the derivative taps amplify the
+    # plan's 1e-12; its gradient test allows 1e-9 at small sizes) times the gradient scale,
+    # and alpha_phi = dPhi/dphi / sin(theta) amplifies it by up to 1 / sin(pi / (2 rings)) on
+    # the rings next to the poles
     amp = 1.0 / np.sin(0.5 * np.pi / rings)
-    assert d.max() <= 1e-11 * moved.max() * amp
+    assert d.max() <= 1e-10 * moved.max() * amp
     # mixed plans cannot run the derivative synthesis
     plm = P.Plan(lmax, lmax, dev(T), dev(Ph), 1e-5, dtype="mixed")
     with pytest.raises(P.NushtError) as e:
