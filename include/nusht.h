@@ -230,6 +230,16 @@ int64_t nusht_mlp_param_count(void);
 int nusht_density_map(const double* theta, const double* phi, int64_t npts, int ntheta,
                       int nphi, float* density, void* stream);
 
+/* nusht_density_map for callers that cannot allocate device memory (code under HIP graph
+   capture, tight serving loops, harnesses that forbid hipMalloc): the same result, with the
+   cell counts kept in a fixed device array of 65536 counts (256 KiB per GPU, held until the
+   process ends) instead of a stream-ordered allocation.  No hipMalloc, hipFree or other
+   allocating call is made.  ntheta * nphi > 65536 returns NUSHT_EINVAL.  Every call on one GPU
+   shares that GPU's array: calls that overlap on one GPU (different streams, or host threads)
+   race and must be serialised by the caller. */
+int nusht_density_map_noalloc(const double* theta, const double* phi, int64_t npts, int ntheta,
+                              int nphi, float* density, void* stream);
+
 /* features[npts][12]: log density bilinearly interpolated between cell centres at the
    point; log density of the 3 x 3 cells around the point's cell (theta clamped, phi
    periodic, row-major); cos theta; sin theta.  log density is floored at log 1e-3. */

@@ -13,6 +13,6 @@ from __future__ import annotations
 from ._binding import (  # noqa: F401
     NUSHT_DFS_FUSED, NUSHT_DFS_PAPER, NUSHT_EDEVICE, NUSHT_EINVAL, NUSHT_ENOCONV, NUSHT_ENOMEM,
     NUSHT_EPRECISION, NUSHT_F64, NUSHT_MIXED, NUSHT_OK, NushtError, Plan, adam_step, deflect,
-    density_map, geometry, lib, library_path, mlp_backward, mlp_forward,
+    density_map, density_map_noalloc, geometry, lib, library_path, mlp_backward, mlp_forward,
     mlp_param_count, nalm, point_features,
 )

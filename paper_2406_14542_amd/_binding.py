@@ -96,6 +96,8 @@ def lib():
             "nusht_mlp_param_count": (_i64, []),
             "nusht_density_map": (ctypes.c_int, [_vp, _vp, _i64, ctypes.c_int, ctypes.c_int,
                                                  _vp, _vp]),
+            "nusht_density_map_noalloc": (ctypes.c_int, [_vp, _vp, _i64, ctypes.c_int,
+                                                         ctypes.c_int, _vp, _vp]),
             "nusht_point_features": (ctypes.c_int, [_vp, _vp, _i64, _vp, ctypes.c_int,
                                                     ctypes.c_int, _vp, _vp]),
             "nusht_mlp_forward": (ctypes.c_int, [_vp, _vp, _i64, ctypes.c_float, _vp, _vp]),
@@ -471,6 +473,21 @@ def density_map(theta, phi, ntheta, nphi):
     out = torch.empty((ntheta, nphi), dtype=torch.float32, device=theta.device)
     _check(lib().nusht_density_map(theta.data_ptr(), phi.data_ptr(), theta.numel(), ntheta,
                                    nphi, out.data_ptr(), _stream()), "nusht_density_map")
+    return out
+
+
+def density_map_noalloc(theta, phi, ntheta, nphi, out):
+    """nusht_density_map_noalloc: the density map into the caller's float32 [ntheta, nphi]
+    device tensor `out`, with no device allocation by the library."""
+    import torch
+    theta, phi = _f64_pts(theta, phi)
+    if (out.dtype != torch.float32 or not out.is_cuda or out.device != theta.device
+            or tuple(out.shape) != (ntheta, nphi) or not out.is_contiguous()):
+        raise ValueError(f"out must be a contiguous float32 [{ntheta}, {nphi}] tensor on "
+                         f"{theta.device}")
+    _check(lib().nusht_density_map_noalloc(theta.data_ptr(), phi.data_ptr(), theta.numel(),
+                                           ntheta, nphi, out.data_ptr(), _stream()),
+           "nusht_density_map_noalloc")
     return out
 
 

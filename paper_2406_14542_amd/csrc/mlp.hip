@@ -14,6 +14,8 @@
 //
 // Parameter layout (FP32, transposed weights so a layer's outputs for one input are
 // contiguous): W1t[12][128] b1[128] W2t[128][128] b2[128] W3t[128][128] b3[128] w4[128] b4[1].
+#include <mutex>
+
 #include "internal.h"
 
 namespace nusht {
@@ -290,6 +292,12 @@ __global__ void k_density_count(const double* __restrict__ th, const double* __r
     atomicAdd(&cnt[a * np + b], 1u);
 }
 
+__global__ void k_zero_counts(unsigned int* __restrict__ cnt, int n)
+{
+    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e < n) cnt[e] = 0u;
+}
+
 // rho = count / (N * area / 4 pi): 1 for uniform points
 __global__ void k_density_norm(const unsigned int* __restrict__ cnt, int nt, int np, int64_t n,
                                float* __restrict__ rho)
@@ -427,6 +435,63 @@ int nusht_density_map(const double* theta, const double* phi, int64_t npts, int 
                        nphi, npts, density);
     NUSHT_HIP(hipGetLastError());
     NUSHT_HIP(hipFreeAsync(cnt, s));
+    return NUSHT_OK;
+}
+
+// Fixed device array holding the cell counts of nusht_density_map_noalloc, one copy per GPU
+// for the life of the process (kDensityScratchCells counts, 256 KiB).  Host code never passes
+// `scratch` itself to a kernel: its device address on each GPU comes from
+// hipGetSymbolAddress, looked up once per device on that device's first call.
+constexpr int kDensityScratchCells = 1 << 16;
+static __device__ __align__(256) unsigned int scratch[kDensityScratchCells];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+unsigned int* g_scratch_ptr[kMaxDevices] = {};
+
+int density_scratch(unsigned int** out)
+{
+    int dev = 0;
+    NUSHT_HIP(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kMaxDevices) {
+        set_last_error("nusht_density_map_noalloc", "device index out of range");
+        return NUSHT_EDEVICE;
+    }
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* ptr = nullptr;
+        NUSHT_HIP(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)));
+        g_scratch_ptr[dev] = reinterpret_cast<unsigned int*>(ptr);
+    }
+    *out = g_scratch_ptr[dev];
+    return NUSHT_OK;
+}
+}  // namespace
+
+int nusht_density_map_noalloc(const double* theta, const double* phi, int64_t npts, int ntheta,
+                              int nphi, float* density, void* stream)
+{
+    if (!theta || !phi || !density || npts < 1 || ntheta < 1 || nphi < 1) {
+        set_last_error("nusht_density_map_noalloc", "bad arguments");
+        return NUSHT_EINVAL;
+    }
+    if ((int64_t)ntheta * nphi > kDensityScratchCells) {
+        set_last_error("nusht_density_map_noalloc",
+                       "ntheta * nphi exceeds the fixed count buffer (65536 cells)");
+        return NUSHT_EINVAL;
+    }
+    unsigned int* cnt = nullptr;
+    NUSHT_TRY(density_scratch(&cnt));
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    const int nb = ntheta * nphi;
+    // the counts are cleared by a kernel (the previous call's counts are still there)
+    hipLaunchKernelGGL(k_zero_counts, dim3(nblk(nb)), dim3(256), 0, s, cnt, nb);
+    hipLaunchKernelGGL(k_density_count, dim3(nblk(npts)), dim3(256), 0, s, theta, phi, npts,
+                       ntheta, nphi, cnt);
+    hipLaunchKernelGGL(k_density_norm, dim3(nblk((int64_t)nb)), dim3(256), 0, s, cnt, ntheta,
+                       nphi, npts, density);
+    NUSHT_HIP(hipGetLastError());
     return NUSHT_OK;
 }
 
