@@ -264,6 +264,9 @@ def run_cg(args):
             res[kind] = {"iters": it, "relres": rr, "s": round(time.perf_counter() - t1, 3),
                          "iters_to": {f"{m:g}": first_below(h, m) for m in marks}}
         rows.append(res)
+        if args.cg_rows:
+            with open(args.cg_rows, "a") as fh:
+                fh.write(json.dumps(res) + "\n")
         log(f"held-out {1160 + s}: " + ", ".join(
             f"{k} {res[k]['iters']} it ({res[k]['relres']:.2e}), to 1e-4 in "
             f"{res[k]['iters_to']['0.0001']}" for k in ("plain", "learned", "analytic")))
@@ -292,6 +295,75 @@ def run_cg(args):
            "wall_s_mean": {k: float(np.mean([r[k]["s"] for r in rows]))
                            for k in ("plain", "learned", "analytic")},
            "held_out": rows}
+    print(json.dumps(out), flush=True)
+
+
+def run_pointing(args):
+    """Lensing-pointing leg (`--pointing`, App. C, Fig. C1): for each lmax, a regular grid of
+    (lmax + 1) rings x (2 lmax + 1) pixels (ring centres, pixel 0 at phi = 0) and a potential
+    Phi_lm with C_l ~ l^-4 scaled to 2.5' rms deflection.  Times, after one warm-up call, the
+    whole pointing (derivative synthesis for Eq. C2, then Eq. C1 per point) and the Eq. (C1)
+    kernel on its own (nusht_deflect on the resulting alpha), FP64 plans at `--pointing-eps`.
+    Prints ONE JSON line."""
+    import torch
+    import paper_2406_14542_amd as P
+    from paper_2406_14542_amd import inputs
+
+    P.lib()
+    rows = []
+    for L in [int(x) for x in args.pointing_lmax.split(",") if x]:
+        rings, pix = L + 1, 2 * L + 1
+        th1 = (np.arange(rings) + 0.5) * np.pi / rings
+        ph1 = 2.0 * np.pi * np.arange(pix) / pix
+        T, Ph = np.meshgrid(th1, ph1, indexing="ij")
+        th = torch.from_numpy(np.ascontiguousarray(T.ravel())).cuda()
+        ph = torch.from_numpy(np.ascontiguousarray(Ph.ravel())).cuda()
+        dlm = torch.from_numpy(inputs.potential_alm(np.random.default_rng(105), L, L, 2.5)).cuda()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        pl = P.Plan(L, L, th, ph, args.pointing_eps)
+        torch.cuda.synchronize()
+        plan_s = time.perf_counter() - t0
+        n = pl.npts
+        pl.pointing(dlm)
+        _, dth, dph = pl.synthesis_deriv(dlm)
+        s = torch.sin(th)
+        ath = dth[0].contiguous()
+        aph = torch.where(s != 0, dph[0] / s, torch.zeros_like(s)).contiguous()
+        t2, p2 = P.deflect(th, ph, ath, aph)
+        torch.cuda.synchronize()
+        times, ktimes = [], []
+        for _ in range(max(args.steps, 1)):
+            t0 = time.perf_counter()
+            pl.pointing(dlm)
+            torch.cuda.synchronize()
+            times.append(time.perf_counter() - t0)
+        ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        for _ in range(max(args.steps, 1)):
+            ev0.record()
+            t2, p2 = P.deflect(th, ph, ath, aph)
+            ev1.record()
+            torch.cuda.synchronize()
+            ktimes.append(ev0.elapsed_time(ev1) * 1e-3)
+        pl.status()
+        t = float(np.median(times))
+        k = float(np.median(ktimes))
+        rows.append({"lmax": L, "npts": n, "plan_s": round(plan_s, 3),
+                     "pointing_ms": round(1e3 * t, 3), "pointing_gpts_s": round(n / t / 1e9, 3),
+                     "c1_kernel_ms": round(1e3 * k, 4),
+                     "c1_kernel_gbs": round(48.0 * n / k / 1e9, 1)})
+        log(f"pointing lmax {L}: N = {n}, {1e3 * t:.2f} ms ({n / t / 1e9:.2f} Gpts/s); "
+            f"Eq. C1 kernel alone {1e3 * k:.3f} ms")
+        pl.close()
+        del th, ph, dlm, dth, dph, ath, aph, t2, p2, s
+        torch.cuda.empty_cache()
+    out = {"metric": "lensing pointing time (Eq. C2 + C1) per call", "value": rows[-1]["pointing_ms"],
+           "unit": "ms", "n_gpus": 1, "steps": max(args.steps, 1), "higher_is_better": False,
+           "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+           "config": {"workload": "regular grids of (lmax+1) x (2 lmax+1) points, potential "
+                                  "C_l ~ l^-4 at 2.5 arcmin rms deflection",
+                      "eps": args.pointing_eps},
+           "c1_kernel_bytes_per_point": 48, "rows": rows}
     print(json.dumps(out), flush=True)
 
 
@@ -324,6 +396,12 @@ def main():
     ap.add_argument("--cg-seed", type=int, default=7)
     ap.add_argument("--cg-save", default="gpurun_out/c5_network.npz")
     ap.add_argument("--cg-load", default="gpurun_out/c5_network.npz")
+    ap.add_argument("--cg-rows", default="",
+                    help="eval: also append each held-out row to this JSON-lines file as it ends")
+    ap.add_argument("--pointing", action="store_true",
+                    help="run the lensing-pointing leg (Eq. C2 + C1) instead of the transform step")
+    ap.add_argument("--pointing-lmax", default="1023,2047,4095")
+    ap.add_argument("--pointing-eps", type=float, default=1e-12)
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
                     help="only run one elementwise device copy of BYTES bytes (the reference "
                          "kernel that scales HBM byte counters)")
@@ -342,6 +420,9 @@ def main():
         print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported",
               file=sys.stderr)
         sys.exit(2)
+    if args.pointing:
+        run_pointing(args)
+        return
     if args.cg:
         run_cg(args)
         return

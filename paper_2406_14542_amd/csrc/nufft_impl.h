@@ -557,28 +557,141 @@ __device__ inline int band_lower_bound(const BandRec<T>* __restrict__ recs, int 
     return a;
 }
 
-// r = lane's bit of mask ? b : a, per lane, on registers (v_cndmask with the lane mask in an
-// SGPR pair).  Written out so that the compiler keeps the register rows of the spreading sweep
-// in place: a select it is free to rewrite became a select between two addresses, which put
-// the rows in scratch memory.
-__device__ inline float lane_select(float a, float b, uint64_t mask)
-{
-    float r;
-    asm("v_cndmask_b32_e64 %0, %1, %2, %3" : "=v"(r) : "v"(a), "v"(b), "s"(mask));
-    return r;
-}
+// Row shift of the spreading sweep for one map: r[a] = lane's bit of mk ? r[a + 1] : r[a]
+// (a < W - 1), r[W - 1] = lane's bit of mk ? 0 : r[W - 1], as one block of in-place selects
+// on the registers themselves, in ascending a (each r[a + 1] is read before it is
+// replaced).  One statement for the whole shift leaves the compiler no room to copy the rows.
+template <int W>
+__device__ inline void shift_rows(uint32_t (&r)[W], uint64_t mk);
 
-__device__ inline double lane_select(double a, double b, uint64_t mask)
+#define NUSHT_SEL(i, j) "v_cndmask_b32_e64 %" #i ", %" #i ", %" #j ", %[mk]\n\t"
+#define NUSHT_SEL0(i) "v_cndmask_b32_e64 %" #i ", %" #i ", 0, %[mk]"
+template <>
+__device__ inline void shift_rows<2>(uint32_t (&r)[2], uint64_t mk)
 {
-    const uint64_t ua = __builtin_bit_cast(uint64_t, a), ub = __builtin_bit_cast(uint64_t, b);
-    unsigned lo, hi;
-    asm("v_cndmask_b32_e64 %0, %1, %2, %3"
-        : "=v"(lo)
-        : "v"((unsigned)ua), "v"((unsigned)ub), "s"(mask));
-    asm("v_cndmask_b32_e64 %0, %1, %2, %3"
-        : "=v"(hi)
-        : "v"((unsigned)(ua >> 32)), "v"((unsigned)(ub >> 32)), "s"(mask));
-    return __builtin_bit_cast(double, ((uint64_t)hi << 32) | lo);
+    asm(NUSHT_SEL(0, 1) NUSHT_SEL0(1)
+        : "+v"(r[0]), "+v"(r[1])
+        : [mk] "s"(mk));
+}
+template <>
+__device__ inline void shift_rows<3>(uint32_t (&r)[3], uint64_t mk)
+{
+    asm(NUSHT_SEL(0, 1) NUSHT_SEL(1, 2) NUSHT_SEL0(2)
+        : "+v"(r[0]), "+v"(r[1]), "+v"(r[2])
+        : [mk] "s"(mk));
+}
+template <>
+__device__ inline void shift_rows<4>(uint32_t (&r)[4], uint64_t mk)
+{
+    asm(NUSHT_SEL(0, 1) NUSHT_SEL(1, 2) NUSHT_SEL(2, 3) NUSHT_SEL0(3)
+        : "+v"(r[0]), "+v"(r[1]), "+v"(r[2]), "+v"(r[3])
+        : [mk] "s"(mk));
+}
+template <>
+__device__ inline void shift_rows<5>(uint32_t (&r)[5], uint64_t mk)
+{
+    asm(NUSHT_SEL(0, 1) NUSHT_SEL(1, 2) NUSHT_SEL(2, 3) NUSHT_SEL(3, 4) NUSHT_SEL0(4)
+        : "+v"(r[0]), "+v"(r[1]), "+v"(r[2]), "+v"(r[3]), "+v"(r[4])
+        : [mk] "s"(mk));
+}
+template <>
+__device__ inline void shift_rows<6>(uint32_t (&r)[6], uint64_t mk)
+{
+    asm(NUSHT_SEL(0, 1) NUSHT_SEL(1, 2) NUSHT_SEL(2, 3) NUSHT_SEL(3, 4) NUSHT_SEL(4, 5) NUSHT_SEL0(5)
+        : "+v"(r[0]), "+v"(r[1]), "+v"(r[2]), "+v"(r[3]), "+v"(r[4]), "+v"(r[5])
+        : [mk] "s"(mk));
+}
+template <>
+__device__ inline void shift_rows<7>(uint32_t (&r)[7], uint64_t mk)
+{
+    asm(NUSHT_SEL(0, 1) NUSHT_SEL(1, 2) NUSHT_SEL(2, 3) NUSHT_SEL(3, 4) NUSHT_SEL(4, 5) NUSHT_SEL(5, 6) NUSHT_SEL0(6)
+        : "+v"(r[0]), "+v"(r[1]), "+v"(r[2]), "+v"(r[3]), "+v"(r[4]), "+v"(r[5]), "+v"(r[6])
+        : [mk] "s"(mk));
+}
+template <>
+__device__ inline void shift_rows<8>(uint32_t (&r)[8], uint64_t mk)
+{
+    asm(NUSHT_SEL(0, 1) NUSHT_SEL(1, 2) NUSHT_SEL(2, 3) NUSHT_SEL(3, 4) NUSHT_SEL(4, 5) NUSHT_SEL(5, 6) NUSHT_SEL(6, 7) NUSHT_SEL0(7)
+        : "+v"(r[0]), "+v"(r[1]), "+v"(r[2]), "+v"(r[3]), "+v"(r[4]), "+v"(r[5]), "+v"(r[6]), "+v"(r[7])
+        : [mk] "s"(mk));
+}
+template <>
+__device__ inline void shift_rows<9>(uint32_t (&r)[9], uint64_t mk)
+{
+    asm(NUSHT_SEL(0, 1) NUSHT_SEL(1, 2) NUSHT_SEL(2, 3) NUSHT_SEL(3, 4) NUSHT_SEL(4, 5) NUSHT_SEL(5, 6) NUSHT_SEL(6, 7) NUSHT_SEL(7, 8) NUSHT_SEL0(8)
+        : "+v"(r[0]), "+v"(r[1]), "+v"(r[2]), "+v"(r[3]), "+v"(r[4]), "+v"(r[5]), "+v"(r[6]), "+v"(r[7]), "+v"(r[8])
+        : [mk] "s"(mk));
+}
+template <>
+__device__ inline void shift_rows<10>(uint32_t (&r)[10], uint64_t mk)
+{
+    asm(NUSHT_SEL(0, 1) NUSHT_SEL(1, 2) NUSHT_SEL(2, 3) NUSHT_SEL(3, 4) NUSHT_SEL(4, 5) NUSHT_SEL(5, 6) NUSHT_SEL(6, 7) NUSHT_SEL(7, 8) NUSHT_SEL(8, 9) NUSHT_SEL0(9)
+        : "+v"(r[0]), "+v"(r[1]), "+v"(r[2]), "+v"(r[3]), "+v"(r[4]), "+v"(r[5]), "+v"(r[6]), "+v"(r[7]), "+v"(r[8]), "+v"(r[9])
+        : [mk] "s"(mk));
+}
+template <>
+__device__ inline void shift_rows<11>(uint32_t (&r)[11], uint64_t mk)
+{
+    asm(NUSHT_SEL(0, 1) NUSHT_SEL(1, 2) NUSHT_SEL(2, 3) NUSHT_SEL(3, 4) NUSHT_SEL(4, 5) NUSHT_SEL(5, 6) NUSHT_SEL(6, 7) NUSHT_SEL(7, 8) NUSHT_SEL(8, 9) NUSHT_SEL(9, 10) NUSHT_SEL0(10)
+        : "+v"(r[0]), "+v"(r[1]), "+v"(r[2]), "+v"(r[3]), "+v"(r[4]), "+v"(r[5]), "+v"(r[6]), "+v"(r[7]), "+v"(r[8]), "+v"(r[9]), "+v"(r[10])
+        : [mk] "s"(mk));
+}
+template <>
+__device__ inline void shift_rows<12>(uint32_t (&r)[12], uint64_t mk)
+{
+    asm(NUSHT_SEL(0, 1) NUSHT_SEL(1, 2) NUSHT_SEL(2, 3) NUSHT_SEL(3, 4) NUSHT_SEL(4, 5) NUSHT_SEL(5, 6) NUSHT_SEL(6, 7) NUSHT_SEL(7, 8) NUSHT_SEL(8, 9) NUSHT_SEL(9, 10) NUSHT_SEL(10, 11) NUSHT_SEL0(11)
+        : "+v"(r[0]), "+v"(r[1]), "+v"(r[2]), "+v"(r[3]), "+v"(r[4]), "+v"(r[5]), "+v"(r[6]), "+v"(r[7]), "+v"(r[8]), "+v"(r[9]), "+v"(r[10]), "+v"(r[11])
+        : [mk] "s"(mk));
+}
+template <>
+__device__ inline void shift_rows<13>(uint32_t (&r)[13], uint64_t mk)
+{
+    asm(NUSHT_SEL(0, 1) NUSHT_SEL(1, 2) NUSHT_SEL(2, 3) NUSHT_SEL(3, 4) NUSHT_SEL(4, 5) NUSHT_SEL(5, 6) NUSHT_SEL(6, 7) NUSHT_SEL(7, 8) NUSHT_SEL(8, 9) NUSHT_SEL(9, 10) NUSHT_SEL(10, 11) NUSHT_SEL(11, 12) NUSHT_SEL0(12)
+        : "+v"(r[0]), "+v"(r[1]), "+v"(r[2]), "+v"(r[3]), "+v"(r[4]), "+v"(r[5]), "+v"(r[6]), "+v"(r[7]), "+v"(r[8]), "+v"(r[9]), "+v"(r[10]), "+v"(r[11]), "+v"(r[12])
+        : [mk] "s"(mk));
+}
+template <>
+__device__ inline void shift_rows<14>(uint32_t (&r)[14], uint64_t mk)
+{
+    asm(NUSHT_SEL(0, 1) NUSHT_SEL(1, 2) NUSHT_SEL(2, 3) NUSHT_SEL(3, 4) NUSHT_SEL(4, 5) NUSHT_SEL(5, 6) NUSHT_SEL(6, 7) NUSHT_SEL(7, 8) NUSHT_SEL(8, 9) NUSHT_SEL(9, 10) NUSHT_SEL(10, 11) NUSHT_SEL(11, 12) NUSHT_SEL(12, 13) NUSHT_SEL0(13)
+        : "+v"(r[0]), "+v"(r[1]), "+v"(r[2]), "+v"(r[3]), "+v"(r[4]), "+v"(r[5]), "+v"(r[6]), "+v"(r[7]), "+v"(r[8]), "+v"(r[9]), "+v"(r[10]), "+v"(r[11]), "+v"(r[12]), "+v"(r[13])
+        : [mk] "s"(mk));
+}
+template <>
+__device__ inline void shift_rows<15>(uint32_t (&r)[15], uint64_t mk)
+{
+    asm(NUSHT_SEL(0, 1) NUSHT_SEL(1, 2) NUSHT_SEL(2, 3) NUSHT_SEL(3, 4) NUSHT_SEL(4, 5) NUSHT_SEL(5, 6) NUSHT_SEL(6, 7) NUSHT_SEL(7, 8) NUSHT_SEL(8, 9) NUSHT_SEL(9, 10) NUSHT_SEL(10, 11) NUSHT_SEL(11, 12) NUSHT_SEL(12, 13) NUSHT_SEL(13, 14) NUSHT_SEL0(14)
+        : "+v"(r[0]), "+v"(r[1]), "+v"(r[2]), "+v"(r[3]), "+v"(r[4]), "+v"(r[5]), "+v"(r[6]), "+v"(r[7]), "+v"(r[8]), "+v"(r[9]), "+v"(r[10]), "+v"(r[11]), "+v"(r[12]), "+v"(r[13]), "+v"(r[14])
+        : [mk] "s"(mk));
+}
+template <>
+__device__ inline void shift_rows<16>(uint32_t (&r)[16], uint64_t mk)
+{
+    asm(NUSHT_SEL(0, 1) NUSHT_SEL(1, 2) NUSHT_SEL(2, 3) NUSHT_SEL(3, 4) NUSHT_SEL(4, 5) NUSHT_SEL(5, 6) NUSHT_SEL(6, 7) NUSHT_SEL(7, 8) NUSHT_SEL(8, 9) NUSHT_SEL(9, 10) NUSHT_SEL(10, 11) NUSHT_SEL(11, 12) NUSHT_SEL(12, 13) NUSHT_SEL(13, 14) NUSHT_SEL(14, 15) NUSHT_SEL0(15)
+        : "+v"(r[0]), "+v"(r[1]), "+v"(r[2]), "+v"(r[3]), "+v"(r[4]), "+v"(r[5]), "+v"(r[6]), "+v"(r[7]), "+v"(r[8]), "+v"(r[9]), "+v"(r[10]), "+v"(r[11]), "+v"(r[12]), "+v"(r[13]), "+v"(r[14]), "+v"(r[15])
+        : [mk] "s"(mk));
+}
+#undef NUSHT_SEL
+#undef NUSHT_SEL0
+
+// N consecutive values from LDS in 16-byte reads (N * sizeof(T) a multiple of 16, or N < that,
+// src aligned to the row size)
+template <typename T, int N>
+__device__ inline void load_row(const T* src, T (&out)[N])
+{
+    constexpr int kBytes = N * (int)sizeof(T);
+    if constexpr (kBytes % 16 == 0) {
+        const float4* s4 = reinterpret_cast<const float4*>(src);
+#pragma unroll
+        for (int i = 0; i < kBytes / 16; ++i) {
+            const float4 x = s4[i];
+            T* o = out + i * (16 / (int)sizeof(T));
+            __builtin_memcpy(o, &x, 16);
+        }
+    } else {
+#pragma unroll
+        for (int i = 0; i < N; ++i) out[i] = src[i];
+    }
 }
 
 template <typename T, int W, int MB, int SW>
@@ -597,7 +710,9 @@ __global__ __launch_bounds__(256) void k_spread_band(const BandRec<T>* __restric
         T s1, s2;
     };
     __shared__ Staged s_rec[4][64];
-    __shared__ T s_val[4][64 * MB];
+    __shared__ __align__(16) T s_val[4][64 * MB];
+    // the current point's taps: row tap q and column tap q of each group, from its lane q
+    __shared__ __align__(16) T s_tap[4][2][64];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int grp = lane / SW, q = lane - grp * SW;
     const int band = (int)(blockIdx.x * 4 + wave) * K + grp;
@@ -666,12 +781,52 @@ __global__ __launch_bounds__(256) void k_spread_band(const BandRec<T>* __restric
         }
         const uint64_t mask = __builtin_amdgcn_ballot_w64(adv);
 #pragma unroll
-        for (int a = 0; a < W - 1; ++a)
+        for (int m = 0; m < MB; ++m) {
+            if constexpr (sizeof(T) == 4) {
+                uint32_t r[W];
 #pragma unroll
-            for (int m = 0; m < MB; ++m) acc[a][m] = lane_select(acc[a][m], acc[a + 1][m], mask);
+                for (int a = 0; a < W; ++a) r[a] = __builtin_bit_cast(uint32_t, acc[a][m]);
+                shift_rows<W>(r, mask);
 #pragma unroll
-        for (int m = 0; m < MB; ++m) acc[W - 1][m] = lane_select(acc[W - 1][m], T(0), mask);
+                for (int a = 0; a < W; ++a) acc[a][m] = __builtin_bit_cast(T, r[a]);
+            } else {
+                uint32_t lo[W], hi[W];
+#pragma unroll
+                for (int a = 0; a < W; ++a) {
+                    const uint64_t u = __builtin_bit_cast(uint64_t, acc[a][m]);
+                    lo[a] = (uint32_t)u;
+                    hi[a] = (uint32_t)(u >> 32);
+                }
+                shift_rows<W>(lo, mask);
+                shift_rows<W>(hi, mask);
+#pragma unroll
+                for (int a = 0; a < W; ++a)
+                    acc[a][m] = __builtin_bit_cast(T, ((uint64_t)hi[a] << 32) | lo[a]);
+            }
+        }
         R += adv ? 1 : 0;
+    };
+
+    // push rows R .. tgt - 1 out of the lanes that are behind tgt: up to W row shifts with the
+    // rows in registers, unrolled (a loop around the shift made the compiler copy every row
+    // into the loop and back), after which a lane still behind has only zero rows left, and
+    // its remaining rows are written as zeros
+    auto push_to = [&](int tgt) {
+#pragma unroll
+        for (int i = 0; i < W; ++i) {
+            if (!__any(R < tgt)) return;
+            advance(R < tgt);
+        }
+        while (__any(R < tgt)) {
+            const bool adv = R < tgt;
+            if (adv && bvalid && R >= own_lo && R < own_hi) {
+                const int pr = R < 0 ? R + bb.n1 : R;
+                T* o = fine + (int64_t)pr * bb.n2 + c0 + q;
+#pragma unroll
+                for (int m = 0; m < MB; ++m) o[m * map_stride] = T(0);
+            }
+            R += adv ? 1 : 0;
+        }
     };
 
     // pipeline: recA / valA = batch b (staged at the top of iteration b), recB = batch b + 1
@@ -717,36 +872,45 @@ __global__ __launch_bounds__(256) void k_spread_band(const BandRec<T>* __restric
             const int t = b * SW + jj;
             const bool has = bvalid && t < total;
             const Staged h = s_rec[wave][grp * SW + jj];
+            // this lane's taps first (row tap q and column tap q of the group's point), so that
+            // their latency overlaps the row advance; a group without a point has zero taps
+            T t1 = T(0), t2 = T(0);
+            if (poly) {
+                t1 = es_tap_poly<T, W>(h.s1, creg);
+                t2 = es_tap_poly<T, W>(h.s2, creg);
+            } else if (q < W) {
+                // z of tap a = 2 (d - a) / w = (s + w - 1 - 2 a) / w
+                t1 = es_value<T>((h.s1 + T(W - 1 - 2 * q)) * cw * T(0.5), beta);
+                t2 = es_value<T>((h.s2 + T(W - 1 - 2 * q)) * cw * T(0.5), beta);
+            }
+            s_tap[wave][0][lane] = has ? t1 : T(0);
+            s_tap[wave][1][lane] = has ? t2 : T(0);
             // push the rows above the point's first row
             const int target = has ? h.r : R;
-            while (__any(R < target)) advance(R < target);
-            // column tap of this lane, row taps from lanes 0 .. W-1 of the group (a group
-            // without a point adds exact zeros)
+            push_to(target);
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+            // the group's W row taps (one broadcast read), this lane's column tap (tap q - c,
+            // zero outside the point's columns) and the point's MB values
             const int cb = q - h.c;
             const bool act = has && cb >= 0 && cb < W;
-            T p1, p2;
-            if (poly) {
-                const T t1 = (has && q < W) ? es_tap_poly<T, W>(h.s1, creg) : T(0);
-                const T t2 = (has && q < W) ? es_tap_poly<T, W>(h.s2, creg) : T(0);
-                const T t2b = __shfl(t2, grp * SW + (act ? cb : 0), 64);
-                p1 = t1;
-                p2 = act ? t2b : T(0);
-            } else {
-                // z of tap a = 2 (d - a) / w = (s + w - 1 - 2 a) / w
-                p2 = act ? es_value<T>((h.s2 + T(W - 1 - 2 * cb)) * cw * T(0.5), beta) : T(0);
-                p1 = (has && q < W) ? es_value<T>((h.s1 + T(W - 1 - 2 * q)) * cw * T(0.5), beta)
-                                    : T(0);
-            }
+            const T p2 = s_tap[wave][1][grp * SW + (act ? cb : 0)];
+            T rt[SW];
+            load_row<T, SW>(&s_tap[wave][0][grp * SW], rt);
+            T v[MB];
+            load_row<T, MB>(&s_val[wave][(grp * SW + jj) * MB], v);
             T g[MB];
 #pragma unroll
-            for (int m = 0; m < MB; ++m) g[m] = act ? s_val[wave][(grp * SW + jj) * MB + m] * p2
-                                                    : T(0);
+            for (int m = 0; m < MB; ++m) g[m] = act ? v[m] * p2 : T(0);
 #pragma unroll
-            for (int a = 0; a < W; ++a) {
-                const T pa = __shfl(p1, grp * SW + a, 64);
+            for (int a = 0; a < W; ++a)
 #pragma unroll
-                for (int m = 0; m < MB; ++m) acc[a][m] += g[m] * pa;
-            }
+                for (int m = 0; m < MB; ++m) acc[a][m] += g[m] * rt[a];
+            // the taps are read before the next point writes them
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
         }
         // every lane's reads of the staged batch come before the next batch is staged
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
@@ -761,7 +925,7 @@ __global__ __launch_bounds__(256) void k_spread_band(const BandRec<T>* __restric
         voB = voC;
     }
     // the rows after the last point, up to the end of the segment
-    while (__any(R < own_hi)) advance(R < own_hi);
+    push_to(own_hi);
 }
 
 // ---- dispatch over the kernel width ---------------------------------------------------
