@@ -205,9 +205,13 @@ struct BandRec {
 // Maps are processed by the point kernels in groups of four, the remainder one by one.
 inline int group_width(int nmaps, int b) { return (nmaps - b) >= 4 ? 4 : 1; }
 
-// Spreading strategy: the band sweep for kernels of width <= 8 and for deterministic plans;
-// tile subgrids with LDS atomics and a halo pass for wider kernels.
-inline bool spread_uses_tiles(const nusht_plan_s* p) { return p->g.width > 8 && !p->deterministic; }
+// Spreading strategy: the band sweep for every FP32 (mixed-precision) kernel, for FP64 kernels
+// of width <= 8 and for deterministic plans; tile subgrids with LDS atomics and a halo pass for
+// wider FP64 kernels (whose band sweep runs one map per pass).
+inline bool spread_uses_tiles(const nusht_plan_s* p)
+{
+    return p->g.dtype == NUSHT_F64 && p->g.width > 8 && !p->deterministic;
+}
 
 // ---- geometry (plan.hip) ----
 int compute_geometry(int lmax, int mmax, double eps, int dtype, const nusht_plan_opts* opts,

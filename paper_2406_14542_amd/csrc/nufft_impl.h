@@ -9,11 +9,13 @@
 //  * interpolation: a workgroup owns one non-empty tile ("slot") and stages the tile's window
 //    of (kTile + w - 1)^2 cells in LDS once; every point of the tile reads its w x w taps from
 //    LDS; results are written packed per point;
-//  * spreading, w <= 8 or deterministic plans: waves sweep column bands row by row and keep
-//    the rows a point can reach in registers (k_spread_band): every fine cell is written once,
-//    with its points summed in a fixed order, and no atomics or partial grids are involved;
-//  * spreading, w > 8: tile subgrids accumulated with LDS atomics (k_spread_lds) and a halo
-//    pass that sums, for every fine cell, the subgrids of the windows covering it (k_halo).
+//  * spreading, FP32 windows, FP64 windows of w <= 8 and deterministic plans: waves sweep
+//    column bands row by row and keep the rows a point can reach in registers
+//    (k_spread_band): every fine cell is written once, with its points summed in a fixed
+//    order, and no atomics or partial grids are involved;
+//  * spreading, FP64 windows of w > 8: tile subgrids accumulated with LDS atomics
+//    (k_spread_lds) and a halo pass that sums, for every fine cell, the subgrids of the
+//    windows covering it (k_halo).
 // Offsets are formed in FP64 from FP64 coordinates before any cast to the kernel's type T.
 #pragma once
 
@@ -368,9 +370,10 @@ __global__ __launch_bounds__(256) void k_interp_deriv(const double* __restrict__
     }
 }
 
-// Spreading of wide kernels (w > 8), not deterministic: tile subgrids with LDS atomics and a
-// halo pass.  (The band sweep below does only 64 / 16 = 4 points per wave step once w > 8, and
-// its per-point tap and broadcast work then outweighs the atomics this kernel pays.)
+// Spreading of wide FP64 kernels (w > 8), not deterministic: tile subgrids with LDS atomics
+// and a halo pass.  (The band sweep below does only 64 / 16 = 4 points per wave step once
+// w > 8 and runs FP64 maps one per pass; for FP64 its per-point work then outweighs the
+// atomics this kernel pays.)
 // Batched: the block stages up to NB of the slot's points (tap
 // offsets, first cells relative to the tile, values) in LDS, then every wave takes
 // PPW = 64 / LPP points at a time with LPP lanes per point, lane = column tap: each lane forms
