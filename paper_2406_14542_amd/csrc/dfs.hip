@@ -234,8 +234,9 @@ __global__ __launch_bounds__(256) void k_band_to_rows(const C* __restrict__ band
     }
 }
 
-// band[mu][i] = rows[i][mu] for window rows, 0 for the other rows; mu <= M.
-template <typename C>
+// band[mu][i] = rows[i][mu] for window rows, 0 for the other rows; mu <= M.  COMPACT: the
+// window rows only (tile rows index the compact rows q < ra + rb), nothing else written.
+template <typename C, bool COMPACT>
 __global__ __launch_bounds__(256) void k_rows_to_band(const C* __restrict__ rows,
                                                       C* __restrict__ band, int n1, int fw,
                                                       int ncol, int ra, int rb)
@@ -243,19 +244,22 @@ __global__ __launch_bounds__(256) void k_rows_to_band(const C* __restrict__ rows
     __shared__ C tile[kT][kT + 1];
     const int i0 = blockIdx.y * kT, mu0 = blockIdx.x * kT;
     const int tx = threadIdx.x, ty = threadIdx.y;
+    const int nrow = COMPACT ? ra + rb : n1;
     // read along mu (contiguous in the row spectrum)
     for (int r = ty; r < kT; r += blockDim.y) {
-        const int i = i0 + r, mu = mu0 + tx;
+        const int q = i0 + r, mu = mu0 + tx;
+        const int i = COMPACT ? window_row(q, ra, rb, n1) : q;
         C v;
         v.x = 0;
         v.y = 0;
-        if (i < n1 && mu < ncol && (i < ra || i >= n1 - rb)) v = rows[(int64_t)i * fw + mu];
+        if (q < nrow && mu < ncol && (i < ra || i >= n1 - rb)) v = rows[(int64_t)i * fw + mu];
         tile[r][tx] = v;
     }
     __syncthreads();
     for (int r = ty; r < kT; r += blockDim.y) {
-        const int mu = mu0 + r, i = i0 + tx;
-        if (mu >= ncol || i >= n1) continue;
+        const int mu = mu0 + r, q = i0 + tx;
+        if (mu >= ncol || q >= nrow) continue;
+        const int i = COMPACT ? window_row(q, ra, rb, n1) : q;
         band[(int64_t)mu * n1 + i] = tile[tx][r];
     }
 }
@@ -295,21 +299,25 @@ int launch_band_to_rows(const nusht_plan_s* p, const void* band, void* rows, int
 }
 
 int launch_rows_to_band(const nusht_plan_s* p, const void* rows, int rw, void* band,
-                        hipStream_t s)
+                        hipStream_t s, bool window_only)
 {
     const nusht_geometry& g = p->g;
     const int fw = rw;
-    dim3 grid((g.mmax + 1 + kT - 1) / kT, (g.n1 + kT - 1) / kT);
+    const int nrow = window_only ? p->fine_ra + p->fine_rb : g.n1;
+    dim3 grid((g.mmax + 1 + kT - 1) / kT, (nrow + kT - 1) / kT);
     dim3 block(kT, 8);
-    if (g.dtype == NUSHT_MIXED)
-        hipLaunchKernelGGL(k_rows_to_band<float2>, grid, block, 0, s,
-                           reinterpret_cast<const float2*>(rows), reinterpret_cast<float2*>(band),
-                           g.n1, fw, g.mmax + 1, p->fine_ra, p->fine_rb);
-    else
-        hipLaunchKernelGGL(k_rows_to_band<double2>, grid, block, 0, s,
-                           reinterpret_cast<const double2*>(rows),
-                           reinterpret_cast<double2*>(band), g.n1, fw, g.mmax + 1, p->fine_ra,
-                           p->fine_rb);
+#define NUSHT_R2B(C, COMPACT)                                                                  \
+    hipLaunchKernelGGL((k_rows_to_band<C, COMPACT>), grid, block, 0, s,                        \
+                       reinterpret_cast<const C*>(rows), reinterpret_cast<C*>(band), g.n1, fw, \
+                       g.mmax + 1, p->fine_ra, p->fine_rb)
+    if (g.dtype == NUSHT_MIXED) {
+        if (window_only) NUSHT_R2B(float2, true);
+        else NUSHT_R2B(float2, false);
+    } else {
+        if (window_only) NUSHT_R2B(double2, true);
+        else NUSHT_R2B(double2, false);
+    }
+#undef NUSHT_R2B
     NUSHT_HIP(hipGetLastError());
     return NUSHT_OK;
 }

@@ -173,6 +173,11 @@ struct nusht_plan_s {
     // row spectra of width mmax + 1 (no zero columns), instead of the rocFFT row plans.
     bool row_custom = false;
     void* rowtw = nullptr;  // [n2] e^{2 pi i k / n2} in the plan's FFT precision
+    // Fused mode with power-of-two n1 that fits one LDS column: the theta pass and the
+    // deconvolution run as one kernel per direction (rowfft.hip) instead of the rocFFT column
+    // plans and the pad / truncate kernels.
+    bool theta_custom = false;
+    void* thetatw = nullptr;  // [2 n1] e^{2 pi i k / (2 n1)} in the plan's FFT precision
 
     // Timing.
     // Timing: every execution call takes the next slot of a ring of kTimingSlots slots, each
@@ -251,17 +256,22 @@ int launch_deconv_trunc(const nusht_plan_s* p, const void* fspec, void* tspec, i
 // band spectrum [mmax+1][n1] <-> row spectrum [n1][rw] of one map, rows [0, fine_ra) and
 // [n1 - fine_rb, n1) only (rw = n2/2+1 for the rocFFT row plans, mmax+1 for the row kernels).
 // band_to_rows zero-fills the columns mmax+1 .. rw-1; rows_to_band writes zeros for the rows
-// no window reaches.
+// no window reaches, unless window_only (the fused theta pass reads the window rows only).
 int launch_band_to_rows(const nusht_plan_s* p, const void* band, void* rows, int rw,
                         hipStream_t s);
 int launch_rows_to_band(const nusht_plan_s* p, const void* rows, int rw, void* band,
-                        hipStream_t s);
+                        hipStream_t s, bool window_only = false);
 
 // ---- fine-grid row transforms for power-of-two n2 (rowfft.hip) ----
 bool rowfft_supported(const nusht_geometry& g);
 // window rows of one map: rows [n1][rw] (columns 0 .. mmax) <-> real fine grid [n1][n2]
 int launch_row_c2r(const nusht_plan_s* p, const void* rows, int64_t rw, void* fine, hipStream_t s);
 int launch_row_r2c(const nusht_plan_s* p, const void* fine, void* rows, int64_t rw, hipStream_t s);
+// theta pass fused with the deconvolution, maps [0, nmaps): torus spectrum cs [b][mmax+1][N_t]
+// <-> band spectrum [b][mmax+1][n1] (window rows only)
+bool thetafft_supported(const nusht_geometry& g);
+int launch_theta_inv(const nusht_plan_s* p, const void* cs, void* band, int nmaps, hipStream_t s);
+int launch_theta_fwd(const nusht_plan_s* p, const void* band, void* cs, int nmaps, hipStream_t s);
 
 // ---- nonuniform part (nufft_*.hip) ----
 int launch_interp(const nusht_plan_s* p, const void* fine, double* out, int nmaps, int f32,

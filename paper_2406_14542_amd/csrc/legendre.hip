@@ -178,8 +178,8 @@ __device__ inline void xcd_block(int b, int nbx, int& m, int& rb)
 // so none of their lam_lm ever needs the power-of-two scale; their waves run the
 // SCALED = false instance, which has no scaled step at all (the scaled step's extra live
 // registers would otherwise cost the whole kernel almost half of its occupancy).  The pairs
-// below jscale[m] (a multiple of 64 R of the plain instance, so that the two instances'
-// waves partition the pairs) run SCALED = true with one pair per lane.
+// below jscale[m] (a multiple of 64 R of both instances, so that their waves partition the
+// pairs) run SCALED = true.
 template <int MB, int R, bool FUSED, typename OutT, bool SCALED>
 __global__ __launch_bounds__(256) void k_legendre_synth(
     const double2* __restrict__ alm, int64_t nalm, int lmax, int mmax, int nbx,
@@ -813,9 +813,9 @@ int launch_legendre_synth(const nusht_plan_s* p, const double* alm, void* out, i
 {
     const nusht_geometry& g = p->g;
     const int npairs = (g.nrings + 1) / 2;
-    // the plain instance takes two ring pairs per lane once there are enough pairs to fill
-    // the waves; the scaled instance one, which halves the spread of the scaled phases'
-    // lengths across the lanes of a wave and keeps its occupancy higher
+    // both instances take two ring pairs per lane once there are enough pairs to fill the
+    // waves (one pair per lane in the scaled instance, which halves the spread of the scaled
+    // phases' lengths across a wave, measured slower at C3: 7.41 against 7.07 ms)
     const int R = synth_pairs_per_lane(npairs);
     const int RS = synth_scaled_pairs_per_lane(npairs);
     auto shape = [&](int r, int& bx, int& threads) {

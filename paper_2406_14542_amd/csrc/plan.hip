@@ -875,7 +875,7 @@ void nusht_destroy(nusht_plan_t p)
                     p->dec2f, p->sth,    p->sph,      p->perm,      p->iperm,     p->V,
                     p->slot_off,  p->slot_tile,
                     p->tile_slot, p->boff, p->brec, p->dflag, p->dstatus, p->X,     p->Y,         p->W,   p->Z,
-                    p->fftwork,   p->rowtw,
+                    p->fftwork,   p->rowtw, p->thetatw,
                     p->red,      p->jlive,  p->jscale, p->adj_part, p->es_coef, p->es_coeff};
     for (void* b : bufs)
         if (b) hipFree(b);

@@ -8,6 +8,15 @@
 //   O[k] = (X[k] - X[k + N]) e^{2 pi i k / n2},  X[k + N] = conj X[N - k];
 // and backwards E = (Z[k] + conj Z[N-k]) / 2, O = (Z[k] - conj Z[N-k]) / (2i),
 //   X[k] = E + e^{-2 pi i k / n2} O.
+// The theta pass of the same 2-D FFT (power-of-two n1, one workgroup per band column mu of
+// one map) runs here as well, fused with the deconvolution of N(i) / N^H(iii):
+//   synthesis  band[mu][i] = sum_{|k| <= L} C[k][mu] h(k, mu) e^{+2 pi i k i / n1}, window rows i
+//   adjoint    C[k][mu] = h(k, mu) sum_{window rows i} band[mu][i] e^{-2 pi i k i / n1}, |k| <= L
+// (h = the deconvolution factors d1[|k|] d2[mu]; k of entry t of the length-N_t torus column is
+// t or t - N_t): the column is read once from the torus spectrum (synthesis: only its |k| <= L
+// entries exist, the padding is zeros in registers) or from the window rows of the band
+// (adjoint), transformed in LDS, and written once, so the zero-padded spectrum is never
+// stored and no separate deconvolution pass reads or writes it.
 // The N-point transform runs in LDS as Stockham radix passes (a first pass of radix
 // 2^(log2 N mod 4) when needed, then radix 16), reading the row straight from HBM in the
 // first pass and writing it in the last: one read and one write of each row, and only the
@@ -345,6 +354,136 @@ __global__ __launch_bounds__(RowShape<K>::NT) void k_row_r2c(
     }
 }
 
+
+// ---- theta pass (band columns, complex, length n1 = 2^K) ----------------------------------
+
+__device__ inline int kappa_of(int i, int n) { return i <= n / 2 ? i : i - n; }
+
+// synthesis: torus spectrum cs[b][mu][t] (t < nt) -> band[b][mu][i], window rows only
+template <typename T, int K>
+__global__ __launch_bounds__(RowShape<K>::NT) void k_theta_inv(
+    const typename Cx<T>::type* __restrict__ cs, typename Cx<T>::type* __restrict__ band, int nt,
+    int lmax, int mmax, const T* __restrict__ d1, const T* __restrict__ d2, int ra, int rb,
+    const typename Cx<T>::type* __restrict__ tw)
+{
+    using C = typename Cx<T>::type;
+    using S = RowShape<K>;
+    constexpr int N = S::N, R0 = S::R0;
+    __shared__ C buf[N + N / 16];
+    const int mu = blockIdx.x, b = blockIdx.y, t = threadIdx.x;
+    const int64_t col = (int64_t)b * (mmax + 1) + mu;
+    const C* src = cs + col * nt;
+    C* dst = band + col * N;
+    const T fm = d2[mu];
+    // first pass (span 1) from the torus column: entry i of the padded column has wave number
+    // k = kappa_of(i, N); only |k| <= L is loaded (the rest of the column is zero)
+    constexpr int NU = (N / R0 + S::NT - 1) / S::NT;
+    C x[NU][R0];
+#pragma unroll
+    for (int u = 0; u < NU; ++u)
+#pragma unroll
+        for (int r = 0; r < R0; ++r) {
+            const int i = t + u * S::NT + r * (N / R0);
+            const int k = kappa_of(i, N);
+            const int ak = k < 0 ? -k : k;
+            C v = cmk<C>(0, 0);
+            if (i < N && ak <= lmax) {
+                const C c = src[k < 0 ? k + nt : k];
+                const T f = d1[ak] * fm;
+                v = cmk<C>(c.x * f, c.y * f);
+            }
+            x[u][r] = v;
+        }
+#pragma unroll
+    for (int u = 0; u < NU; ++u) {
+        const int idx = t + u * S::NT;
+        if (idx < N / R0) {
+            dft<R0, +1>(x[u]);
+#pragma unroll
+            for (int r = 0; r < R0; ++r) buf[pad16(idx * R0 + r)] = x[u][r];
+        }
+    }
+    __syncthreads();
+    middle_passes<K, +1>(buf, t, tw);
+    // last pass (radix 16, span N / 16) straight into the band column's window rows
+    if (t < S::NB16) {
+        C v[16], w[16];
+        load_twiddles<16, +1>(w, t, N / 16, N, tw);
+#pragma unroll
+        for (int r = 0; r < 16; ++r) v[r] = buf[pad16(t + r * (N / 16))];
+        apply_twiddles(v, w);
+        dft<16, +1>(v);
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+            const int i = t + r * (N / 16);
+            if (i < ra || i >= N - rb) dst[i] = v[r];
+        }
+    }
+}
+
+// adjoint: band[b][mu][i] (window rows; the others are taken as zero) -> torus spectrum
+// cs[b][mu][t], deconvolved, zero for |k| > L
+template <typename T, int K>
+__global__ __launch_bounds__(RowShape<K>::NT) void k_theta_fwd(
+    const typename Cx<T>::type* __restrict__ band, typename Cx<T>::type* __restrict__ cs, int nt,
+    int lmax, int mmax, const T* __restrict__ d1, const T* __restrict__ d2, int ra, int rb,
+    const typename Cx<T>::type* __restrict__ tw)
+{
+    using C = typename Cx<T>::type;
+    using S = RowShape<K>;
+    constexpr int N = S::N, R0 = S::R0;
+    __shared__ C buf[N + N / 16];
+    const int mu = blockIdx.x, b = blockIdx.y, t = threadIdx.x;
+    const int64_t col = (int64_t)b * (mmax + 1) + mu;
+    const C* src = band + col * N;
+    C* dst = cs + col * nt;
+    const T fm = d2[mu];
+    constexpr int NU = (N / R0 + S::NT - 1) / S::NT;
+    C x[NU][R0];
+#pragma unroll
+    for (int u = 0; u < NU; ++u)
+#pragma unroll
+        for (int r = 0; r < R0; ++r) {
+            const int i = t + u * S::NT + r * (N / R0);
+            x[u][r] = (i < N && (i < ra || i >= N - rb)) ? src[i] : cmk<C>(0, 0);
+        }
+#pragma unroll
+    for (int u = 0; u < NU; ++u) {
+        const int idx = t + u * S::NT;
+        if (idx < N / R0) {
+            dft<R0, -1>(x[u]);
+#pragma unroll
+            for (int r = 0; r < R0; ++r) buf[pad16(idx * R0 + r)] = x[u][r];
+        }
+    }
+    __syncthreads();
+    middle_passes<K, -1>(buf, t, tw);
+    if (t < S::NB16) {
+        C v[16], w[16];
+        load_twiddles<16, -1>(w, t, N / 16, N, tw);
+#pragma unroll
+        for (int r = 0; r < 16; ++r) v[r] = buf[pad16(t + r * (N / 16))];
+        apply_twiddles(v, w);
+        dft<16, -1>(v);
+        // output i carries wave number k = kappa_of(i, N); |k| <= L lands at torus entry t(k)
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+            const int i = t + r * (N / 16);
+            const int k = kappa_of(i, N);
+            const int ak = k < 0 ? -k : k;
+            if (ak <= lmax) {
+                const T f = d1[ak] * fm;
+                dst[k < 0 ? k + nt : k] = cmk<C>(v[r].x * f, v[r].y * f);
+            }
+        }
+    }
+    // torus entries beyond the band limit
+    for (int e = t; e < nt; e += S::NT) {
+        const int k = kappa_of(e, nt);
+        if ((k < 0 ? -k : k) > lmax) dst[e] = cmk<C>(0, 0);
+    }
+}
+
 }  // namespace
 
 bool rowfft_supported(const nusht_geometry& g)
@@ -412,6 +551,89 @@ int launch_row_r2c(const nusht_plan_s* p, const void* fine, void* rows, int64_t 
                                reinterpret_cast<const double*>(fine), g.n1, p->fine_ra,
                                p->fine_rb, reinterpret_cast<double2*>(rows), rw, g.mmax + 1,
                                reinterpret_cast<const double2*>(p->rowtw));
+    });
+    NUSHT_HIP(hipGetLastError());
+    return NUSHT_OK;
+}
+
+bool thetafft_supported(const nusht_geometry& g)
+{
+    const int n1 = g.n1;
+    if (g.dfs_mode != NUSHT_DFS_FUSED || !rowfft_supported(g)) return false;
+    if (n1 < 32 || (n1 & (n1 - 1))) return false;
+    // the column in LDS: 16384 FP32 or 8192 FP64 complex values
+    return n1 <= (g.dtype == NUSHT_MIXED ? 16384 : 8192);
+}
+
+#define NUSHT_THETAK_SWITCH(K_, BODY)                  \
+    switch (K_) {                                      \
+        case 5: { constexpr int KV = 5; BODY; } break;   \
+        case 6: { constexpr int KV = 6; BODY; } break;   \
+        case 7: { constexpr int KV = 7; BODY; } break;   \
+        case 8: { constexpr int KV = 8; BODY; } break;   \
+        case 9: { constexpr int KV = 9; BODY; } break;   \
+        case 10: { constexpr int KV = 10; BODY; } break; \
+        case 11: { constexpr int KV = 11; BODY; } break; \
+        case 12: { constexpr int KV = 12; BODY; } break; \
+        case 13: { constexpr int KV = 13; BODY; } break; \
+        case 14: { constexpr int KV = 14; BODY; } break; \
+        default: set_last_error("thetafft", "unsupported column length"); return NUSHT_EINVAL; \
+    }
+
+static int col_log2(int n1)
+{
+    int k = 0;
+    while ((1 << k) < n1) ++k;
+    return k;
+}
+
+int launch_theta_inv(const nusht_plan_s* p, const void* cs, void* band, int nmaps, hipStream_t s)
+{
+    const nusht_geometry& g = p->g;
+    const int K = col_log2(g.n1);
+    const dim3 grid(g.mmax + 1, nmaps);
+    NUSHT_THETAK_SWITCH(K, {
+        if (g.dtype == NUSHT_MIXED) {
+            hipLaunchKernelGGL((k_theta_inv<float, KV>), grid, dim3(RowShape<KV>::NT), 0, s,
+                               reinterpret_cast<const float2*>(cs), reinterpret_cast<float2*>(band),
+                               g.ntorus, g.lmax, g.mmax, p->dec1f, p->dec2f, p->fine_ra,
+                               p->fine_rb, reinterpret_cast<const float2*>(p->thetatw));
+        } else if constexpr (KV <= 13) {
+            hipLaunchKernelGGL((k_theta_inv<double, KV>), grid, dim3(RowShape<KV>::NT), 0, s,
+                               reinterpret_cast<const double2*>(cs),
+                               reinterpret_cast<double2*>(band), g.ntorus, g.lmax, g.mmax,
+                               p->dec1, p->dec2, p->fine_ra, p->fine_rb,
+                               reinterpret_cast<const double2*>(p->thetatw));
+        } else {
+            set_last_error("thetafft", "FP64 column too long for LDS");
+            return NUSHT_EINVAL;
+        }
+    });
+    NUSHT_HIP(hipGetLastError());
+    return NUSHT_OK;
+}
+
+int launch_theta_fwd(const nusht_plan_s* p, const void* band, void* cs, int nmaps, hipStream_t s)
+{
+    const nusht_geometry& g = p->g;
+    const int K = col_log2(g.n1);
+    const dim3 grid(g.mmax + 1, nmaps);
+    NUSHT_THETAK_SWITCH(K, {
+        if (g.dtype == NUSHT_MIXED) {
+            hipLaunchKernelGGL((k_theta_fwd<float, KV>), grid, dim3(RowShape<KV>::NT), 0, s,
+                               reinterpret_cast<const float2*>(band), reinterpret_cast<float2*>(cs),
+                               g.ntorus, g.lmax, g.mmax, p->dec1f, p->dec2f, p->fine_ra,
+                               p->fine_rb, reinterpret_cast<const float2*>(p->thetatw));
+        } else if constexpr (KV <= 13) {
+            hipLaunchKernelGGL((k_theta_fwd<double, KV>), grid, dim3(RowShape<KV>::NT), 0, s,
+                               reinterpret_cast<const double2*>(band),
+                               reinterpret_cast<double2*>(cs), g.ntorus, g.lmax, g.mmax, p->dec1,
+                               p->dec2, p->fine_ra, p->fine_rb,
+                               reinterpret_cast<const double2*>(p->thetatw));
+        } else {
+            set_last_error("thetafft", "FP64 column too long for LDS");
+            return NUSHT_EINVAL;
+        }
     });
     NUSHT_HIP(hipGetLastError());
     return NUSHT_OK;

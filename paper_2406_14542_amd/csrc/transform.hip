@@ -131,11 +131,35 @@ int create_fft_plans(nusht_plan_s* p)
     }
     const size_t fw = (size_t)g.n2 / 2 + 1;
     const size_t ncol = (size_t)g.mmax + 1;
-    NUSHT_TRY(make_fft_1d(p->fine_col_inv, rocfft_transform_type_complex_inverse, prec, g.n1,
-                          ncol, 1, g.n1, 1, g.n1, rocfft_placement_inplace));
-    NUSHT_TRY(make_fft_1d(p->fine_col_fwd, rocfft_transform_type_complex_forward, prec, g.n1,
-                          ncol, 1, g.n1, 1, g.n1, rocfft_placement_inplace));
     p->row_custom = rowfft_supported(g);
+    p->theta_custom = thetafft_supported(g);
+    if (p->theta_custom) {
+        // twiddles of the fused theta pass: [2 n1] e^{2 pi i k / (2 n1)}, rounded once from
+        // long double (the row kernels' table convention for an n1-point transform)
+        const int n = 2 * g.n1;
+        const bool f32 = g.dtype == NUSHT_MIXED;
+        std::vector<double> tw(2 * (size_t)n);
+        std::vector<float> twf(2 * (size_t)n);
+        for (int k = 0; k < n; ++k) {
+            const long double a = 2.0L * 3.14159265358979323846264338327950288L * k / n;
+            tw[2 * k] = (double)cosl(a);
+            tw[2 * k + 1] = (double)sinl(a);
+            twf[2 * k] = (float)cosl(a);
+            twf[2 * k + 1] = (float)sinl(a);
+        }
+        const size_t tb = 2 * (size_t)n * (f32 ? sizeof(float) : sizeof(double));
+        if (hipMalloc(&p->thetatw, tb) != hipSuccess) {
+            set_last_error("nusht_plan", "device allocation failed");
+            return NUSHT_ENOMEM;
+        }
+        NUSHT_HIP(hipMemcpy(p->thetatw, f32 ? (const void*)twf.data() : (const void*)tw.data(),
+                            tb, hipMemcpyHostToDevice));
+    } else {
+        NUSHT_TRY(make_fft_1d(p->fine_col_inv, rocfft_transform_type_complex_inverse, prec, g.n1,
+                              ncol, 1, g.n1, 1, g.n1, rocfft_placement_inplace));
+        NUSHT_TRY(make_fft_1d(p->fine_col_fwd, rocfft_transform_type_complex_forward, prec, g.n1,
+                              ncol, 1, g.n1, 1, g.n1, rocfft_placement_inplace));
+    }
     if (p->row_custom) {
         // twiddle table of the row kernels, rounded once from long double
         const int n2 = g.n2;
@@ -291,16 +315,17 @@ size_t fine_band_bytes(const nusht_plan_s* p)
     return (size_t)(p->g.mmax + 1) * p->g.n1 * 2 * fine_elem_bytes(p);
 }
 
-// Band spectrum -> fine grid of one map (N(ii)): theta pass in place over the band, transpose
-// into the row spectrum of the window rows (p->W), phi pass into those rows of the grid.
-// Other rows of the grid are left untouched (no window reads them).
+// Band spectrum -> fine grid of one map (N(ii)): theta pass in place over the band (unless the
+// fused theta pass has already written the band's window rows), transpose into the row
+// spectrum of the window rows (p->W), phi pass into those rows of the grid.  Other rows of the
+// grid are left untouched (no window reads them).
 int fine_c2r(nusht_plan_s* p, char* band, char* real, hipStream_t s)
 {
     const nusht_geometry& g = p->g;
     const size_t e = fine_elem_bytes(p);
     const size_t fw = (size_t)g.n2 / 2 + 1;
     char* rows = bytes(p->W);
-    NUSHT_TRY(fft_exec(p, p->fine_col_inv, band, nullptr, s));
+    if (!p->theta_custom) NUSHT_TRY(fft_exec(p, p->fine_col_inv, band, nullptr, s));
     if (p->row_custom) {
         NUSHT_TRY(launch_band_to_rows(p, band, rows, g.mmax + 1, s));
         return launch_row_c2r(p, rows, g.mmax + 1, real, s);
@@ -316,7 +341,8 @@ int fine_c2r(nusht_plan_s* p, char* band, char* real, hipStream_t s)
 
 // Fine grid -> band spectrum of one map (N^H(ii)), reading only the window rows: phi pass
 // over those rows into p->W, transpose into the band (zeros for the other rows), theta pass
-// in place.
+// in place.  With the fused theta pass only the window rows of the band are written and its
+// theta pass runs later, with the deconvolution.
 int fine_r2c(nusht_plan_s* p, char* real, char* band, hipStream_t s)
 {
     const nusht_geometry& g = p->g;
@@ -325,7 +351,8 @@ int fine_r2c(nusht_plan_s* p, char* real, char* band, hipStream_t s)
     char* rows = bytes(p->W);
     if (p->row_custom) {
         NUSHT_TRY(launch_row_r2c(p, real, rows, g.mmax + 1, s));
-        NUSHT_TRY(launch_rows_to_band(p, rows, g.mmax + 1, band, s));
+        NUSHT_TRY(launch_rows_to_band(p, rows, g.mmax + 1, band, s, p->theta_custom));
+        if (p->theta_custom) return NUSHT_OK;
         return fft_exec(p, p->fine_col_fwd, band, nullptr, s);
     }
     NUSHT_TRY(fft_exec(p, p->fine_rowa_r2c, real, rows, s));
@@ -373,7 +400,10 @@ int synthesis_to_fine(nusht_plan_s* p, const double* alm, int nmaps, hipStream_t
             NUSHT_TRY(fft_exec(p, p->theta_fwd, bytes(p->X) + b * cstride, nullptr, s));
         stage_end(p, ST_TORUS_FFT, s);
         stage_begin(p, ST_DECONV, s);
-        NUSHT_TRY(launch_deconv_pad(p, p->X, p->Y, nmaps, 1, f32, s));
+        if (p->theta_custom)
+            NUSHT_TRY(launch_theta_inv(p, p->X, p->Y, nmaps, s));
+        else
+            NUSHT_TRY(launch_deconv_pad(p, p->X, p->Y, nmaps, 1, f32, s));
         stage_end(p, ST_DECONV, s);
         stage_begin(p, ST_FINE_FFT, s);
         for (int b = 0; b < nmaps; ++b)
@@ -496,7 +526,10 @@ int nusht_adjoint(nusht_plan_t p, const double* map, double* alm, int nmaps, voi
     stage_end(p, ST_FINE_FFT, s);
     if (g.dfs_mode == NUSHT_DFS_FUSED) {
         stage_begin(p, ST_DECONV, s);
-        NUSHT_TRY(launch_deconv_trunc(p, p->Y, p->X, nmaps, 1, f32, s));
+        if (p->theta_custom)
+            NUSHT_TRY(launch_theta_fwd(p, p->Y, p->X, nmaps, s));
+        else
+            NUSHT_TRY(launch_deconv_trunc(p, p->Y, p->X, nmaps, 1, f32, s));
         stage_end(p, ST_DECONV, s);
         stage_begin(p, ST_TORUS_FFT, s);
         const size_t cstride = (size_t)(g.mmax + 1) * g.ntorus * 2 * e;
