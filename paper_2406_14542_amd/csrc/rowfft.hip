@@ -484,6 +484,175 @@ __global__ __launch_bounds__(RowShape<K>::NT) void k_theta_fwd(
     }
 }
 
+// Long columns (16384 FP64 values, 256 KB as complex numbers): the column lives in registers,
+// 32 values per thread (two radix-16 butterflies, or 32 / R0 first-pass butterflies), and only
+// the exchange between two passes goes through LDS -- the real parts, then the imaginary
+// parts, through one array of N reals, half the LDS of a complex column.
+template <int K>
+struct ThetaHalf {
+    static constexpr int N = 1 << K;
+    static constexpr int NT = N / 32;
+    static constexpr int R0 = RowShape<K>::R0;
+    static constexpr int NP16 = RowShape<K>::NPASS16;
+};
+
+// one Stockham pass of radix R and span ns on the thread's butterflies idx = t + q NT
+template <int R, int DIR, int N, int NT, typename C>
+__device__ inline void pass_in_regs(C (&v)[32], int t, int ns, const C* __restrict__ tw)
+{
+#pragma unroll
+    for (int q = 0; q < 32 / R; ++q) {
+        C u[R];
+#pragma unroll
+        for (int r = 0; r < R; ++r) u[r] = v[q * R + r];
+        if (ns > 1) {
+            C w[R];
+            load_twiddles<R, DIR>(w, (t + q * NT) & (ns - 1), ns, N, tw);
+            apply_twiddles(u, w);
+        }
+        dft<R, DIR>(u);
+#pragma unroll
+        for (int r = 0; r < R; ++r) v[q * R + r] = u[r];
+    }
+}
+
+// part P (0 real, 1 imaginary) of the exchange between a pass of radix RP and span nsp (its
+// outputs at (idx - j) RP + j + r nsp) and a pass of radix RN (inputs at idx + r N / RN)
+template <int P, int RP, int RN, int N, int NT, typename T, typename C>
+__device__ inline void exchange_part(T* lds, C (&v)[32], int t, int nsp)
+{
+#pragma unroll
+    for (int q = 0; q < 32 / RP; ++q) {
+        const int idx = t + q * NT;
+        const int j = idx & (nsp - 1);
+        const int base = (idx - j) * RP + j;
+#pragma unroll
+        for (int r = 0; r < RP; ++r) lds[pad16(base + r * nsp)] = P ? v[q * RP + r].y : v[q * RP + r].x;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < 32 / RN; ++q) {
+        const int idx = t + q * NT;
+#pragma unroll
+        for (int r = 0; r < RN; ++r) {
+            const T x = lds[pad16(idx + r * (N / RN))];
+            if (P)
+                v[q * RN + r].y = x;
+            else
+                v[q * RN + r].x = x;
+        }
+    }
+    __syncthreads();
+}
+
+template <int RP, int RN, int N, int NT, typename T, typename C>
+__device__ inline void exchange(T* lds, C (&v)[32], int t, int nsp)
+{
+    exchange_part<0, RP, RN, N, NT>(lds, v, t, nsp);
+    exchange_part<1, RP, RN, N, NT>(lds, v, t, nsp);
+}
+
+// the passes after the first: radix 16, span R0 16^p; the outputs of the last one are in
+// natural order at idx + r N / 16
+template <int K, int DIR, typename T, typename C>
+__device__ inline void passes_after_first(T* lds, C (&v)[32], int t, const C* __restrict__ tw)
+{
+    using S = ThetaHalf<K>;
+    exchange<S::R0, 16, S::N, S::NT>(lds, v, t, 1);
+    int ns = S::R0;
+#pragma unroll
+    for (int p = 0; p < S::NP16; ++p) {
+        pass_in_regs<16, DIR, S::N, S::NT>(v, t, ns, tw);
+        if (p < S::NP16 - 1) exchange<16, 16, S::N, S::NT>(lds, v, t, ns);
+        ns *= 16;
+    }
+}
+
+template <typename T, int K>
+__global__ __launch_bounds__(ThetaHalf<K>::NT) void k_theta_inv_h(
+    const typename Cx<T>::type* __restrict__ cs, typename Cx<T>::type* __restrict__ band, int nt,
+    int lmax, int mmax, const T* __restrict__ d1, const T* __restrict__ d2, int ra, int rb,
+    const typename Cx<T>::type* __restrict__ tw)
+{
+    using C = typename Cx<T>::type;
+    using S = ThetaHalf<K>;
+    constexpr int N = S::N, R0 = S::R0, NT = S::NT;
+    __shared__ T lds[N + N / 16];
+    const int mu = blockIdx.x, b = blockIdx.y, t = threadIdx.x;
+    const int64_t col = (int64_t)b * (mmax + 1) + mu;
+    const C* src = cs + col * nt;
+    C* dst = band + col * N;
+    const T fm = d2[mu];
+    C v[32];
+#pragma unroll
+    for (int q = 0; q < 32 / R0; ++q)
+#pragma unroll
+        for (int r = 0; r < R0; ++r) {
+            const int i = t + q * NT + r * (N / R0);
+            const int k = kappa_of(i, N);
+            const int ak = k < 0 ? -k : k;
+            C x = cmk<C>(0, 0);
+            if (ak <= lmax) {
+                const C c = src[k < 0 ? k + nt : k];
+                const T f = d1[ak] * fm;
+                x = cmk<C>(c.x * f, c.y * f);
+            }
+            v[q * R0 + r] = x;
+        }
+    pass_in_regs<R0, +1, N, NT>(v, t, 1, tw);
+    passes_after_first<K, +1>(lds, v, t, tw);
+#pragma unroll
+    for (int q = 0; q < 2; ++q)
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+            const int i = t + q * NT + r * (N / 16);
+            if (i < ra || i >= N - rb) dst[i] = v[q * 16 + r];
+        }
+}
+
+template <typename T, int K>
+__global__ __launch_bounds__(ThetaHalf<K>::NT) void k_theta_fwd_h(
+    const typename Cx<T>::type* __restrict__ band, typename Cx<T>::type* __restrict__ cs, int nt,
+    int lmax, int mmax, const T* __restrict__ d1, const T* __restrict__ d2, int ra, int rb,
+    const typename Cx<T>::type* __restrict__ tw)
+{
+    using C = typename Cx<T>::type;
+    using S = ThetaHalf<K>;
+    constexpr int N = S::N, R0 = S::R0, NT = S::NT;
+    __shared__ T lds[N + N / 16];
+    const int mu = blockIdx.x, b = blockIdx.y, t = threadIdx.x;
+    const int64_t col = (int64_t)b * (mmax + 1) + mu;
+    const C* src = band + col * N;
+    C* dst = cs + col * nt;
+    const T fm = d2[mu];
+    C v[32];
+#pragma unroll
+    for (int q = 0; q < 32 / R0; ++q)
+#pragma unroll
+        for (int r = 0; r < R0; ++r) {
+            const int i = t + q * NT + r * (N / R0);
+            v[q * R0 + r] = (i < ra || i >= N - rb) ? src[i] : cmk<C>(0, 0);
+        }
+    pass_in_regs<R0, -1, N, NT>(v, t, 1, tw);
+    passes_after_first<K, -1>(lds, v, t, tw);
+#pragma unroll
+    for (int q = 0; q < 2; ++q)
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+            const int i = t + q * NT + r * (N / 16);
+            const int k = kappa_of(i, N);
+            const int ak = k < 0 ? -k : k;
+            if (ak <= lmax) {
+                const T f = d1[ak] * fm;
+                dst[k < 0 ? k + nt : k] = cmk<C>(v[q * 16 + r].x * f, v[q * 16 + r].y * f);
+            }
+        }
+    for (int e = t; e < nt; e += NT) {
+        const int k = kappa_of(e, nt);
+        if ((k < 0 ? -k : k) > lmax) dst[e] = cmk<C>(0, 0);
+    }
+}
+
 }  // namespace
 
 bool rowfft_supported(const nusht_geometry& g)
@@ -561,8 +730,8 @@ bool thetafft_supported(const nusht_geometry& g)
     const int n1 = g.n1;
     if (g.dfs_mode != NUSHT_DFS_FUSED || !rowfft_supported(g)) return false;
     if (n1 < 32 || (n1 & (n1 - 1))) return false;
-    // the column in LDS: 16384 FP32 or 8192 FP64 complex values
-    return n1 <= (g.dtype == NUSHT_MIXED ? 16384 : 8192);
+    // columns up to 16384 values in LDS (complex, or real and imaginary parts in turn)
+    return n1 <= 16384;
 }
 
 #define NUSHT_THETAK_SWITCH(K_, BODY)                  \
@@ -587,28 +756,42 @@ static int col_log2(int n1)
     return k;
 }
 
+// columns whose complex values exceed the LDS (FP64, 16384) take the register-resident kernels
+// whose passes exchange through half of it.  (For the shorter columns the register-resident
+// form needs 200-260 registers per lane and would not run two workgroups per CU after all.)
+template <typename T>
+constexpr bool theta_half(int K)
+{
+    return sizeof(T) == 8 && K >= 14;
+}
+
 int launch_theta_inv(const nusht_plan_s* p, const void* cs, void* band, int nmaps, hipStream_t s)
 {
     const nusht_geometry& g = p->g;
     const int K = col_log2(g.n1);
     const dim3 grid(g.mmax + 1, nmaps);
+#define NUSHT_THETA_INV(T, KK, KERN, SHAPE)                                                     \
+    hipLaunchKernelGGL((KERN<T, KK>), grid, dim3(SHAPE<KK>::NT), 0, s,                          \
+                       reinterpret_cast<const typename Cx<T>::type*>(cs),                       \
+                       reinterpret_cast<typename Cx<T>::type*>(band), g.ntorus, g.lmax, g.mmax, \
+                       std::is_same<T, float>::value ? (const T*)p->dec1f : (const T*)p->dec1,  \
+                       std::is_same<T, float>::value ? (const T*)p->dec2f : (const T*)p->dec2,  \
+                       p->fine_ra, p->fine_rb,                                                  \
+                       reinterpret_cast<const typename Cx<T>::type*>(p->thetatw))
     NUSHT_THETAK_SWITCH(K, {
         if (g.dtype == NUSHT_MIXED) {
-            hipLaunchKernelGGL((k_theta_inv<float, KV>), grid, dim3(RowShape<KV>::NT), 0, s,
-                               reinterpret_cast<const float2*>(cs), reinterpret_cast<float2*>(band),
-                               g.ntorus, g.lmax, g.mmax, p->dec1f, p->dec2f, p->fine_ra,
-                               p->fine_rb, reinterpret_cast<const float2*>(p->thetatw));
-        } else if constexpr (KV <= 13) {
-            hipLaunchKernelGGL((k_theta_inv<double, KV>), grid, dim3(RowShape<KV>::NT), 0, s,
-                               reinterpret_cast<const double2*>(cs),
-                               reinterpret_cast<double2*>(band), g.ntorus, g.lmax, g.mmax,
-                               p->dec1, p->dec2, p->fine_ra, p->fine_rb,
-                               reinterpret_cast<const double2*>(p->thetatw));
+            if constexpr (theta_half<float>(KV))
+                NUSHT_THETA_INV(float, KV, k_theta_inv_h, ThetaHalf);
+            else
+                NUSHT_THETA_INV(float, KV, k_theta_inv, RowShape);
         } else {
-            set_last_error("thetafft", "FP64 column too long for LDS");
-            return NUSHT_EINVAL;
+            if constexpr (theta_half<double>(KV))
+                NUSHT_THETA_INV(double, KV, k_theta_inv_h, ThetaHalf);
+            else
+                NUSHT_THETA_INV(double, KV, k_theta_inv, RowShape);
         }
     });
+#undef NUSHT_THETA_INV
     NUSHT_HIP(hipGetLastError());
     return NUSHT_OK;
 }
@@ -618,23 +801,28 @@ int launch_theta_fwd(const nusht_plan_s* p, const void* band, void* cs, int nmap
     const nusht_geometry& g = p->g;
     const int K = col_log2(g.n1);
     const dim3 grid(g.mmax + 1, nmaps);
+#define NUSHT_THETA_FWD(T, KK, KERN, SHAPE)                                                     \
+    hipLaunchKernelGGL((KERN<T, KK>), grid, dim3(SHAPE<KK>::NT), 0, s,                          \
+                       reinterpret_cast<const typename Cx<T>::type*>(band),                     \
+                       reinterpret_cast<typename Cx<T>::type*>(cs), g.ntorus, g.lmax, g.mmax,   \
+                       std::is_same<T, float>::value ? (const T*)p->dec1f : (const T*)p->dec1,  \
+                       std::is_same<T, float>::value ? (const T*)p->dec2f : (const T*)p->dec2,  \
+                       p->fine_ra, p->fine_rb,                                                  \
+                       reinterpret_cast<const typename Cx<T>::type*>(p->thetatw))
     NUSHT_THETAK_SWITCH(K, {
         if (g.dtype == NUSHT_MIXED) {
-            hipLaunchKernelGGL((k_theta_fwd<float, KV>), grid, dim3(RowShape<KV>::NT), 0, s,
-                               reinterpret_cast<const float2*>(band), reinterpret_cast<float2*>(cs),
-                               g.ntorus, g.lmax, g.mmax, p->dec1f, p->dec2f, p->fine_ra,
-                               p->fine_rb, reinterpret_cast<const float2*>(p->thetatw));
-        } else if constexpr (KV <= 13) {
-            hipLaunchKernelGGL((k_theta_fwd<double, KV>), grid, dim3(RowShape<KV>::NT), 0, s,
-                               reinterpret_cast<const double2*>(band),
-                               reinterpret_cast<double2*>(cs), g.ntorus, g.lmax, g.mmax, p->dec1,
-                               p->dec2, p->fine_ra, p->fine_rb,
-                               reinterpret_cast<const double2*>(p->thetatw));
+            if constexpr (theta_half<float>(KV))
+                NUSHT_THETA_FWD(float, KV, k_theta_fwd_h, ThetaHalf);
+            else
+                NUSHT_THETA_FWD(float, KV, k_theta_fwd, RowShape);
         } else {
-            set_last_error("thetafft", "FP64 column too long for LDS");
-            return NUSHT_EINVAL;
+            if constexpr (theta_half<double>(KV))
+                NUSHT_THETA_FWD(double, KV, k_theta_fwd_h, ThetaHalf);
+            else
+                NUSHT_THETA_FWD(double, KV, k_theta_fwd, RowShape);
         }
     });
+#undef NUSHT_THETA_FWD
     NUSHT_HIP(hipGetLastError());
     return NUSHT_OK;
 }
