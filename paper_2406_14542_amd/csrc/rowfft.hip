@@ -93,7 +93,7 @@ __device__ __forceinline__ C rot16(C a, int e)
     return cmul(a, cmk<C>((T)kCos16[e], (T)(DIR * kSin16[e])));
 }
 
-// in-place DFT of R = 1, 2, 4, 8 or 16 values, natural order in and out:
+// in-place DFT of R = 1, 2, 4, 5, 8 or 16 values, natural order in and out:
 // V[k] = sum_n v[n] e^{DIR 2 pi i n k / R}
 template <int R, int DIR, typename C>
 __device__ inline void dft(C (&v)[R])
@@ -109,6 +109,23 @@ __device__ inline void dft(C (&v)[R])
         v[2] = csub(a0, a2);
         v[1] = cadd(a1, a3);
         v[3] = csub(a1, a3);
+    } else if constexpr (R == 5) {
+        // V[k] = sum_n v[n] w^(n k), w = e^{DIR 2 pi i / 5}: pairs (1, 4) and (2, 3) share
+        // cos(2 pi / 5), cos(4 pi / 5) and sin(2 pi / 5), sin(4 pi / 5)
+        using T = decltype(C::x);
+        const T c1 = (T)0.30901699437494742410, c2 = (T)-0.80901699437494742410;
+        const T s1 = (T)0.95105651629515357212, s2 = (T)0.58778525229247312917;
+        const C t1 = cadd(v[1], v[4]), t2 = cadd(v[2], v[3]);
+        const C t3 = csub(v[1], v[4]), t4 = csub(v[2], v[3]);
+        const C a1 = cmk<C>(v[0].x + c1 * t1.x + c2 * t2.x, v[0].y + c1 * t1.y + c2 * t2.y);
+        const C a2 = cmk<C>(v[0].x + c2 * t1.x + c1 * t2.x, v[0].y + c2 * t1.y + c1 * t2.y);
+        const C b1 = cmul_i<DIR>(cmk<C>(s1 * t3.x + s2 * t4.x, s1 * t3.y + s2 * t4.y));
+        const C b2 = cmul_i<DIR>(cmk<C>(s2 * t3.x - s1 * t4.x, s2 * t3.y - s1 * t4.y));
+        v[0] = cadd(v[0], cadd(t1, t2));
+        v[1] = cadd(a1, b1);
+        v[4] = csub(a1, b1);
+        v[2] = cadd(a2, b2);
+        v[3] = csub(a2, b2);
     } else if constexpr (R == 8 || R == 16) {
         // R = 4 Q: n = Q n1 + n2, k = k1 + 4 k2; DFT_4 over n1, twiddle e^{DIR 2 pi i n2 k1 / R},
         // DFT_Q over n2
@@ -133,13 +150,17 @@ __device__ inline void dft(C (&v)[R])
 // LDS index with one pad slot per 16 entries (stride-16 accesses stay off one bank)
 __device__ inline int pad16(int i) { return i + (i >> 4); }
 
-template <int K>
+// Transform length N = F 2^K, F = 1 or 5.  Passes: radix R0 (from HBM), for F = 5 a radix
+// R1 = 2^(K mod 4) pass when K mod 4 > 0, then NPASS16 radix-16 passes (the last one to HBM).
+template <int K, int F = 1>
 struct RowShape {
-    static constexpr int N = 1 << K;                          // complex points
+    static_assert(F == 1 || F == 5, "length 2^K or 5 2^K");
+    static constexpr int N = F << K;                          // complex points
     static constexpr int NB16 = N / 16;                       // radix-16 butterflies per pass
     static constexpr int NT = NB16 < 64 ? 64 : NB16;          // threads
-    static constexpr int R0 = (K % 4) ? (1 << (K % 4)) : 16;  // first pass radix
-    static constexpr int NPASS16 = (K % 4) ? K / 4 : K / 4 - 1;  // radix-16 passes after it
+    static constexpr int R0 = F == 5 ? 5 : ((K % 4) ? (1 << (K % 4)) : 16);  // first pass radix
+    static constexpr int R1 = (F == 5 && (K % 4)) ? (1 << (K % 4)) : 1;      // second (1: none)
+    static constexpr int NPASS16 = F == 5 ? K / 4 : ((K % 4) ? K / 4 : K / 4 - 1);
 };
 
 // One Stockham pass (radix R, span Ns) over LDS, in place: every thread loads the inputs of
@@ -191,17 +212,52 @@ __device__ inline void apply_twiddles(C (&v)[R], const C (&w)[R])
     for (int r = 1; r < R; ++r) v[r] = cmul(v[r], w[r]);
 }
 
-template <int K, int DIR, typename C>
+// One in-LDS Stockham pass of radix R and span Ns with N / R butterflies spread over the
+// threads (several per thread): the radix-R1 pass of 5 2^K lengths.
+template <int R, int DIR, int N, int NT, typename C>
+__device__ inline void lds_pass(C* buf, int t, int Ns, const C* __restrict__ tw)
+{
+    constexpr int NB = N / R;
+    constexpr int NBT = (NB + NT - 1) / NT;
+    C v[NBT][R], w[NBT][R];
+#pragma unroll
+    for (int q = 0; q < NBT; ++q) {
+        const int b = t + q * NT;
+        if (b < NB) {
+            load_twiddles<R, DIR>(w[q], b % Ns, Ns, N, tw);
+#pragma unroll
+            for (int r = 0; r < R; ++r) v[q][r] = buf[pad16(b + r * NB)];
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < NBT; ++q) {
+        const int b = t + q * NT;
+        if (b < NB) {
+            apply_twiddles(v[q], w[q]);
+            dft<R, DIR>(v[q]);
+            const int j = b % Ns;
+            const int base = (b - j) * R + j;
+#pragma unroll
+            for (int r = 0; r < R; ++r) buf[pad16(base + r * Ns)] = v[q][r];
+        }
+    }
+    __syncthreads();
+}
+
+template <int K, int DIR, int F = 1, typename C>
 __device__ inline void middle_passes(C* buf, int t, const C* __restrict__ tw)
 {
-    using S = RowShape<K>;
+    using S = RowShape<K, F>;
     constexpr int N = S::N;
+    constexpr int NS0 = S::R0 * S::R1;  // span of the first radix-16 pass
+    if constexpr (S::R1 > 1) lds_pass<S::R1, DIR, N, S::NT>(buf, t, S::R0, tw);
     const bool act = t < S::NB16;
 #pragma unroll
     for (int p = 0; p < S::NPASS16 - 1; ++p) {
-        int Ns = S::R0;
+        int Ns = NS0;
         for (int e = 0; e < p; ++e) Ns *= 16;
-        const int j = t & (Ns - 1);
+        const int j = t % Ns;
         C v[16], w[16];
         if (act) {
             load_twiddles<16, DIR>(w, j, Ns, N, tw);
@@ -223,13 +279,13 @@ __device__ inline void middle_passes(C* buf, int t, const C* __restrict__ tw)
 // C2R of window rows: blockIdx.x = compact window row q, fine row i = q for q < ra, else
 // n1 - rb + (q - ra).  rows: [i][rw] spectrum columns 0 .. ncol-1 (ncol = M + 1 <= N);
 // fine: real [n1][n2].
-template <typename T, int K>
-__global__ __launch_bounds__(RowShape<K>::NT) void k_row_c2r(
+template <typename T, int K, int F>
+__global__ __launch_bounds__((RowShape<K, F>::NT)) void k_row_c2r(
     const typename Cx<T>::type* __restrict__ rows, int64_t rw, int ncol,
     T* __restrict__ fine, int n1, int ra, int rb, const typename Cx<T>::type* __restrict__ tw)
 {
     using C = typename Cx<T>::type;
-    using S = RowShape<K>;
+    using S = RowShape<K, F>;
     constexpr int N = S::N, R0 = S::R0;
     __shared__ C buf[N + N / 16];
     const int q = blockIdx.x, t = threadIdx.x;
@@ -277,7 +333,7 @@ __global__ __launch_bounds__(RowShape<K>::NT) void k_row_c2r(
         }
     }
     __syncthreads();
-    middle_passes<K, +1>(buf, t, tw);
+    middle_passes<K, +1, F>(buf, t, tw);
     // last pass (radix 16, span N / 16) into the fine row: z[n] = x[2n] + i x[2n+1]
     if (t < S::NB16) {
         C v[16], w[16];
@@ -293,13 +349,13 @@ __global__ __launch_bounds__(RowShape<K>::NT) void k_row_c2r(
 }
 
 // R2C of window rows, columns 0 .. ncol-1 of each row's spectrum into rows[i][.]
-template <typename T, int K>
-__global__ __launch_bounds__(RowShape<K>::NT) void k_row_r2c(
+template <typename T, int K, int F>
+__global__ __launch_bounds__((RowShape<K, F>::NT)) void k_row_r2c(
     const T* __restrict__ fine, int n1, int ra, int rb, typename Cx<T>::type* __restrict__ rows,
     int64_t rw, int ncol, const typename Cx<T>::type* __restrict__ tw)
 {
     using C = typename Cx<T>::type;
-    using S = RowShape<K>;
+    using S = RowShape<K, F>;
     constexpr int N = S::N, R0 = S::R0;
     __shared__ C buf[N + N / 16];
     const int q = blockIdx.x, t = threadIdx.x;
@@ -321,7 +377,7 @@ __global__ __launch_bounds__(RowShape<K>::NT) void k_row_r2c(
         }
     }
     __syncthreads();
-    middle_passes<K, -1>(buf, t, tw);
+    middle_passes<K, -1, F>(buf, t, tw);
     {
         C v[16], w[16];
         const bool act = t < S::NB16;
@@ -343,7 +399,7 @@ __global__ __launch_bounds__(RowShape<K>::NT) void k_row_r2c(
     const C wt = tw[t];  // e^{-2 pi i k / n2} = conj(tw[t] tw[k - t]), k - t wave-uniform
     for (int k = t; k < ncol; k += S::NT) {
         const C zk = buf[pad16(k)];
-        const C zm = buf[pad16((N - k) & (N - 1))];
+        const C zm = buf[pad16(k == 0 ? 0 : N - k)];
         const C e = cmk<C>((zk.x + zm.x) / 2, (zk.y - zm.y) / 2);
         // O = (Z[k] - conj Z[N-k]) / (2 i)
         const C d = cmk<C>((zk.x - zm.x) / 2, (zk.y + zm.y) / 2);
@@ -360,14 +416,14 @@ __global__ __launch_bounds__(RowShape<K>::NT) void k_row_r2c(
 __device__ inline int kappa_of(int i, int n) { return i <= n / 2 ? i : i - n; }
 
 // synthesis: torus spectrum cs[b][mu][t] (t < nt) -> band[b][mu][i], window rows only
-template <typename T, int K>
-__global__ __launch_bounds__(RowShape<K>::NT) void k_theta_inv(
+template <typename T, int K, int F>
+__global__ __launch_bounds__((RowShape<K, F>::NT)) void k_theta_inv(
     const typename Cx<T>::type* __restrict__ cs, typename Cx<T>::type* __restrict__ band, int nt,
     int lmax, int mmax, const T* __restrict__ d1, const T* __restrict__ d2, int ra, int rb,
     const typename Cx<T>::type* __restrict__ tw)
 {
     using C = typename Cx<T>::type;
-    using S = RowShape<K>;
+    using S = RowShape<K, F>;
     constexpr int N = S::N, R0 = S::R0;
     __shared__ C buf[N + N / 16];
     const int mu = blockIdx.x, b = blockIdx.y, t = threadIdx.x;
@@ -404,7 +460,7 @@ __global__ __launch_bounds__(RowShape<K>::NT) void k_theta_inv(
         }
     }
     __syncthreads();
-    middle_passes<K, +1>(buf, t, tw);
+    middle_passes<K, +1, F>(buf, t, tw);
     // last pass (radix 16, span N / 16) straight into the band column's window rows
     if (t < S::NB16) {
         C v[16], w[16];
@@ -423,14 +479,14 @@ __global__ __launch_bounds__(RowShape<K>::NT) void k_theta_inv(
 
 // adjoint: band[b][mu][i] (window rows; the others are taken as zero) -> torus spectrum
 // cs[b][mu][t], deconvolved, zero for |k| > L
-template <typename T, int K>
-__global__ __launch_bounds__(RowShape<K>::NT) void k_theta_fwd(
+template <typename T, int K, int F>
+__global__ __launch_bounds__((RowShape<K, F>::NT)) void k_theta_fwd(
     const typename Cx<T>::type* __restrict__ band, typename Cx<T>::type* __restrict__ cs, int nt,
     int lmax, int mmax, const T* __restrict__ d1, const T* __restrict__ d2, int ra, int rb,
     const typename Cx<T>::type* __restrict__ tw)
 {
     using C = typename Cx<T>::type;
-    using S = RowShape<K>;
+    using S = RowShape<K, F>;
     constexpr int N = S::N, R0 = S::R0;
     __shared__ C buf[N + N / 16];
     const int mu = blockIdx.x, b = blockIdx.y, t = threadIdx.x;
@@ -457,7 +513,7 @@ __global__ __launch_bounds__(RowShape<K>::NT) void k_theta_fwd(
         }
     }
     __syncthreads();
-    middle_passes<K, -1>(buf, t, tw);
+    middle_passes<K, -1, F>(buf, t, tw);
     if (t < S::NB16) {
         C v[16], w[16];
         load_twiddles<16, -1>(w, t, N / 16, N, tw);
@@ -655,105 +711,112 @@ __global__ __launch_bounds__(ThetaHalf<K>::NT) void k_theta_fwd_h(
 
 }  // namespace
 
+// n = F 2^K with F = 1 or 5; false otherwise
+static bool split_len(int n, int& K, int& F)
+{
+    F = (n % 5 == 0) ? 5 : 1;
+    const int m = n / F;
+    if (m < 1 || (m & (m - 1))) return false;
+    K = 0;
+    while ((1 << K) < m) ++K;
+    return true;
+}
+
+// one transform of N complex values held in LDS (with the pad slots)
+template <typename T>
+constexpr bool lds_fits(int N)
+{
+    return (size_t)(N + N / 16) * 2 * sizeof(T) <= 150 * 1024;
+}
+
+// lengths the kernels are built for: 2^K (K = 5 .. 14) and 5 2^K (K = 4 .. 11)
+static bool len_supported(int K, int F)
+{
+    return F == 1 ? (K >= 5 && K <= 14) : (K >= 4 && K <= 11);
+}
+
 bool rowfft_supported(const nusht_geometry& g)
 {
     const int n2 = g.n2;
-    if (n2 < 64 || n2 > 16384 || (n2 & (n2 - 1))) return false;
-    return g.mmax + 1 <= n2 / 2;
+    int K, F;
+    if (n2 % 2 || !split_len(n2 / 2, K, F) || !len_supported(K, F)) return false;
+    if (F == 1 && K > 13) return false;  // rows up to 16384 real values
+    const int N = n2 / 2;
+    if (!(g.dtype == NUSHT_MIXED ? lds_fits<float>(N) : lds_fits<double>(N))) return false;
+    return g.mmax + 1 <= N;
 }
 
-#define NUSHT_ROWK_SWITCH(K_, BODY)                    \
-    switch (K_) {                                      \
-        case 5: { constexpr int KV = 5; BODY; } break;   \
-        case 6: { constexpr int KV = 6; BODY; } break;   \
-        case 7: { constexpr int KV = 7; BODY; } break;   \
-        case 8: { constexpr int KV = 8; BODY; } break;   \
-        case 9: { constexpr int KV = 9; BODY; } break;   \
-        case 10: { constexpr int KV = 10; BODY; } break; \
-        case 11: { constexpr int KV = 11; BODY; } break; \
-        case 12: { constexpr int KV = 12; BODY; } break; \
-        case 13: { constexpr int KV = 13; BODY; } break; \
-        default: set_last_error("rowfft", "unsupported row length"); return NUSHT_EINVAL; \
+#define NUSHT_FK_CASE(FF, KK, ...) \
+    case (FF) * 100 + (KK): { constexpr int FV = FF, KV = KK; __VA_ARGS__; } break;
+#define NUSHT_FK_SWITCH(F_, K_, ...)                                                             \
+    switch ((F_) * 100 + (K_)) {                                                                 \
+        NUSHT_FK_CASE(1, 5, __VA_ARGS__) NUSHT_FK_CASE(1, 6, __VA_ARGS__)                        \
+        NUSHT_FK_CASE(1, 7, __VA_ARGS__) NUSHT_FK_CASE(1, 8, __VA_ARGS__)                        \
+        NUSHT_FK_CASE(1, 9, __VA_ARGS__) NUSHT_FK_CASE(1, 10, __VA_ARGS__)                       \
+        NUSHT_FK_CASE(1, 11, __VA_ARGS__) NUSHT_FK_CASE(1, 12, __VA_ARGS__)                      \
+        NUSHT_FK_CASE(1, 13, __VA_ARGS__) NUSHT_FK_CASE(1, 14, __VA_ARGS__)                      \
+        NUSHT_FK_CASE(5, 4, __VA_ARGS__) NUSHT_FK_CASE(5, 5, __VA_ARGS__)                        \
+        NUSHT_FK_CASE(5, 6, __VA_ARGS__) NUSHT_FK_CASE(5, 7, __VA_ARGS__)                        \
+        NUSHT_FK_CASE(5, 8, __VA_ARGS__) NUSHT_FK_CASE(5, 9, __VA_ARGS__)                        \
+        NUSHT_FK_CASE(5, 10, __VA_ARGS__) NUSHT_FK_CASE(5, 11, __VA_ARGS__)                      \
+        default: set_last_error("rowfft", "unsupported transform length"); return NUSHT_EINVAL; \
     }
 
-static int row_log2(int n2)
+template <typename T, int KV, int FV, bool C2R>
+int launch_row_k(const nusht_plan_s* p, const void* in, void* out, int64_t rw, hipStream_t s)
 {
-    int k = 0;
-    while ((2 << k) < n2) ++k;
-    return k;  // n2 / 2 = 2^k
+    using C = typename Cx<T>::type;
+    const nusht_geometry& g = p->g;
+    const int nq = p->fine_ra + p->fine_rb;
+    const C* tw = reinterpret_cast<const C*>(p->rowtw);
+    if constexpr ((KV <= 13 || FV == 5) && lds_fits<T>(RowShape<KV, FV>::N)) {
+        if (C2R)
+            hipLaunchKernelGGL((k_row_c2r<T, KV, FV>), dim3(nq), dim3(RowShape<KV, FV>::NT), 0, s,
+                               reinterpret_cast<const C*>(in), rw, g.mmax + 1,
+                               reinterpret_cast<T*>(out), g.n1, p->fine_ra, p->fine_rb, tw);
+        else
+            hipLaunchKernelGGL((k_row_r2c<T, KV, FV>), dim3(nq), dim3(RowShape<KV, FV>::NT), 0, s,
+                               reinterpret_cast<const T*>(in), g.n1, p->fine_ra, p->fine_rb,
+                               reinterpret_cast<C*>(out), rw, g.mmax + 1, tw);
+    } else {
+        set_last_error("rowfft", "unsupported row length");
+        return NUSHT_EINVAL;
+    }
+    NUSHT_HIP(hipGetLastError());
+    return NUSHT_OK;
+}
+
+template <bool C2R>
+int launch_row(const nusht_plan_s* p, const void* in, void* out, int64_t rw, hipStream_t s)
+{
+    int K = 0, F = 1;
+    split_len(p->g.n2 / 2, K, F);
+    NUSHT_FK_SWITCH(F, K, {
+        if (p->g.dtype == NUSHT_MIXED) return launch_row_k<float, KV, FV, C2R>(p, in, out, rw, s);
+        return launch_row_k<double, KV, FV, C2R>(p, in, out, rw, s);
+    });
+    return NUSHT_OK;
 }
 
 int launch_row_c2r(const nusht_plan_s* p, const void* rows, int64_t rw, void* fine, hipStream_t s)
 {
-    const nusht_geometry& g = p->g;
-    const int nq = p->fine_ra + p->fine_rb;
-    const int K = row_log2(g.n2);
-    NUSHT_ROWK_SWITCH(K, {
-        if (g.dtype == NUSHT_MIXED)
-            hipLaunchKernelGGL((k_row_c2r<float, KV>), dim3(nq), dim3(RowShape<KV>::NT), 0, s,
-                               reinterpret_cast<const float2*>(rows), rw, g.mmax + 1,
-                               reinterpret_cast<float*>(fine), g.n1, p->fine_ra, p->fine_rb,
-                               reinterpret_cast<const float2*>(p->rowtw));
-        else
-            hipLaunchKernelGGL((k_row_c2r<double, KV>), dim3(nq), dim3(RowShape<KV>::NT), 0, s,
-                               reinterpret_cast<const double2*>(rows), rw, g.mmax + 1,
-                               reinterpret_cast<double*>(fine), g.n1, p->fine_ra, p->fine_rb,
-                               reinterpret_cast<const double2*>(p->rowtw));
-    });
-    NUSHT_HIP(hipGetLastError());
-    return NUSHT_OK;
+    return launch_row<true>(p, rows, fine, rw, s);
 }
 
 int launch_row_r2c(const nusht_plan_s* p, const void* fine, void* rows, int64_t rw, hipStream_t s)
 {
-    const nusht_geometry& g = p->g;
-    const int nq = p->fine_ra + p->fine_rb;
-    const int K = row_log2(g.n2);
-    NUSHT_ROWK_SWITCH(K, {
-        if (g.dtype == NUSHT_MIXED)
-            hipLaunchKernelGGL((k_row_r2c<float, KV>), dim3(nq), dim3(RowShape<KV>::NT), 0, s,
-                               reinterpret_cast<const float*>(fine), g.n1, p->fine_ra, p->fine_rb,
-                               reinterpret_cast<float2*>(rows), rw, g.mmax + 1,
-                               reinterpret_cast<const float2*>(p->rowtw));
-        else
-            hipLaunchKernelGGL((k_row_r2c<double, KV>), dim3(nq), dim3(RowShape<KV>::NT), 0, s,
-                               reinterpret_cast<const double*>(fine), g.n1, p->fine_ra,
-                               p->fine_rb, reinterpret_cast<double2*>(rows), rw, g.mmax + 1,
-                               reinterpret_cast<const double2*>(p->rowtw));
-    });
-    NUSHT_HIP(hipGetLastError());
-    return NUSHT_OK;
+    return launch_row<false>(p, fine, rows, rw, s);
 }
 
 bool thetafft_supported(const nusht_geometry& g)
 {
     const int n1 = g.n1;
+    int K, F;
     if (g.dfs_mode != NUSHT_DFS_FUSED || !rowfft_supported(g)) return false;
-    if (n1 < 32 || (n1 & (n1 - 1))) return false;
-    // columns up to 16384 values in LDS (complex, or real and imaginary parts in turn)
-    return n1 <= 16384;
-}
-
-#define NUSHT_THETAK_SWITCH(K_, BODY)                  \
-    switch (K_) {                                      \
-        case 5: { constexpr int KV = 5; BODY; } break;   \
-        case 6: { constexpr int KV = 6; BODY; } break;   \
-        case 7: { constexpr int KV = 7; BODY; } break;   \
-        case 8: { constexpr int KV = 8; BODY; } break;   \
-        case 9: { constexpr int KV = 9; BODY; } break;   \
-        case 10: { constexpr int KV = 10; BODY; } break; \
-        case 11: { constexpr int KV = 11; BODY; } break; \
-        case 12: { constexpr int KV = 12; BODY; } break; \
-        case 13: { constexpr int KV = 13; BODY; } break; \
-        case 14: { constexpr int KV = 14; BODY; } break; \
-        default: set_last_error("thetafft", "unsupported column length"); return NUSHT_EINVAL; \
-    }
-
-static int col_log2(int n1)
-{
-    int k = 0;
-    while ((1 << k) < n1) ++k;
-    return k;
+    if (!split_len(n1, K, F) || !len_supported(K, F)) return false;
+    // a complex column in LDS, or (FP64, 16384) real and imaginary parts in turn
+    if (g.dtype == NUSHT_MIXED) return lds_fits<float>(n1);
+    return lds_fits<double>(n1) || (F == 1 && K == 14);
 }
 
 // columns whose complex values exceed the LDS (FP64, 16384) take the register-resident kernels
@@ -765,66 +828,61 @@ constexpr bool theta_half(int K)
     return sizeof(T) == 8 && K >= 14;
 }
 
-int launch_theta_inv(const nusht_plan_s* p, const void* cs, void* band, int nmaps, hipStream_t s)
+// the theta-pass launch for one precision and length (a template, so that the kernels of the
+// other branches are never instantiated)
+template <typename T, int KV, int FV, bool INV>
+int launch_theta_k(const nusht_plan_s* p, const void* in, void* out, int nmaps, hipStream_t s)
 {
+    using C = typename Cx<T>::type;
     const nusht_geometry& g = p->g;
-    const int K = col_log2(g.n1);
     const dim3 grid(g.mmax + 1, nmaps);
-#define NUSHT_THETA_INV(T, KK, KERN, SHAPE)                                                     \
-    hipLaunchKernelGGL((KERN<T, KK>), grid, dim3(SHAPE<KK>::NT), 0, s,                          \
-                       reinterpret_cast<const typename Cx<T>::type*>(cs),                       \
-                       reinterpret_cast<typename Cx<T>::type*>(band), g.ntorus, g.lmax, g.mmax, \
-                       std::is_same<T, float>::value ? (const T*)p->dec1f : (const T*)p->dec1,  \
-                       std::is_same<T, float>::value ? (const T*)p->dec2f : (const T*)p->dec2,  \
-                       p->fine_ra, p->fine_rb,                                                  \
-                       reinterpret_cast<const typename Cx<T>::type*>(p->thetatw))
-    NUSHT_THETAK_SWITCH(K, {
-        if (g.dtype == NUSHT_MIXED) {
-            if constexpr (theta_half<float>(KV))
-                NUSHT_THETA_INV(float, KV, k_theta_inv_h, ThetaHalf);
-            else
-                NUSHT_THETA_INV(float, KV, k_theta_inv, RowShape);
-        } else {
-            if constexpr (theta_half<double>(KV))
-                NUSHT_THETA_INV(double, KV, k_theta_inv_h, ThetaHalf);
-            else
-                NUSHT_THETA_INV(double, KV, k_theta_inv, RowShape);
-        }
-    });
-#undef NUSHT_THETA_INV
+    const T* d1 = std::is_same<T, float>::value ? (const T*)p->dec1f : (const T*)p->dec1;
+    const T* d2 = std::is_same<T, float>::value ? (const T*)p->dec2f : (const T*)p->dec2;
+    const C* tw = reinterpret_cast<const C*>(p->thetatw);
+    const C* src = reinterpret_cast<const C*>(in);
+    C* dst = reinterpret_cast<C*>(out);
+    if constexpr (FV == 1 && theta_half<T>(KV)) {
+        if (INV)
+            hipLaunchKernelGGL((k_theta_inv_h<T, KV>), grid, dim3(ThetaHalf<KV>::NT), 0, s, src, dst,
+                               g.ntorus, g.lmax, g.mmax, d1, d2, p->fine_ra, p->fine_rb, tw);
+        else
+            hipLaunchKernelGGL((k_theta_fwd_h<T, KV>), grid, dim3(ThetaHalf<KV>::NT), 0, s, src, dst,
+                               g.ntorus, g.lmax, g.mmax, d1, d2, p->fine_ra, p->fine_rb, tw);
+    } else if constexpr (lds_fits<T>(RowShape<KV, FV>::N)) {
+        if (INV)
+            hipLaunchKernelGGL((k_theta_inv<T, KV, FV>), grid, dim3(RowShape<KV, FV>::NT), 0, s, src,
+                               dst, g.ntorus, g.lmax, g.mmax, d1, d2, p->fine_ra, p->fine_rb, tw);
+        else
+            hipLaunchKernelGGL((k_theta_fwd<T, KV, FV>), grid, dim3(RowShape<KV, FV>::NT), 0, s, src,
+                               dst, g.ntorus, g.lmax, g.mmax, d1, d2, p->fine_ra, p->fine_rb, tw);
+    } else {
+        set_last_error("thetafft", "unsupported column length");
+        return NUSHT_EINVAL;
+    }
     NUSHT_HIP(hipGetLastError());
     return NUSHT_OK;
 }
 
+template <bool INV>
+int launch_theta(const nusht_plan_s* p, const void* in, void* out, int nmaps, hipStream_t s)
+{
+    int K = 0, F = 1;
+    split_len(p->g.n1, K, F);
+    NUSHT_FK_SWITCH(F, K, {
+        if (p->g.dtype == NUSHT_MIXED) return launch_theta_k<float, KV, FV, INV>(p, in, out, nmaps, s);
+        return launch_theta_k<double, KV, FV, INV>(p, in, out, nmaps, s);
+    });
+    return NUSHT_OK;
+}
+
+int launch_theta_inv(const nusht_plan_s* p, const void* cs, void* band, int nmaps, hipStream_t s)
+{
+    return launch_theta<true>(p, cs, band, nmaps, s);
+}
+
 int launch_theta_fwd(const nusht_plan_s* p, const void* band, void* cs, int nmaps, hipStream_t s)
 {
-    const nusht_geometry& g = p->g;
-    const int K = col_log2(g.n1);
-    const dim3 grid(g.mmax + 1, nmaps);
-#define NUSHT_THETA_FWD(T, KK, KERN, SHAPE)                                                     \
-    hipLaunchKernelGGL((KERN<T, KK>), grid, dim3(SHAPE<KK>::NT), 0, s,                          \
-                       reinterpret_cast<const typename Cx<T>::type*>(band),                     \
-                       reinterpret_cast<typename Cx<T>::type*>(cs), g.ntorus, g.lmax, g.mmax,   \
-                       std::is_same<T, float>::value ? (const T*)p->dec1f : (const T*)p->dec1,  \
-                       std::is_same<T, float>::value ? (const T*)p->dec2f : (const T*)p->dec2,  \
-                       p->fine_ra, p->fine_rb,                                                  \
-                       reinterpret_cast<const typename Cx<T>::type*>(p->thetatw))
-    NUSHT_THETAK_SWITCH(K, {
-        if (g.dtype == NUSHT_MIXED) {
-            if constexpr (theta_half<float>(KV))
-                NUSHT_THETA_FWD(float, KV, k_theta_fwd_h, ThetaHalf);
-            else
-                NUSHT_THETA_FWD(float, KV, k_theta_fwd, RowShape);
-        } else {
-            if constexpr (theta_half<double>(KV))
-                NUSHT_THETA_FWD(double, KV, k_theta_fwd_h, ThetaHalf);
-            else
-                NUSHT_THETA_FWD(double, KV, k_theta_fwd, RowShape);
-        }
-    });
-#undef NUSHT_THETA_FWD
-    NUSHT_HIP(hipGetLastError());
-    return NUSHT_OK;
+    return launch_theta<false>(p, band, cs, nmaps, s);
 }
 
 }  // namespace nusht
