@@ -315,13 +315,28 @@ __global__ __launch_bounds__(256) void k_legendre_synth(
                     }
                 }
             }
-            // Phase 2: some lane still carries a scale factor: per-step rescaling and masked
-            // accumulation.
+            // Phase 2: some lane still carries a scale factor: the rescale test once per pair
+            // of steps, as in phase 1, and the pair's two values accumulated for the lanes
+            // whose count is zero after it (scaling by 2^-256 is exact, so the values are the
+            // ones a per-step test would give).
             for (; l + 1 <= lmax && __any(any_scaled); l += 2) {
                 prefetch();
                 const double2 c0 = rec[moff + l], c1 = rec[moff + l + 1];
-                scaled_step(c0, moff + l, E);
-                scaled_step(c1, moff + l + 1, O);
+                any_scaled = false;
+#pragma unroll
+                for (int r = 0; r < R; ++r) {
+                    const double v0 = rec_step(c0, y[r], vc[r], vp[r]);
+                    const double v1 = rec_step(c1, y[r], v0, vc[r]);
+                    const bool big = (k[r] > 0) && fmax(fabs(v0), fabs(v1)) >= kBig;
+                    const double sc = big ? kUnit : 1.0;
+                    vp[r] = v0 * sc;
+                    vc[r] = v1 * sc;
+                    k[r] -= big ? 1 : 0;
+                    const bool live = k[r] == 0;
+                    any_scaled |= !live;
+                    accum<MB>(E[r], alm, nalm, moff + l, live ? vp[r] : 0.0);
+                    accum<MB>(O[r], alm, nalm, moff + l + 1, live ? vc[r] : 0.0);
+                }
             }
         }
         // Phase 3: every lane is in plain FP64 range.
