@@ -169,13 +169,13 @@ struct nusht_plan_s {
     nusht::FftPlan fine_rowa_c2r, fine_rowa_r2c;  // 1D over n2, batch fine_ra
     nusht::FftPlan fine_rowb_c2r, fine_rowb_r2c;  // 1D over n2, batch fine_rb (may be empty)
     int fine_ra = 0, fine_rb = 0;
-    // Power-of-two n2: the phi pass runs in the library's own row kernels (rowfft.hip), on
-    // row spectra of width mmax + 1 (no zero columns), instead of the rocFFT row plans.
+    // n2 / 2 = 2^K or 5 2^K: the phi pass runs in the library's own row kernels (rowfft.hip),
+    // on row spectra of width mmax + 1 (no zero columns), instead of the rocFFT row plans.
     bool row_custom = false;
     void* rowtw = nullptr;  // [n2] e^{2 pi i k / n2} in the plan's FFT precision
-    // Fused mode with power-of-two n1 that fits one LDS column: the theta pass and the
-    // deconvolution run as one kernel per direction (rowfft.hip) instead of the rocFFT column
-    // plans and the pad / truncate kernels.
+    // Fused mode with n1 = 2^K or 5 2^K up to 16384: the theta pass and the deconvolution run
+    // as one kernel per direction (rowfft.hip) instead of the rocFFT column plans and the pad /
+    // truncate kernels.
     bool theta_custom = false;
     void* thetatw = nullptr;  // [2 n1] e^{2 pi i k / (2 n1)} in the plan's FFT precision
 
@@ -262,7 +262,7 @@ int launch_band_to_rows(const nusht_plan_s* p, const void* band, void* rows, int
 int launch_rows_to_band(const nusht_plan_s* p, const void* rows, int rw, void* band,
                         hipStream_t s, bool window_only = false);
 
-// ---- fine-grid row transforms for power-of-two n2 (rowfft.hip) ----
+// ---- fine-grid row transforms for n2 / 2 = 2^K or 5 2^K (rowfft.hip) ----
 bool rowfft_supported(const nusht_geometry& g);
 // window rows of one map: rows [n1][rw] (columns 0 .. mmax) <-> real fine grid [n1][n2]
 int launch_row_c2r(const nusht_plan_s* p, const void* rows, int64_t rw, void* fine, hipStream_t s);

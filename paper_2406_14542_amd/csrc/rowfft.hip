@@ -1,5 +1,5 @@
 // Row transforms of the fine grid (the phi direction of N's 2-D FFT, arXiv:2406.14542
-// Sec. III) for power-of-two row lengths n2, one workgroup per window row:
+// Sec. III) for row lengths n2 = 2 N with N = 2^K or 5 2^K, one workgroup per window row:
 //   C2R  x[n] = sum_{k=0}^{n2-1} X[k] e^{+2 pi i k n / n2},  X[n2 - k] = conj X[k],
 //        X[k] = 0 for M < k < n2 - M (the band limit), Im X[0] ignored;
 //   R2C  X[k] = sum_n x[n] e^{-2 pi i k n / n2}, k = 0 .. M only.
@@ -8,7 +8,7 @@
 //   O[k] = (X[k] - X[k + N]) e^{2 pi i k / n2},  X[k + N] = conj X[N - k];
 // and backwards E = (Z[k] + conj Z[N-k]) / 2, O = (Z[k] - conj Z[N-k]) / (2i),
 //   X[k] = E + e^{-2 pi i k / n2} O.
-// The theta pass of the same 2-D FFT (power-of-two n1, one workgroup per band column mu of
+// The theta pass of the same 2-D FFT (n1 = 2^K or 5 2^K, one workgroup per band column mu of
 // one map) runs here as well, fused with the deconvolution of N(i) / N^H(iii):
 //   synthesis  band[mu][i] = sum_{|k| <= L} C[k][mu] h(k, mu) e^{+2 pi i k i / n1}, window rows i
 //   adjoint    C[k][mu] = h(k, mu) sum_{window rows i} band[mu][i] e^{-2 pi i k i / n1}, |k| <= L
@@ -17,10 +17,11 @@
 // entries exist, the padding is zeros in registers) or from the window rows of the band
 // (adjoint), transformed in LDS, and written once, so the zero-padded spectrum is never
 // stored and no separate deconvolution pass reads or writes it.
-// The N-point transform runs in LDS as Stockham radix passes (a first pass of radix
-// 2^(log2 N mod 4) when needed, then radix 16), reading the row straight from HBM in the
-// first pass and writing it in the last: one read and one write of each row, and only the
-// M + 1 band columns of the spectrum are read (C2R) or written (R2C).
+// The N-point transform runs in LDS as Stockham radix passes (N = 2^K: a first pass of radix
+// 2^(K mod 4) when needed, then radix 16; N = 5 2^K: radix 5, then 2^(K mod 4), then radix
+// 16), reading the row straight from HBM in the first pass and writing it in the last: one
+// read and one write of each row, and only the M + 1 band columns of the spectrum are read
+// (C2R) or written (R2C).
 #include "internal.h"
 
 namespace nusht {
