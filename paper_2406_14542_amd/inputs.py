@@ -49,6 +49,16 @@ def red_alm(rng: np.random.Generator, lmax: int, mmax: int, nmaps: int = 1) -> n
     return out
 
 
+def spin_alm(rng: np.random.Generator, lmax: int, mmax: int, spin: int,
+             nfields: int = 1) -> np.ndarray:
+    """[nfields, 2, nalm] complex128 gradient/curl coefficients of spin-`spin` fields: the
+    red_alm law for each of the 2 nfields rows, and 0 where l < spin (no such harmonic)."""
+    ls, _ = ell_of_index(lmax, mmax)
+    a = red_alm(rng, lmax, mmax, 2 * nfields).reshape(nfields, 2, ls.size)
+    a[:, :, ls < spin] = 0.0
+    return a
+
+
 def potential_alm(rng: np.random.Generator, lmax: int, mmax: int, rms_arcmin: float) -> np.ndarray:
     """A lensing-potential-like field Phi_lm [1, nalm]: C_l proportional to l^-4 for l >= 2
     (0 below), scaled so that the rms of the gradient (the deflection) over the sphere is
