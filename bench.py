@@ -367,6 +367,117 @@ def run_pointing(args):
     print(json.dumps(out), flush=True)
 
 
+def spin_legendre_flops(g, nfields):
+    """Algorithmic flops of one spin-weighted Legendre launch (synthesis or adjoint): per
+    (l, m, ring pair) one step of the two Wigner-d recurrences (an FMA for the x-dependent
+    factor, a multiply and an FMA for the step: 5 flops each), the two combinations W+- (an
+    FMA each, 4 flops) and, per field, 8 real multiply-adds (16 flops: the synthesis' four
+    complex-by-real accumulations; the adjoint's four products with the ring data and their
+    sums over rings): nalm x ceil(N_r / 2) x (14 + 16 F)."""
+    pairs = (g["nrings"] + 1) // 2
+    return float(g["nalm"]) * pairs * (14 + 16 * nfields)
+
+
+def run_spin(args):
+    """Spin-weighted leg (`--spin S`, the spin-n extension of Sec. V): the headline workload's
+    lmax = 4095 and 33,550,336 uniform points, `--spin-fields` spin-S fields (two real maps
+    each: F = 2 gives the same four real maps as the spin-0 step), one step = one
+    synthesis_spin + one adjoint_spin, mixed precision at eps = 1e-5 and FP64 at 1e-12.  The
+    accuracy columns: the mixed synthesis against the FP64 one, the FP64 synthesis against the
+    oracle's direct sums on 48 of the points, and the dot test <d, S a> = <S^H d, a>_m.
+    Prints ONE JSON line."""
+    import torch
+    import paper_2406_14542_amd as P
+    from paper_2406_14542_amd import inputs
+
+    P.lib()
+    spin, F = args.spin, args.spin_fields
+    cfg = inputs.config_c3(nmaps=1)
+    L = cfg["lmax"]
+    rng = np.random.default_rng(106)
+    a_np = inputs.spin_alm(rng, L, L, spin, F)
+    d_np = rng.standard_normal((F, 2, cfg["theta"].size))
+    a = torch.from_numpy(a_np).cuda()
+    d = torch.from_numpy(d_np).cuda()
+    _, ms = inputs.ell_of_index(L, L)
+    w = torch.from_numpy(np.where(ms == 0, 1.0, 2.0)).cuda()
+    res = {}
+    maps = {}
+    for dtype, eps in (("mixed", 1e-5), ("f64", 1e-12)):
+        th = torch.from_numpy(cfg["theta"]).cuda()
+        ph = torch.from_numpy(cfg["phi"]).cuda()
+        pl = P.Plan(L, L, th, ph, eps, dtype=dtype, timing=True)
+        del th, ph
+        f = torch.empty((F, 2, pl.npts), dtype=torch.float64, device="cuda")
+        c = torch.empty((F, 2, pl.nalm), dtype=torch.complex128, device="cuda")
+
+        def step():
+            pl.synthesis_spin(spin, a, out=f)
+            pl.adjoint_spin(spin, d, out=c)
+
+        for _ in range(args.warmup):
+            step()
+        torch.cuda.synchronize()
+        pl.stage_reset()
+        evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+               for _ in range(args.steps)]
+        for e0, e1 in evs:
+            e0.record()
+            step()
+            e1.record()
+        torch.cuda.synchronize()
+        pl.status()
+        per = [e0.elapsed_time(e1) * 1e-3 for e0, e1 in evs]
+        syn = {k: v[0] for k, v in pl.stage_stats("synthesis_spin").items() if v[0] > 0}
+        adj = {k: v[0] for k, v in pl.stage_stats("adjoint_spin").items() if v[0] > 0}
+        g = pl.geometry
+        fl = spin_legendre_flops(g, F)
+        lhs = float(torch.sum(d * f))
+        rhs = float(torch.sum(w * (torch.conj(c) * a).real))
+        maps[dtype] = f.cpu().numpy()
+        st = step_stats(per)
+        res[dtype] = {"ms_per_step": round(1e3 * st["median_s"], 3), **st, "eps": eps,
+                      "width": g["width"], "synthesis_stages_ms": syn, "adjoint_stages_ms": adj,
+                      "roofline_kernels": {
+                          "spin_legendre_synthesis": {
+                              "ms": round(syn["legendre"], 4),
+                              "achieved": round(fl / (syn["legendre"] * 1e-3) / 1e12, 3),
+                              "unit": "TFLOP/s",
+                              "frac": round(fl / (syn["legendre"] * 1e-3) / 1e12 / FP64_PEAK_TFLOPS, 4)},
+                          "spin_legendre_adjoint": {
+                              "ms": round(adj["legendre"], 4),
+                              "achieved": round(fl / (adj["legendre"] * 1e-3) / 1e12, 3),
+                              "unit": "TFLOP/s",
+                              "frac": round(fl / (adj["legendre"] * 1e-3) / 1e12 / FP64_PEAK_TFLOPS, 4)}},
+                      "dot_test_rel": abs(lhs - rhs) / abs(lhs),
+                      "legendre_flops_per_launch": fl}
+        log(f"spin {spin} {dtype}: {res[dtype]['ms_per_step']:.2f} ms/step; syn {syn} adj {adj}")
+        pl.close()
+        del f, c
+        torch.cuda.empty_cache()
+    acc = {"mixed_vs_fp64_synthesis_rel_l2": float(
+        np.linalg.norm(maps["mixed"] - maps["f64"]) / np.linalg.norm(maps["f64"]))}
+    try:
+        import oracle
+        sel = np.linspace(0, cfg["theta"].size - 1, 48).astype(np.int64)
+        ref = oracle.spin_synthesis(L, L, spin, cfg["theta"][sel], cfg["phi"][sel], a_np)
+        acc["fp64_vs_oracle_sample_rel_l2"] = float(
+            np.linalg.norm(maps["f64"][:, :, sel] - ref) / np.linalg.norm(ref))
+    except Exception as e:  # the oracle is optional for the timing itself
+        log(f"oracle sample skipped: {e}")
+    out = {"metric": f"spin-{spin} nuSHT synthesis+adjoint seconds at lmax={L} "
+                     f"({F} fields = {2 * F} real maps)",
+           "value": res["mixed"]["median_s"], "unit": "s", "n_gpus": 1, "steps": args.steps,
+           "warmup": args.warmup, "ms_per_step": res["mixed"]["ms_per_step"],
+           "higher_is_better": False, "scaling": "weak", "vs_baseline": None,
+           "dtype": "f32+f64", "data": "synthetic",
+           "config": {"workload": f"c3 points (N={cfg['theta'].size} uniform), lmax=mmax={L}, "
+                                  f"spin {spin}, {F} fields", "spin": spin, "nfields": F},
+           "mixed": res["mixed"], "fp64": res["f64"], "accuracy": acc,
+           "legendre_flops_per_launch": res["mixed"]["legendre_flops_per_launch"]}
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -402,6 +513,9 @@ def main():
                     help="run the lensing-pointing leg (Eq. C2 + C1) instead of the transform step")
     ap.add_argument("--pointing-lmax", default="1023,2047,4095")
     ap.add_argument("--pointing-eps", type=float, default=1e-12)
+    ap.add_argument("--spin", type=int, default=0,
+                    help="run the spin-weighted leg with this spin instead of the transform step")
+    ap.add_argument("--spin-fields", type=int, default=2)
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
                     help="only run one elementwise device copy of BYTES bytes (the reference "
                          "kernel that scales HBM byte counters)")
@@ -422,6 +536,9 @@ def main():
         sys.exit(2)
     if args.pointing:
         run_pointing(args)
+        return
+    if args.spin:
+        run_spin(args)
         return
     if args.cg:
         run_cg(args)

@@ -1,5 +1,6 @@
 /*
- * nusht: spin-0 nonuniform spherical harmonic transforms on one AMD Instinct MI355X (gfx950).
+ * nusht: nonuniform spherical harmonic transforms (spin 0 and spin s) on one AMD Instinct
+ * MI355X (gfx950).
  *
  * Method: arXiv:2406.14542 (cuNUSHT), Sec. II.B.  The type-2 transform (synthesis, Eq. 3)
  * is factored as Y = N F D S (Eq. 5): S is an iso-latitude Legendre synthesis onto an
@@ -141,6 +142,31 @@ int nusht_synthesis(nusht_plan_t plan, const double* alm, double* map, int nmaps
 /* Type 1 (adjoint), Eq. (2): alm[b][lm] = sum_i map[b][i] conj(Y_lm(theta_i, phi_i)),
    0 <= m <= mmax.  No quadrature weights: this is the adjoint, not an inverse (Sec. II.A). */
 int nusht_adjoint(nusht_plan_t plan, const double* map, double* alm, int nmaps, void* stream);
+
+/* Spin-weighted transforms (the spin-n extension of Sec. V: Wigner's d in place of the
+   Legendre functions in S; D, F and N are the spin-0 ones run on two real maps per field).
+   Definitions: sY_lm(theta, phi) = slam_lm(theta) e^{i m phi} with
+     slam_lm = (-1)^s sqrt((2l+1)/4pi) d^l_{m,-s}(theta)  (Wigner's d; the spin-raising ladder
+     from the Y_lm above: (s+1)Y = eth(sY) / sqrt((l-s)(l+s+1)),
+     eth = -sin^s(theta) (d/dtheta + i/sin(theta) d/dphi) sin^-s(theta)).
+   A field of spin s >= 1 is a pair of real maps (Q, U) with Q + iU = sum_lm sa_lm sY_lm and
+   gradient / curl coefficients G, C: sa_lm = -(G_lm + i C_lm), (-s)a_lm = -(-1)^s (G_lm - i C_lm);
+   G and C of a real pair obey G_{l,-m} = (-1)^m conj(G_lm), so only m >= 0 is stored, as for
+   spin 0.  Coefficients with l < s do not exist: they are ignored on input and written as 0.
+   Layout: alm [nfields][2][nalm] complex128 (G, then C, of every field); map
+   [nfields][2][npts] float64 (Q, then U).  For spin 1 and G = -sqrt(l(l+1)) a_lm, C = 0 the
+   map is (Q, U) = -(d f/d theta, (d f/d phi)/sin theta) of the spin-0 map f of a_lm.
+   The adjoint is the transpose under <.,.>_m above, applied to G and C alike.
+   Plans: fused DFS mode only, 1 <= spin <= min(lmax, NUSHT_MAX_SPIN) (NUSHT_EINVAL otherwise);
+   the first call with a spin builds its recurrence table (32 bytes per coefficient, kept
+   until the spin changes or the plan is destroyed, so that call synchronises and
+   allocates).  The adjoint adds with device atomics: its results can differ between runs by
+   rounding, and deterministic plans refuse it (NUSHT_EINVAL). */
+#define NUSHT_MAX_SPIN 64
+int nusht_synthesis_spin(nusht_plan_t plan, int spin, const double* alm, double* map,
+                         int nfields, void* stream);
+int nusht_adjoint_spin(nusht_plan_t plan, int spin, const double* map, double* alm, int nfields,
+                       void* stream);
 
 /* Synthesis plus the derivatives of the map with respect to the point coordinates:
    dtheta[b][i] = d map[b][i] / d theta_i, dphi[b][i] = d map[b][i] / d phi_i.  FP64 plans only
@@ -285,7 +311,7 @@ int nusht_stage_times(nusht_plan_t plan, double* ms, const char** names, int max
 
 /* Kinds of execution call, for nusht_stage_stats. */
 enum { NUSHT_CALL_SYNTHESIS = 0, NUSHT_CALL_ADJOINT = 1, NUSHT_CALL_SYNTHESIS_DERIV = 2,
-       NUSHT_CALL_RING = 3 };
+       NUSHT_CALL_RING = 3, NUSHT_CALL_SPIN_SYNTHESIS = 4, NUSHT_CALL_SPIN_ADJOINT = 5 };
 
 /* Mean per-stage device time (ms) over the calls of one kind made since the plan was built
    or since nusht_stage_reset (the most recent 64 calls of the plan count at most); ncalls

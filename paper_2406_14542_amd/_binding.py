@@ -16,6 +16,7 @@ NUSHT_F64, NUSHT_MIXED = 0, 1
 NUSHT_OK, NUSHT_EINVAL, NUSHT_ENOMEM, NUSHT_EDEVICE, NUSHT_ENOCONV, NUSHT_EPRECISION = \
     0, -1, -2, -3, -4, -5
 NUSHT_DFS_FUSED, NUSHT_DFS_PAPER = 0, 1
+NUSHT_MAX_SPIN = 64  # largest spin of nusht_synthesis_spin / nusht_adjoint_spin
 
 
 class PlanOpts(ctypes.Structure):
@@ -81,6 +82,10 @@ def lib():
             "nusht_plan_status": (ctypes.c_int, [_vp]),
             "nusht_synthesis": (ctypes.c_int, [_vp, _vp, _vp, ctypes.c_int, _vp]),
             "nusht_adjoint": (ctypes.c_int, [_vp, _vp, _vp, ctypes.c_int, _vp]),
+            "nusht_synthesis_spin": (ctypes.c_int, [_vp, ctypes.c_int, _vp, _vp, ctypes.c_int,
+                                                    _vp]),
+            "nusht_adjoint_spin": (ctypes.c_int, [_vp, ctypes.c_int, _vp, _vp, ctypes.c_int,
+                                                  _vp]),
             "nusht_synthesis_deriv": (ctypes.c_int, [_vp, _vp, _vp, _vp, _vp, ctypes.c_int,
                                                      _vp]),
             "nusht_pointing": (ctypes.c_int, [_vp, _vp, _vp, _vp, _vp]),
@@ -263,6 +268,37 @@ class Plan:
                "nusht_adjoint")
         return out
 
+    def synthesis_spin(self, spin, alm, out=None):
+        """Spin-`spin` synthesis: alm [F, 2, nalm] complex128 (gradient G, curl C per field)
+        -> [F, 2, npts] float64 (Q, U)."""
+        import torch
+        if alm.dtype != torch.complex128 or not alm.is_cuda or alm.device != self.device:
+            raise TypeError(f"alm must be a complex128 tensor on {self.device}")
+        a = alm.unsqueeze(0) if alm.dim() == 2 else alm
+        if a.dim() != 3 or a.shape[1] != 2 or a.shape[2] != self.nalm:
+            raise ValueError(f"alm must have shape [F, 2, {self.nalm}]")
+        a = a.contiguous()
+        F = a.shape[0]
+        out = self._out(out, (F, 2, self.npts), torch.float64, a)
+        _check(lib().nusht_synthesis_spin(self._h, int(spin), a.data_ptr(), out.data_ptr(), F,
+                                          _stream()), "nusht_synthesis_spin")
+        return out
+
+    def adjoint_spin(self, spin, maps, out=None):
+        """Adjoint of synthesis_spin: maps [F, 2, npts] float64 -> [F, 2, nalm] complex128."""
+        import torch
+        if maps.dtype != torch.float64 or not maps.is_cuda or maps.device != self.device:
+            raise TypeError(f"maps must be a float64 tensor on {self.device}")
+        x = maps.unsqueeze(0) if maps.dim() == 2 else maps
+        if x.dim() != 3 or x.shape[1] != 2 or x.shape[2] != self.npts:
+            raise ValueError(f"maps must have shape [F, 2, {self.npts}]")
+        x = x.contiguous()
+        F = x.shape[0]
+        out = self._out(out, (F, 2, self.nalm), torch.complex128, x)
+        _check(lib().nusht_adjoint_spin(self._h, int(spin), x.data_ptr(), out.data_ptr(), F,
+                                        _stream()), "nusht_adjoint_spin")
+        return out
+
     def synthesis_deriv(self, alm):
         import torch
         a = self._alm_in(alm)
@@ -399,7 +435,8 @@ class Plan:
             _check(n, "nusht_stage_times")
         return {names[i].decode(): ms[i] for i in range(n)}
 
-    CALL_KINDS = {"synthesis": 0, "adjoint": 1, "synthesis_deriv": 2, "ring": 3}
+    CALL_KINDS = {"synthesis": 0, "adjoint": 1, "synthesis_deriv": 2, "ring": 3,
+                  "synthesis_spin": 4, "adjoint_spin": 5}
 
     def stage_stats(self, kind: str) -> dict:
         """Mean per-stage device ms over the recorded calls of one kind (timing plans):

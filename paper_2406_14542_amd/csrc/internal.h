@@ -94,6 +94,13 @@ struct nusht_plan_s {
     int* jscale = nullptr;       // [mmax+1]: first ring pair with lam_mm above 2^-190
     std::vector<int> jlive_host;
 
+    // Wigner-d tables of the spin-weighted Legendre step (spin.hip), for spin spin_s (0: none):
+    // (alpha, c_p, c_q, gamma) of the step to (l, m) and the start constant per m.
+    int spin_s = 0;
+    double4* spin_rec = nullptr;  // [nalm + kRecPad]
+    double* spin_km = nullptr;    // [mmax+1] mantissa
+    int* spin_ke = nullptr;       // [mmax+1] power-of-two exponent
+
     // Deconvolution factors (include the FFT normalisation of the torus transform).
     double* dec1 = nullptr;      // [lmax+1], indexed by |kappa|
     double* dec2 = nullptr;      // [mmax+1], indexed by mu
@@ -244,6 +251,13 @@ int launch_legendre_adjoint(nusht_plan_s* p, const void* in, double* alm, int nm
                             int fused, int in_f32, hipStream_t s);
 
 // ---- DFS glue (dfs.hip) ----
+// ---- spin-weighted Legendre step (spin.hip) ----
+// tables for the given spin (rebuilt when it changes); nfields fields = 2 nfields maps (Q, U)
+int ensure_spin_tables(nusht_plan_s* p, int spin);
+int launch_spin_synth(nusht_plan_s* p, int spin, const double* alm, void* out, int nfields,
+                      int out_f32, hipStream_t s);
+int launch_spin_adjoint(nusht_plan_s* p, int spin, const void* in, double* alm, int nfields,
+                        int in_f32, hipStream_t s);
 int launch_zero_nyquist_rows(const nusht_plan_s* p, double* G, int nmaps, hipStream_t s);
 int launch_double(const nusht_plan_s* p, const double* ring, void* torus, int nmaps, int f32,
                   hipStream_t s);

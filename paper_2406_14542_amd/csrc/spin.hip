@@ -1,0 +1,582 @@
+// Spin-weighted Legendre step: the Wigner-d transform that replaces the Legendre step of S for
+// spin-s fields (arXiv:2406.14542, Sec. V names spin-n transforms through Wigner's d as the
+// extension of the method).  The rest of the path -- the doubled theta-columns, the torus
+// theta-FFT, the nonuniform FFT -- is the spin-0 one run on the two real maps (Q, U) of every
+// field; only the sign of the doubling changes: a spin-s quantity in the local (e_theta, e_phi)
+// basis continues to theta -> -theta as (-1)^s times its value at phi + pi, so column m
+// continues with (-1)^(m+s) instead of (-1)^m.
+//
+// Definitions (s >= 1, m >= 0, l >= l0 = max(m, s)):
+//   slam_lm(theta) = (-1)^s sqrt((2l+1)/4pi) d^l_{m,-s}(theta)   (sY_lm = slam_lm e^{i m phi})
+//   W+ = (slam + (-1)^s (-s)lam) / 2,  W- = (slam - (-1)^s (-s)lam) / 2
+//   synthesis  Q_m = -sum_l (G_lm W+ + i C_lm W-),  U_m = -sum_l (C_lm W+ - i G_lm W-)
+//   adjoint    cG_lm = -sum_j (Q'_m(j) W+ + i U'_m(j) W-),  cC_lm = -sum_j (U'_m(j) W+ - i Q'_m(j) W-)
+// with G, C the gradient and curl coefficients (Q + iU = sum sa_lm sY_lm, sa_lm = -(G + iC)).
+//
+// Both functions p = slam and q = (-s)lam come from the three-term recurrence of Wigner's d in l
+// at fixed (m, -+s): y_l = (c - alpha (1 - cos theta)) y_{l-1} - gamma y_{l-2}, where
+// c = alpha + b for p and alpha - b for q (b carries m s); the coefficients are a host table in
+// long double, rounded once ((alpha, c_p, c_q, gamma) per (l, m), 32 bytes).  The start at l0 is
+// a product of half-angle powers, cos^a(theta/2) sin^b(theta/2), formed with an explicit binary
+// exponent; the two functions share one count of 2^256 factors per lane, as the spin-0 kernel
+// does, and a term enters the sums once the count is zero.
+//
+// gfx950 mapping (same as the spin-0 kernels): one lane = one pair of mirror rings (j, N_r-1-j)
+// -- slam(pi - theta) = (-1)^(l+m) (-s)lam(theta), so W+ has hemisphere parity (-1)^(l+m+s) and
+// W- the opposite, and even/odd-l accumulators serve both rings; the lanes of a block share m,
+// so the coefficient stream is wave-uniform (scalar loads); blocks of one m sit on one XCD.
+#include "internal.h"
+
+#include <thread>
+
+namespace nusht {
+namespace {
+
+constexpr double kSpBig = 0x1p56;     // rescale once a scaled value reaches this
+constexpr double kSpUnit = 0x1p-256;  // one scale unit
+constexpr int kSpAccumExp = -200;     // terms below 2^-200 are not accumulated
+constexpr int kSpLC = 4;              // l values per reduction chunk of the adjoint
+
+// base^n (base >= 0) as mant * 2^e with mant in [0.5, 1); 0^0 = 1, 0^n = 0
+__device__ inline void pow_exp(double base, int n, double& mant, int& e)
+{
+    mant = 0.5;
+    e = 1;
+    if (n == 0) return;
+    if (base == 0.0) {
+        mant = 0.0;
+        e = 0;
+        return;
+    }
+    int be;
+    double b = frexp(base, &be);
+    while (n) {
+        int t;
+        if (n & 1) {
+            mant *= b;
+            e += be;
+            mant = frexp(mant, &t);
+            e += t;
+        }
+        n >>= 1;
+        if (n) {
+            b *= b;
+            be *= 2;
+            b = frexp(b, &t);
+            be += t;
+        }
+    }
+}
+
+__device__ inline void xcd_place(int b, int nbx, int& m, int& rb)
+{
+    const int x = b & 7, q = b >> 3;
+    m = 8 * (q / nbx) + x;
+    rb = q % nbx;
+}
+
+// Ring pair j: y = 1 - cos theta_j, and the start values p = slam_{l0 m}, q = (-s)lam_{l0 m}
+// as p 2^(-256 k), q 2^(-256 k).
+__device__ inline void spin_start(int j, int nr, int m, int spin, double km, int ke, double& y,
+                                  double& p, double& q, int& k)
+{
+    const double a = (double)j / (2.0 * (double)(nr - 1));
+    const double s2 = sinpi(a);
+    const double c2 = (2 * j == nr - 1) ? s2 : cospi(a);
+    y = 2.0 * s2 * s2;
+    const int dms = m > spin ? m - spin : spin - m;
+    double cu, su, cv, sv;
+    int ecu, esu, ecv, esv;
+    pow_exp(c2, dms, cu, ecu);
+    pow_exp(s2, m + spin, su, esu);
+    pow_exp(c2, m + spin, cv, ecv);
+    pow_exp(s2, dms, sv, esv);
+    // signs: d^{l0}_{m,-s} carries (-1)^(m+s); d^{l0}_{m,+s} carries (-1)^(m+s) when m >= s;
+    // both functions carry (-1)^s
+    const double sgu = ((m & 1) ? -1.0 : 1.0);
+    const double sgv = (m >= spin) ? sgu : ((spin & 1) ? -1.0 : 1.0);
+    int t;
+    double mu = frexp(km * cu * su, &t);
+    int eu = ke + ecu + esu + t;
+    double mv = frexp(km * cv * sv, &t);
+    int ev = ke + ecv + esv + t;
+    int e;
+    if (mu == 0.0 && mv == 0.0) {
+        p = q = 0.0;
+        k = 0;
+        return;
+    }
+    if (mu == 0.0)
+        e = ev;
+    else if (mv == 0.0)
+        e = eu;
+    else
+        e = max(eu, ev);
+    k = e >= kSpAccumExp ? 0 : (kSpAccumExp - e + 255) / 256;
+    p = sgu * ldexp(mu, eu + 256 * k);
+    q = sgv * ldexp(mv, ev + 256 * k);
+}
+
+// one recurrence step of both functions
+__device__ inline void spin_step(const double4 c, double y, double& p, double& q, double& pp,
+                                 double& qp)
+{
+    const double tp = fma(-c.x, y, c.y);
+    const double tq = fma(-c.x, y, c.z);
+    const double pn = fma(tp, p, -(c.w * pp));
+    const double qn = fma(tq, q, -(c.w * qp));
+    pp = p;
+    qp = q;
+    p = pn;
+    q = qn;
+}
+
+// the scaled variant: rescales the lane's pair when it reaches kSpBig while k > 0; returns
+// whether the new values are live (k == 0)
+__device__ inline bool spin_step_scaled(const double4 c, double y, double& p, double& q,
+                                        double& pp, double& qp, int& k)
+{
+    spin_step(c, y, p, q, pp, qp);
+    const bool big = (k > 0) && fmax(fabs(p), fabs(q)) >= kSpBig;
+    const double sc = big ? kSpUnit : 1.0;
+    p *= sc;
+    q *= sc;
+    pp *= sc;
+    qp *= sc;
+    k -= big ? 1 : 0;
+    return k == 0;
+}
+
+template <typename OutT>
+__device__ inline OutT make_pair(double re, double im)
+{
+    OutT o;
+    o.x = re;
+    o.y = im;
+    return o;
+}
+
+// accumulators of one parity class, per field: G W+ (re, im), C W- (re, im), C W+ (re, im),
+// G W- (re, im), with W+- still doubled (p +- (-1)^s q)
+template <int MB>
+__device__ inline void spin_accum(double (&A)[MB][8], const double2* __restrict__ alm,
+                                  int64_t nalm, int64_t idx, double wp, double wm)
+{
+#pragma unroll
+    for (int b = 0; b < MB; ++b) {
+        const double2 G = alm[(int64_t)(2 * b) * nalm + idx];
+        const double2 C = alm[(int64_t)(2 * b + 1) * nalm + idx];
+        A[b][0] = fma(G.x, wp, A[b][0]);
+        A[b][1] = fma(G.y, wp, A[b][1]);
+        A[b][2] = fma(C.x, wm, A[b][2]);
+        A[b][3] = fma(C.y, wm, A[b][3]);
+        A[b][4] = fma(C.x, wp, A[b][4]);
+        A[b][5] = fma(C.y, wp, A[b][5]);
+        A[b][6] = fma(G.x, wm, A[b][6]);
+        A[b][7] = fma(G.y, wm, A[b][7]);
+    }
+}
+
+// Synthesis: out[map][m][t] (t < N_t) for maps 2f (Q) and 2f+1 (U) of field f, the doubled
+// columns of the fused path: out(t) = X(t) for t < N_r, (-1)^(m+s) X(N_t - t) for t >= N_r.
+template <int MB, typename OutT>
+__global__ __launch_bounds__(256) void k_spin_synth(
+    const double2* __restrict__ alm, int64_t nalm, int lmax, int mmax, int spin, int nbx,
+    const double4* __restrict__ rec, const double* __restrict__ km, const int* __restrict__ ke,
+    int nr, int nt, OutT* __restrict__ out, int64_t out_map_stride, int64_t out_row_stride)
+{
+    int m, rb;
+    xcd_place(blockIdx.x, nbx, m, rb);
+    if (m > mmax) return;
+    const int npairs = (nr + 1) / 2;
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int wbase = (rb * (blockDim.x >> 6) + wave) * 64;
+    if (wbase >= npairs) return;
+    alm += (int64_t)blockIdx.y * MB * 2 * nalm;
+    out += (int64_t)blockIdx.y * MB * 2 * out_map_stride;
+    const int64_t moff = (int64_t)m * (2 * lmax + 1 - m) / 2;
+    const int l0 = max(m, spin);
+    const double sg = (spin & 1) ? -1.0 : 1.0;
+
+    double E[MB][8], O[MB][8];
+#pragma unroll
+    for (int b = 0; b < MB; ++b)
+#pragma unroll
+        for (int i = 0; i < 8; ++i) E[b][i] = O[b][i] = 0.0;
+
+    const int j = min(wbase + lane, npairs - 1);
+    {
+        double y, p, q;
+        int k;
+        spin_start(j, nr, m, spin, km[m], ke[m], y, p, q, k);
+        double pp = 0.0, qp = 0.0;
+        bool any_scaled = k > 0;
+        if (k == 0) spin_accum<MB>(E, alm, nalm, moff + l0, fma(sg, q, p), fma(-sg, q, p));
+        auto scaled = [&](int l, double (&A)[MB][8]) {
+            const bool live = spin_step_scaled(rec[moff + l], y, p, q, pp, qp, k);
+            any_scaled = !live;
+            spin_accum<MB>(A, alm, nalm, moff + l, live ? fma(sg, q, p) : 0.0,
+                           live ? fma(-sg, q, p) : 0.0);
+        };
+        auto plain = [&](int l, double (&A)[MB][8]) {
+            spin_step(rec[moff + l], y, p, q, pp, qp);
+            spin_accum<MB>(A, alm, nalm, moff + l, fma(sg, q, p), fma(-sg, q, p));
+        };
+        int l = l0 + 1;
+        for (; l + 1 <= lmax; l += 2) {
+            if (__any(any_scaled)) {
+                scaled(l, O);
+                scaled(l + 1, E);
+            } else {
+                plain(l, O);
+                plain(l + 1, E);
+            }
+        }
+        if (l <= lmax) {
+            if (__any(any_scaled))
+                scaled(l, O);
+            else
+                plain(l, O);
+        }
+    }
+
+    const int jj = wbase + lane;
+    if (jj >= npairs) return;
+    const int js = nr - 1 - jj;
+    const double dsg = ((m + spin) & 1) ? -1.0 : 1.0;     // doubling sign
+    const double tau = ((l0 + m + spin) & 1) ? -0.5 : 0.5;  // south parity of the even class, x 1/2
+#pragma unroll
+    for (int b = 0; b < MB; ++b) {
+        double S[8], D[8];
+#pragma unroll
+        for (int i = 0; i < 8; ++i) {
+            S[i] = E[b][i] + O[b][i];
+            D[i] = E[b][i] - O[b][i];
+        }
+        double qn_re = -0.5 * (S[0] - S[3]), qn_im = -0.5 * (S[1] + S[2]);
+        double un_re = -0.5 * (S[4] + S[7]), un_im = -0.5 * (S[5] - S[6]);
+        double qs_re = -tau * (D[0] + D[3]), qs_im = -tau * (D[1] - D[2]);
+        double us_re = -tau * (D[4] - D[7]), us_im = -tau * (D[5] + D[6]);
+        if (m == 0) qn_im = un_im = qs_im = us_im = 0.0;  // imaginary parts of m = 0 are ignored
+        OutT* cq = out + (int64_t)(2 * b) * out_map_stride + (int64_t)m * out_row_stride;
+        OutT* cu = cq + out_map_stride;
+        cq[jj] = make_pair<OutT>(qn_re, qn_im);
+        cu[jj] = make_pair<OutT>(un_re, un_im);
+        if (jj >= 1 && jj <= nr - 2) {
+            cq[nt - jj] = make_pair<OutT>(dsg * qn_re, dsg * qn_im);
+            cu[nt - jj] = make_pair<OutT>(dsg * un_re, dsg * un_im);
+        }
+        if (js != jj) {
+            cq[js] = make_pair<OutT>(qs_re, qs_im);
+            cu[js] = make_pair<OutT>(us_re, us_im);
+            if (js >= 1 && js <= nr - 2) {
+                cq[nt - js] = make_pair<OutT>(dsg * qs_re, dsg * qs_im);
+                cu[nt - js] = make_pair<OutT>(dsg * us_re, dsg * us_im);
+            }
+        }
+    }
+}
+
+template <typename InT>
+__device__ inline double2 load2(const InT* p)
+{
+    const InT v = *p;
+    return make_double2((double)v.x, (double)v.y);
+}
+
+// folded ring value of the fused input column: X(j) + [1 <= j <= N_r - 2] sgn X(N_t - j)
+template <typename InT>
+__device__ inline double2 folded(const InT* col, int j, int nr, int nt, double sgn)
+{
+    double2 v = load2(col + j);
+    if (j >= 1 && j <= nr - 2) {
+        const double2 w = load2(col + (nt - j));
+        v.x = fma(sgn, w.x, v.x);
+        v.y = fma(sgn, w.y, v.y);
+    }
+    return v;
+}
+
+// Adjoint.  Each lane multiplies W+- of its ring pair with the folded ring data; the sums over
+// ring pairs are formed per chunk of kSpLC values of l: every lane parks its 4 MB products per
+// l in LDS, the wave reads them back transposed (a row per lane group) and sums, the block's
+// waves are summed through a small LDS array after one barrier, and the block adds its sums
+// into the zeroed output with FP64 atomics (the blocks of one m run on one XCD: the atomics
+// resolve in its L2; the order of those additions is not fixed).
+template <int MB, typename InT>
+__global__ __launch_bounds__(256) void k_spin_adj(
+    const InT* __restrict__ in, int64_t in_map_stride, int64_t in_row_stride,
+    double* __restrict__ alm, int64_t nalm, int lmax, int mmax, int spin, int nbx,
+    const double4* __restrict__ rec, const double* __restrict__ km, const int* __restrict__ ke,
+    int nr, int nt)
+{
+    constexpr int NV = 4 * MB;          // products per l per lane
+    constexpr int ROWS = kSpLC * NV;    // rows of one chunk
+    constexpr int LPR = 64 / ROWS;      // lanes per row in the transposed read
+    constexpr int PER = 64 / LPR;       // entries summed per lane
+    static_assert(ROWS * LPR == 64, "chunk shape");
+    __shared__ double buf[4][ROWS][65];
+    __shared__ double xw[2][4][ROWS];
+
+    int m, rb;
+    xcd_place(blockIdx.x, nbx, m, rb);
+    if (m > mmax) return;  // uniform over the block
+    const int npairs = (nr + 1) / 2;
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int nw = blockDim.x >> 6;
+    const int jraw = (rb * nw + wave) * 64 + lane;
+    const int j = min(jraw, npairs - 1);
+    const int js = nr - 1 - j;
+    in += (int64_t)blockIdx.y * MB * 2 * in_map_stride;
+    alm += (int64_t)blockIdx.y * MB * 2 * nalm * 2;
+    const int64_t moff = (int64_t)m * (2 * lmax + 1 - m) / 2;
+    const int l0 = max(m, spin);
+    const double sg = (spin & 1) ? -1.0 : 1.0;
+    const double dsg = ((m + spin) & 1) ? -1.0 : 1.0;
+    const bool even_plus = ((l0 + m + spin) & 1) == 0;
+
+    // data sets of the two parity classes: {P, Um, Up, Qm} style, see the formulas below
+    double dE[MB][8], dO[MB][8];
+#pragma unroll
+    for (int b = 0; b < MB; ++b) {
+        const InT* colq = in + (int64_t)(2 * b) * in_map_stride + (int64_t)m * in_row_stride;
+        const InT* colu = colq + in_map_stride;
+        double2 qn = folded(colq, j, nr, nt, dsg), un = folded(colu, j, nr, nt, dsg);
+        double2 qs = make_double2(0.0, 0.0), us = make_double2(0.0, 0.0);
+        if (js != j) {
+            qs = folded(colq, js, nr, nt, dsg);
+            us = folded(colu, js, nr, nt, dsg);
+        }
+        if (jraw >= npairs) qn = un = qs = us = make_double2(0.0, 0.0);
+        // tau = +1: cG <- W+ (Qn + Qs) + i W- (Un - Us), cC <- W+ (Un + Us) - i W- (Qn - Qs)
+        // tau = -1: the same with the sums and differences exchanged
+        const double plus[8] = {qn.x + qs.x, qn.y + qs.y, un.x - us.x, un.y - us.y,
+                                un.x + us.x, un.y + us.y, qn.x - qs.x, qn.y - qs.y};
+        const double minus[8] = {qn.x - qs.x, qn.y - qs.y, un.x + us.x, un.y + us.y,
+                                 un.x - us.x, un.y - us.y, qn.x + qs.x, qn.y + qs.y};
+#pragma unroll
+        for (int i = 0; i < 8; ++i) {
+            dE[b][i] = even_plus ? plus[i] : minus[i];
+            dO[b][i] = even_plus ? minus[i] : plus[i];
+        }
+    }
+
+    double y, p, q;
+    int k;
+    spin_start(j, nr, m, spin, km[m], ke[m], y, p, q, k);
+    double pp = 0.0, qp = 0.0;
+    bool any_scaled = k > 0;
+    bool live = k == 0;
+
+    // products of one l into row li of the chunk
+    auto put = [&](int li, const double (&d)[MB][8], bool on) {
+        const double wp = on ? fma(sg, q, p) : 0.0;
+        const double wm = on ? fma(-sg, q, p) : 0.0;
+#pragma unroll
+        for (int b = 0; b < MB; ++b) {
+            buf[wave][li * NV + 4 * b + 0][lane] = fma(wp, d[b][0], -(wm * d[b][3]));
+            buf[wave][li * NV + 4 * b + 1][lane] = fma(wp, d[b][1], wm * d[b][2]);
+            buf[wave][li * NV + 4 * b + 2][lane] = fma(wp, d[b][4], wm * d[b][7]);
+            buf[wave][li * NV + 4 * b + 3][lane] = fma(wp, d[b][5], -(wm * d[b][6]));
+        }
+    };
+
+    int par = 0;
+    for (int lc = l0; lc <= lmax; lc += kSpLC) {
+        const bool sc = __any(any_scaled);
+#pragma unroll
+        for (int li = 0; li < kSpLC; ++li) {
+            const int l = lc + li;
+            bool on = false;
+            if (l <= lmax) {
+                if (l > l0) {
+                    if (sc) {
+                        live = spin_step_scaled(rec[moff + l], y, p, q, pp, qp, k);
+                        any_scaled = !live;
+                    } else {
+                        spin_step(rec[moff + l], y, p, q, pp, qp);
+                    }
+                }
+                on = live;
+            }
+            put(li, (li & 1) ? dO : dE, on);
+        }
+        // transposed read of this wave's chunk
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        const int r = lane / LPR, h = lane % LPR;
+        double acc = 0.0;
+#pragma unroll 8
+        for (int i = 0; i < PER; ++i) acc += buf[wave][r][h * PER + i];
+#pragma unroll
+        for (int o = 1; o < LPR; o <<= 1) acc += __shfl_xor(acc, o);
+        if (h == 0) xw[par][wave][r] = acc;
+        __syncthreads();
+        if (wave == 0 && lane < ROWS) {
+            double tot = 0.0;
+            for (int w = 0; w < nw; ++w) tot += xw[par][w][lane];
+            const int li = lane / NV, v = lane % NV;
+            const int l = lc + li;
+            // (imaginary parts of m = 0 stay zero: that coefficient is real)
+            if (l <= lmax && !(m == 0 && (v & 1))) {
+                const int b = v >> 2, t = v & 3;
+                double* dst = alm + (((int64_t)(2 * b + (t >> 1)) * nalm + moff + l) * 2 + (t & 1));
+                atomicAdd(dst, -0.5 * tot);
+            }
+        }
+        par ^= 1;
+        // this wave's reads of buf are done before its next writes
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    }
+}
+
+__global__ void k_spin_zero(double* __restrict__ a, int64_t n)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) a[i] = 0.0;
+}
+
+}  // namespace
+
+// (alpha, c_p, c_q, gamma) of the step to every (l, m), l >= l0 + 1, and the start constants
+// K_m = sqrt((2 l0 + 1)/4pi) sqrt(binom(2 l0, l0 + min(m, s))) as mantissa * 2^exponent, all
+// in long double; rebuilt when the spin changes.
+int ensure_spin_tables(nusht_plan_s* p, int spin)
+{
+    if (p->spin_s == spin && p->spin_rec) return NUSHT_OK;
+    const nusht_geometry& g = p->g;
+    const int L = g.lmax, M = g.mmax;
+    std::vector<double> rec(4 * ((size_t)g.nalm + kRecPad), 0.0);
+    std::vector<double> km(M + 1);
+    std::vector<int> ke(M + 1);
+    const unsigned nth = std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
+    std::vector<std::thread> pool;
+    for (unsigned t = 0; t < nth; ++t)
+        pool.emplace_back([&, t] {
+            for (int m = (int)t; m <= M; m += (int)nth) {
+                const int64_t moff = (int64_t)m * (2 * L + 1 - m) / 2;
+                const int l0 = std::max(m, spin), lo = std::min(m, spin);
+                const long double mm = m, ss = spin;
+                for (int l = l0 + 1; l <= L; ++l) {
+                    const long double c = l - 1, c1 = l;  // step from degree c to c + 1
+                    const long double dc = sqrtl((c * c - mm * mm) * (c * c - ss * ss));
+                    const long double dc1 = sqrtl((c1 * c1 - mm * mm) * (c1 * c1 - ss * ss));
+                    const long double r = sqrtl((2 * c + 3) * (2 * c + 1));
+                    const long double alpha = r * c1 / dc1;
+                    const long double b = (m == 0) ? 0.0L : r * mm * ss / (c * dc1);
+                    const long double gam =
+                        (l - 1 == l0) ? 0.0L : sqrtl((2 * c + 3) / (2 * c - 1)) * c1 * dc / (c * dc1);
+                    double* e = &rec[4 * (size_t)(moff + l)];
+                    e[0] = (double)alpha;
+                    e[1] = (double)(alpha + b);
+                    e[2] = (double)(alpha - b);
+                    e[3] = (double)gam;
+                }
+                long double v = sqrtl((2.0L * l0 + 1.0L) / (4.0L * 3.14159265358979323846264338327950288L));
+                int ex = 0, tt;
+                v = frexpl(v, &tt);
+                ex += tt;
+                for (int kk = 1; kk <= l0 - lo; ++kk) {
+                    v *= sqrtl((long double)(l0 + lo + kk) / (long double)kk);
+                    v = frexpl(v, &tt);
+                    ex += tt;
+                }
+                km[m] = (double)v;
+                ke[m] = ex;
+            }
+        });
+    for (auto& th : pool) th.join();
+    if (p->spin_rec) {
+        NUSHT_HIP(hipDeviceSynchronize());
+        hipFree(p->spin_rec);
+        hipFree(p->spin_km);
+        hipFree(p->spin_ke);
+        p->spin_rec = nullptr;
+        p->spin_km = nullptr;
+        p->spin_ke = nullptr;
+    }
+    p->spin_s = 0;
+    NUSHT_HIP(hipMalloc((void**)&p->spin_rec, ((size_t)g.nalm + kRecPad) * sizeof(double4)));
+    NUSHT_HIP(hipMalloc((void**)&p->spin_km, (M + 1) * sizeof(double)));
+    NUSHT_HIP(hipMalloc((void**)&p->spin_ke, (M + 1) * sizeof(int)));
+    NUSHT_HIP(hipMemcpy(p->spin_rec, rec.data(), rec.size() * sizeof(double), hipMemcpyHostToDevice));
+    NUSHT_HIP(hipMemcpy(p->spin_km, km.data(), km.size() * sizeof(double), hipMemcpyHostToDevice));
+    NUSHT_HIP(hipMemcpy(p->spin_ke, ke.data(), ke.size() * sizeof(int), hipMemcpyHostToDevice));
+    p->spin_s = spin;
+    return NUSHT_OK;
+}
+
+int launch_spin_synth(nusht_plan_s* p, int spin, const double* alm, void* out, int nfields,
+                      int out_f32, hipStream_t s)
+{
+    NUSHT_TRY(ensure_spin_tables(p, spin));
+    const nusht_geometry& g = p->g;
+    const int npairs = (g.nrings + 1) / 2;
+    const int waves_needed = (npairs + 63) / 64;
+    const int wpb = waves_needed >= 4 ? 4 : waves_needed;
+    const int nbx = (waves_needed + wpb - 1) / wpb;
+    const int mpad = (g.mmax + 1 + 7) / 8 * 8;
+    const int64_t row_stride = g.ntorus;
+    const int64_t map_stride = (int64_t)(g.mmax + 1) * g.ntorus;
+    const double2* a = reinterpret_cast<const double2*>(alm);
+    int f = 0;
+    while (f < nfields) {
+        const int mb = nfields - f >= 2 ? 2 : 1;
+        const int groups = (nfields - f) / mb;
+        const double2* af = a + (int64_t)f * 2 * g.nalm;
+#define SPS(MBV, OT)                                                                             \
+    hipLaunchKernelGGL((k_spin_synth<MBV, OT>), dim3(nbx * mpad, groups), dim3(64 * wpb), 0, s,   \
+                       af, g.nalm, g.lmax, g.mmax, spin, nbx, p->spin_rec, p->spin_km,           \
+                       p->spin_ke, g.nrings, g.ntorus,                                           \
+                       reinterpret_cast<OT*>(out) + (int64_t)f * 2 * map_stride, map_stride,     \
+                       row_stride)
+        if (out_f32) {
+            if (mb == 2) SPS(2, float2); else SPS(1, float2);
+        } else {
+            if (mb == 2) SPS(2, double2); else SPS(1, double2);
+        }
+#undef SPS
+        NUSHT_HIP(hipGetLastError());
+        f += groups * mb;
+    }
+    return NUSHT_OK;
+}
+
+int launch_spin_adjoint(nusht_plan_s* p, int spin, const void* in, double* alm, int nfields,
+                        int in_f32, hipStream_t s)
+{
+    NUSHT_TRY(ensure_spin_tables(p, spin));
+    const nusht_geometry& g = p->g;
+    const int npairs = (g.nrings + 1) / 2;
+    const int nbx = (npairs + 255) / 256;  // four waves per block: the cross-wave sum uses them
+    const int mpad = (g.mmax + 1 + 7) / 8 * 8;
+    const int64_t row_stride = g.ntorus;
+    const int64_t map_stride = (int64_t)(g.mmax + 1) * g.ntorus;
+    const int64_t nz = (int64_t)nfields * 2 * g.nalm * 2;
+    hipLaunchKernelGGL(k_spin_zero, dim3((unsigned)((nz + 255) / 256)), dim3(256), 0, s, alm, nz);
+    int f = 0;
+    while (f < nfields) {
+        const int mb = nfields - f >= 2 ? 2 : 1;
+        const int groups = (nfields - f) / mb;
+        double* af = alm + (int64_t)f * 2 * g.nalm * 2;
+#define SPA(MBV, IT)                                                                             \
+    hipLaunchKernelGGL((k_spin_adj<MBV, IT>), dim3(nbx * mpad, groups), dim3(256), 0, s,          \
+                       reinterpret_cast<const IT*>(in) + (int64_t)f * 2 * map_stride, map_stride, \
+                       row_stride, af, g.nalm, g.lmax, g.mmax, spin, nbx, p->spin_rec,           \
+                       p->spin_km, p->spin_ke, g.nrings, g.ntorus)
+        if (in_f32) {
+            if (mb == 2) SPA(2, float2); else SPA(1, float2);
+        } else {
+            if (mb == 2) SPA(2, double2); else SPA(1, double2);
+        }
+#undef SPA
+        NUSHT_HIP(hipGetLastError());
+        f += groups * mb;
+    }
+    return NUSHT_OK;
+}
+
+}  // namespace nusht

@@ -385,14 +385,20 @@ int ring_synthesis_into(nusht_plan_s* p, const double* alm, double* ring, void* 
 
 // torus spectrum (fused: doubled theta-columns [b][m][t] transformed over t; paper: 2D R2C
 // of the doubled map) into X, for maps [0, nmaps)
-int synthesis_to_fine(nusht_plan_s* p, const double* alm, int nmaps, hipStream_t s, void** fine_out)
+// spin > 0: the nmaps maps are the (Q, U) pairs of nmaps / 2 spin-weighted fields, whose
+// theta-columns come from the Wigner-d step (fused mode only)
+int synthesis_to_fine(nusht_plan_s* p, const double* alm, int nmaps, hipStream_t s, void** fine_out,
+                      int spin = 0)
 {
     const nusht_geometry& g = p->g;
     const int f32 = g.dtype == NUSHT_MIXED;
     const size_t e = fine_elem_bytes(p);
     if (g.dfs_mode == NUSHT_DFS_FUSED) {
         stage_begin(p, ST_LEGENDRE, s);
-        NUSHT_TRY(launch_legendre_synth(p, alm, p->X, nmaps, 1, f32, s));
+        if (spin)
+            NUSHT_TRY(launch_spin_synth(p, spin, alm, p->X, nmaps / 2, f32, s));
+        else
+            NUSHT_TRY(launch_legendre_synth(p, alm, p->X, nmaps, 1, f32, s));
         stage_end(p, ST_LEGENDRE, s);
         stage_begin(p, ST_TORUS_FFT, s);
         const size_t cstride = (size_t)(g.mmax + 1) * g.ntorus * 2 * e;
@@ -432,6 +438,20 @@ int synthesis_to_fine(nusht_plan_s* p, const double* alm, int nmaps, hipStream_t
                                bytes(p->Y) + b * fine_real_bytes(p), s));
         stage_end(p, ST_FINE_FFT, s);
         *fine_out = p->Y;
+    }
+    return NUSHT_OK;
+}
+
+// the spin-weighted calls: fused mode, 1 <= spin <= min(lmax, kMaxSpin), no deterministic plan
+int check_spin(nusht_plan_s* p, int spin, const char* who)
+{
+    if (p->g.dfs_mode != NUSHT_DFS_FUSED) {
+        set_last_error(who, "spin-weighted transforms need a plan in the fused DFS mode");
+        return NUSHT_EINVAL;
+    }
+    if (spin < 1 || spin > p->g.lmax || spin > NUSHT_MAX_SPIN) {
+        set_last_error(who, "spin must satisfy 1 <= spin <= min(lmax, NUSHT_MAX_SPIN)");
+        return NUSHT_EINVAL;
     }
     return NUSHT_OK;
 }
@@ -496,13 +516,15 @@ int nusht_synthesis_deriv(nusht_plan_t p, const double* alm, double* map, double
     return NUSHT_OK;
 }
 
-int nusht_adjoint(nusht_plan_t p, const double* map, double* alm, int nmaps, void* stream)
+}  // extern "C"
+
+namespace nusht {
+namespace {
+
+// N^H, then the fused or paper-mode S^H; spin > 0: nmaps / 2 spin-weighted fields (fused only)
+int adjoint_impl(nusht_plan_s* p, const double* map, double* alm, int nmaps, hipStream_t s,
+                 int spin)
 {
-    NUSHT_TRY(check_exec(p, map, alm, nmaps));
-    DeviceGuard dg(p->device);
-    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
-    NUSHT_TRY(ensure_capacity(p, nmaps));
-    begin_call(p, NUSHT_CALL_ADJOINT);
     const nusht_geometry& g = p->g;
     const int f32 = g.dtype == NUSHT_MIXED;
     const size_t e = fine_elem_bytes(p);
@@ -537,7 +559,10 @@ int nusht_adjoint(nusht_plan_t p, const double* map, double* alm, int nmaps, voi
             NUSHT_TRY(fft_exec(p, p->theta_bwd, bytes(p->X) + b * cstride, nullptr, s));
         stage_end(p, ST_TORUS_FFT, s);
         stage_begin(p, ST_LEGENDRE, s);
-        NUSHT_TRY(launch_legendre_adjoint(p, p->X, alm, nmaps, 1, f32, s));
+        if (spin)
+            NUSHT_TRY(launch_spin_adjoint(p, spin, p->X, alm, nmaps / 2, f32, s));
+        else
+            NUSHT_TRY(launch_legendre_adjoint(p, p->X, alm, nmaps, 1, f32, s));
         stage_end(p, ST_LEGENDRE, s);
     } else {
         stage_begin(p, ST_DECONV, s);
@@ -565,6 +590,57 @@ int nusht_adjoint(nusht_plan_t p, const double* map, double* alm, int nmaps, voi
         stage_end(p, ST_LEGENDRE, s);
     }
     return NUSHT_OK;
+}
+
+}  // namespace
+}  // namespace nusht
+
+extern "C" {
+
+int nusht_adjoint(nusht_plan_t p, const double* map, double* alm, int nmaps, void* stream)
+{
+    NUSHT_TRY(check_exec(p, map, alm, nmaps));
+    DeviceGuard dg(p->device);
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    NUSHT_TRY(ensure_capacity(p, nmaps));
+    begin_call(p, NUSHT_CALL_ADJOINT);
+    return adjoint_impl(p, map, alm, nmaps, s, 0);
+}
+
+int nusht_synthesis_spin(nusht_plan_t p, int spin, const double* alm, double* map, int nfields,
+                         void* stream)
+{
+    NUSHT_TRY(check_exec(p, alm, map, nfields));
+    NUSHT_TRY(check_spin(p, spin, "nusht_synthesis_spin"));
+    DeviceGuard dg(p->device);
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    NUSHT_TRY(ensure_capacity(p, 2 * nfields));
+    begin_call(p, NUSHT_CALL_SPIN_SYNTHESIS);
+    void* fine = nullptr;
+    NUSHT_TRY(synthesis_to_fine(p, alm, 2 * nfields, s, &fine, spin));
+    stage_begin(p, ST_POINTS, s);
+    if (p->g.dtype == NUSHT_MIXED)
+        NUSHT_TRY(interp_f32(p, reinterpret_cast<const float*>(fine), map, 2 * nfields, s));
+    else
+        NUSHT_TRY(interp_f64(p, reinterpret_cast<const double*>(fine), map, 2 * nfields, s));
+    stage_end(p, ST_POINTS, s);
+    return NUSHT_OK;
+}
+
+int nusht_adjoint_spin(nusht_plan_t p, int spin, const double* map, double* alm, int nfields,
+                       void* stream)
+{
+    NUSHT_TRY(check_exec(p, map, alm, nfields));
+    NUSHT_TRY(check_spin(p, spin, "nusht_adjoint_spin"));
+    if (p->deterministic) {
+        set_last_error("nusht_adjoint_spin", "no deterministic mode for the spin-weighted adjoint");
+        return NUSHT_EINVAL;
+    }
+    DeviceGuard dg(p->device);
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    NUSHT_TRY(ensure_capacity(p, 2 * nfields));
+    begin_call(p, NUSHT_CALL_SPIN_ADJOINT);
+    return adjoint_impl(p, map, alm, 2 * nfields, s, spin);
 }
 
 int nusht_ring_synthesis(nusht_plan_t p, const double* alm, double* ring, int nmaps, void* stream)

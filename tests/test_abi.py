@@ -91,6 +91,8 @@ def test_geometry_validation():
     # null plan handles are rejected before any device work
     assert lib.nusht_synthesis(None, 1, 1, 1, None) == P.NUSHT_EINVAL
     assert lib.nusht_adjoint(None, 1, 1, 1, None) == P.NUSHT_EINVAL
+    assert lib.nusht_synthesis_spin(None, 2, 1, 1, 1, None) == P.NUSHT_EINVAL
+    assert lib.nusht_adjoint_spin(None, 2, 1, 1, 1, None) == P.NUSHT_EINVAL
     lib.nusht_destroy(None)
 
 
