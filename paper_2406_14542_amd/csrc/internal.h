@@ -100,6 +100,7 @@ struct nusht_plan_s {
     double4* spin_rec = nullptr;  // [nalm + kRecPad]
     double* spin_km = nullptr;    // [mmax+1] mantissa
     int* spin_ke = nullptr;       // [mmax+1] power-of-two exponent
+    int* spin_jlive = nullptr;    // [mmax+1] first ring pair with any value above 2^-300
 
     // Deconvolution factors (include the FFT normalisation of the torus transform).
     double* dec1 = nullptr;      // [lmax+1], indexed by |kappa|

@@ -877,7 +877,7 @@ void nusht_destroy(nusht_plan_t p)
                     p->tile_slot, p->boff, p->brec, p->dflag, p->dstatus, p->X,     p->Y,         p->W,   p->Z,
                     p->fftwork,   p->rowtw, p->thetatw,
                     p->red,      p->jlive,  p->jscale, p->adj_part, p->es_coef, p->es_coeff,
-                    p->spin_rec, p->spin_km, p->spin_ke};
+                    p->spin_rec, p->spin_km, p->spin_ke, p->spin_jlive};
     for (void* b : bufs)
         if (b) hipFree(b);
     for (int c = 0; c < nusht_plan_s::kTimingSlots; ++c)

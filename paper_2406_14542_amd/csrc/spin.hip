@@ -27,6 +27,8 @@
 // so the coefficient stream is wave-uniform (scalar loads); blocks of one m sit on one XCD.
 #include "internal.h"
 
+#include <algorithm>
+#include <cmath>
 #include <thread>
 
 namespace nusht {
@@ -36,6 +38,49 @@ constexpr double kSpBig = 0x1p56;     // rescale once a scaled value reaches thi
 constexpr double kSpUnit = 0x1p-256;  // one scale unit
 constexpr int kSpAccumExp = -200;     // terms below 2^-200 are not accumulated
 constexpr int kSpLC = 4;              // l values per reduction chunk of the adjoint
+constexpr int kSpPf = 32;             // l values between two L2 touches of a coefficient stream
+
+// The coefficient streams of one m (recurrence table, 2 MB coefficient rows) are read through
+// the scalar cache, one l at a time, by every wave of that m.  Every kSpPf values of l the wave
+// touches the lines holding the next kSpPf coefficients of every stream, kSpPf steps ahead,
+// with one LDS-DMA load per line: such a load has no register result, so nothing waits for
+// it, and the lines are in L2 by the time the scalar loads reach them.  M0 (the DMA's LDS
+// base, pointed at a per-wave sink that nothing reads) is restored after the load; the
+// returned value is kept live by the caller, which waits for the DMA before the wave ends.
+__device__ inline unsigned l2_touch(const void* src, unsigned lds_sink)
+{
+    unsigned saved;
+    asm("s_mov_b32 %0, m0\n\t"
+        "s_mov_b32 m0, %2\n\t"
+        "s_nop 0\n\t"
+        "global_load_lds_dword %1, off\n\t"
+        "s_mov_b32 m0, %0"
+        : "=&s"(saved)
+        : "v"(src), "s"(lds_sink));
+    return saved;
+}
+
+// lines per stream for kSpPf values of l (one more for an unaligned start)
+constexpr int kSpRecLines = kSpPf * 32 / 128 + 1;
+constexpr int kSpAlmLines = kSpPf * 16 / 128 + 1;
+
+// lane -> (stream, line); streams: the table, then NA coefficient rows spaced nalm apart
+template <int NA>
+__device__ inline unsigned spin_touch(const double4* __restrict__ rec,
+                                      const double2* __restrict__ alm, int64_t nalm,
+                                      int64_t moff, int lmax, int lp, int lane, unsigned sink)
+{
+    if (lp > lmax) return 0u;
+    const void* src;
+    if (lane < kSpRecLines) {
+        src = rec + moff + min(lp + 4 * lane, lmax);
+    } else {
+        const int t = lane - kSpRecLines, st = t / kSpAlmLines, line = t - st * kSpAlmLines;
+        if (st >= NA) return 0u;
+        src = alm + (int64_t)st * nalm + moff + min(lp + 8 * line, lmax);
+    }
+    return l2_touch(src, sink);
+}
 
 // base^n (base >= 0) as mant * 2^e with mant in [0.5, 1); 0^0 = 1, 0^n = 0
 __device__ inline void pow_exp(double base, int n, double& mant, int& e)
@@ -183,7 +228,8 @@ template <int MB, typename OutT>
 __global__ __launch_bounds__(256) void k_spin_synth(
     const double2* __restrict__ alm, int64_t nalm, int lmax, int mmax, int spin, int nbx,
     const double4* __restrict__ rec, const double* __restrict__ km, const int* __restrict__ ke,
-    int nr, int nt, OutT* __restrict__ out, int64_t out_map_stride, int64_t out_row_stride)
+    const int* __restrict__ jlive, int nr, int nt, OutT* __restrict__ out,
+    int64_t out_map_stride, int64_t out_row_stride)
 {
     int m, rb;
     xcd_place(blockIdx.x, nbx, m, rb);
@@ -204,8 +250,10 @@ __global__ __launch_bounds__(256) void k_spin_synth(
 #pragma unroll
         for (int i = 0; i < 8; ++i) E[b][i] = O[b][i] = 0.0;
 
+    __shared__ float pf_sink[4][64];
     const int j = min(wbase + lane, npairs - 1);
-    {
+    // a wave whose ring pairs all lie below the first live pair of this m adds nothing
+    if (wbase + 64 > jlive[m]) {
         double y, p, q;
         int k;
         spin_start(j, nr, m, spin, km[m], ke[m], y, p, q, k);
@@ -223,14 +271,27 @@ __global__ __launch_bounds__(256) void k_spin_synth(
             spin_accum<MB>(A, alm, nalm, moff + l, fma(sg, q, p), fma(-sg, q, p));
         };
         int l = l0 + 1;
-        for (; l + 1 <= lmax; l += 2) {
-            if (__any(any_scaled)) {
-                scaled(l, O);
-                scaled(l + 1, E);
-            } else {
-                plain(l, O);
-                plain(l + 1, E);
+        int pf_at = l;
+        unsigned pf_keep = 0;
+        const unsigned sink = __builtin_amdgcn_readfirstlane(
+            (unsigned)(uintptr_t)(__attribute__((address_space(3))) float*)pf_sink[wave]);
+        auto prefetch = [&]() {
+            if (l >= pf_at) {
+                pf_keep ^= spin_touch<2 * MB>(rec, alm, nalm, moff, lmax, l + kSpPf, lane, sink);
+                pf_at = l + kSpPf;
             }
+        };
+        // while some lane of the wave still carries a 2^256 factor: the scaled steps (the
+        // branch is wave-uniform); then the plain recurrence without further tests
+        for (; l + 1 <= lmax && __any(any_scaled); l += 2) {
+            prefetch();
+            scaled(l, O);
+            scaled(l + 1, E);
+        }
+        for (; l + 1 <= lmax; l += 2) {
+            prefetch();
+            plain(l, O);
+            plain(l + 1, E);
         }
         if (l <= lmax) {
             if (__any(any_scaled))
@@ -238,6 +299,8 @@ __global__ __launch_bounds__(256) void k_spin_synth(
             else
                 plain(l, O);
         }
+        // no LDS-DMA write may be in flight when the workgroup's LDS is released
+        asm volatile("s_waitcnt vmcnt(0)" ::"v"(pf_keep) : "memory");
     }
 
     const int jj = wbase + lane;
@@ -297,19 +360,23 @@ __device__ inline double2 folded(const InT* col, int j, int nr, int nt, double s
     return v;
 }
 
-// Adjoint.  Each lane multiplies W+- of its ring pair with the folded ring data; the sums over
-// ring pairs are formed per chunk of kSpLC values of l: every lane parks its 4 MB products per
-// l in LDS, the wave reads them back transposed (a row per lane group) and sums, the block's
-// waves are summed through a small LDS array after one barrier, and the block adds its sums
-// into the zeroed output with FP64 atomics (the blocks of one m run on one XCD: the atomics
-// resolve in its L2; the order of those additions is not fixed).
+// Adjoint.  Each lane holds two ring pairs (j, j + 64) and multiplies W+- of both with their
+// folded ring data, summing the two in registers; the sums over the wave's ring pairs are then
+// formed per chunk of kSpLC values of l: every lane parks its 4 MB products per l in LDS, the
+// wave reads them back transposed (a row per lane group) and sums, the block's waves are summed
+// through a small LDS array after one barrier, and the block adds its sums into the zeroed
+// output with FP64 atomics (the blocks of one m run on one XCD: the atomics resolve in its L2;
+// the order of those additions is not fixed).
+constexpr int kSpAdjR = 2;  // ring pairs per lane of the adjoint
+
 template <int MB, typename InT>
 __global__ __launch_bounds__(256) void k_spin_adj(
     const InT* __restrict__ in, int64_t in_map_stride, int64_t in_row_stride,
     double* __restrict__ alm, int64_t nalm, int lmax, int mmax, int spin, int nbx,
     const double4* __restrict__ rec, const double* __restrict__ km, const int* __restrict__ ke,
-    int nr, int nt)
+    const int* __restrict__ jlive, int nr, int nt)
 {
+    constexpr int R = kSpAdjR;
     constexpr int NV = 4 * MB;          // products per l per lane
     constexpr int ROWS = kSpLC * NV;    // rows of one chunk
     constexpr int LPR = 64 / ROWS;      // lanes per row in the transposed read
@@ -317,6 +384,7 @@ __global__ __launch_bounds__(256) void k_spin_adj(
     static_assert(ROWS * LPR == 64, "chunk shape");
     __shared__ double buf[4][ROWS][65];
     __shared__ double xw[2][4][ROWS];
+    __shared__ float pf_sink[4][64];
 
     int m, rb;
     xcd_place(blockIdx.x, nbx, m, rb);
@@ -324,9 +392,11 @@ __global__ __launch_bounds__(256) void k_spin_adj(
     const int npairs = (nr + 1) / 2;
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int nw = blockDim.x >> 6;
-    const int jraw = (rb * nw + wave) * 64 + lane;
-    const int j = min(jraw, npairs - 1);
-    const int js = nr - 1 - j;
+    const int wbase = (rb * nw + wave) * 64 * R;
+    const int jl = jlive[m];
+    if ((rb * nw + nw) * 64 * R <= jl) return;  // the whole block is below the first live pair
+    // a wave below the first live pair, or past the last pair, only takes part in the barriers
+    const bool wave_on = wbase + 64 * R > jl && wbase < npairs;
     in += (int64_t)blockIdx.y * MB * 2 * in_map_stride;
     alm += (int64_t)blockIdx.y * MB * 2 * nalm * 2;
     const int64_t moff = (int64_t)m * (2 * lmax + 1 - m) / 2;
@@ -335,83 +405,136 @@ __global__ __launch_bounds__(256) void k_spin_adj(
     const double dsg = ((m + spin) & 1) ? -1.0 : 1.0;
     const bool even_plus = ((l0 + m + spin) & 1) == 0;
 
-    // data sets of the two parity classes: {P, Um, Up, Qm} style, see the formulas below
-    double dE[MB][8], dO[MB][8];
+    // Per ring pair and field the four combinations Q+ = Qn + Qs, Q- = Qn - Qs, U+, U- of the
+    // folded data.  For hemisphere parity tau = +1 of (l + m + s):
+    //   cG <- W+ Q+ + i W- U-,   cC <- W+ U+ - i W- Q-
+    // and for tau = -1 the same with + and - exchanged.  X1/Y1 are the Q/U combinations that
+    // the even class (l - l0 even) takes as (Q+, U-) roles, X2/Y2 the odd class's.
+    double2 X1[R][MB], X2[R][MB], Y1[R][MB], Y2[R][MB];
+    double y[R], p[R], q[R], pp[R], qp[R];
+    int k[R];
+    bool live[R];
+    bool any_scaled = false;
 #pragma unroll
-    for (int b = 0; b < MB; ++b) {
-        const InT* colq = in + (int64_t)(2 * b) * in_map_stride + (int64_t)m * in_row_stride;
-        const InT* colu = colq + in_map_stride;
-        double2 qn = folded(colq, j, nr, nt, dsg), un = folded(colu, j, nr, nt, dsg);
-        double2 qs = make_double2(0.0, 0.0), us = make_double2(0.0, 0.0);
-        if (js != j) {
-            qs = folded(colq, js, nr, nt, dsg);
-            us = folded(colu, js, nr, nt, dsg);
-        }
-        if (jraw >= npairs) qn = un = qs = us = make_double2(0.0, 0.0);
-        // tau = +1: cG <- W+ (Qn + Qs) + i W- (Un - Us), cC <- W+ (Un + Us) - i W- (Qn - Qs)
-        // tau = -1: the same with the sums and differences exchanged
-        const double plus[8] = {qn.x + qs.x, qn.y + qs.y, un.x - us.x, un.y - us.y,
-                                un.x + us.x, un.y + us.y, qn.x - qs.x, qn.y - qs.y};
-        const double minus[8] = {qn.x - qs.x, qn.y - qs.y, un.x + us.x, un.y + us.y,
-                                 un.x - us.x, un.y - us.y, qn.x + qs.x, qn.y + qs.y};
-#pragma unroll
-        for (int i = 0; i < 8; ++i) {
-            dE[b][i] = even_plus ? plus[i] : minus[i];
-            dO[b][i] = even_plus ? minus[i] : plus[i];
-        }
-    }
-
-    double y, p, q;
-    int k;
-    spin_start(j, nr, m, spin, km[m], ke[m], y, p, q, k);
-    double pp = 0.0, qp = 0.0;
-    bool any_scaled = k > 0;
-    bool live = k == 0;
-
-    // products of one l into row li of the chunk
-    auto put = [&](int li, const double (&d)[MB][8], bool on) {
-        const double wp = on ? fma(sg, q, p) : 0.0;
-        const double wm = on ? fma(-sg, q, p) : 0.0;
+    for (int r = 0; r < R; ++r) {
+        const int jraw = wbase + lane + 64 * r;
+        const int j = min(jraw, npairs - 1);
+        const int js = nr - 1 - j;
+        const bool ok = jraw < npairs && wave_on;
 #pragma unroll
         for (int b = 0; b < MB; ++b) {
-            buf[wave][li * NV + 4 * b + 0][lane] = fma(wp, d[b][0], -(wm * d[b][3]));
-            buf[wave][li * NV + 4 * b + 1][lane] = fma(wp, d[b][1], wm * d[b][2]);
-            buf[wave][li * NV + 4 * b + 2][lane] = fma(wp, d[b][4], wm * d[b][7]);
-            buf[wave][li * NV + 4 * b + 3][lane] = fma(wp, d[b][5], -(wm * d[b][6]));
+            double2 qn = make_double2(0.0, 0.0), un = qn, qs = qn, us = qn;
+            if (ok) {
+                const InT* colq = in + (int64_t)(2 * b) * in_map_stride + (int64_t)m * in_row_stride;
+                const InT* colu = colq + in_map_stride;
+                qn = folded(colq, j, nr, nt, dsg);
+                un = folded(colu, j, nr, nt, dsg);
+                if (js != j) {
+                    qs = folded(colq, js, nr, nt, dsg);
+                    us = folded(colu, js, nr, nt, dsg);
+                }
+            }
+            const double2 qpl = make_double2(qn.x + qs.x, qn.y + qs.y);
+            const double2 qmi = make_double2(qn.x - qs.x, qn.y - qs.y);
+            const double2 upl = make_double2(un.x + us.x, un.y + us.y);
+            const double2 umi = make_double2(un.x - us.x, un.y - us.y);
+            X1[r][b] = even_plus ? qpl : qmi;
+            X2[r][b] = even_plus ? qmi : qpl;
+            Y1[r][b] = even_plus ? umi : upl;
+            Y2[r][b] = even_plus ? upl : umi;
         }
+        spin_start(j, nr, m, spin, km[m], ke[m], y[r], p[r], q[r], k[r]);
+        pp[r] = qp[r] = 0.0;
+        live[r] = k[r] == 0;
+        any_scaled |= k[r] > 0;
+    }
+
+    // the products of one l, summed over the lane's ring pairs, into row li of the chunk:
+    // with (A, B, C, D) = (X1, Y1, Y2, X2) for the even class and (X2, Y2, Y1, X1) for the odd
+    //   cG.re += W+ A.x - W- B.y,  cG.im += W+ A.y + W- B.x
+    //   cC.re += W+ C.x + W- D.y,  cC.im += W+ C.y - W- D.x
+    auto put = [&](int li, bool odd, const bool (&on)[R]) {
+        double v[MB][4];
+#pragma unroll
+        for (int b = 0; b < MB; ++b) v[b][0] = v[b][1] = v[b][2] = v[b][3] = 0.0;
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const double wp = on[r] ? fma(sg, q[r], p[r]) : 0.0;
+            const double wm = on[r] ? fma(-sg, q[r], p[r]) : 0.0;
+#pragma unroll
+            for (int b = 0; b < MB; ++b) {
+                const double2 A = odd ? X2[r][b] : X1[r][b];
+                const double2 B = odd ? Y2[r][b] : Y1[r][b];
+                const double2 C = odd ? Y1[r][b] : Y2[r][b];
+                const double2 D = odd ? X1[r][b] : X2[r][b];
+                v[b][0] = fma(wp, A.x, fma(-wm, B.y, v[b][0]));
+                v[b][1] = fma(wp, A.y, fma(wm, B.x, v[b][1]));
+                v[b][2] = fma(wp, C.x, fma(wm, D.y, v[b][2]));
+                v[b][3] = fma(wp, C.y, fma(-wm, D.x, v[b][3]));
+            }
+        }
+#pragma unroll
+        for (int b = 0; b < MB; ++b)
+#pragma unroll
+            for (int t = 0; t < 4; ++t) buf[wave][li * NV + 4 * b + t][lane] = v[b][t];
     };
 
+    int pf_at = l0 + 1;
+    unsigned pf_keep = 0;
+    const unsigned sink = __builtin_amdgcn_readfirstlane(
+        (unsigned)(uintptr_t)(__attribute__((address_space(3))) float*)pf_sink[wave]);
     int par = 0;
     for (int lc = l0; lc <= lmax; lc += kSpLC) {
-        const bool sc = __any(any_scaled);
-#pragma unroll
-        for (int li = 0; li < kSpLC; ++li) {
-            const int l = lc + li;
-            bool on = false;
-            if (l <= lmax) {
-                if (l > l0) {
-                    if (sc) {
-                        live = spin_step_scaled(rec[moff + l], y, p, q, pp, qp, k);
-                        any_scaled = !live;
-                    } else {
-                        spin_step(rec[moff + l], y, p, q, pp, qp);
-                    }
-                }
-                on = live;
+        if (wave_on) {
+            if (lc + 1 >= pf_at) {
+                pf_keep ^= spin_touch<0>(rec, nullptr, 0, moff, lmax, lc + 1 + kSpPf, lane, sink);
+                pf_at = lc + 1 + kSpPf;
             }
-            put(li, (li & 1) ? dO : dE, on);
-        }
-        // transposed read of this wave's chunk
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-        __builtin_amdgcn_wave_barrier();
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-        const int r = lane / LPR, h = lane % LPR;
-        double acc = 0.0;
-#pragma unroll 8
-        for (int i = 0; i < PER; ++i) acc += buf[wave][r][h * PER + i];
+            const bool sc = __any(any_scaled);
 #pragma unroll
-        for (int o = 1; o < LPR; o <<= 1) acc += __shfl_xor(acc, o);
-        if (h == 0) xw[par][wave][r] = acc;
+            for (int li = 0; li < kSpLC; ++li) {
+                const int l = lc + li;
+                bool on[R];
+#pragma unroll
+                for (int r = 0; r < R; ++r) on[r] = false;
+                if (l <= lmax) {
+                    if (l > l0) {
+                        const double4 c = rec[moff + l];
+                        if (sc) {
+                            any_scaled = false;
+#pragma unroll
+                            for (int r = 0; r < R; ++r) {
+                                live[r] = spin_step_scaled(c, y[r], p[r], q[r], pp[r], qp[r], k[r]);
+                                any_scaled |= !live[r];
+                            }
+                        } else {
+#pragma unroll
+                            for (int r = 0; r < R; ++r) spin_step(c, y[r], p[r], q[r], pp[r], qp[r]);
+                        }
+                    }
+#pragma unroll
+                    for (int r = 0; r < R; ++r) on[r] = live[r];
+                }
+                put(li, (li & 1) != 0, on);
+            }
+            // transposed read of this wave's chunk
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+            const int rr = lane / LPR, h = lane % LPR;
+            double acc = 0.0;
+#pragma unroll 8
+            for (int i = 0; i < PER; ++i) acc += buf[wave][rr][h * PER + i];
+#pragma unroll
+            for (int o = 1; o < LPR; o <<= 1) acc += __shfl_xor(acc, o);
+            if (h == 0) xw[par][wave][rr] = acc;
+            // this wave's reads of buf are done before its next writes
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        } else if (lane < ROWS) {
+            xw[par][wave][lane] = 0.0;
+        }
         __syncthreads();
         if (wave == 0 && lane < ROWS) {
             double tot = 0.0;
@@ -426,11 +549,9 @@ __global__ __launch_bounds__(256) void k_spin_adj(
             }
         }
         par ^= 1;
-        // this wave's reads of buf are done before its next writes
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-        __builtin_amdgcn_wave_barrier();
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
     }
+    // no LDS-DMA write may be in flight when the workgroup's LDS is released
+    asm volatile("s_waitcnt vmcnt(0)" ::"v"(pf_keep) : "memory");
 }
 
 __global__ void k_spin_zero(double* __restrict__ a, int64_t n)
@@ -440,6 +561,52 @@ __global__ void k_spin_zero(double* __restrict__ a, int64_t n)
 }
 
 }  // namespace
+
+// Whether slam or (-s)lam of ring pair j reaches 2^-300 for some l <= L (the kernels add
+// nothing below 2^-200): the start value from the closed form in log2, then the recurrence
+// with the table's coefficients and an explicit exponent, as in the kernels.
+static bool spin_ring_reaches(int L, int m, int spin, int j, int nr, const std::vector<double>& rec,
+                              int64_t moff, double km, int ke)
+{
+    const double a = (double)j / (2.0 * (double)(nr - 1));
+    const double s2 = std::sin(M_PI * a);
+    const double c2 = (2 * j == nr - 1) ? s2 : std::cos(M_PI * a);
+    if (s2 == 0.0) return m == spin;  // at the pole only d^l_{s,s} is nonzero
+    const double y = 2.0 * s2 * s2;
+    const int dms = std::abs(m - spin), l0 = std::max(m, spin);
+    const double lk = std::log2(km) + ke;
+    const double lu = lk + dms * std::log2(c2) + (m + spin) * std::log2(s2);
+    const double lv = lk + (m + spin) * std::log2(c2) + dms * std::log2(s2);
+    const double top = std::max(lu, lv);
+    if (top > -300.0) return true;
+    int e = (int)std::floor(top);
+    double p = std::exp2(lu - e), q = std::exp2(lv - e), pp = 0.0, qp = 0.0;
+    for (int l = l0 + 1; l <= L; ++l) {
+        const double* c = &rec[4 * (size_t)(moff + l)];
+        const double pn = (c[1] - c[0] * y) * p - c[3] * pp;
+        const double qn = (c[2] - c[0] * y) * q - c[3] * qp;
+        pp = p;
+        qp = q;
+        p = pn;
+        q = qn;
+        const double big = std::max(std::max(std::fabs(p), std::fabs(q)),
+                                    std::max(std::fabs(pp), std::fabs(qp)));
+        if (big > 0x1p200 || (big < 0x1p-200 && big > 0.0)) {
+            int t;
+            std::frexp(big, &t);
+            p = std::ldexp(p, -t);
+            q = std::ldexp(q, -t);
+            pp = std::ldexp(pp, -t);
+            qp = std::ldexp(qp, -t);
+            e += t;
+        }
+        const double cur = std::max(std::fabs(p), std::fabs(q));
+        int t2;
+        std::frexp(cur, &t2);
+        if (cur != 0.0 && e + t2 > -300) return true;
+    }
+    return false;
+}
 
 // (alpha, c_p, c_q, gamma) of the step to every (l, m), l >= l0 + 1, and the start constants
 // K_m = sqrt((2 l0 + 1)/4pi) sqrt(binom(2 l0, l0 + min(m, s))) as mantissa * 2^exponent, all
@@ -489,19 +656,45 @@ int ensure_spin_tables(nusht_plan_s* p, int spin)
             }
         });
     for (auto& th : pool) th.join();
+    // first live ring pair of every m (bisection: liveness grows towards the equator)
+    std::vector<int> jl(M + 1, 0);
+    {
+        const int npairs = (g.nrings + 1) / 2;
+        std::vector<std::thread> pool2;
+        for (unsigned t = 0; t < nth; ++t)
+            pool2.emplace_back([&, t] {
+                for (int m = (int)t; m <= M; m += (int)nth) {
+                    const int64_t moff = (int64_t)m * (2 * L + 1 - m) / 2;
+                    int lo = 0, hi = npairs;
+                    while (lo < hi) {
+                        const int mid = (lo + hi) / 2;
+                        if (spin_ring_reaches(L, m, spin, mid, g.nrings, rec, moff, km[m], ke[m]))
+                            hi = mid;
+                        else
+                            lo = mid + 1;
+                    }
+                    jl[m] = lo;
+                }
+            });
+        for (auto& th : pool2) th.join();
+    }
     if (p->spin_rec) {
         NUSHT_HIP(hipDeviceSynchronize());
         hipFree(p->spin_rec);
         hipFree(p->spin_km);
         hipFree(p->spin_ke);
+        hipFree(p->spin_jlive);
         p->spin_rec = nullptr;
         p->spin_km = nullptr;
         p->spin_ke = nullptr;
+        p->spin_jlive = nullptr;
     }
     p->spin_s = 0;
     NUSHT_HIP(hipMalloc((void**)&p->spin_rec, ((size_t)g.nalm + kRecPad) * sizeof(double4)));
     NUSHT_HIP(hipMalloc((void**)&p->spin_km, (M + 1) * sizeof(double)));
     NUSHT_HIP(hipMalloc((void**)&p->spin_ke, (M + 1) * sizeof(int)));
+    NUSHT_HIP(hipMalloc((void**)&p->spin_jlive, (M + 1) * sizeof(int)));
+    NUSHT_HIP(hipMemcpy(p->spin_jlive, jl.data(), jl.size() * sizeof(int), hipMemcpyHostToDevice));
     NUSHT_HIP(hipMemcpy(p->spin_rec, rec.data(), rec.size() * sizeof(double), hipMemcpyHostToDevice));
     NUSHT_HIP(hipMemcpy(p->spin_km, km.data(), km.size() * sizeof(double), hipMemcpyHostToDevice));
     NUSHT_HIP(hipMemcpy(p->spin_ke, ke.data(), ke.size() * sizeof(int), hipMemcpyHostToDevice));
@@ -530,7 +723,7 @@ int launch_spin_synth(nusht_plan_s* p, int spin, const double* alm, void* out, i
 #define SPS(MBV, OT)                                                                             \
     hipLaunchKernelGGL((k_spin_synth<MBV, OT>), dim3(nbx * mpad, groups), dim3(64 * wpb), 0, s,   \
                        af, g.nalm, g.lmax, g.mmax, spin, nbx, p->spin_rec, p->spin_km,           \
-                       p->spin_ke, g.nrings, g.ntorus,                                           \
+                       p->spin_ke, p->spin_jlive, g.nrings, g.ntorus,                            \
                        reinterpret_cast<OT*>(out) + (int64_t)f * 2 * map_stride, map_stride,     \
                        row_stride)
         if (out_f32) {
@@ -551,7 +744,8 @@ int launch_spin_adjoint(nusht_plan_s* p, int spin, const void* in, double* alm, 
     NUSHT_TRY(ensure_spin_tables(p, spin));
     const nusht_geometry& g = p->g;
     const int npairs = (g.nrings + 1) / 2;
-    const int nbx = (npairs + 255) / 256;  // four waves per block: the cross-wave sum uses them
+    // four waves per block (the cross-wave sum uses them), kSpAdjR ring pairs per lane
+    const int nbx = (npairs + 256 * kSpAdjR - 1) / (256 * kSpAdjR);
     const int mpad = (g.mmax + 1 + 7) / 8 * 8;
     const int64_t row_stride = g.ntorus;
     const int64_t map_stride = (int64_t)(g.mmax + 1) * g.ntorus;
@@ -566,7 +760,7 @@ int launch_spin_adjoint(nusht_plan_s* p, int spin, const void* in, double* alm, 
     hipLaunchKernelGGL((k_spin_adj<MBV, IT>), dim3(nbx * mpad, groups), dim3(256), 0, s,          \
                        reinterpret_cast<const IT*>(in) + (int64_t)f * 2 * map_stride, map_stride, \
                        row_stride, af, g.nalm, g.lmax, g.mmax, spin, nbx, p->spin_rec,           \
-                       p->spin_km, p->spin_ke, g.nrings, g.ntorus)
+                       p->spin_km, p->spin_ke, p->spin_jlive, g.nrings, g.ntorus)
         if (in_f32) {
             if (mb == 2) SPA(2, float2); else SPA(1, float2);
         } else {
