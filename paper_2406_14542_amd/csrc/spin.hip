@@ -383,7 +383,6 @@ __global__ __launch_bounds__(256) void k_spin_adj(
     constexpr int PER = 64 / LPR;       // entries summed per lane
     static_assert(ROWS * LPR == 64, "chunk shape");
     __shared__ double buf[4][ROWS][65];
-    __shared__ double xw[2][4][ROWS];
     __shared__ float pf_sink[4][64];
 
     int m, rb;
@@ -393,10 +392,9 @@ __global__ __launch_bounds__(256) void k_spin_adj(
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int nw = blockDim.x >> 6;
     const int wbase = (rb * nw + wave) * 64 * R;
-    const int jl = jlive[m];
-    if ((rb * nw + nw) * 64 * R <= jl) return;  // the whole block is below the first live pair
-    // a wave below the first live pair, or past the last pair, only takes part in the barriers
-    const bool wave_on = wbase + 64 * R > jl && wbase < npairs;
+    // a wave below the first live pair of this m, or past the last pair, adds nothing
+    if (wbase + 64 * R <= jlive[m] || wbase >= npairs) return;
+    constexpr bool wave_on = true;
     in += (int64_t)blockIdx.y * MB * 2 * in_map_stride;
     alm += (int64_t)blockIdx.y * MB * 2 * nalm * 2;
     const int64_t moff = (int64_t)m * (2 * lmax + 1 - m) / 2;
@@ -483,7 +481,6 @@ __global__ __launch_bounds__(256) void k_spin_adj(
     unsigned pf_keep = 0;
     const unsigned sink = __builtin_amdgcn_readfirstlane(
         (unsigned)(uintptr_t)(__attribute__((address_space(3))) float*)pf_sink[wave]);
-    int par = 0;
     for (int lc = l0; lc <= lmax; lc += kSpLC) {
         if (wave_on) {
             if (lc + 1 >= pf_at) {
@@ -491,6 +488,11 @@ __global__ __launch_bounds__(256) void k_spin_adj(
                 pf_at = lc + 1 + kSpPf;
             }
             const bool sc = __any(any_scaled);
+            // the chunk's coefficients in one go: a scalar load waits on the same counter as
+            // the LDS writes of the steps, so none is issued between them
+            double4 cc[kSpLC];
+#pragma unroll
+            for (int li = 0; li < kSpLC; ++li) cc[li] = rec[moff + min(lc + li, lmax)];
 #pragma unroll
             for (int li = 0; li < kSpLC; ++li) {
                 const int l = lc + li;
@@ -499,7 +501,7 @@ __global__ __launch_bounds__(256) void k_spin_adj(
                 for (int r = 0; r < R; ++r) on[r] = false;
                 if (l <= lmax) {
                     if (l > l0) {
-                        const double4 c = rec[moff + l];
+                        const double4 c = cc[li];
                         if (sc) {
                             any_scaled = false;
 #pragma unroll
@@ -527,28 +529,22 @@ __global__ __launch_bounds__(256) void k_spin_adj(
             for (int i = 0; i < PER; ++i) acc += buf[wave][rr][h * PER + i];
 #pragma unroll
             for (int o = 1; o < LPR; o <<= 1) acc += __shfl_xor(acc, o);
-            if (h == 0) xw[par][wave][rr] = acc;
+            if (h == 0) {
+                const int li = rr / NV, v = rr % NV;
+                const int l = lc + li;
+                // (imaginary parts of m = 0 stay zero: that coefficient is real)
+                if (l <= lmax && !(m == 0 && (v & 1))) {
+                    const int b = v >> 2, t = v & 3;
+                    double* dst =
+                        alm + (((int64_t)(2 * b + (t >> 1)) * nalm + moff + l) * 2 + (t & 1));
+                    atomicAdd(dst, -0.5 * acc);
+                }
+            }
             // this wave's reads of buf are done before its next writes
             __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
             __builtin_amdgcn_wave_barrier();
             __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-        } else if (lane < ROWS) {
-            xw[par][wave][lane] = 0.0;
         }
-        __syncthreads();
-        if (wave == 0 && lane < ROWS) {
-            double tot = 0.0;
-            for (int w = 0; w < nw; ++w) tot += xw[par][w][lane];
-            const int li = lane / NV, v = lane % NV;
-            const int l = lc + li;
-            // (imaginary parts of m = 0 stay zero: that coefficient is real)
-            if (l <= lmax && !(m == 0 && (v & 1))) {
-                const int b = v >> 2, t = v & 3;
-                double* dst = alm + (((int64_t)(2 * b + (t >> 1)) * nalm + moff + l) * 2 + (t & 1));
-                atomicAdd(dst, -0.5 * tot);
-            }
-        }
-        par ^= 1;
     }
     // no LDS-DMA write may be in flight when the workgroup's LDS is released
     asm volatile("s_waitcnt vmcnt(0)" ::"v"(pf_keep) : "memory");
