@@ -382,7 +382,9 @@ __global__ __launch_bounds__(256) void k_spin_adj(
     constexpr int LPR = 64 / ROWS;      // lanes per row in the transposed read
     constexpr int PER = 64 / LPR;       // entries summed per lane
     static_assert(ROWS * LPR == 64, "chunk shape");
-    __shared__ double buf[4][ROWS][65];
+    // rows of 64 lane entries, the upper half shifted by one slot (entry e at e + e / 32):
+    // the transposed read's two lanes of a row then fall on different banks
+    __shared__ double buf[4][ROWS][66];
     __shared__ float pf_sink[4][64];
 
     int m, rb;
@@ -451,14 +453,19 @@ __global__ __launch_bounds__(256) void k_spin_adj(
     // with (A, B, C, D) = (X1, Y1, Y2, X2) for the even class and (X2, Y2, Y1, X1) for the odd
     //   cG.re += W+ A.x - W- B.y,  cG.im += W+ A.y + W- B.x
     //   cC.re += W+ C.x + W- D.y,  cC.im += W+ C.y - W- D.x
-    auto put = [&](int li, bool odd, const bool (&on)[R]) {
+    const int slot = lane + (lane >> 5);
+    auto put = [&](int li, bool odd, bool gated, const bool (&on)[R]) {
         double v[MB][4];
 #pragma unroll
         for (int b = 0; b < MB; ++b) v[b][0] = v[b][1] = v[b][2] = v[b][3] = 0.0;
 #pragma unroll
         for (int r = 0; r < R; ++r) {
-            const double wp = on[r] ? fma(sg, q[r], p[r]) : 0.0;
-            const double wm = on[r] ? fma(-sg, q[r], p[r]) : 0.0;
+            double wp = fma(sg, q[r], p[r]);
+            double wm = fma(-sg, q[r], p[r]);
+            if (gated) {
+                wp = on[r] ? wp : 0.0;
+                wm = on[r] ? wm : 0.0;
+            }
 #pragma unroll
             for (int b = 0; b < MB; ++b) {
                 const double2 A = odd ? X2[r][b] : X1[r][b];
@@ -474,7 +481,7 @@ __global__ __launch_bounds__(256) void k_spin_adj(
 #pragma unroll
         for (int b = 0; b < MB; ++b)
 #pragma unroll
-            for (int t = 0; t < 4; ++t) buf[wave][li * NV + 4 * b + t][lane] = v[b][t];
+            for (int t = 0; t < 4; ++t) buf[wave][li * NV + 4 * b + t][slot] = v[b][t];
     };
 
     int pf_at = l0 + 1;
@@ -493,31 +500,44 @@ __global__ __launch_bounds__(256) void k_spin_adj(
             double4 cc[kSpLC];
 #pragma unroll
             for (int li = 0; li < kSpLC; ++li) cc[li] = rec[moff + min(lc + li, lmax)];
+            if (sc || lc + kSpLC - 1 > lmax || lc == l0) {
+                // some lane still scaled, the last chunk or the first: every step tested
 #pragma unroll
-            for (int li = 0; li < kSpLC; ++li) {
-                const int l = lc + li;
-                bool on[R];
+                for (int li = 0; li < kSpLC; ++li) {
+                    const int l = lc + li;
+                    bool on[R];
 #pragma unroll
-                for (int r = 0; r < R; ++r) on[r] = false;
-                if (l <= lmax) {
-                    if (l > l0) {
-                        const double4 c = cc[li];
-                        if (sc) {
-                            any_scaled = false;
+                    for (int r = 0; r < R; ++r) on[r] = false;
+                    if (l <= lmax) {
+                        if (l > l0) {
+                            const double4 c = cc[li];
+                            if (sc) {
+                                any_scaled = false;
 #pragma unroll
-                            for (int r = 0; r < R; ++r) {
-                                live[r] = spin_step_scaled(c, y[r], p[r], q[r], pp[r], qp[r], k[r]);
-                                any_scaled |= !live[r];
+                                for (int r = 0; r < R; ++r) {
+                                    live[r] = spin_step_scaled(c, y[r], p[r], q[r], pp[r], qp[r], k[r]);
+                                    any_scaled |= !live[r];
+                                }
+                            } else {
+#pragma unroll
+                                for (int r = 0; r < R; ++r)
+                                    spin_step(c, y[r], p[r], q[r], pp[r], qp[r]);
                             }
-                        } else {
-#pragma unroll
-                            for (int r = 0; r < R; ++r) spin_step(c, y[r], p[r], q[r], pp[r], qp[r]);
                         }
-                    }
 #pragma unroll
-                    for (int r = 0; r < R; ++r) on[r] = live[r];
+                        for (int r = 0; r < R; ++r) on[r] = live[r];
+                    }
+                    put(li, (li & 1) != 0, true, on);
                 }
-                put(li, (li & 1) != 0, on);
+            } else {
+                // every lane live, every step in range
+                const bool all_on[R] = {};
+#pragma unroll
+                for (int li = 0; li < kSpLC; ++li) {
+#pragma unroll
+                    for (int r = 0; r < R; ++r) spin_step(cc[li], y[r], p[r], q[r], pp[r], qp[r]);
+                    put(li, (li & 1) != 0, false, all_on);
+                }
             }
             // transposed read of this wave's chunk
             __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
@@ -526,7 +546,10 @@ __global__ __launch_bounds__(256) void k_spin_adj(
             const int rr = lane / LPR, h = lane % LPR;
             double acc = 0.0;
 #pragma unroll 8
-            for (int i = 0; i < PER; ++i) acc += buf[wave][rr][h * PER + i];
+            for (int i = 0; i < PER; ++i) {
+                const int e = h * PER + i;
+                acc += buf[wave][rr][e + (e >> 5)];
+            }
 #pragma unroll
             for (int o = 1; o < LPR; o <<= 1) acc += __shfl_xor(acc, o);
             if (h == 0) {
