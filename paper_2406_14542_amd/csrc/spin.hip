@@ -367,7 +367,7 @@ __device__ inline double2 folded(const InT* col, int j, int nr, int nt, double s
 // through a small LDS array after one barrier, and the block adds its sums into the zeroed
 // output with FP64 atomics (the blocks of one m run on one XCD: the atomics resolve in its L2;
 // the order of those additions is not fixed).
-constexpr int kSpAdjR = 2;  // ring pairs per lane of the adjoint
+constexpr int kSpAdjR = 3;  // ring pairs per lane of the adjoint
 
 template <int MB, typename InT>
 __global__ __launch_bounds__(256) void k_spin_adj(
