@@ -160,8 +160,10 @@ int nusht_adjoint(nusht_plan_t plan, const double* map, double* alm, int nmaps, 
    Plans: fused DFS mode only, 1 <= spin <= min(lmax, NUSHT_MAX_SPIN) (NUSHT_EINVAL otherwise);
    the first call with a spin builds its recurrence table (32 bytes per coefficient, kept
    until the spin changes or the plan is destroyed, so that call synchronises and
-   allocates).  The adjoint adds with device atomics: its results can differ between runs by
-   rounding, and deterministic plans refuse it (NUSHT_EINVAL). */
+   allocates).  The adjoint adds the sums of its waves with device atomics, so its results
+   can differ between runs by rounding; on a deterministic plan it writes per-wave partial
+   sums instead (16 bytes x 2 nfields x nalm per wave of one m, about 11 waves at lmax 4095,
+   as plan scratch grown on demand like the batch scratch) and adds them in a fixed order: bit-identical repeats. */
 #define NUSHT_MAX_SPIN 64
 int nusht_synthesis_spin(nusht_plan_t plan, int spin, const double* alm, double* map,
                          int nfields, void* stream);

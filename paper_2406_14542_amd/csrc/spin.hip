@@ -369,12 +369,15 @@ __device__ inline double2 folded(const InT* col, int j, int nr, int nt, double s
 // the order of those additions is not fixed).
 constexpr int kSpAdjR = 3;  // ring pairs per lane of the adjoint
 
-template <int MB, typename InT>
+// DET: instead of the atomic adds, wave w of the m's waves writes its sums (unscaled) to
+// alm + w * part_stride, a zeroed per-wave partial array that k_spin_adj_reduce then adds in
+// wave order (bit-identical results from run to run).
+template <int MB, typename InT, bool DET>
 __global__ __launch_bounds__(256) void k_spin_adj(
     const InT* __restrict__ in, int64_t in_map_stride, int64_t in_row_stride,
     double* __restrict__ alm, int64_t nalm, int lmax, int mmax, int spin, int nbx,
     const double4* __restrict__ rec, const double* __restrict__ km, const int* __restrict__ ke,
-    const int* __restrict__ jlive, int nr, int nt)
+    const int* __restrict__ jlive, int nr, int nt, int64_t part_stride)
 {
     constexpr int R = kSpAdjR;
     constexpr int NV = 4 * MB;          // products per l per lane
@@ -558,9 +561,11 @@ __global__ __launch_bounds__(256) void k_spin_adj(
                 // (imaginary parts of m = 0 stay zero: that coefficient is real)
                 if (l <= lmax && !(m == 0 && (v & 1))) {
                     const int b = v >> 2, t = v & 3;
-                    double* dst =
-                        alm + (((int64_t)(2 * b + (t >> 1)) * nalm + moff + l) * 2 + (t & 1));
-                    atomicAdd(dst, -0.5 * acc);
+                    const int64_t o = ((int64_t)(2 * b + (t >> 1)) * nalm + moff + l) * 2 + (t & 1);
+                    if (DET)
+                        alm[(int64_t)(rb * nw + wave) * part_stride + o] = acc;
+                    else
+                        atomicAdd(alm + o, -0.5 * acc);
                 }
             }
             // this wave's reads of buf are done before its next writes
@@ -577,6 +582,17 @@ __global__ void k_spin_zero(double* __restrict__ a, int64_t n)
 {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i < n) a[i] = 0.0;
+}
+
+// out[i] = -1/2 sum_w part[w * n + i], w = 0..nw-1 in order
+__global__ void k_spin_adj_reduce(const double* __restrict__ part, int nw, int64_t n,
+                                  double* __restrict__ out)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    double acc = 0.0;
+    for (int w = 0; w < nw; ++w) acc += part[(int64_t)w * n + i];
+    out[i] = -0.5 * acc;
 }
 
 }  // namespace
@@ -768,26 +784,60 @@ int launch_spin_adjoint(nusht_plan_s* p, int spin, const void* in, double* alm, 
     const int mpad = (g.mmax + 1 + 7) / 8 * 8;
     const int64_t row_stride = g.ntorus;
     const int64_t map_stride = (int64_t)(g.mmax + 1) * g.ntorus;
-    const int64_t nz = (int64_t)nfields * 2 * g.nalm * 2;
-    hipLaunchKernelGGL(k_spin_zero, dim3((unsigned)((nz + 255) / 256)), dim3(256), 0, s, alm, nz);
+    const int64_t nz = (int64_t)nfields * 2 * g.nalm * 2;  // doubles of the output
+    const int nwm = 4 * nbx;                                // waves per m
+    const bool det = p->deterministic != 0;
+    double* target = alm;
+    if (det) {
+        // per-wave partial sums, zeroed (waves below the first live pair write nothing)
+        const size_t need = (size_t)nwm * nz * sizeof(double);
+        if (need > p->adj_part_bytes) {
+            NUSHT_HIP(hipStreamSynchronize(s));
+            if (p->adj_part) hipFree(p->adj_part);
+            p->adj_part = nullptr;
+            p->adj_part_bytes = 0;
+            NUSHT_HIP(hipMalloc((void**)&p->adj_part, need));
+            p->adj_part_bytes = need;
+        }
+        target = p->adj_part;
+        const int64_t np = (int64_t)nwm * nz;
+        hipLaunchKernelGGL(k_spin_zero, dim3((unsigned)((np + 255) / 256)), dim3(256), 0, s,
+                           target, np);
+    } else {
+        hipLaunchKernelGGL(k_spin_zero, dim3((unsigned)((nz + 255) / 256)), dim3(256), 0, s, alm,
+                           nz);
+    }
     int f = 0;
     while (f < nfields) {
         const int mb = nfields - f >= 2 ? 2 : 1;
         const int groups = (nfields - f) / mb;
-        double* af = alm + (int64_t)f * 2 * g.nalm * 2;
-#define SPA(MBV, IT)                                                                             \
-    hipLaunchKernelGGL((k_spin_adj<MBV, IT>), dim3(nbx * mpad, groups), dim3(256), 0, s,          \
+        double* af = target + (int64_t)f * 2 * g.nalm * 2;
+#define SPA(MBV, IT, D)                                                                          \
+    hipLaunchKernelGGL((k_spin_adj<MBV, IT, D>), dim3(nbx * mpad, groups), dim3(256), 0, s,       \
                        reinterpret_cast<const IT*>(in) + (int64_t)f * 2 * map_stride, map_stride, \
                        row_stride, af, g.nalm, g.lmax, g.mmax, spin, nbx, p->spin_rec,           \
-                       p->spin_km, p->spin_ke, p->spin_jlive, g.nrings, g.ntorus)
-        if (in_f32) {
-            if (mb == 2) SPA(2, float2); else SPA(1, float2);
+                       p->spin_km, p->spin_ke, p->spin_jlive, g.nrings, g.ntorus, nz)
+        if (det) {
+            if (in_f32) {
+                if (mb == 2) SPA(2, float2, true); else SPA(1, float2, true);
+            } else {
+                if (mb == 2) SPA(2, double2, true); else SPA(1, double2, true);
+            }
         } else {
-            if (mb == 2) SPA(2, double2); else SPA(1, double2);
+            if (in_f32) {
+                if (mb == 2) SPA(2, float2, false); else SPA(1, float2, false);
+            } else {
+                if (mb == 2) SPA(2, double2, false); else SPA(1, double2, false);
+            }
         }
 #undef SPA
         NUSHT_HIP(hipGetLastError());
         f += groups * mb;
+    }
+    if (det) {
+        hipLaunchKernelGGL(k_spin_adj_reduce, dim3((unsigned)((nz + 255) / 256)), dim3(256), 0, s,
+                           target, nwm, nz, alm);
+        NUSHT_HIP(hipGetLastError());
     }
     return NUSHT_OK;
 }

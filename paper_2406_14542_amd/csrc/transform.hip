@@ -632,10 +632,6 @@ int nusht_adjoint_spin(nusht_plan_t p, int spin, const double* map, double* alm,
 {
     NUSHT_TRY(check_exec(p, map, alm, nfields));
     NUSHT_TRY(check_spin(p, spin, "nusht_adjoint_spin"));
-    if (p->deterministic) {
-        set_last_error("nusht_adjoint_spin", "no deterministic mode for the spin-weighted adjoint");
-        return NUSHT_EINVAL;
-    }
     DeviceGuard dg(p->device);
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
     NUSHT_TRY(ensure_capacity(p, 2 * nfields));

@@ -104,7 +104,7 @@ def test_spin_small_degrees_and_truncated_m(P, oracle_mod):
 
 def test_spin_argument_checks(P):
     """Rejected on the host, with no device work: spin 0, spin > lmax, spin above the cap, the
-    paper DFS mode, a deterministic plan's adjoint, wrong shapes."""
+    paper DFS mode, wrong shapes."""
     rng = np.random.default_rng(421)
     th, ph = inputs.uniform_points(rng, 500)
     L = 20
@@ -118,13 +118,36 @@ def test_spin_argument_checks(P):
     pp = P.Plan(L, L, dev(th), dev(ph), 1e-10, dfs_mode="paper")
     with pytest.raises(P.NushtError):
         pp.synthesis_spin(1, a)
-    pd = P.Plan(L, L, dev(th), dev(ph), 1e-10, deterministic=True)
-    pd.synthesis_spin(1, a)  # the synthesis has no atomics
-    with pytest.raises(P.NushtError):
-        pd.adjoint_spin(1, dev(np.zeros((1, 2, th.size))))
     big = P.Plan(80, 80, dev(th), dev(ph), 1e-10)
     with pytest.raises(P.NushtError):
         big.synthesis_spin(P.NUSHT_MAX_SPIN + 1, dev(inputs.spin_alm(rng, 80, 80, 1, 1)))
+
+
+@pytest.mark.parametrize("dtype,eps,tol", [("f64", 1e-12, 1e-11), ("mixed", 1e-5, 1e-5)])
+def test_spin_adjoint_deterministic_mode(P, oracle_mod, dtype, eps, tol):
+    """A deterministic plan's spin adjoint (per-wave partial sums added in a fixed order):
+    repeats are bit-identical, and it matches the oracle like the atomic one (three fields:
+    a group of two and a single one; at lmax 1023 three waves of every m hold ring pairs)."""
+    print(f"[spin det {dtype}]", flush=True)
+    rng = np.random.default_rng(425)
+    L, s = 1023, 2
+    th, ph = points_with_poles(rng, 20000)
+    d = rng.standard_normal((3, 2, th.size))
+    pd = P.Plan(L, L, dev(th), dev(ph), eps, dtype=dtype, deterministic=True)
+    c1 = pd.adjoint_spin(s, dev(d)).cpu().numpy()
+    c2 = pd.adjoint_spin(s, dev(d)).cpu().numpy()
+    assert np.array_equal(c1, c2)
+    ml = [0, 1, 2, 3, 500, 1023]
+    cols = oracle_mod.spin_adjoint_columns(L, s, th, ph, d, ml)
+    for k, m in enumerate(ml):
+        off = m * (2 * L + 1 - m) // 2
+        got = c1[:, :, off + m: off + L + 1]
+        # column m = s carries the exact-pole points' flat spectrum (see the full-degree test)
+        ctol = 5 * tol if (m == s and dtype == "f64") else tol
+        assert rel(got, cols[:, :, k, m:]) <= ctol, (m, rel(got, cols[:, :, k, m:]))
+    pn = P.Plan(L, L, dev(th), dev(ph), eps, dtype=dtype)
+    cn = pn.adjoint_spin(s, dev(d)).cpu().numpy()
+    assert mrel(c1, cn, L, L) <= 1e-13
 
 
 def test_spin1_is_minus_the_gradient_on_the_gpu(P):
