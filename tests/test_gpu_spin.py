@@ -84,6 +84,24 @@ def test_spin_synthesis_and_adjoint_match_oracle(P, case, s, dtype, eps, tol):
     assert np.all(c[:, :, ms == 0].imag == 0)
 
 
+def test_spin_at_sigma_1_25(P, oracle_mod):
+    """The spin path on a plan with the paper's upsampling sigma = 1.25 (radix-5 fine grid,
+    wider polynomial taps), mixed precision at eps 1e-5."""
+    print("[spin sigma 1.25]", flush=True)
+    rng = np.random.default_rng(426)
+    L, s = 200, 3
+    th, ph = points_with_poles(rng, 8000)
+    a = inputs.spin_alm(rng, L, L, s, 2)
+    pl = P.Plan(L, L, dev(th), dev(ph), 1e-5, dtype="mixed", sigma=1.25)
+    f = pl.synthesis_spin(s, dev(a)).cpu().numpy()
+    ref = oracle_mod.spin_synthesis(L, L, s, th, ph, a)
+    assert rel(f, ref) <= 1e-5, rel(f, ref)
+    d = rng.standard_normal((2, 2, th.size))
+    c = pl.adjoint_spin(s, dev(d)).cpu().numpy()
+    cref = oracle_mod.spin_adjoint(L, L, s, th, ph, d)
+    assert mrel(c, cref, L, L) <= 1e-5, mrel(c, cref, L, L)
+
+
 def test_spin_small_degrees_and_truncated_m(P, oracle_mod):
     """lmax = spin (a single degree), and mmax < spin < lmax (every m starts at l0 = s)."""
     print("[spin edges]", flush=True)
