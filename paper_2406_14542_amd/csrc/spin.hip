@@ -21,7 +21,7 @@
 // exponent; the two functions share one count of 2^256 factors per lane, as the spin-0 kernel
 // does, and a term enters the sums once the count is zero.
 //
-// gfx950 mapping (same as the spin-0 kernels): one lane = one pair of mirror rings (j, N_r-1-j)
+// gfx950 mapping (as the spin-0 kernels): a lane takes pairs of mirror rings (j, N_r-1-j)
 // -- slam(pi - theta) = (-1)^(l+m) (-s)lam(theta), so W+ has hemisphere parity (-1)^(l+m+s) and
 // W- the opposite, and even/odd-l accumulators serve both rings; the lanes of a block share m,
 // so the coefficient stream is wave-uniform (scalar loads); blocks of one m sit on one XCD.
@@ -360,13 +360,13 @@ __device__ inline double2 folded(const InT* col, int j, int nr, int nt, double s
     return v;
 }
 
-// Adjoint.  Each lane holds two ring pairs (j, j + 64) and multiplies W+- of both with their
-// folded ring data, summing the two in registers; the sums over the wave's ring pairs are then
-// formed per chunk of kSpLC values of l: every lane parks its 4 MB products per l in LDS, the
-// wave reads them back transposed (a row per lane group) and sums, the block's waves are summed
-// through a small LDS array after one barrier, and the block adds its sums into the zeroed
-// output with FP64 atomics (the blocks of one m run on one XCD: the atomics resolve in its L2;
-// the order of those additions is not fixed).
+// Adjoint.  Each lane holds kSpAdjR ring pairs (j, j + 64, ...) and multiplies W+- of each
+// with its folded ring data, summing them in registers; the sums over the wave's ring pairs
+// are then formed per chunk of kSpLC values of l: every lane parks its 4 MB products per l in
+// LDS, the wave reads them back transposed (a row per lane group) and sums, and each wave adds
+// its sums into the zeroed output with FP64 atomics, with no barrier between the waves (the
+// blocks of one m run on one XCD: the atomics resolve in its L2; the order of those additions
+// is not fixed, see DET for the fixed-order variant).
 constexpr int kSpAdjR = 3;  // ring pairs per lane of the adjoint
 
 // DET: instead of the atomic adds, wave w of the m's waves writes its sums (unscaled) to
@@ -779,7 +779,7 @@ int launch_spin_adjoint(nusht_plan_s* p, int spin, const void* in, double* alm, 
     NUSHT_TRY(ensure_spin_tables(p, spin));
     const nusht_geometry& g = p->g;
     const int npairs = (g.nrings + 1) / 2;
-    // four waves per block (the cross-wave sum uses them), kSpAdjR ring pairs per lane
+    // four independent waves per block, kSpAdjR ring pairs per lane
     const int nbx = (npairs + 256 * kSpAdjR - 1) / (256 * kSpAdjR);
     const int mpad = (g.mmax + 1 + 7) / 8 * 8;
     const int64_t row_stride = g.ntorus;
