@@ -453,6 +453,14 @@ int check_spin(nusht_plan_s* p, int spin, const char* who)
         set_last_error(who, "spin must satisfy 1 <= spin <= min(lmax, NUSHT_MAX_SPIN)");
         return NUSHT_EINVAL;
     }
+    // The two Wigner-d functions of a ring share one binary exponent; at the ring next to a
+    // pole, d^l_{m,-s} starts tan^(2 min(m, s))(theta_1 / 2) times d^l_{m,+s}.  Below 2^-800
+    // it could leave the FP64 range and stay zero for every l, so such spins are refused.
+    const double t1 = std::tan(0.5 * M_PI / (double)(p->g.nrings - 1));
+    if (2.0 * spin * -std::log2(t1) > 800.0) {
+        set_last_error(who, "spin too high for this ring grid (2 s log2(1/tan(theta_1/2)) > 800)");
+        return NUSHT_EINVAL;
+    }
     return NUSHT_OK;
 }
 

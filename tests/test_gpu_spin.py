@@ -139,6 +139,14 @@ def test_spin_argument_checks(P):
     big = P.Plan(80, 80, dev(th), dev(ph), 1e-10)
     with pytest.raises(P.NushtError):
         big.synthesis_spin(P.NUSHT_MAX_SPIN + 1, dev(inputs.spin_alm(rng, 80, 80, 1, 1)))
+    # the shared-exponent limit near the poles: at lmax 4095 spin 35 passes the check, 36 not
+    g = P.geometry(4095, 4095, 1e-5, "mixed")
+    t1 = np.tan(0.5 * np.pi / (g["nrings"] - 1))
+    smax = int(np.floor(800.0 / (2.0 * -np.log2(t1))))
+    assert smax == 35, smax
+    fine = P.Plan(4095, 4095, dev(th[:64]), dev(ph[:64]), 1e-5, dtype="mixed")
+    with pytest.raises(P.NushtError):
+        fine.synthesis_spin(smax + 1, dev(inputs.spin_alm(rng, 4095, 4095, 1, 1)))
 
 
 @pytest.mark.parametrize("dtype,eps,tol", [("f64", 1e-12, 1e-11), ("mixed", 1e-5, 1e-5)])
