@@ -207,6 +207,12 @@ int nusht_vjp_alm(nusht_plan_t plan, const double* grad_map, double* grad_alm, i
                   void* stream);
 int nusht_vjp_points(const double* grad_map, const double* dtheta, const double* dphi,
                      double* grad_theta, double* grad_phi, int nmaps, int64_t npts, void* stream);
+/* The same coefficient gradient for the spin-weighted synthesis: grad_map [nfields][2][npts]
+   (dL/dQ, dL/dU) -> grad_alm [nfields][2][nalm] (dL/dRe + i dL/dIm of G and C): the spin
+   adjoint scaled by 2 for m > 0 and real for m = 0.  Same plan conditions as
+   nusht_adjoint_spin. */
+int nusht_vjp_alm_spin(nusht_plan_t plan, int spin, const double* grad_map, double* grad_alm,
+                       int nfields, void* stream);
 
 /* Iso-latitude parts on their own (the S operator of Eq. 5 and its adjoint) on the plan's
    CC grid: ring[b][j][k] = map at (theta_j = j pi/(N_r-1), phi_k = 2 pi k / N_phi).

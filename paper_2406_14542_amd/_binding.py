@@ -91,6 +91,8 @@ def lib():
             "nusht_pointing": (ctypes.c_int, [_vp, _vp, _vp, _vp, _vp]),
             "nusht_deflect": (ctypes.c_int, [_vp, _vp, _vp, _vp, _i64, _vp, _vp, _vp]),
             "nusht_vjp_alm": (ctypes.c_int, [_vp, _vp, _vp, ctypes.c_int, _vp]),
+            "nusht_vjp_alm_spin": (ctypes.c_int, [_vp, ctypes.c_int, _vp, _vp, ctypes.c_int,
+                                                  _vp]),
             "nusht_vjp_points": (ctypes.c_int, [_vp, _vp, _vp, _vp, _vp, ctypes.c_int, _i64,
                                                 _vp]),
             "nusht_ring_synthesis": (ctypes.c_int, [_vp, _vp, _vp, ctypes.c_int, _vp]),
@@ -297,6 +299,21 @@ class Plan:
         out = self._out(out, (F, 2, self.nalm), torch.complex128, x)
         _check(lib().nusht_adjoint_spin(self._h, int(spin), x.data_ptr(), out.data_ptr(), F,
                                         _stream()), "nusht_adjoint_spin")
+        return out
+
+    def vjp_alm_spin(self, spin, grad_maps):
+        """dL/dRe + i dL/dIm of the gradient/curl coefficients for dL/d(Q, U) = grad_maps
+        [F, 2, npts] (the spin adjoint with the complex-gradient convention)."""
+        import torch
+        if grad_maps.dtype != torch.float64 or not grad_maps.is_cuda:
+            raise TypeError("grad_maps must be a float64 device tensor")
+        x = grad_maps.unsqueeze(0) if grad_maps.dim() == 2 else grad_maps
+        if x.dim() != 3 or x.shape[1] != 2 or x.shape[2] != self.npts:
+            raise ValueError(f"grad_maps must have shape [F, 2, {self.npts}]")
+        x = x.contiguous()
+        out = torch.empty((x.shape[0], 2, self.nalm), dtype=torch.complex128, device=x.device)
+        _check(lib().nusht_vjp_alm_spin(self._h, int(spin), x.data_ptr(), out.data_ptr(),
+                                        x.shape[0], _stream()), "nusht_vjp_alm_spin")
         return out
 
     def synthesis_deriv(self, alm):

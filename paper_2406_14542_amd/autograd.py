@@ -10,6 +10,8 @@ respect to the point positions.  Forward and backward only call the library:
   convention dL/dRe a + i dL/dIm a: 2 Y^H g for m > 0, Re Y^H g for m = 0) and
   ``nusht_vjp_points`` (sum over maps of g * dmap/dtheta, g * dmap/dphi).
 The plan's points are fixed; ``theta`` / ``phi`` only carry the gradient back to the caller.
+``synthesis_spin(plan, spin, alm)`` is the spin-weighted synthesis with its coefficient
+gradient (``nusht_vjp_alm_spin``).
 """
 from __future__ import annotations
 
@@ -47,6 +49,28 @@ class SynthesisFn(torch.autograd.Function):
             grad_th = gt if ctx.needs_input_grad[1] else None
             grad_ph = gp if ctx.needs_input_grad[2] else None
         return grad_alm, grad_th, grad_ph, None
+
+
+class SpinSynthesisFn(torch.autograd.Function):
+    @staticmethod
+    def forward(ctx, alm, plan, spin):
+        ctx.plan = plan
+        ctx.spin = spin
+        ctx.squeeze = alm.dim() == 2
+        f = plan.synthesis_spin(spin, alm.detach())
+        return f[0] if ctx.squeeze else f
+
+    @staticmethod
+    def backward(ctx, g):
+        grad = ctx.plan.vjp_alm_spin(ctx.spin, g.reshape(-1, 2, ctx.plan.npts).contiguous())
+        return (grad[0] if ctx.squeeze else grad), None, None
+
+
+def synthesis_spin(plan, spin, alm):
+    """Differentiable spin-weighted synthesis (gradient/curl coefficients [F, 2, nalm] ->
+    (Q, U) maps [F, 2, npts]) with respect to the coefficients; the backward pass is
+    ``nusht_vjp_alm_spin``."""
+    return SpinSynthesisFn.apply(alm, plan, spin)
 
 
 def synthesis(plan, alm, theta=None, phi=None):

@@ -61,6 +61,19 @@ int nusht_vjp_alm(nusht_plan_t p, const double* grad_map, double* grad_alm, int 
     return NUSHT_OK;
 }
 
+int nusht_vjp_alm_spin(nusht_plan_t p, int spin, const double* grad_map, double* grad_alm,
+                       int nfields, void* stream)
+{
+    NUSHT_TRY(nusht_adjoint_spin(p, spin, grad_map, grad_alm, nfields, stream));
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    const int64_t nalm = p->g.nalm;
+    // G and C of every field are coefficient rows of the same triangle layout
+    hipLaunchKernelGGL(k_grad_alm_convention, dim3((unsigned)((nalm + 255) / 256)), dim3(256), 0,
+                       s, reinterpret_cast<double2*>(grad_alm), nalm, p->g.lmax, 2 * nfields);
+    NUSHT_HIP(hipGetLastError());
+    return NUSHT_OK;
+}
+
 int nusht_vjp_points(const double* grad_map, const double* dtheta, const double* dphi,
                      double* grad_theta, double* grad_phi, int nmaps, int64_t npts, void* stream)
 {
