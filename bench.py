@@ -505,8 +505,8 @@ def main():
     ap.add_argument("--cg-steps-per-set", type=int, default=1)
     ap.add_argument("--cg-lr", type=float, default=1e-3)
     ap.add_argument("--cg-seed", type=int, default=7)
-    ap.add_argument("--cg-save", default="gpurun_out/c5_network.npz")
-    ap.add_argument("--cg-load", default="gpurun_out/c5_network.npz")
+    ap.add_argument("--cg-save", default="c5_network.npz")
+    ap.add_argument("--cg-load", default="c5_network.npz")
     ap.add_argument("--cg-rows", default="",
                     help="eval: also append each held-out row to this JSON-lines file as it ends")
     ap.add_argument("--pointing", action="store_true",
