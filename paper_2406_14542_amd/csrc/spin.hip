@@ -201,24 +201,25 @@ __device__ inline OutT make_pair(double re, double im)
     return o;
 }
 
-// accumulators of one parity class, per field: G W+ (re, im), C W- (re, im), C W+ (re, im),
-// G W- (re, im), with W+- still doubled (p +- (-1)^s q)
+// accumulators of one parity class, per field, in the basis of the two functions:
+// G p (re, im), C p (re, im), G q (re, im), C q (re, im); W+- are formed from them once, at
+// the end (the sums are linear in p and q)
 template <int MB>
 __device__ inline void spin_accum(double (&A)[MB][8], const double2* __restrict__ alm,
-                                  int64_t nalm, int64_t idx, double wp, double wm)
+                                  int64_t nalm, int64_t idx, double p, double q)
 {
 #pragma unroll
     for (int b = 0; b < MB; ++b) {
         const double2 G = alm[(int64_t)(2 * b) * nalm + idx];
         const double2 C = alm[(int64_t)(2 * b + 1) * nalm + idx];
-        A[b][0] = fma(G.x, wp, A[b][0]);
-        A[b][1] = fma(G.y, wp, A[b][1]);
-        A[b][2] = fma(C.x, wm, A[b][2]);
-        A[b][3] = fma(C.y, wm, A[b][3]);
-        A[b][4] = fma(C.x, wp, A[b][4]);
-        A[b][5] = fma(C.y, wp, A[b][5]);
-        A[b][6] = fma(G.x, wm, A[b][6]);
-        A[b][7] = fma(G.y, wm, A[b][7]);
+        A[b][0] = fma(G.x, p, A[b][0]);
+        A[b][1] = fma(G.y, p, A[b][1]);
+        A[b][2] = fma(C.x, p, A[b][2]);
+        A[b][3] = fma(C.y, p, A[b][3]);
+        A[b][4] = fma(G.x, q, A[b][4]);
+        A[b][5] = fma(G.y, q, A[b][5]);
+        A[b][6] = fma(C.x, q, A[b][6]);
+        A[b][7] = fma(C.y, q, A[b][7]);
     }
 }
 
@@ -259,16 +260,15 @@ __global__ __launch_bounds__(256) void k_spin_synth(
         spin_start(j, nr, m, spin, km[m], ke[m], y, p, q, k);
         double pp = 0.0, qp = 0.0;
         bool any_scaled = k > 0;
-        if (k == 0) spin_accum<MB>(E, alm, nalm, moff + l0, fma(sg, q, p), fma(-sg, q, p));
+        if (k == 0) spin_accum<MB>(E, alm, nalm, moff + l0, p, q);
         auto scaled = [&](int l, double (&A)[MB][8]) {
             const bool live = spin_step_scaled(rec[moff + l], y, p, q, pp, qp, k);
             any_scaled = !live;
-            spin_accum<MB>(A, alm, nalm, moff + l, live ? fma(sg, q, p) : 0.0,
-                           live ? fma(-sg, q, p) : 0.0);
+            spin_accum<MB>(A, alm, nalm, moff + l, live ? p : 0.0, live ? q : 0.0);
         };
         auto plain = [&](int l, double (&A)[MB][8]) {
             spin_step(rec[moff + l], y, p, q, pp, qp);
-            spin_accum<MB>(A, alm, nalm, moff + l, fma(sg, q, p), fma(-sg, q, p));
+            spin_accum<MB>(A, alm, nalm, moff + l, p, q);
         };
         int l = l0 + 1;
         int pf_at = l;
@@ -306,20 +306,29 @@ __global__ __launch_bounds__(256) void k_spin_synth(
     const int jj = wbase + lane;
     if (jj >= npairs) return;
     const int js = nr - 1 - jj;
-    const double dsg = ((m + spin) & 1) ? -1.0 : 1.0;     // doubling sign
-    const double tau = ((l0 + m + spin) & 1) ? -0.5 : 0.5;  // south parity of the even class, x 1/2
+    const double dsg = ((m + spin) & 1) ? -1.0 : 1.0;  // doubling sign
+    const double tau = ((l0 + m) & 1) ? -1.0 : 1.0;     // (-1)^(l+m) of the even class
 #pragma unroll
     for (int b = 0; b < MB; ++b) {
         double S[8], D[8];
 #pragma unroll
         for (int i = 0; i < 8; ++i) {
             S[i] = E[b][i] + O[b][i];
-            D[i] = E[b][i] - O[b][i];
+            D[i] = tau * (E[b][i] - O[b][i]);
         }
-        double qn_re = -0.5 * (S[0] - S[3]), qn_im = -0.5 * (S[1] + S[2]);
-        double un_re = -0.5 * (S[4] + S[7]), un_im = -0.5 * (S[5] - S[6]);
-        double qs_re = -tau * (D[0] + D[3]), qs_im = -tau * (D[1] - D[2]);
-        double us_re = -tau * (D[4] - D[7]), us_im = -tau * (D[5] + D[6]);
+        // With P = sum (G + iC) slam and M = sum (G - iC) (-s)lam:
+        //   Q = -(P + (-1)^s M) / 2,  U = i (P - (-1)^s M) / 2.
+        // North: P = Gp + i Cp, M = Gq - i Cq.  South, where slam(pi - theta) =
+        // (-1)^(l+m) (-s)lam(theta) and vice versa: P = Gq' + i Cq', M = Gp' - i Cp' with the
+        // parity-signed sums (').
+        const double pnr = S[0] - S[3], pni = S[1] + S[2];
+        const double mnr = S[4] + S[7], mni = S[5] - S[6];
+        const double psr = D[4] - D[7], psi = D[5] + D[6];
+        const double msr = D[0] + D[3], msi = D[1] - D[2];
+        double qn_re = -0.5 * fma(sg, mnr, pnr), qn_im = -0.5 * fma(sg, mni, pni);
+        double un_re = -0.5 * fma(-sg, mni, pni), un_im = 0.5 * fma(-sg, mnr, pnr);
+        double qs_re = -0.5 * fma(sg, msr, psr), qs_im = -0.5 * fma(sg, msi, psi);
+        double us_re = -0.5 * fma(-sg, msi, psi), us_im = 0.5 * fma(-sg, msr, psr);
         if (m == 0) qn_im = un_im = qs_im = us_im = 0.0;  // imaginary parts of m = 0 are ignored
         OutT* cq = out + (int64_t)(2 * b) * out_map_stride + (int64_t)m * out_row_stride;
         OutT* cu = cq + out_map_stride;
