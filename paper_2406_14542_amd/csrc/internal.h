@@ -85,6 +85,10 @@ struct nusht_plan_s {
     double eps = 0;
     int device = 0;
     hipStream_t plan_stream = nullptr;
+    // Second stream of the Legendre synthesis (default priority): its plain-range instance runs
+    // there beside the scaled-range instance on the call's stream; fork / join events.
+    hipStream_t side = nullptr;
+    hipEvent_t fork_ev = nullptr, join_ev = nullptr;
 
     // Legendre tables (host-computed, FP64).
     double2* rec = nullptr;      // [nalm]: (a_lm, a_lm * b_lm) of the recurrence, l >= m+1

@@ -853,6 +853,14 @@ int launch_legendre_synth(const nusht_plan_s* p, const double* alm, void* out, i
         map_stride = (int64_t)g.nrings * row_stride;
     }
     const int mpad = (g.mmax + 1 + 7) / 8 * 8;
+    // the two instances write disjoint ring pairs: the plain one runs on the plan's side
+    // stream, forked from and joined back into the call's stream, so that each fills the
+    // other's tail
+    hipStream_t sp = p->side ? p->side : s;
+    if (sp != s) {
+        NUSHT_HIP(hipEventRecord(p->fork_ev, s));
+        NUSHT_HIP(hipStreamWaitEvent(sp, p->fork_ev, 0));
+    }
     int b = 0;
     while (b < nmaps) {
         const int left = nmaps - b;
@@ -861,7 +869,7 @@ int launch_legendre_synth(const nusht_plan_s* p, const double* alm, void* out, i
         const double2* ab = a + (int64_t)b * nalm;
 #define SYN1(MBV, RV, F, OT, SC, BX, TH)                                                         \
     hipLaunchKernelGGL((k_legendre_synth<MBV, RV, F, OT, SC>), dim3(BX * mpad, groups),          \
-                       dim3(TH), 0, s, ab, nalm, g.lmax, g.mmax, BX, p->rec, p->cm_mant,          \
+                       dim3(TH), 0, SC ? s : sp, ab, nalm, g.lmax, g.mmax, BX, p->rec, p->cm_mant, \
                        p->cm_exp, p->jlive, p->jscale, g.nrings, g.ntorus,                        \
                        reinterpret_cast<OT*>(out) + (int64_t)b * map_stride, map_stride,          \
                        row_stride)
@@ -893,6 +901,10 @@ int launch_legendre_synth(const nusht_plan_s* p, const double* alm, void* out, i
 #undef SYN1
         NUSHT_HIP(hipGetLastError());
         b += groups * mb;
+    }
+    if (sp != s) {
+        NUSHT_HIP(hipEventRecord(p->join_ev, sp));
+        NUSHT_HIP(hipStreamWaitEvent(s, p->join_ev, 0));
     }
     return NUSHT_OK;
 }

@@ -885,6 +885,9 @@ void nusht_destroy(nusht_plan_t p)
             if (p->ev[c][i][0]) hipEventDestroy(p->ev[c][i][0]);
             if (p->ev[c][i][1]) hipEventDestroy(p->ev[c][i][1]);
         }
+    if (p->fork_ev) hipEventDestroy(p->fork_ev);
+    if (p->join_ev) hipEventDestroy(p->join_ev);
+    if (p->side) hipStreamDestroy(p->side);
     hipSetDevice(cur);
     delete p;
 }
@@ -918,6 +921,12 @@ int nusht_plan_ex(int lmax, int mmax, int64_t npts, const double* theta, const d
         if ((rc = build_band_records(p, s))) break;
         p->g.ntiles_used = p->nslots;
         if ((rc = create_fft_plans(p))) break;
+        if (hipStreamCreateWithFlags(&p->side, hipStreamNonBlocking) != hipSuccess ||
+            hipEventCreateWithFlags(&p->fork_ev, hipEventDisableTiming) != hipSuccess ||
+            hipEventCreateWithFlags(&p->join_ev, hipEventDisableTiming) != hipSuccess) {
+            rc = NUSHT_EDEVICE;
+            break;
+        }
         if (p->timing) {
             for (int c = 0; c < nusht_plan_s::kTimingSlots && rc == NUSHT_OK; ++c)
                 for (int i = 0; i < ST_COUNT; ++i) {
