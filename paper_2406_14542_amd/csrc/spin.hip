@@ -408,7 +408,6 @@ __global__ __launch_bounds__(256) void k_spin_adj(
     const int wbase = (rb * nw + wave) * 64 * R;
     // a wave below the first live pair of this m, or past the last pair, adds nothing
     if (wbase + 64 * R <= jlive[m] || wbase >= npairs) return;
-    constexpr bool wave_on = true;
     in += (int64_t)blockIdx.y * MB * 2 * in_map_stride;
     alm += (int64_t)blockIdx.y * MB * 2 * nalm * 2;
     const int64_t moff = (int64_t)m * (2 * lmax + 1 - m) / 2;
@@ -432,7 +431,7 @@ __global__ __launch_bounds__(256) void k_spin_adj(
         const int jraw = wbase + lane + 64 * r;
         const int j = min(jraw, npairs - 1);
         const int js = nr - 1 - j;
-        const bool ok = jraw < npairs && wave_on;
+        const bool ok = jraw < npairs;
 #pragma unroll
         for (int b = 0; b < MB; ++b) {
             double2 qn = make_double2(0.0, 0.0), un = qn, qs = qn, us = qn;
@@ -501,87 +500,85 @@ __global__ __launch_bounds__(256) void k_spin_adj(
     const unsigned sink = __builtin_amdgcn_readfirstlane(
         (unsigned)(uintptr_t)(__attribute__((address_space(3))) float*)pf_sink[wave]);
     for (int lc = l0; lc <= lmax; lc += kSpLC) {
-        if (wave_on) {
-            if (lc + 1 >= pf_at) {
-                pf_keep ^= spin_touch<0>(rec, nullptr, 0, moff, lmax, lc + 1 + kSpPf, lane, sink);
-                pf_at = lc + 1 + kSpPf;
-            }
-            const bool sc = __any(any_scaled);
-            // the chunk's coefficients in one go: a scalar load waits on the same counter as
-            // the LDS writes of the steps, so none is issued between them
-            double4 cc[kSpLC];
-#pragma unroll
-            for (int li = 0; li < kSpLC; ++li) cc[li] = rec[moff + min(lc + li, lmax)];
-            if (sc || lc + kSpLC - 1 > lmax || lc == l0) {
-                // some lane still scaled, the last chunk or the first: every step tested
-#pragma unroll
-                for (int li = 0; li < kSpLC; ++li) {
-                    const int l = lc + li;
-                    bool on[R];
-#pragma unroll
-                    for (int r = 0; r < R; ++r) on[r] = false;
-                    if (l <= lmax) {
-                        if (l > l0) {
-                            const double4 c = cc[li];
-                            if (sc) {
-                                any_scaled = false;
-#pragma unroll
-                                for (int r = 0; r < R; ++r) {
-                                    live[r] = spin_step_scaled(c, y[r], p[r], q[r], pp[r], qp[r], k[r]);
-                                    any_scaled |= !live[r];
-                                }
-                            } else {
-#pragma unroll
-                                for (int r = 0; r < R; ++r)
-                                    spin_step(c, y[r], p[r], q[r], pp[r], qp[r]);
-                            }
-                        }
-#pragma unroll
-                        for (int r = 0; r < R; ++r) on[r] = live[r];
-                    }
-                    put(li, (li & 1) != 0, true, on);
-                }
-            } else {
-                // every lane live, every step in range
-                const bool all_on[R] = {};
-#pragma unroll
-                for (int li = 0; li < kSpLC; ++li) {
-#pragma unroll
-                    for (int r = 0; r < R; ++r) spin_step(cc[li], y[r], p[r], q[r], pp[r], qp[r]);
-                    put(li, (li & 1) != 0, false, all_on);
-                }
-            }
-            // transposed read of this wave's chunk
-            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-            __builtin_amdgcn_wave_barrier();
-            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-            const int rr = lane / LPR, h = lane % LPR;
-            double acc = 0.0;
-#pragma unroll 8
-            for (int i = 0; i < PER; ++i) {
-                const int e = h * PER + i;
-                acc += buf[wave][rr][e + (e >> 5)];
-            }
-#pragma unroll
-            for (int o = 1; o < LPR; o <<= 1) acc += __shfl_xor(acc, o);
-            if (h == 0) {
-                const int li = rr / NV, v = rr % NV;
-                const int l = lc + li;
-                // (imaginary parts of m = 0 stay zero: that coefficient is real)
-                if (l <= lmax && !(m == 0 && (v & 1))) {
-                    const int b = v >> 2, t = v & 3;
-                    const int64_t o = ((int64_t)(2 * b + (t >> 1)) * nalm + moff + l) * 2 + (t & 1);
-                    if (DET)
-                        alm[(int64_t)(rb * nw + wave) * part_stride + o] = acc;
-                    else
-                        atomicAdd(alm + o, -0.5 * acc);
-                }
-            }
-            // this wave's reads of buf are done before its next writes
-            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-            __builtin_amdgcn_wave_barrier();
-            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        if (lc + 1 >= pf_at) {
+            pf_keep ^= spin_touch<0>(rec, nullptr, 0, moff, lmax, lc + 1 + kSpPf, lane, sink);
+            pf_at = lc + 1 + kSpPf;
         }
+        const bool sc = __any(any_scaled);
+        // the chunk's coefficients in one go: a scalar load waits on the same counter as
+        // the LDS writes of the steps, so none is issued between them
+        double4 cc[kSpLC];
+#pragma unroll
+        for (int li = 0; li < kSpLC; ++li) cc[li] = rec[moff + min(lc + li, lmax)];
+        if (sc || lc + kSpLC - 1 > lmax || lc == l0) {
+            // some lane still scaled, the last chunk or the first: every step tested
+#pragma unroll
+            for (int li = 0; li < kSpLC; ++li) {
+                const int l = lc + li;
+                bool on[R];
+#pragma unroll
+                for (int r = 0; r < R; ++r) on[r] = false;
+                if (l <= lmax) {
+                    if (l > l0) {
+                        const double4 c = cc[li];
+                        if (sc) {
+                            any_scaled = false;
+#pragma unroll
+                            for (int r = 0; r < R; ++r) {
+                                live[r] = spin_step_scaled(c, y[r], p[r], q[r], pp[r], qp[r], k[r]);
+                                any_scaled |= !live[r];
+                            }
+                        } else {
+#pragma unroll
+                            for (int r = 0; r < R; ++r)
+                                spin_step(c, y[r], p[r], q[r], pp[r], qp[r]);
+                        }
+                    }
+#pragma unroll
+                    for (int r = 0; r < R; ++r) on[r] = live[r];
+                }
+                put(li, (li & 1) != 0, true, on);
+            }
+        } else {
+            // every lane live, every step in range
+            const bool all_on[R] = {};
+#pragma unroll
+            for (int li = 0; li < kSpLC; ++li) {
+#pragma unroll
+                for (int r = 0; r < R; ++r) spin_step(cc[li], y[r], p[r], q[r], pp[r], qp[r]);
+                put(li, (li & 1) != 0, false, all_on);
+            }
+        }
+        // transposed read of this wave's chunk
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        const int rr = lane / LPR, h = lane % LPR;
+        double acc = 0.0;
+#pragma unroll 8
+        for (int i = 0; i < PER; ++i) {
+            const int e = h * PER + i;
+            acc += buf[wave][rr][e + (e >> 5)];
+        }
+#pragma unroll
+        for (int o = 1; o < LPR; o <<= 1) acc += __shfl_xor(acc, o);
+        if (h == 0) {
+            const int li = rr / NV, v = rr % NV;
+            const int l = lc + li;
+            // (imaginary parts of m = 0 stay zero: that coefficient is real)
+            if (l <= lmax && !(m == 0 && (v & 1))) {
+                const int b = v >> 2, t = v & 3;
+                const int64_t o = ((int64_t)(2 * b + (t >> 1)) * nalm + moff + l) * 2 + (t & 1);
+                if (DET)
+                    alm[(int64_t)(rb * nw + wave) * part_stride + o] = acc;
+                else
+                    atomicAdd(alm + o, -0.5 * acc);
+            }
+        }
+        // this wave's reads of buf are done before its next writes
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
     }
     // no LDS-DMA write may be in flight when the workgroup's LDS is released
     asm volatile("s_waitcnt vmcnt(0)" ::"v"(pf_keep) : "memory");
