@@ -232,6 +232,33 @@ def test_spin2_full_degree_against_oracle(P, oracle_mod, dtype, eps, tol):
         assert e <= ctol, (m, e)
 
 
+def test_spin3_three_fields_at_c3_against_oracle(P, oracle_mod):
+    """Three spin-3 fields (a group of two and a single one) on the 33.5 M C3 points at
+    lmax 4095, mixed precision: the synthesis on 24 sampled points against the direct sums,
+    and the adjoint's column m = 0 and m = 4000 against the direct sums over a 2e5-point subset
+    plan (the columns at full N take the oracle core-hours)."""
+    print("[spin3 c3 three fields]", flush=True)
+    cfg = inputs.config_c3(nmaps=1)
+    L, s = cfg["lmax"], 3
+    rng = np.random.default_rng(428)
+    a = inputs.spin_alm(rng, L, L, s, 3)
+    pl = P.Plan(L, L, dev(cfg["theta"]), dev(cfg["phi"]), 1e-5, dtype="mixed")
+    f = pl.synthesis_spin(s, dev(a)).cpu().numpy()
+    sel = np.linspace(0, cfg["theta"].size - 1, 24).astype(np.int64)
+    ref = oracle_mod.spin_synthesis(L, L, s, cfg["theta"][sel], cfg["phi"][sel], a)
+    assert rel(f[:, :, sel], ref) <= 1e-5, rel(f[:, :, sel], ref)
+    pl.close()
+    th, ph = cfg["theta"][:200000], cfg["phi"][:200000]
+    d = rng.standard_normal((3, 2, th.size))
+    ps = P.Plan(L, L, dev(th), dev(ph), 1e-5, dtype="mixed")
+    c = ps.adjoint_spin(s, dev(d)).cpu().numpy()
+    cols = oracle_mod.spin_adjoint_columns(L, s, th, ph, d, [0, 4000])
+    for k, m in enumerate([0, 4000]):
+        off = m * (2 * L + 1 - m) // 2
+        got = c[:, :, off + m: off + L + 1]
+        assert rel(got, cols[:, :, k, m:]) <= 1e-5, (m, rel(got, cols[:, :, k, m:]))
+
+
 @pytest.mark.parametrize("dtype,tol", [("f64", 1e-11), ("mixed", 2e-5)])
 def test_spin2_c3_shape_dot_test(P, dtype, tol):
     """At the headline shape (lmax 4095, 33.5 M uniform points, two spin-2 fields = four real
