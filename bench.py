@@ -378,20 +378,18 @@ def spin_legendre_flops(g, nfields):
     return float(g["nalm"]) * pairs * (14 + 16 * nfields)
 
 
-def run_spin(args):
-    """Spin-weighted leg (`--spin S`, the spin-n extension of Sec. V): the headline workload's
-    lmax = 4095 and 33,550,336 uniform points, `--spin-fields` spin-S fields (two real maps
-    each: F = 2 gives the same four real maps as the spin-0 step), one step = one
-    synthesis_spin + one adjoint_spin, mixed precision at eps = 1e-5 and FP64 at 1e-12.  The
-    accuracy columns: the mixed synthesis against the FP64 one, the FP64 synthesis against the
-    oracle's direct sums on 48 of the points, and the dot test <d, S a> = <S^H d, a>_m.
-    Prints ONE JSON line."""
+def spin_leg(spin, F, dtypes, steps, warmup):
+    """The spin-weighted step on the headline workload's points: lmax = 4095, the 33,550,336
+    uniform C3 points (the nmaps = 1 draw), F spin-`spin` fields (two real maps each; F = 2
+    gives the same four real maps as the spin-0 step), one step = one synthesis_spin + one
+    adjoint_spin, for each (dtype, eps) in dtypes.  Accuracy: the dot test
+    <d, S a> = <S^H d, a>_m per dtype and, for spin 2 with two fields, the synthesis against the
+    oracle's direct sums stored by tests/golden/make_large_oracle_values.py (48 points)."""
     import torch
     import paper_2406_14542_amd as P
     from paper_2406_14542_amd import inputs
 
     P.lib()
-    spin, F = args.spin, args.spin_fields
     cfg = inputs.config_c3(nmaps=1)
     L = cfg["lmax"]
     rng = np.random.default_rng(106)
@@ -401,9 +399,14 @@ def run_spin(args):
     d = torch.from_numpy(d_np).cuda()
     _, ms = inputs.ell_of_index(L, L)
     w = torch.from_numpy(np.where(ms == 0, 1.0, 2.0)).cuda()
+    golden = None
+    gpath = os.path.join(ROOT, "tests", "golden", "c3_spin2_sample_synthesis.npz")
+    if spin == 2 and F == 2 and os.path.exists(gpath):
+        with np.load(gpath) as z:
+            golden = (z["idx"], z["f"])
     res = {}
     maps = {}
-    for dtype, eps in (("mixed", 1e-5), ("f64", 1e-12)):
+    for dtype, eps in dtypes:
         th = torch.from_numpy(cfg["theta"]).cuda()
         ph = torch.from_numpy(cfg["phi"]).cuda()
         pl = P.Plan(L, L, th, ph, eps, dtype=dtype, timing=True)
@@ -415,12 +418,12 @@ def run_spin(args):
             pl.synthesis_spin(spin, a, out=f)
             pl.adjoint_spin(spin, d, out=c)
 
-        for _ in range(args.warmup):
+        for _ in range(warmup):
             step()
         torch.cuda.synchronize()
         pl.stage_reset()
         evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
-               for _ in range(args.steps)]
+               for _ in range(steps)]
         for e0, e1 in evs:
             e0.record()
             step()
@@ -451,20 +454,30 @@ def run_spin(args):
                               "frac": round(fl / (adj["legendre"] * 1e-3) / 1e12 / FP64_PEAK_TFLOPS, 4)}},
                       "dot_test_rel": abs(lhs - rhs) / abs(lhs),
                       "legendre_flops_per_launch": fl}
+        if golden is not None:
+            idx, ref = golden
+            res[dtype]["synthesis_vs_oracle_sample_rel_l2"] = float(
+                np.linalg.norm(maps[dtype][:, :, idx] - ref) / np.linalg.norm(ref))
         log(f"spin {spin} {dtype}: {res[dtype]['ms_per_step']:.2f} ms/step; syn {syn} adj {adj}")
         pl.close()
         del f, c
         torch.cuda.empty_cache()
+    return res, maps, cfg
+
+
+def run_spin(args):
+    """Spin-weighted leg (`--spin S`, the spin-n extension of Sec. V): spin_leg for mixed
+    precision at eps = 1e-5 and FP64 at 1e-12, plus the mixed synthesis against the FP64 one.
+    Prints ONE JSON line."""
+    spin, F = args.spin, args.spin_fields
+    res, maps, cfg = spin_leg(spin, F, (("mixed", 1e-5), ("f64", 1e-12)), args.steps,
+                              args.warmup)
+    L = cfg["lmax"]
     acc = {"mixed_vs_fp64_synthesis_rel_l2": float(
         np.linalg.norm(maps["mixed"] - maps["f64"]) / np.linalg.norm(maps["f64"]))}
-    try:
-        import oracle
-        sel = np.linspace(0, cfg["theta"].size - 1, 48).astype(np.int64)
-        ref = oracle.spin_synthesis(L, L, spin, cfg["theta"][sel], cfg["phi"][sel], a_np)
-        acc["fp64_vs_oracle_sample_rel_l2"] = float(
-            np.linalg.norm(maps["f64"][:, :, sel] - ref) / np.linalg.norm(ref))
-    except Exception as e:  # the oracle is optional for the timing itself
-        log(f"oracle sample skipped: {e}")
+    for dt in ("mixed", "f64"):
+        if "synthesis_vs_oracle_sample_rel_l2" in res[dt]:
+            acc[f"{dt}_vs_oracle_sample_rel_l2"] = res[dt]["synthesis_vs_oracle_sample_rel_l2"]
     out = {"metric": f"spin-{spin} nuSHT synthesis+adjoint seconds at lmax={L} "
                      f"({F} fields = {2 * F} real maps)",
            "value": res["mixed"]["median_s"], "unit": "s", "n_gpus": 1, "steps": args.steps,
@@ -516,6 +529,9 @@ def main():
     ap.add_argument("--spin", type=int, default=0,
                     help="run the spin-weighted leg with this spin instead of the transform step")
     ap.add_argument("--spin-fields", type=int, default=2)
+    ap.add_argument("--no-spin", action="store_true",
+                    help="leave out the spin-2 entry of the default line")
+    ap.add_argument("--spin-steps", type=int, default=5)
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
                     help="only run one elementwise device copy of BYTES bytes (the reference "
                          "kernel that scales HBM byte counters)")
@@ -712,6 +728,16 @@ def main():
                                    "fine_grid": [g125["n1"], g125["n2"]],
                                    "synthesis_stages_ms": s125["syn"],
                                    "adjoint_stages_ms": s125["adj"], "accuracy": e125}
+    if not args.no_spin:
+        # the spin-weighted extension on the same points: two spin-2 fields, mixed precision
+        for obj in (mx, fp, s125):
+            if obj is not None:
+                obj["plan"].close()
+        torch.cuda.empty_cache()
+        log("spin 2, mixed")
+        sres, _, _ = spin_leg(2, 2, (("mixed", 1e-5),), args.spin_steps, 2)
+        out["spin2_mixed"] = {"workload": "the C3 points (nmaps = 1 draw), two spin-2 fields",
+                              "steps": args.spin_steps, **sres["mixed"]}
     if cpu is not None:
         model, ncpu = host_cpu()
         out["cpu_baseline"] = {"value": round(cpu["value"], 3), "unit": "s", "cores": cpu["threads"],

@@ -14,6 +14,9 @@ Outputs (numpy .npz, plain arrays, no pickles):
                           idx [4096], f [4, 4096]
   c3_adjoint_columns.npz  m = 0, 1, 2048, 4000, 4095 of the C3 adjoint of all 4 maps over
                           all 33,550,336 points: cols [4, 5, 4096] complex
+  c3_spin2_sample_synthesis.npz
+                          spin-2 synthesis (Q, U) of the spin benchmark's two fields (seed 106)
+                          on 48 evenly spaced C3 points: idx [48], f [2, 2, 48]
 """
 import argparse
 import os
@@ -33,6 +36,11 @@ C2_MS = [0, 1, 2, 64, 511, 1024, 2000, 2047]
 C3_MS = [0, 1, 2048, 4000, 4095]
 C3_SAMPLE = 4096
 C3_SAMPLE_SEED = 3
+SPIN_SEED, SPIN, SPIN_FIELDS, SPIN_SAMPLE = 106, 2, 2, 48
+
+
+def spin_sample_index(n):
+    return np.linspace(0, n - 1, SPIN_SAMPLE).astype(np.int64)
 
 
 def c3_sample_index(n):
@@ -42,7 +50,7 @@ def c3_sample_index(n):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--threads", type=int, default=0)
-    ap.add_argument("--only", choices=["c2", "c3s", "c3a"], default=None)
+    ap.add_argument("--only", choices=["c2", "c3s", "c3a", "spin"], default=None)
     a = ap.parse_args()
     oracle.build(force=False)
     t = a.threads
@@ -54,6 +62,15 @@ def main():
         np.savez_compressed(os.path.join(HERE, "c2_adjoint_columns.npz"), ms=np.array(C2_MS),
                             cols=cols)
         print(f"c2 columns: {time.time() - t0:.0f} s", flush=True)
+    if a.only in (None, "spin"):
+        t0 = time.time()
+        cfg = inputs.config_c3(nmaps=1)
+        L = cfg["lmax"]
+        alm = inputs.spin_alm(np.random.default_rng(SPIN_SEED), L, L, SPIN, SPIN_FIELDS)
+        idx = spin_sample_index(cfg["theta"].size)
+        f = oracle.spin_synthesis(L, L, SPIN, cfg["theta"][idx], cfg["phi"][idx], alm, nthreads=t)
+        np.savez_compressed(os.path.join(HERE, "c3_spin2_sample_synthesis.npz"), idx=idx, f=f)
+        print(f"c3 spin-2 sample synthesis: {time.time() - t0:.0f} s", flush=True)
     if a.only in (None, "c3s", "c3a"):
         cfg = inputs.config_c3()
         L = cfg["lmax"]
