@@ -331,3 +331,26 @@ def test_spin_synthesis_rotates_with_phi(oracle_mod):
     q0 = oracle_mod.spin_synthesis(L, L, s, th, ph, a)
     q1 = oracle_mod.spin_synthesis(L, L, s, th, ph + psi, rot)
     np.testing.assert_allclose(q1, q0, atol=1e-13 * np.max(np.abs(q0)))
+
+
+@pytest.mark.parametrize("s", [1, 2])
+@pytest.mark.parametrize("th", [0.02, 0.7, 2.9])
+def test_spin_addition_theorem_4095(oracle_mod, s, th):
+    """sum_{m=-l}^{l} |sY_lm|^2 = (2l+1)/4pi for every l <= 4095 and any spin s; with only
+    m >= 0 stored, sY_{l,-m} = (-1)^(s+m) conj((-s)Y_lm) puts |(-s)lam_lm|^2 in for m < 0:
+    sum_{m>=0} slam_lm^2 + sum_{m>0} (-s)lam_lm^2 = (2l+1)/4pi.  One identity over all 4096
+    columns at once, independent of the recurrence in s used by the eth identity."""
+    L = 4095
+    tot = np.zeros(L + 1)
+    for m in range(L + 1):
+        pu, pv, ex = oracle_mod.spin_lambda_column(L, m, s, th)
+        sc = np.exp2(np.clip(ex.astype(float), -1100, 1100))
+        up, vm = pu * sc, pv * sc
+        tot += up * up
+        if m > 0:
+            tot += vm * vm
+    ls = np.arange(L + 1)
+    want = (2 * ls + 1) / (4 * math.pi)
+    r = np.abs(tot[s:] / want[s:] - 1.0)
+    assert np.all(r <= 2e-12 * np.sqrt(ls[s:] + 1.0)), (s, th, float(r.max()))
+    assert np.all(tot[:s] == 0.0)
