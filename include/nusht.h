@@ -157,7 +157,7 @@ int nusht_adjoint(nusht_plan_t plan, const double* map, double* alm, int nmaps, 
    [nfields][2][npts] float64 (Q, then U).  For spin 1 and G = -sqrt(l(l+1)) a_lm, C = 0 the
    map is (Q, U) = -(d f/d theta, (d f/d phi)/sin theta) of the spin-0 map f of a_lm.
    The adjoint is the transpose under <.,.>_m above, applied to G and C alike.
-   Plans: fused DFS mode only, 1 <= spin <= min(lmax, NUSHT_MAX_SPIN), and
+   Plans: either DFS mode, 1 <= spin <= min(lmax, NUSHT_MAX_SPIN), and
    2 spin log2(1/tan(theta_1/2)) <= 800 with theta_1 = pi/(N_r - 1) the ring next to a pole
    (the two Wigner-d functions of a ring share one exponent; spin <= 35 at lmax 4095,
    <= 32 up to lmax 9000) -- NUSHT_EINVAL otherwise;

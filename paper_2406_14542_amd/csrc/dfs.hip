@@ -38,9 +38,12 @@ __global__ void k_zero_rows(double2* __restrict__ G, int nr, int row_len, int m_
     for (int m = m_from; m < row_len; ++m) row[m] = make_double2(0.0, 0.0);
 }
 
+// D of Fig. 1: torus row t < N_r is ring t, row t >= N_r is ring N_t - t shifted by pi in phi,
+// times sgn (1 for spin 0; (-1)^s for the Q, U components of a spin-s field, whose local basis
+// turns over with the doubling).  k_fold is its adjoint.
 template <typename TO>
 __global__ void k_double(const double* __restrict__ ring, TO* __restrict__ torus, int nr, int nt,
-                         int nphi)
+                         int nphi, double sgn)
 {
     const int k = blockIdx.x * blockDim.x + threadIdx.x;
     const int t = blockIdx.y;
@@ -53,14 +56,14 @@ __global__ void k_double(const double* __restrict__ ring, TO* __restrict__ torus
     } else {
         int kk = k + nphi / 2;
         if (kk >= nphi) kk -= nphi;
-        v = rg[(int64_t)(nt - t) * nphi + kk];
+        v = sgn * rg[(int64_t)(nt - t) * nphi + kk];
     }
     torus[(int64_t)b * nt * nphi + (int64_t)t * nphi + k] = (TO)v;
 }
 
 template <typename TI>
 __global__ void k_fold(const TI* __restrict__ torus, double* __restrict__ ring, int nr, int nt,
-                       int nphi)
+                       int nphi, double sgn)
 {
     const int k = blockIdx.x * blockDim.x + threadIdx.x;
     const int j = blockIdx.y;
@@ -71,7 +74,7 @@ __global__ void k_fold(const TI* __restrict__ torus, double* __restrict__ ring, 
     if (j >= 1 && j <= nr - 2) {
         int kk = k + nphi / 2;
         if (kk >= nphi) kk -= nphi;
-        v += (double)tg[(int64_t)(nt - j) * nphi + kk];
+        v += sgn * (double)tg[(int64_t)(nt - j) * nphi + kk];
     }
     ring[(int64_t)b * nr * nphi + (int64_t)j * nphi + k] = v;
 }
@@ -323,32 +326,33 @@ int launch_rows_to_band(const nusht_plan_s* p, const void* rows, int rw, void* b
 }
 
 int launch_double(const nusht_plan_s* p, const double* ring, void* torus, int nmaps, int f32,
-                  hipStream_t s)
+                  hipStream_t s, double sgn)
 {
     const nusht_geometry& g = p->g;
     dim3 grid((g.nphi + 255) / 256, g.ntorus, nmaps);
     if (f32)
         hipLaunchKernelGGL(k_double<float>, grid, dim3(256), 0, s, ring,
-                           reinterpret_cast<float*>(torus), g.nrings, g.ntorus, g.nphi);
+                           reinterpret_cast<float*>(torus), g.nrings, g.ntorus, g.nphi, sgn);
     else
         hipLaunchKernelGGL(k_double<double>, grid, dim3(256), 0, s, ring,
-                           reinterpret_cast<double*>(torus), g.nrings, g.ntorus, g.nphi);
+                           reinterpret_cast<double*>(torus), g.nrings, g.ntorus, g.nphi, sgn);
     NUSHT_HIP(hipGetLastError());
     return NUSHT_OK;
 }
 
 int launch_fold(const nusht_plan_s* p, const void* torus, double* ring, int nmaps, int f32,
-                hipStream_t s)
+                hipStream_t s, double sgn)
 {
     const nusht_geometry& g = p->g;
     dim3 grid((g.nphi + 255) / 256, g.nrings, nmaps);
     if (f32)
         hipLaunchKernelGGL(k_fold<float>, grid, dim3(256), 0, s,
-                           reinterpret_cast<const float*>(torus), ring, g.nrings, g.ntorus, g.nphi);
+                           reinterpret_cast<const float*>(torus), ring, g.nrings, g.ntorus, g.nphi,
+                           sgn);
     else
         hipLaunchKernelGGL(k_fold<double>, grid, dim3(256), 0, s,
                            reinterpret_cast<const double*>(torus), ring, g.nrings, g.ntorus,
-                           g.nphi);
+                           g.nphi, sgn);
     NUSHT_HIP(hipGetLastError());
     return NUSHT_OK;
 }

@@ -259,15 +259,18 @@ int launch_legendre_adjoint(nusht_plan_s* p, const void* in, double* alm, int nm
 // ---- spin-weighted Legendre step (spin.hip) ----
 // tables for the given spin (rebuilt when it changes); nfields fields = 2 nfields maps (Q, U)
 int ensure_spin_tables(nusht_plan_s* p, int spin);
+// fused: the doubled theta-columns [map][m][t]; otherwise the ring layout [map][j][m] with rows
+// of N_phi/2 + 1 (FP64) of the paper composition
 int launch_spin_synth(nusht_plan_s* p, int spin, const double* alm, void* out, int nfields,
-                      int out_f32, hipStream_t s);
+                      int out_f32, hipStream_t s, bool fused = true);
 int launch_spin_adjoint(nusht_plan_s* p, int spin, const void* in, double* alm, int nfields,
-                        int in_f32, hipStream_t s);
+                        int in_f32, hipStream_t s, bool fused = true);
 int launch_zero_nyquist_rows(const nusht_plan_s* p, double* G, int nmaps, hipStream_t s);
+// sgn: sign of the doubled half ((-1)^s for spin-s components, 1 otherwise)
 int launch_double(const nusht_plan_s* p, const double* ring, void* torus, int nmaps, int f32,
-                  hipStream_t s);
+                  hipStream_t s, double sgn = 1.0);
 int launch_fold(const nusht_plan_s* p, const void* torus, double* ring, int nmaps, int f32,
-                hipStream_t s);
+                hipStream_t s, double sgn = 1.0);
 int launch_deconv_pad(const nusht_plan_s* p, const void* tspec, void* fspec, int nmaps, int fused,
                       int f32, hipStream_t s);
 int launch_deconv_trunc(const nusht_plan_s* p, const void* fspec, void* tspec, int nmaps,

@@ -223,9 +223,10 @@ __device__ inline void spin_accum(double (&A)[MB][8], const double2* __restrict_
     }
 }
 
-// Synthesis: out[map][m][t] (t < N_t) for maps 2f (Q) and 2f+1 (U) of field f, the doubled
-// columns of the fused path: out(t) = X(t) for t < N_r, (-1)^(m+s) X(N_t - t) for t >= N_r.
-template <int MB, typename OutT>
+// Synthesis, for maps 2f (Q) and 2f+1 (U) of field f.  FUSED: out[map][m][t] (t < N_t), the
+// doubled columns: out(t) = X(t) for t < N_r, (-1)^(m+s) X(N_t - t) for t >= N_r.  Otherwise
+// out[map][j][m], the ring rows of the paper composition (its doubling comes later).
+template <int MB, typename OutT, bool FUSED>
 __global__ __launch_bounds__(256) void k_spin_synth(
     const double2* __restrict__ alm, int64_t nalm, int lmax, int mmax, int spin, int nbx,
     const double4* __restrict__ rec, const double* __restrict__ km, const int* __restrict__ ke,
@@ -330,6 +331,17 @@ __global__ __launch_bounds__(256) void k_spin_synth(
         double qs_re = -0.5 * fma(sg, msr, psr), qs_im = -0.5 * fma(sg, msi, psi);
         double us_re = -0.5 * fma(-sg, msi, psi), us_im = 0.5 * fma(-sg, msr, psr);
         if (m == 0) qn_im = un_im = qs_im = us_im = 0.0;  // imaginary parts of m = 0 are ignored
+        if (!FUSED) {
+            OutT* rq = out + (int64_t)(2 * b) * out_map_stride + m;
+            OutT* ru = rq + out_map_stride;
+            rq[(int64_t)jj * out_row_stride] = make_pair<OutT>(qn_re, qn_im);
+            ru[(int64_t)jj * out_row_stride] = make_pair<OutT>(un_re, un_im);
+            if (js != jj) {
+                rq[(int64_t)js * out_row_stride] = make_pair<OutT>(qs_re, qs_im);
+                ru[(int64_t)js * out_row_stride] = make_pair<OutT>(us_re, us_im);
+            }
+            continue;
+        }
         OutT* cq = out + (int64_t)(2 * b) * out_map_stride + (int64_t)m * out_row_stride;
         OutT* cu = cq + out_map_stride;
         cq[jj] = make_pair<OutT>(qn_re, qn_im);
@@ -381,7 +393,7 @@ constexpr int kSpAdjR = 3;  // ring pairs per lane of the adjoint
 // DET: instead of the atomic adds, wave w of the m's waves writes its sums (unscaled) to
 // alm + w * part_stride, a zeroed per-wave partial array that k_spin_adj_reduce then adds in
 // wave order (bit-identical results from run to run).
-template <int MB, typename InT, bool DET>
+template <int MB, typename InT, bool DET, bool FUSED>
 __global__ __launch_bounds__(256) void k_spin_adj(
     const InT* __restrict__ in, int64_t in_map_stride, int64_t in_row_stride,
     double* __restrict__ alm, int64_t nalm, int lmax, int mmax, int spin, int nbx,
@@ -435,7 +447,7 @@ __global__ __launch_bounds__(256) void k_spin_adj(
 #pragma unroll
         for (int b = 0; b < MB; ++b) {
             double2 qn = make_double2(0.0, 0.0), un = qn, qs = qn, us = qn;
-            if (ok) {
+            if (ok && FUSED) {
                 const InT* colq = in + (int64_t)(2 * b) * in_map_stride + (int64_t)m * in_row_stride;
                 const InT* colu = colq + in_map_stride;
                 qn = folded(colq, j, nr, nt, dsg);
@@ -443,6 +455,16 @@ __global__ __launch_bounds__(256) void k_spin_adj(
                 if (js != j) {
                     qs = folded(colq, js, nr, nt, dsg);
                     us = folded(colu, js, nr, nt, dsg);
+                }
+            } else if (ok) {
+                // ring rows [map][j][m] of the paper composition, already folded
+                const InT* rq = in + (int64_t)(2 * b) * in_map_stride + m;
+                const InT* ru = rq + in_map_stride;
+                qn = load2(rq + (int64_t)j * in_row_stride);
+                un = load2(ru + (int64_t)j * in_row_stride);
+                if (js != j) {
+                    qs = load2(rq + (int64_t)js * in_row_stride);
+                    us = load2(ru + (int64_t)js * in_row_stride);
                 }
             }
             const double2 qpl = make_double2(qn.x + qs.x, qn.y + qs.y);
@@ -744,7 +766,7 @@ int ensure_spin_tables(nusht_plan_s* p, int spin)
 }
 
 int launch_spin_synth(nusht_plan_s* p, int spin, const double* alm, void* out, int nfields,
-                      int out_f32, hipStream_t s)
+                      int out_f32, hipStream_t s, bool fused)
 {
     NUSHT_TRY(ensure_spin_tables(p, spin));
     const nusht_geometry& g = p->g;
@@ -753,24 +775,27 @@ int launch_spin_synth(nusht_plan_s* p, int spin, const double* alm, void* out, i
     const int wpb = waves_needed >= 4 ? 4 : waves_needed;
     const int nbx = (waves_needed + wpb - 1) / wpb;
     const int mpad = (g.mmax + 1 + 7) / 8 * 8;
-    const int64_t row_stride = g.ntorus;
-    const int64_t map_stride = (int64_t)(g.mmax + 1) * g.ntorus;
+    const int64_t row_stride = fused ? g.ntorus : g.nphi / 2 + 1;
+    const int64_t map_stride = fused ? (int64_t)(g.mmax + 1) * g.ntorus : (int64_t)g.nrings * row_stride;
     const double2* a = reinterpret_cast<const double2*>(alm);
     int f = 0;
     while (f < nfields) {
         const int mb = nfields - f >= 2 ? 2 : 1;
         const int groups = (nfields - f) / mb;
         const double2* af = a + (int64_t)f * 2 * g.nalm;
-#define SPS(MBV, OT)                                                                             \
-    hipLaunchKernelGGL((k_spin_synth<MBV, OT>), dim3(nbx * mpad, groups), dim3(64 * wpb), 0, s,   \
+#define SPS(MBV, OT, FU)                                                                         \
+    hipLaunchKernelGGL((k_spin_synth<MBV, OT, FU>), dim3(nbx * mpad, groups), dim3(64 * wpb), 0, \
+                       s,                                                                        \
                        af, g.nalm, g.lmax, g.mmax, spin, nbx, p->spin_rec, p->spin_km,           \
                        p->spin_ke, p->spin_jlive, g.nrings, g.ntorus,                            \
                        reinterpret_cast<OT*>(out) + (int64_t)f * 2 * map_stride, map_stride,     \
                        row_stride)
-        if (out_f32) {
-            if (mb == 2) SPS(2, float2); else SPS(1, float2);
+        if (!fused) {
+            if (mb == 2) SPS(2, double2, false); else SPS(1, double2, false);
+        } else if (out_f32) {
+            if (mb == 2) SPS(2, float2, true); else SPS(1, float2, true);
         } else {
-            if (mb == 2) SPS(2, double2); else SPS(1, double2);
+            if (mb == 2) SPS(2, double2, true); else SPS(1, double2, true);
         }
 #undef SPS
         NUSHT_HIP(hipGetLastError());
@@ -780,7 +805,7 @@ int launch_spin_synth(nusht_plan_s* p, int spin, const double* alm, void* out, i
 }
 
 int launch_spin_adjoint(nusht_plan_s* p, int spin, const void* in, double* alm, int nfields,
-                        int in_f32, hipStream_t s)
+                        int in_f32, hipStream_t s, bool fused)
 {
     NUSHT_TRY(ensure_spin_tables(p, spin));
     const nusht_geometry& g = p->g;
@@ -788,8 +813,8 @@ int launch_spin_adjoint(nusht_plan_s* p, int spin, const void* in, double* alm, 
     // four independent waves per block, kSpAdjR ring pairs per lane
     const int nbx = (npairs + 256 * kSpAdjR - 1) / (256 * kSpAdjR);
     const int mpad = (g.mmax + 1 + 7) / 8 * 8;
-    const int64_t row_stride = g.ntorus;
-    const int64_t map_stride = (int64_t)(g.mmax + 1) * g.ntorus;
+    const int64_t row_stride = fused ? g.ntorus : g.nphi / 2 + 1;
+    const int64_t map_stride = fused ? (int64_t)(g.mmax + 1) * g.ntorus : (int64_t)g.nrings * row_stride;
     const int64_t nz = (int64_t)nfields * 2 * g.nalm * 2;  // doubles of the output
     const int nwm = 4 * nbx;                                // waves per m
     const bool det = p->deterministic != 0;
@@ -818,22 +843,28 @@ int launch_spin_adjoint(nusht_plan_s* p, int spin, const void* in, double* alm, 
         const int mb = nfields - f >= 2 ? 2 : 1;
         const int groups = (nfields - f) / mb;
         double* af = target + (int64_t)f * 2 * g.nalm * 2;
-#define SPA(MBV, IT, D)                                                                          \
-    hipLaunchKernelGGL((k_spin_adj<MBV, IT, D>), dim3(nbx * mpad, groups), dim3(256), 0, s,       \
+#define SPA(MBV, IT, D, FU)                                                                      \
+    hipLaunchKernelGGL((k_spin_adj<MBV, IT, D, FU>), dim3(nbx * mpad, groups), dim3(256), 0, s,   \
                        reinterpret_cast<const IT*>(in) + (int64_t)f * 2 * map_stride, map_stride, \
                        row_stride, af, g.nalm, g.lmax, g.mmax, spin, nbx, p->spin_rec,           \
                        p->spin_km, p->spin_ke, p->spin_jlive, g.nrings, g.ntorus, nz)
-        if (det) {
-            if (in_f32) {
-                if (mb == 2) SPA(2, float2, true); else SPA(1, float2, true);
+        if (!fused) {
+            if (det) {
+                if (mb == 2) SPA(2, double2, true, false); else SPA(1, double2, true, false);
             } else {
-                if (mb == 2) SPA(2, double2, true); else SPA(1, double2, true);
+                if (mb == 2) SPA(2, double2, false, false); else SPA(1, double2, false, false);
+            }
+        } else if (det) {
+            if (in_f32) {
+                if (mb == 2) SPA(2, float2, true, true); else SPA(1, float2, true, true);
+            } else {
+                if (mb == 2) SPA(2, double2, true, true); else SPA(1, double2, true, true);
             }
         } else {
             if (in_f32) {
-                if (mb == 2) SPA(2, float2, false); else SPA(1, float2, false);
+                if (mb == 2) SPA(2, float2, false, true); else SPA(1, float2, false, true);
             } else {
-                if (mb == 2) SPA(2, double2, false); else SPA(1, double2, false);
+                if (mb == 2) SPA(2, double2, false, true); else SPA(1, double2, false, true);
             }
         }
 #undef SPA

@@ -365,13 +365,17 @@ int fine_r2c(nusht_plan_s* p, char* real, char* band, hipStream_t s)
     return NUSHT_OK;
 }
 
-// S (Legendre + per-ring phi-FFT) of the paper composition into ring maps [b][N_r][N_phi]
+// S (Legendre + per-ring phi-FFT) of the paper composition into ring maps [b][N_r][N_phi];
+// spin > 0: the maps are the (Q, U) pairs of nmaps / 2 spin-weighted fields
 int ring_synthesis_into(nusht_plan_s* p, const double* alm, double* ring, void* G, int nmaps,
-                        hipStream_t s)
+                        hipStream_t s, int spin = 0)
 {
     const nusht_geometry& g = p->g;
     stage_begin(p, ST_LEGENDRE, s);
-    NUSHT_TRY(launch_legendre_synth(p, alm, G, nmaps, 0, 0, s));
+    if (spin)
+        NUSHT_TRY(launch_spin_synth(p, spin, alm, G, nmaps / 2, 0, s, false));
+    else
+        NUSHT_TRY(launch_legendre_synth(p, alm, G, nmaps, 0, 0, s));
     NUSHT_TRY(launch_zero_nyquist_rows(p, reinterpret_cast<double*>(G), nmaps, s));
     stage_end(p, ST_LEGENDRE, s);
     stage_begin(p, ST_RING_FFT, s);
@@ -386,7 +390,7 @@ int ring_synthesis_into(nusht_plan_s* p, const double* alm, double* ring, void* 
 // torus spectrum (fused: doubled theta-columns [b][m][t] transformed over t; paper: 2D R2C
 // of the doubled map) into X, for maps [0, nmaps)
 // spin > 0: the nmaps maps are the (Q, U) pairs of nmaps / 2 spin-weighted fields, whose
-// theta-columns come from the Wigner-d step (fused mode only)
+// columns come from the Wigner-d step and whose doubling carries (-1)^spin
 int synthesis_to_fine(nusht_plan_s* p, const double* alm, int nmaps, hipStream_t s, void** fine_out,
                       int spin = 0)
 {
@@ -418,9 +422,11 @@ int synthesis_to_fine(nusht_plan_s* p, const double* alm, int nmaps, hipStream_t
         stage_end(p, ST_FINE_FFT, s);
         *fine_out = p->X;
     } else {
-        NUSHT_TRY(ring_synthesis_into(p, alm, reinterpret_cast<double*>(p->Y), p->X, nmaps, s));
+        NUSHT_TRY(ring_synthesis_into(p, alm, reinterpret_cast<double*>(p->Y), p->X, nmaps, s,
+                                      spin));
         stage_begin(p, ST_DOUBLE, s);
-        NUSHT_TRY(launch_double(p, reinterpret_cast<const double*>(p->Y), p->X, nmaps, f32, s));
+        NUSHT_TRY(launch_double(p, reinterpret_cast<const double*>(p->Y), p->X, nmaps, f32, s,
+                                (spin & 1) ? -1.0 : 1.0));
         stage_end(p, ST_DOUBLE, s);
         stage_begin(p, ST_TORUS_FFT, s);
         const size_t tstride = (size_t)g.ntorus * g.nphi * e;
@@ -442,13 +448,9 @@ int synthesis_to_fine(nusht_plan_s* p, const double* alm, int nmaps, hipStream_t
     return NUSHT_OK;
 }
 
-// the spin-weighted calls: fused mode, 1 <= spin <= min(lmax, kMaxSpin), no deterministic plan
+// the spin-weighted calls: 1 <= spin <= min(lmax, NUSHT_MAX_SPIN) and the exponent-range limit
 int check_spin(nusht_plan_s* p, int spin, const char* who)
 {
-    if (p->g.dfs_mode != NUSHT_DFS_FUSED) {
-        set_last_error(who, "spin-weighted transforms need a plan in the fused DFS mode");
-        return NUSHT_EINVAL;
-    }
     if (spin < 1 || spin > p->g.lmax || spin > NUSHT_MAX_SPIN) {
         set_last_error(who, "spin must satisfy 1 <= spin <= min(lmax, NUSHT_MAX_SPIN)");
         return NUSHT_EINVAL;
@@ -529,7 +531,7 @@ int nusht_synthesis_deriv(nusht_plan_t p, const double* alm, double* map, double
 namespace nusht {
 namespace {
 
-// N^H, then the fused or paper-mode S^H; spin > 0: nmaps / 2 spin-weighted fields (fused only)
+// N^H, then the fused or paper-mode S^H; spin > 0: nmaps / 2 spin-weighted fields
 int adjoint_impl(nusht_plan_s* p, const double* map, double* alm, int nmaps, hipStream_t s,
                  int spin)
 {
@@ -584,7 +586,8 @@ int adjoint_impl(nusht_plan_s* p, const double* map, double* alm, int nmaps, hip
                                bytes(p->Y) + b * tstride, s));
         stage_end(p, ST_TORUS_FFT, s);
         stage_begin(p, ST_DOUBLE, s);
-        NUSHT_TRY(launch_fold(p, p->Y, reinterpret_cast<double*>(p->X), nmaps, f32, s));
+        NUSHT_TRY(launch_fold(p, p->Y, reinterpret_cast<double*>(p->X), nmaps, f32, s,
+                              (spin & 1) ? -1.0 : 1.0));
         stage_end(p, ST_DOUBLE, s);
         stage_begin(p, ST_RING_FFT, s);
         const size_t rstride = (size_t)g.nrings * g.nphi * 8;
@@ -594,7 +597,10 @@ int adjoint_impl(nusht_plan_s* p, const double* map, double* alm, int nmaps, hip
                                bytes(p->Y) + b * gstride, s));
         stage_end(p, ST_RING_FFT, s);
         stage_begin(p, ST_LEGENDRE, s);
-        NUSHT_TRY(launch_legendre_adjoint(p, p->Y, alm, nmaps, 0, 0, s));
+        if (spin)
+            NUSHT_TRY(launch_spin_adjoint(p, spin, p->Y, alm, nmaps / 2, 0, s, false));
+        else
+            NUSHT_TRY(launch_legendre_adjoint(p, p->Y, alm, nmaps, 0, 0, s));
         stage_end(p, ST_LEGENDRE, s);
     }
     return NUSHT_OK;

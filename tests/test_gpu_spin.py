@@ -84,6 +84,22 @@ def test_spin_synthesis_and_adjoint_match_oracle(P, case, s, dtype, eps, tol):
     assert np.all(c[:, :, ms == 0].imag == 0)
 
 
+@pytest.mark.parametrize("s", [1, 2])
+def test_spin_paper_dfs_mode(P, case, s):
+    """The spin path in the paper composition (ring phi-FFT, doubling with (-1)^s, 2D torus
+    FFT) against the oracle, FP64, and against the fused mode."""
+    print(f"[spin {s} paper mode]", flush=True)
+    L = case["L"]
+    pp = P.Plan(L, L, dev(case["th"]), dev(case["ph"]), 1e-12, dfs_mode="paper")
+    f = pp.synthesis_spin(s, dev(case[s])).cpu().numpy()
+    assert rel(f, case["ref"][s]) <= 1e-11, rel(f, case["ref"][s])
+    c = pp.adjoint_spin(s, dev(case["d"])).cpu().numpy()
+    assert mrel(c, case["cref"][s], L, L) <= 1e-11, mrel(c, case["cref"][s], L, L)
+    pf = P.Plan(L, L, dev(case["th"]), dev(case["ph"]), 1e-12)
+    f2 = pf.synthesis_spin(s, dev(case[s])).cpu().numpy()
+    assert rel(f, f2) <= 1e-12
+
+
 def test_spin_at_sigma_1_25(P, oracle_mod):
     """The spin path on a plan with the paper's upsampling sigma = 1.25 (radix-5 fine grid,
     wider polynomial taps), mixed precision at eps 1e-5."""
@@ -121,8 +137,8 @@ def test_spin_small_degrees_and_truncated_m(P, oracle_mod):
 
 
 def test_spin_argument_checks(P):
-    """Rejected on the host, with no device work: spin 0, spin > lmax, spin above the cap, the
-    paper DFS mode, wrong shapes."""
+    """Rejected on the host, with no device work: spin 0, spin > lmax, spin above the cap, wrong
+    shapes."""
     rng = np.random.default_rng(421)
     th, ph = inputs.uniform_points(rng, 500)
     L = 20
@@ -133,9 +149,6 @@ def test_spin_argument_checks(P):
             pl.synthesis_spin(s, a)
     with pytest.raises(ValueError):
         pl.synthesis_spin(1, a[:, :1])
-    pp = P.Plan(L, L, dev(th), dev(ph), 1e-10, dfs_mode="paper")
-    with pytest.raises(P.NushtError):
-        pp.synthesis_spin(1, a)
     big = P.Plan(80, 80, dev(th), dev(ph), 1e-10)
     with pytest.raises(P.NushtError):
         big.synthesis_spin(P.NUSHT_MAX_SPIN + 1, dev(inputs.spin_alm(rng, 80, 80, 1, 1)))
