@@ -172,6 +172,12 @@ int nusht_synthesis_spin(nusht_plan_t plan, int spin, const double* alm, double*
                          int nfields, void* stream);
 int nusht_adjoint_spin(nusht_plan_t plan, int spin, const double* map, double* alm, int nfields,
                        void* stream);
+/* Spin-weighted synthesis plus the derivatives of Q and U with respect to the point
+   coordinates (the component functions in the local basis, differentiated as functions of
+   (theta, phi)): map, dtheta, dphi [nfields][2][npts].  FP64 plans only (NUSHT_EPRECISION
+   otherwise); the same plan conditions as nusht_synthesis_spin. */
+int nusht_synthesis_spin_deriv(nusht_plan_t plan, int spin, const double* alm, double* map,
+                               double* dtheta, double* dphi, int nfields, void* stream);
 
 /* Synthesis plus the derivatives of the map with respect to the point coordinates:
    dtheta[b][i] = d map[b][i] / d theta_i, dphi[b][i] = d map[b][i] / d phi_i.  FP64 plans only

@@ -93,6 +93,8 @@ def lib():
             "nusht_vjp_alm": (ctypes.c_int, [_vp, _vp, _vp, ctypes.c_int, _vp]),
             "nusht_vjp_alm_spin": (ctypes.c_int, [_vp, ctypes.c_int, _vp, _vp, ctypes.c_int,
                                                   _vp]),
+            "nusht_synthesis_spin_deriv": (ctypes.c_int, [_vp, ctypes.c_int, _vp, _vp, _vp, _vp,
+                                                          ctypes.c_int, _vp]),
             "nusht_vjp_points": (ctypes.c_int, [_vp, _vp, _vp, _vp, _vp, ctypes.c_int, _i64,
                                                 _vp]),
             "nusht_ring_synthesis": (ctypes.c_int, [_vp, _vp, _vp, ctypes.c_int, _vp]),
@@ -300,6 +302,25 @@ class Plan:
         _check(lib().nusht_adjoint_spin(self._h, int(spin), x.data_ptr(), out.data_ptr(), F,
                                         _stream()), "nusht_adjoint_spin")
         return out
+
+    def synthesis_spin_deriv(self, spin, alm):
+        """(Q, U) maps and their theta / phi derivatives at the points, each [F, 2, npts]
+        (FP64 plans)."""
+        import torch
+        if alm.dtype != torch.complex128 or not alm.is_cuda or alm.device != self.device:
+            raise TypeError(f"alm must be a complex128 tensor on {self.device}")
+        a = alm.unsqueeze(0) if alm.dim() == 2 else alm
+        if a.dim() != 3 or a.shape[1] != 2 or a.shape[2] != self.nalm:
+            raise ValueError(f"alm must have shape [F, 2, {self.nalm}]")
+        a = a.contiguous()
+        F = a.shape[0]
+        f = torch.empty((F, 2, self.npts), dtype=torch.float64, device=a.device)
+        dt = torch.empty_like(f)
+        dp = torch.empty_like(f)
+        _check(lib().nusht_synthesis_spin_deriv(self._h, int(spin), a.data_ptr(), f.data_ptr(),
+                                                dt.data_ptr(), dp.data_ptr(), F, _stream()),
+               "nusht_synthesis_spin_deriv")
+        return f, dt, dp
 
     def vjp_alm_spin(self, spin, grad_maps):
         """dL/dRe + i dL/dIm of the gradient/curl coefficients for dL/d(Q, U) = grad_maps

@@ -526,6 +526,29 @@ int nusht_synthesis_deriv(nusht_plan_t p, const double* alm, double* map, double
     return NUSHT_OK;
 }
 
+int nusht_synthesis_spin_deriv(nusht_plan_t p, int spin, const double* alm, double* map,
+                               double* dtheta, double* dphi, int nfields, void* stream)
+{
+    NUSHT_TRY(check_exec(p, alm, map, nfields));
+    NUSHT_TRY(check_spin(p, spin, "nusht_synthesis_spin_deriv"));
+    if (!dtheta || !dphi) return NUSHT_EINVAL;
+    if (p->g.dtype != NUSHT_F64) {
+        set_last_error("nusht_synthesis_spin_deriv", "needs an FP64 plan");
+        return NUSHT_EPRECISION;
+    }
+    DeviceGuard dg(p->device);
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    NUSHT_TRY(ensure_capacity(p, 2 * nfields));
+    begin_call(p, NUSHT_CALL_SYNTHESIS_DERIV);
+    void* fine = nullptr;
+    NUSHT_TRY(synthesis_to_fine(p, alm, 2 * nfields, s, &fine, spin));
+    stage_begin(p, ST_POINTS, s);
+    NUSHT_TRY(launch_interp_deriv(p, reinterpret_cast<const double*>(fine), map, dtheta, dphi,
+                                  2 * nfields, s));
+    stage_end(p, ST_POINTS, s);
+    return NUSHT_OK;
+}
+
 }  // extern "C"
 
 namespace nusht {
