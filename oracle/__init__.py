@@ -243,14 +243,14 @@ def spin_adjoint_columns(lmax, s, theta, phi, maps, mlist, nthreads=0):
 
 
 from .pointing import alpha_from_potential, deflect_by_alpha, pointing  # noqa: E402
-from .twin import (cgls_dense, density_map, mdot, mlp_backward, mlp_forward,  # noqa: E402
-                   mlp_init, mlp_pack, mlp_unpack, point_features, synthesis_matrix,
+from .twin import (cgls_dense, cgls_spin, density_map, mdot, mlp_backward,  # noqa: E402
+                   mlp_forward, mlp_init, mlp_pack, mlp_unpack, point_features, synthesis_matrix,
                    weight_loss_dense, ylm_dense)
 
 __all__ = [
     "build", "nalm", "alm_index", "synthesis", "adjoint", "adjoint_columns", "synthesis_grad",
     "lambda_column", "spin_lambda_column", "spin_synthesis", "spin_adjoint",
-    "spin_adjoint_columns", "ylm_dense", "synthesis_matrix", "mdot", "cgls_dense", "mlp_init",
-    "mlp_forward", "mlp_backward", "mlp_pack", "mlp_unpack", "density_map", "point_features",
-    "weight_loss_dense", "pointing", "deflect_by_alpha", "alpha_from_potential",
+    "spin_adjoint_columns", "ylm_dense", "synthesis_matrix", "mdot", "cgls_dense", "cgls_spin",
+    "mlp_init", "mlp_forward", "mlp_backward", "mlp_pack", "mlp_unpack", "density_map",
+    "point_features", "weight_loss_dense", "pointing", "deflect_by_alpha", "alpha_from_potential",
 ]

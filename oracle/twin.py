@@ -9,6 +9,8 @@
   Eq. (2) are exact adjoints: <a, b>_m = sum_l [Re(a_l0* b_l0) + 2 sum_{m>0} Re(a_lm* b_lm)].
 * ``cgls_dense``: CGLS for min ||W^(1/2)(S a - d)|| with dense S (least squares on the
   synthesis, the setting in which transforms are called repeatedly, Sec. I).
+* ``cgls_spin``: the same CGLS for one spin-s field, with S and S^H the oracle's spin-s
+  synthesis and adjoint (direct sums) and <.,.>_m summed over the G and C triangles.
 * ``density_map``, ``point_features``, ``weight_loss_dense``: the learned-weight inputs and
   loss for the weighted least-squares inverse, written out plainly.
 * ``mlp_*``: an FP64 multilayer perceptron (tanh hidden layers, softplus output) with its
@@ -90,6 +92,43 @@ def cgls_dense(lmax, mmax, theta, phi, d, weights=None, x0=None, tol=1e-8, maxit
 
     w = np.ones_like(d) if weights is None else np.asarray(weights, dtype=np.float64)
     a = np.zeros(Y.shape[1], dtype=np.complex128) if x0 is None else x0.astype(np.complex128)
+    u = d - S(a)
+    s = SH(w * u)
+    p = s.copy()
+    gamma = mdot(s, s, lmax, mmax)
+    dn = np.linalg.norm(d)
+    hist = [np.linalg.norm(u) / dn]
+    it = 0
+    while hist[-1] > tol and it < maxiter:
+        q = S(p)
+        alpha = gamma / float(np.sum(w * q * q))
+        a = a + alpha * p
+        u = u - alpha * q
+        s = SH(w * u)
+        gnew = mdot(s, s, lmax, mmax)
+        p = s + (gnew / gamma) * p
+        gamma = gnew
+        it += 1
+        hist.append(np.linalg.norm(u) / dn)
+    return a, it, np.array(hist)
+
+
+def cgls_spin(lmax, mmax, spin, theta, phi, d, weights=None, x0=None, tol=1e-8, maxiter=1000):
+    """cgls_dense for one spin-s field: d [2, N] (Q, U) -> (a [2, nalm] (G, C), iterations,
+    history).  S is the oracle's spin synthesis, S^H its adjoint; a point's weight scales its
+    Q and its U residual."""
+    from . import spin_adjoint, spin_synthesis
+
+    def S(a):
+        return spin_synthesis(lmax, mmax, spin, theta, phi, a[None])[0]
+
+    def SH(f):
+        return spin_adjoint(lmax, mmax, spin, theta, phi, f[None])[0]
+
+    d = np.asarray(d, dtype=np.float64)
+    w = np.ones(d.shape[1]) if weights is None else np.asarray(weights, dtype=np.float64)
+    a = np.zeros((2, _nalm(lmax, mmax)), dtype=np.complex128) if x0 is None \
+        else np.array(x0, dtype=np.complex128)
     u = d - S(a)
     s = SH(w * u)
     p = s.copy()

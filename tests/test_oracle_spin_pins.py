@@ -354,3 +354,48 @@ def test_spin_addition_theorem_4095(oracle_mod, s, th):
     r = np.abs(tot[s:] / want[s:] - 1.0)
     assert np.all(r <= 2e-12 * np.sqrt(ls[s:] + 1.0)), (s, th, float(r.max()))
     assert np.all(tot[:s] == 0.0)
+
+
+def test_spin_cgls_reaches_library_least_squares(oracle_mod):
+    """The spin CGLS twin, run to its iteration limit on an inconsistent 600-row system (one
+    spin-2 field at L = 8: 154 real unknowns, condition number about 5, 50 iterations),
+    equals numpy's lstsq on the real matrix whose columns are the oracle's spin synthesis of
+    each unit coefficient, unweighted and with point weights (lstsq on W^(1/2) A, a point's
+    weight on both its Q and U rows).  Unknowns with l < s and the m = 0 imaginary parts are
+    outside the model.  Unweighted, the residual norm never grows (CGLS minimises it over
+    growing Krylov spaces)."""
+    rng = np.random.default_rng(51)
+    L = M = 8
+    s = 2
+    N = 300
+    th, ph = inputs.uniform_points(rng, N)
+    d = rng.standard_normal((2, N))
+    ls, ms = inputs.ell_of_index(L, M)
+    na = ls.size
+    cols = []                       # (component, index, imaginary?)
+    for c in range(2):
+        for j in range(na):
+            if ls[j] < s:
+                continue
+            cols.append((c, j, False))
+            if ms[j] > 0:
+                cols.append((c, j, True))
+    unit = np.zeros((len(cols), 2, na), dtype=np.complex128)
+    for k, (c, j, im) in enumerate(cols):
+        unit[k, c, j] = 1j if im else 1.0
+    A = oracle_mod.spin_synthesis(L, M, s, th, ph, unit).reshape(len(cols), 2 * N).T
+    for w in (None, rng.uniform(0.2, 3.0, N)):
+        sw = np.ones(2 * N) if w is None else np.sqrt(np.concatenate([w, w]))
+        z = np.linalg.lstsq(A * sw[:, None], d.reshape(-1) * sw, rcond=None)[0]
+        want = np.zeros((2, na), dtype=np.complex128)
+        for k, (c, j, im) in enumerate(cols):
+            want[c, j] += 1j * z[k] if im else z[k]
+        got, it, hist = oracle_mod.cgls_spin(L, M, s, th, ph, d, weights=w, tol=0.0,
+                                             maxiter=50)
+        err = np.sqrt(oracle_mod.mdot(got - want, got - want, L, M)
+                      / oracle_mod.mdot(want, want, L, M))
+        assert err <= 1e-10, err
+        assert it == 50
+        assert np.all(got[:, ls < s] == 0)
+        if w is None:
+            assert np.all(hist[1:] <= hist[:-1] * (1 + 1e-12))
