@@ -250,6 +250,20 @@ int nusht_solve_ex(nusht_plan_t plan, const double* map, double* alm, const floa
                    double tol, int maxiter, int* iters, double* relres, double* history,
                    void* stream);
 
+/* Spin-s least-squares inverse of nusht_synthesis_spin for one field: minimises
+   ||W^(1/2) (S_s a - d)||_2 over its gradient and curl coefficients a by the CGLS iteration of
+   nusht_solve_ex (same stopping test, restarts, status codes and history), with S_s^H
+   = nusht_adjoint_spin, the transpose of S_s in <.,.>_m summed over the G and C triangles.
+   spin: 1 <= spin <= min(lmax, NUSHT_MAX_SPIN), within the ring-grid limit of
+   nusht_synthesis_spin.  map: FP64 [2][npts] (Q then U), device.  alm: complex FP64
+   [2][nalm] (G then C), device, in/out: the initial iterate on entry (zeros for a cold
+   start), the solution on return.  weights: FP32 [npts] > 0, device, or NULL; point i's
+   weight multiplies its Q and its U residual.  Entries with l < spin stay as given (no
+   harmonic reaches them).  Synchronises. */
+int nusht_solve_spin(nusht_plan_t plan, int spin, const double* map, double* alm,
+                     const float* weights, double tol, int maxiter, int* iters, double* relres,
+                     double* history, void* stream);
+
 /* ---------------------------------------------------------------------------------------
  * Learned quadrature weights for the weighted least-squares inverse.
  *

@@ -122,6 +122,11 @@ def lib():
                                               ctypes.POINTER(ctypes.c_int),
                                               ctypes.POINTER(ctypes.c_double),
                                               ctypes.POINTER(ctypes.c_double), _vp]),
+            "nusht_solve_spin": (ctypes.c_int, [_vp, ctypes.c_int, _vp, _vp, _vp,
+                                                ctypes.c_double, ctypes.c_int,
+                                                ctypes.POINTER(ctypes.c_int),
+                                                ctypes.POINTER(ctypes.c_double),
+                                                ctypes.POINTER(ctypes.c_double), _vp]),
             "nusht_stage_times": (ctypes.c_int, [_vp, ctypes.POINTER(ctypes.c_double),
                                                  ctypes.POINTER(ctypes.c_char_p), ctypes.c_int]),
             "nusht_stage_stats": (ctypes.c_int, [_vp, ctypes.c_int, ctypes.POINTER(ctypes.c_double),
@@ -431,6 +436,43 @@ class Plan:
                                   _stream())
         if st not in (NUSHT_OK, NUSHT_ENOCONV) or (check and st != NUSHT_OK):
             _check(st, "nusht_solve")
+        if history:
+            import numpy as np
+            return alm, it.value, rr.value, st, np.array(hist[:it.value + 1])
+        return alm, it.value, rr.value, st
+
+    def solve_spin(self, spin, d, x0=None, weights=None, tol=1e-8, maxiter=1000, check=True,
+                   history=False):
+        """Spin-`spin` CGLS inverse of one field (nusht_solve_spin): d [2, npts] (Q, U) float64
+        -> (alm [2, nalm] complex128 (G, C), iterations, true relative residual, status),
+        plus the recurred relative residuals (numpy) if history."""
+        import torch
+        if d.dtype != torch.float64 or not d.is_cuda or d.device != self.device:
+            raise TypeError(f"d must be a float64 tensor on {self.device}")
+        x = d.reshape(-1)
+        if x.numel() != 2 * self.npts:
+            raise ValueError(f"d must hold one field's (Q, U): [2, {self.npts}]")
+        x = x.contiguous()
+        if x0 is None:
+            alm = torch.zeros((2, self.nalm), dtype=torch.complex128, device=x.device)
+        else:
+            if x0.dtype != torch.complex128 or x0.numel() != 2 * self.nalm:
+                raise ValueError(f"x0 must be complex128 [2, {self.nalm}]")
+            alm = x0.reshape(2, self.nalm).to(x.device).clone()
+        wptr = None
+        if weights is not None:
+            if weights.dtype != torch.float32 or weights.numel() != self.npts:
+                raise ValueError("weights must be float32 [npts]")
+            weights = weights.contiguous()
+            wptr = weights.data_ptr()
+        it = ctypes.c_int(0)
+        rr = ctypes.c_double(0.0)
+        hist = (ctypes.c_double * (int(maxiter) + 1))() if history else None
+        st = lib().nusht_solve_spin(self._h, int(spin), x.data_ptr(), alm.data_ptr(), wptr,
+                                    float(tol), int(maxiter), ctypes.byref(it), ctypes.byref(rr),
+                                    hist, _stream())
+        if st not in (NUSHT_OK, NUSHT_ENOCONV) or (check and st != NUSHT_OK):
+            _check(st, "nusht_solve_spin")
         if history:
             import numpy as np
             return alm, it.value, rr.value, st, np.array(hist[:it.value + 1])

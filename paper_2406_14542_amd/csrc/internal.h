@@ -259,6 +259,8 @@ int launch_legendre_adjoint(nusht_plan_s* p, const void* in, double* alm, int nm
 // ---- spin-weighted Legendre step (spin.hip) ----
 // tables for the given spin (rebuilt when it changes); nfields fields = 2 nfields maps (Q, U)
 int ensure_spin_tables(nusht_plan_s* p, int spin);
+// host check of a spin argument (range, and the shared-exponent limit of the ring grid)
+int check_spin(nusht_plan_s* p, int spin, const char* who);
 // fused: the doubled theta-columns [map][m][t]; otherwise the ring layout [map][j][m] with rows
 // of N_phi/2 + 1 (FP64) of the paper composition
 int launch_spin_synth(nusht_plan_s* p, int spin, const double* alm, void* out, int nfields,

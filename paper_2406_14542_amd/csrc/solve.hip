@@ -14,6 +14,11 @@
 // true residual d - S x is formed again; if it is still above tol (the recurrence drifts, more
 // so in mixed precision or with weights), CGLS restarts from x with that true residual, at
 // most kMaxRestarts times.
+//
+// The spin-s solve runs the same iteration with S the spin-s synthesis of one field (its
+// G, C coefficients to its Q, U maps) and S^H that synthesis's adjoint, which is its
+// transpose in the same <.,.>_m product summed over the two coefficient triangles; the
+// per-point weight applies to Q and U alike.
 #include <cmath>
 
 #include "internal.h"
@@ -39,18 +44,25 @@ __device__ inline double block_sum(double v, double* sh)
     return sh[0];
 }
 
+// A map-space vector holds one map (spin 0) or the two maps Q, U (spin s) of npts values
+// each, and a coefficient vector one or two (G, C) triangles of nalm; the weights and the
+// m = 0 test repeat per component.  wrap(i, n) maps an index of either component to its
+// position within the component.
+__device__ inline int64_t wrap(int64_t i, int64_t n) { return i < n ? i : i - n; }
+
 // partial[blk] = sum over the block's grid-stride range of w_i a_i b_i (w = 1 if null)
 __global__ __launch_bounds__(kRedThreads) void k_dot_map(const double* __restrict__ a,
                                                          const double* __restrict__ b,
                                                          const float* __restrict__ w,
-                                                         int64_t n, double* __restrict__ partial)
+                                                         int64_t n, int64_t npts,
+                                                         double* __restrict__ partial)
 {
     __shared__ double sh[kRedThreads];
     double acc = 0.0;
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
          i += (int64_t)gridDim.x * blockDim.x) {
         const double v = a[i] * b[i];
-        acc += w ? (double)w[i] * v : v;
+        acc += w ? (double)w[wrap(i, npts)] * v : v;
     }
     const double s = block_sum(acc, sh);
     if (threadIdx.x == 0) partial[blockIdx.x] = s;
@@ -59,16 +71,16 @@ __global__ __launch_bounds__(kRedThreads) void k_dot_map(const double* __restric
 // partial[blk] = sum of the <a, b>_m terms in the block's range (m = 0 block: idx <= lmax)
 __global__ __launch_bounds__(kRedThreads) void k_dot_alm(const double2* __restrict__ a,
                                                          const double2* __restrict__ b,
-                                                         int64_t nalm, int lmax,
+                                                         int64_t n, int64_t nalm, int lmax,
                                                          double* __restrict__ partial)
 {
     __shared__ double sh[kRedThreads];
     double acc = 0.0;
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < nalm;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
          i += (int64_t)gridDim.x * blockDim.x) {
         const double2 x = a[i], y = b[i];
         const double v = x.x * y.x + x.y * y.y;
-        acc += (i <= lmax) ? v : 2.0 * v;
+        acc += (wrap(i, nalm) <= lmax) ? v : 2.0 * v;
     }
     const double s = block_sum(acc, sh);
     if (threadIdx.x == 0) partial[blockIdx.x] = s;
@@ -114,25 +126,25 @@ __global__ void k_axpy_alm(double2* __restrict__ x, const double2* __restrict__ 
 // u -= alpha q; wu = w u (w = 1 if null)
 __global__ void k_update_u(double* __restrict__ u, const double* __restrict__ q,
                            const float* __restrict__ w, double* __restrict__ wu,
-                           const double* __restrict__ sc, int64_t n)
+                           const double* __restrict__ sc, int64_t n, int64_t npts)
 {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
     const double v = fma(-sc[SC_ALPHA], q[i], u[i]);
     u[i] = v;
-    wu[i] = w ? (double)w[i] * v : v;
+    wu[i] = w ? (double)w[wrap(i, npts)] * v : v;
 }
 
 // u = d - q; wu = w u
 __global__ void k_residual(const double* __restrict__ d, const double* __restrict__ q,
                            const float* __restrict__ w, double* __restrict__ u,
-                           double* __restrict__ wu, int64_t n)
+                           double* __restrict__ wu, int64_t n, int64_t npts)
 {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
     const double v = d[i] - q[i];
     u[i] = v;
-    if (wu) wu[i] = w ? (double)w[i] * v : v;
+    if (wu) wu[i] = w ? (double)w[wrap(i, npts)] * v : v;
 }
 
 // p = s + beta p
@@ -166,25 +178,33 @@ inline unsigned blocks_for(int64_t n) { return (unsigned)((n + 255) / 256); }
 
 using namespace nusht;
 
-extern "C" {
+namespace {
 
-int nusht_solve(nusht_plan_t p, const double* map, double* alm, const float* weights, double tol,
-                int maxiter, int* iters, double* relres, void* stream)
-{
-    return nusht_solve_ex(p, map, alm, weights, tol, maxiter, iters, relres, nullptr, stream);
-}
-
-int nusht_solve_ex(nusht_plan_t p, const double* map, double* alm, const float* weights,
-                   double tol, int maxiter, int* iters, double* relres, double* history,
-                   void* stream)
+// The CGLS loop for spin 0 (one map, one coefficient triangle) or spin s >= 1 (the Q, U
+// maps of one field and its G, C triangles): the same iteration on vectors of nc = 1 or 2
+// components, with S and S^H the transforms of that spin.
+int solve_impl(nusht_plan_t p, int spin, const char* who, const double* map, double* alm,
+               const float* weights, double tol, int maxiter, int* iters, double* relres,
+               double* history, void* stream)
 {
     if (!p || !map || !alm || !(tol > 0.0) || maxiter < 0) {
-        set_last_error("nusht_solve", "null plan/buffer, tol <= 0 or maxiter < 0");
+        set_last_error(who, "null plan/buffer, tol <= 0 or maxiter < 0");
         return NUSHT_EINVAL;
     }
+    if (spin != 0) NUSHT_TRY(check_spin(p, spin, who));
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
-    const int64_t n = p->g.npts, na = p->g.nalm;
+    const int nc = spin != 0 ? 2 : 1;
+    const int64_t npts = p->g.npts, nalm = p->g.nalm;
+    const int64_t n = nc * npts, na = nc * nalm;
     const int lmax = p->g.lmax;
+    auto synth = [&](const double* a, double* f) -> int {
+        return spin != 0 ? nusht_synthesis_spin(p, spin, a, f, 1, stream)
+                         : nusht_synthesis(p, a, f, 1, stream);
+    };
+    auto adjoint = [&](const double* f, double* a) -> int {
+        return spin != 0 ? nusht_adjoint_spin(p, spin, f, a, 1, stream)
+                         : nusht_adjoint(p, f, a, 1, stream);
+    };
     // solve scratch lives in the plan and is reused by later solves
     const size_t need = (size_t)na * 2 * sizeof(double2) + (size_t)n * 3 * sizeof(double) +
                         (kRedBlocks + SC_COUNT + 8) * sizeof(double);
@@ -210,7 +230,7 @@ int nusht_solve_ex(nusht_plan_t p, const double* map, double* alm, const float* 
     double2* x = reinterpret_cast<double2*>(alm);
 
     auto dot_map = [&](const double* a, const double* c, const float* w, int slot) -> int {
-        hipLaunchKernelGGL(k_dot_map, dim3(kRedBlocks), dim3(kRedThreads), 0, s, a, c, w, n,
+        hipLaunchKernelGGL(k_dot_map, dim3(kRedBlocks), dim3(kRedThreads), 0, s, a, c, w, n, npts,
                            b.partial);
         hipLaunchKernelGGL(k_finish, dim3(1), dim3(kRedThreads), 0, s, b.partial, kRedBlocks,
                            b.sc + slot);
@@ -218,8 +238,8 @@ int nusht_solve_ex(nusht_plan_t p, const double* map, double* alm, const float* 
         return NUSHT_OK;
     };
     auto dot_alm = [&](const double2* a, const double2* c, int slot) -> int {
-        hipLaunchKernelGGL(k_dot_alm, dim3(kRedBlocks), dim3(kRedThreads), 0, s, a, c, na, lmax,
-                           b.partial);
+        hipLaunchKernelGGL(k_dot_alm, dim3(kRedBlocks), dim3(kRedThreads), 0, s, a, c, na, nalm,
+                           lmax, b.partial);
         hipLaunchKernelGGL(k_finish, dim3(1), dim3(kRedThreads), 0, s, b.partial, kRedBlocks,
                            b.sc + slot);
         NUSHT_HIP(hipGetLastError());
@@ -240,26 +260,26 @@ int nusht_solve_ex(nusht_plan_t p, const double* map, double* alm, const float* 
     int it = 0;
     for (int restart = 0;; ++restart) {
         // u = d - S x (the true residual), then s = S^H W u, p = s, gamma = <s, s>_m
-        NUSHT_TRY(nusht_synthesis(p, alm, b.q, 1, stream));
+        NUSHT_TRY(synth(alm, b.q));
         hipLaunchKernelGGL(k_residual, dim3(blocks_for(n)), dim3(256), 0, s, map, b.q, weights,
-                           b.u, b.wu, n);
+                           b.u, b.wu, n, npts);
         NUSHT_TRY(dot_map(b.u, b.u, nullptr, SC_RR));
         NUSHT_TRY(read_scalar(SC_RR, &rr));
         if (history && restart == 0) history[0] = std::sqrt(rr / dn2);
         if (rr <= tol2 * dn2 || it >= maxiter || restart > kMaxRestarts) break;
-        NUSHT_TRY(nusht_adjoint(p, b.wu, reinterpret_cast<double*>(b.s), 1, stream));
+        NUSHT_TRY(adjoint(b.wu, reinterpret_cast<double*>(b.s)));
         NUSHT_HIP(hipMemcpyAsync(b.p, b.s, (size_t)na * sizeof(double2), hipMemcpyDeviceToDevice,
                                  s));
         NUSHT_TRY(dot_alm(b.s, b.s, SC_GAMMA));
         while (rr > tol2 * dn2 && it < maxiter) {
-            NUSHT_TRY(nusht_synthesis(p, reinterpret_cast<const double*>(b.p), b.q, 1, stream));
+            NUSHT_TRY(synth(reinterpret_cast<const double*>(b.p), b.q));
             NUSHT_TRY(dot_map(b.q, b.q, weights, SC_DELTA));
             hipLaunchKernelGGL(k_alpha, dim3(1), dim3(1), 0, s, b.sc);
             hipLaunchKernelGGL(k_axpy_alm, dim3(blocks_for(na)), dim3(256), 0, s, x, b.p, b.sc,
                                na);
             hipLaunchKernelGGL(k_update_u, dim3(blocks_for(n)), dim3(256), 0, s, b.u, b.q,
-                               weights, b.wu, b.sc, n);
-            NUSHT_TRY(nusht_adjoint(p, b.wu, reinterpret_cast<double*>(b.s), 1, stream));
+                               weights, b.wu, b.sc, n, npts);
+            NUSHT_TRY(adjoint(b.wu, reinterpret_cast<double*>(b.s)));
             NUSHT_TRY(dot_alm(b.s, b.s, SC_GNEW));
             hipLaunchKernelGGL(k_beta, dim3(1), dim3(1), 0, s, b.sc);
             hipLaunchKernelGGL(k_update_p, dim3(blocks_for(na)), dim3(256), 0, s, b.p, b.s, b.sc,
@@ -276,6 +296,33 @@ int nusht_solve_ex(nusht_plan_t p, const double* map, double* alm, const float* 
     if (relres) *relres = std::sqrt(rr / dn2);
     NUSHT_TRY(check_device_status(p));
     return rr <= tol2 * dn2 ? NUSHT_OK : NUSHT_ENOCONV;
+}
+
+}  // namespace
+
+extern "C" {
+
+int nusht_solve(nusht_plan_t p, const double* map, double* alm, const float* weights, double tol,
+                int maxiter, int* iters, double* relres, void* stream)
+{
+    return solve_impl(p, 0, "nusht_solve", map, alm, weights, tol, maxiter, iters, relres,
+                      nullptr, stream);
+}
+
+int nusht_solve_ex(nusht_plan_t p, const double* map, double* alm, const float* weights,
+                   double tol, int maxiter, int* iters, double* relres, double* history,
+                   void* stream)
+{
+    return solve_impl(p, 0, "nusht_solve", map, alm, weights, tol, maxiter, iters, relres,
+                      history, stream);
+}
+
+int nusht_solve_spin(nusht_plan_t p, int spin, const double* map, double* alm,
+                     const float* weights, double tol, int maxiter, int* iters, double* relres,
+                     double* history, void* stream)
+{
+    return solve_impl(p, spin, "nusht_solve_spin", map, alm, weights, tol, maxiter, iters,
+                      relres, history, stream);
 }
 
 }  // extern "C"

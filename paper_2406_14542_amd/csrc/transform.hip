@@ -449,6 +449,8 @@ int synthesis_to_fine(nusht_plan_s* p, const double* alm, int nmaps, hipStream_t
 }
 
 // the spin-weighted calls: 1 <= spin <= min(lmax, NUSHT_MAX_SPIN) and the exponent-range limit
+}  // namespace
+
 int check_spin(nusht_plan_s* p, int spin, const char* who)
 {
     if (spin < 1 || spin > p->g.lmax || spin > NUSHT_MAX_SPIN) {
@@ -465,6 +467,8 @@ int check_spin(nusht_plan_s* p, int spin, const char* who)
     }
     return NUSHT_OK;
 }
+
+namespace {
 
 int check_exec(nusht_plan_s* p, const void* a, const void* b, int nmaps)
 {

@@ -93,6 +93,8 @@ def test_geometry_validation():
     assert lib.nusht_adjoint(None, 1, 1, 1, None) == P.NUSHT_EINVAL
     assert lib.nusht_synthesis_spin(None, 2, 1, 1, 1, None) == P.NUSHT_EINVAL
     assert lib.nusht_adjoint_spin(None, 2, 1, 1, 1, None) == P.NUSHT_EINVAL
+    assert lib.nusht_solve_spin(None, 2, 1, 1, None, 1e-6, 5, None, None, None, None) == \
+        P.NUSHT_EINVAL
     lib.nusht_destroy(None)
 
 
