@@ -1,5 +1,6 @@
 """Spin-s CGLS inverse (nusht_solve_spin) against the oracle's spin CGLS twin, on consistent
-data with and without weights, from a warm start, and its argument checks."""
+data with and without weights, from a warm start, bit-reproducible on a deterministic plan in
+the paper DFS composition, and its argument checks."""
 import numpy as np
 import pytest
 
@@ -102,3 +103,23 @@ def test_spin_solve_arguments(P):
     x, it, rr, st = pl.solve_spin(2, d, tol=1e-12, maxiter=3, check=False)
     assert st == P.NUSHT_ENOCONV and it == 3 and 0 < rr < 1
     assert np.all(np.isfinite(x.cpu().numpy()))
+
+
+def test_spin_solve_deterministic_paper_mode(P):
+    """On a deterministic plan in the paper DFS composition, two spin solves of the same data
+    give identical bits, and they agree with the fused plan's solve."""
+    print("[spin cg deterministic, paper mode]", flush=True)
+    rng = np.random.default_rng(78)
+    L = 24
+    th, ph = inputs.uniform_points(rng, 3 * (L + 1) ** 2)
+    d = rng.standard_normal((2, th.size))
+    pp = P.Plan(L, L, dev(th), dev(ph), 1e-12, dfs_mode="paper", deterministic=True)
+    pf = P.Plan(L, L, dev(th), dev(ph), 1e-12)
+    x1, it1, rr1, _ = pp.solve_spin(2, dev(d), tol=1e-6, maxiter=30, check=False)
+    x2, it2, rr2, _ = pp.solve_spin(2, dev(d), tol=1e-6, maxiter=30, check=False)
+    assert it1 == it2 and rr1 == rr2
+    assert torch.equal(x1, x2)
+    xf, itf, rrf, _ = pf.solve_spin(2, dev(d), tol=1e-6, maxiter=30, check=False)
+    assert itf == it1
+    x1 = x1.cpu().numpy()
+    assert mnorm(xf.cpu().numpy() - x1, L, L) <= 1e-9 * mnorm(x1, L, L)
