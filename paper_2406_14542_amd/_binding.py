@@ -167,6 +167,13 @@ def _opts(sigma=0.0, width=0, beta_per_w=0.0, dfs_mode="fused", timing=False,
     return o
 
 
+def _coord_signature(x):
+    """Sums of x, x^2 and (i mod 1021) x_i over a device coordinate tensor (FP64)."""
+    import torch
+    w = torch.arange(x.numel(), dtype=torch.float64, device=x.device).remainder_(1021.0)
+    return torch.stack([x.sum(), (x * x).sum(), (w * x).sum()])
+
+
 def _dtype_code(dtype):
     return {"f64": NUSHT_F64, "mixed": NUSHT_MIXED}[dtype]
 
@@ -212,6 +219,25 @@ class Plan:
         _check(lib().nusht_plan_info(h, ctypes.byref(g)), "nusht_plan_info")
         self.geometry = g.as_dict()
         self.nalm = int(self.geometry["nalm"])
+        self._sig_theta = _coord_signature(theta)
+        self._sig_phi = _coord_signature(phi)
+
+    def check_points(self, theta=None, phi=None):
+        """Raise ValueError unless the given coordinate tensors hold the plan's points in the
+        caller's order (compared through sums of the values, their squares and an
+        index-weighted sum, so a moved or reordered point is caught)."""
+        import torch
+        for name, x, sig in (("theta", theta, self._sig_theta), ("phi", phi, self._sig_phi)):
+            if x is None:
+                continue
+            if x.dim() != 1 or x.numel() != self.npts or x.device != self.device:
+                raise ValueError(f"{name} must be a 1-D tensor of the plan's {self.npts} points "
+                                 f"on {self.device}")
+            got = _coord_signature(x.detach().to(torch.float64))
+            if not torch.allclose(got, sig, rtol=1e-13, atol=0.0):
+                raise ValueError(f"{name} differs from the coordinates the plan was built on; "
+                                 "gradients are taken at the plan's points: build a plan on "
+                                 "the new coordinates")
 
     def status(self):
         """Raise NushtError if a kernel of this plan flagged a device-side failure (waits for

@@ -9,7 +9,8 @@ respect to the point positions.  Forward and backward only call the library:
 * backward: ``nusht_vjp_alm`` (the adjoint kernel path, Eq. 2, with the complex-gradient
   convention dL/dRe a + i dL/dIm a: 2 Y^H g for m > 0, Re Y^H g for m = 0) and
   ``nusht_vjp_points`` (sum over maps of g * dmap/dtheta, g * dmap/dphi).
-The plan's points are fixed; ``theta`` / ``phi`` only carry the gradient back to the caller.
+The plan's points are fixed; ``theta`` / ``phi`` only carry the gradient back to the caller,
+and must hold the coordinates the plan was built on (checked: ValueError otherwise).
 ``synthesis_spin(plan, spin, alm)`` is the spin-weighted synthesis with its coefficient
 gradient (``nusht_vjp_alm_spin``).
 """
@@ -75,6 +76,8 @@ def synthesis_spin(plan, spin, alm):
 
 def synthesis(plan, alm, theta=None, phi=None):
     """Differentiable type-2 transform on the plan's points."""
+    if theta is not None or phi is not None:
+        plan.check_points(theta, phi)
     if theta is None:
         theta = torch.zeros(plan.npts, dtype=torch.float64, device=alm.device)
     if phi is None:

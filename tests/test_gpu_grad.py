@@ -124,6 +124,28 @@ def test_autograd_positions_against_oracle_and_fd(P, oracle_mod):
         assert abs(fd - an) <= 1e-5 * abs(an), (which, fd, an)
 
 
+def test_autograd_refuses_other_points(P):
+    """Position gradients are taken at the plan's points, so coordinates that differ from
+    them (moved, or the same points in another order) are refused; the plan's own
+    coordinates, as new tensors, are accepted."""
+    print("[autograd point check]", flush=True)
+    from paper_2406_14542_amd.autograd import synthesis
+    rng = np.random.default_rng(34)
+    L = 16
+    th0, ph0 = inputs.uniform_points(rng, 800)
+    a = dev(inputs.red_alm(rng, L, L, 1))
+    pl = P.Plan(L, L, dev(th0), dev(ph0), 1e-10)
+    ok = synthesis(pl, a, dev(th0.copy()).requires_grad_(True), dev(ph0).requires_grad_(True))
+    assert ok.shape == (1, 800)
+    perm = rng.permutation(800)
+    for t, p in ((th0 + 1e-4 * rng.standard_normal(800), ph0), (th0, ph0[perm]),
+                 (th0[perm], ph0[perm]), (th0[:799], ph0[:799])):
+        with pytest.raises(ValueError):
+            synthesis(pl, a, dev(t).requires_grad_(True), dev(p).requires_grad_(True))
+    with pytest.raises(ValueError):
+        synthesis(pl, a, None, dev(ph0 + 1e-3).requires_grad_(True))
+
+
 def test_c4_gradients_full_size(P, oracle_mod):
     """lmax = 1023, 8 maps, the deflected 1024 x 2047 grid (2' rms): loss = sum w f^2.
     Position gradients are summed over the batch; checked against the oracle on sampled
